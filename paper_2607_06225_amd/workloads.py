@@ -1,0 +1,328 @@
+"""Seeded synthetic alignment workloads (inputs only, no alignment arithmetic).
+
+This module builds sequences, lengths and scoring schemes.  It is the only
+code shared between the GPU path's tests/benchmark and the CPU oracle's tests:
+both sides receive the same bytes from here.
+
+Random numbers come from SplitMix64 used as a counter-based generator: draw n
+of stream (seed, stream_id) is  mix(key + (n+1) * 0x9E3779B97F4A7C15)  with
+key = mix(seed * 0x100000001B3 + stream_id) and mix() the SplitMix64 output
+function (Steele, Lea & Flood, "Fast splittable pseudorandom number
+generators", OOPSLA 2014).  Draws are reproducible independent of NumPy's own
+generators.  Uniform doubles use the top 53 bits; integers in [lo, hi] are
+floor(u * (hi - lo + 1)) + lo.
+
+Workloads (codes: DNA A,C,G,T = 0..3; protein = 0..19):
+  nw_dna_1k      256 pairs, reference 1000 bp, query = reference with 10% edits
+                 (substitution:insertion:deletion = 2:1:1); NW, +2/-4, open -4,
+                 extend -2; full matrix + CIGAR.
+  sw_protein     65,536 pairs, lengths lognormal (median 350, sigma 0.6) clipped
+                 to [50, 2000] per side, 30% homologous (40% identity window);
+                 symmetric seeded 20x20 matrix (diagonal U{4..11}, off-diagonal
+                 U{-4..3}); SW, open -11, extend -1; score + end cell.
+  band_long      2,048 pairs, reference U{10,000..100,000} bp, query with 12%
+                 errors (insertion:deletion:substitution = 5:4:3); NW, +1/-2,
+                 open -2, extend -1; static band half-width 256 + CIGAR.
+  xdrop_ext      200,000 seed extensions (31 bp exact seed), each side of length
+                 U{150..5,000} at divergence U[0.05, 0.25] (2:1:1) followed by
+                 an unrelated random flank of ceil(0.1 L) bases; EXTEND + X-drop
+                 X = 100, +2/-4, open -4, extend -2.  Both sides are stored as
+                 sequences read away from the seed (the left side reversed).
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+GLOBAL, LOCAL, EXTEND = 0, 1, 2
+FULL, BAND, XDROP = 0, 1, 2
+
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def _mix(z):
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+class Stream:
+    """Counter-based SplitMix64 stream; every call consumes fresh counters."""
+
+    def __init__(self, seed, stream_id=0):
+        with np.errstate(over="ignore"):
+            k = np.uint64(seed) * np.uint64(0x100000001B3) + np.uint64(stream_id)
+        self.key = _mix(np.array([k], dtype=np.uint64))[0]
+        self.ctr = 0
+
+    def u64(self, n):
+        idx = np.arange(self.ctr + 1, self.ctr + 1 + n, dtype=np.uint64)
+        self.ctr += n
+        with np.errstate(over="ignore"):
+            return _mix(self.key + idx * _GAMMA)
+
+    def uniform(self, n):
+        return (self.u64(n) >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))
+
+    def integers(self, lo, hi, n):
+        """n integers uniform in [lo, hi] (inclusive), as int64."""
+        span = np.asarray(hi, dtype=np.int64) - np.asarray(lo, dtype=np.int64) + 1
+        u = self.uniform(n)
+        return (np.floor(u * span).astype(np.int64) + lo).astype(np.int64)
+
+    def normal(self, n):
+        """Box-Muller standard normals."""
+        u1 = self.uniform(n)
+        u2 = self.uniform(n)
+        u1 = np.where(u1 <= 0.0, 1.0 / (1 << 53), u1)
+        return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+@dataclass
+class Batch:
+    """A batch of pairs in the layout the library consumes."""
+    name: str
+    q: np.ndarray          # uint8 codes, concatenated
+    q_off: np.ndarray      # int64
+    q_len: np.ndarray      # int32
+    r: np.ndarray
+    r_off: np.ndarray
+    r_len: np.ndarray
+    matrix: np.ndarray     # int32 [alphabet, alphabet]
+    gap_open: int
+    gap_extend: int
+    mode: int
+    prune: int
+    band_w: int = 0
+    xdrop: int = 0
+    want_cigar: bool = False
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self):
+        return int(self.q_len.size)
+
+    @property
+    def alphabet(self):
+        return int(self.matrix.shape[0])
+
+    def pair(self, p):
+        qs = self.q[self.q_off[p]: self.q_off[p] + self.q_len[p]]
+        rs = self.r[self.r_off[p]: self.r_off[p] + self.r_len[p]]
+        return qs, rs
+
+    def subset(self, idx, name=None):
+        idx = np.asarray(idx, dtype=np.int64)
+        qs = [self.pair(int(p))[0] for p in idx]
+        rs = [self.pair(int(p))[1] for p in idx]
+        b = pack_pairs(qs, rs, self.matrix, self.gap_open, self.gap_extend,
+                       self.mode, self.prune, self.band_w, self.xdrop,
+                       self.want_cigar, name or self.name + "_subset")
+        b.meta = dict(self.meta, subset_of=self.name, subset_idx=idx)
+        return b
+
+
+def pack_pairs(qs, rs, matrix, gap_open, gap_extend, mode, prune, band_w=0,
+               xdrop=0, want_cigar=False, name="pairs"):
+    ql = np.array([len(x) for x in qs], dtype=np.int32)
+    rl = np.array([len(x) for x in rs], dtype=np.int32)
+    qo = np.zeros(len(qs), dtype=np.int64)
+    ro = np.zeros(len(rs), dtype=np.int64)
+    if len(qs) > 1:
+        qo[1:] = np.cumsum(ql[:-1], dtype=np.int64)
+        ro[1:] = np.cumsum(rl[:-1], dtype=np.int64)
+    q = (np.concatenate([np.asarray(x, dtype=np.uint8) for x in qs])
+         if len(qs) and ql.sum() else np.zeros(0, dtype=np.uint8))
+    r = (np.concatenate([np.asarray(x, dtype=np.uint8) for x in rs])
+         if len(rs) and rl.sum() else np.zeros(0, dtype=np.uint8))
+    return Batch(name, q, qo, ql, r, ro, rl, np.ascontiguousarray(matrix, dtype=np.int32),
+                 int(gap_open), int(gap_extend), int(mode), int(prune), int(band_w),
+                 int(xdrop), bool(want_cigar))
+
+
+def dna_matrix(match, mismatch):
+    m = np.full((4, 4), mismatch, dtype=np.int32)
+    np.fill_diagonal(m, match)
+    return m
+
+
+def protein_matrix(seed):
+    """Symmetric 20x20: S[a][a] ~ U{4..11}; for a < b, S[a][b] = S[b][a] ~
+    U{-4..3}, drawn in the order a = 0..19 (diagonal first), then b = a+1..19."""
+    st = Stream(seed, 99)
+    m = np.zeros((20, 20), dtype=np.int32)
+    for a in range(20):
+        m[a, a] = st.integers(4, 11, 1)[0]
+        for b in range(a + 1, 20):
+            v = st.integers(-4, 3, 1)[0]
+            m[a, b] = v
+            m[b, a] = v
+    return m
+
+
+def mutate(ref, rate, w_sub, w_ins, w_del, alphabet, st):
+    """Walk ref; each base is edited with probability ``rate``, the edit type
+    drawn with weights sub:ins:del.  sub = a uniformly random different code;
+    ins = copy the base, then insert one random code; del = drop the base."""
+    n = ref.size
+    u_edit = st.uniform(n)
+    u_type = st.uniform(n)
+    u_c1 = st.uniform(n)
+    u_c2 = st.uniform(n)
+    tot = float(w_sub + w_ins + w_del)
+    edit = u_edit < rate
+    t = u_type * tot
+    is_sub = edit & (t < w_sub)
+    is_ins = edit & (t >= w_sub) & (t < w_sub + w_ins)
+    is_del = edit & (t >= w_sub + w_ins)
+    first = ref.astype(np.int64).copy()
+    shift = 1 + np.floor(u_c1 * (alphabet - 1)).astype(np.int64)
+    first[is_sub] = (first[is_sub] + shift[is_sub]) % alphabet
+    second = np.floor(u_c2 * alphabet).astype(np.int64)
+    cnt = np.ones(n, dtype=np.int64)
+    cnt[is_ins] = 2
+    cnt[is_del] = 0
+    out = np.empty(int(cnt.sum()), dtype=np.uint8)
+    starts = np.cumsum(cnt) - cnt
+    keep = cnt >= 1
+    out[starts[keep]] = first[keep]
+    out[starts[is_ins] + 1] = second[is_ins]
+    return out
+
+
+def random_codes(st, n, alphabet):
+    return np.floor(st.uniform(n) * alphabet).astype(np.uint8)
+
+
+# ---------------------------------------------------------------- configs
+def nw_dna_1k(n=256, ref_len=1000, seed=101):
+    st = Stream(seed, 1)
+    qs, rs = [], []
+    for _ in range(n):
+        ref = random_codes(st, ref_len, 4)
+        qry = mutate(ref, 0.10, 2, 1, 1, 4, st)
+        qs.append(qry)
+        rs.append(ref)
+    b = pack_pairs(qs, rs, dna_matrix(2, -4), -4, -2, GLOBAL, FULL,
+                   want_cigar=True, name="nw_dna_1k")
+    b.meta = dict(seed=seed)
+    return b
+
+
+def _lognormal_lengths(st, n, median, sigma, lo, hi):
+    z = st.normal(n)
+    x = np.exp(np.log(median) + sigma * z)
+    return np.clip(np.rint(x), lo, hi).astype(np.int64)
+
+
+def sw_protein(n=65536, seed=202, sigma=0.6, homolog_frac=0.3, identity=0.4):
+    st = Stream(seed, 2)
+    mat = protein_matrix(seed)
+    M = _lognormal_lengths(st, n, 350.0, sigma, 50, 2000)
+    N = _lognormal_lengths(st, n, 350.0, sigma, 50, 2000)
+    hom = st.uniform(n) < homolog_frac
+    q_all = random_codes(st, int(M.sum()), 20)
+    r_all = random_codes(st, int(N.sum()), 20)
+    qo = np.zeros(n, dtype=np.int64)
+    ro = np.zeros(n, dtype=np.int64)
+    qo[1:] = np.cumsum(M[:-1])
+    ro[1:] = np.cumsum(N[:-1])
+    # homologous pairs: a window of length min(M,N) at random offsets in both;
+    # the query window copies the reference window, keeping each residue with
+    # probability `identity`, else a uniformly random different residue
+    idx = np.nonzero(hom)[0]
+    W = np.minimum(M[idx], N[idx])
+    uq = st.uniform(idx.size)
+    ur = st.uniform(idx.size)
+    oq = np.floor(uq * (M[idx] - W + 1)).astype(np.int64)
+    orr = np.floor(ur * (N[idx] - W + 1)).astype(np.int64)
+    tot = int(W.sum())
+    keep = st.uniform(tot) < identity
+    shift = 1 + np.floor(st.uniform(tot) * 19).astype(np.int64)
+    src = np.concatenate([ro[p] + o + np.arange(w) for p, o, w in zip(idx, orr, W)]) \
+        if idx.size else np.zeros(0, dtype=np.int64)
+    dst = np.concatenate([qo[p] + o + np.arange(w) for p, o, w in zip(idx, oq, W)]) \
+        if idx.size else np.zeros(0, dtype=np.int64)
+    base = r_all[src].astype(np.int64)
+    q_all[dst] = np.where(keep, base, (base + shift) % 20).astype(np.uint8)
+    b = Batch("sw_protein", q_all, qo, M.astype(np.int32), r_all, ro, N.astype(np.int32),
+              mat, -11, -1, LOCAL, FULL)
+    b.meta = dict(seed=seed, sigma=sigma, homologous=hom)
+    return b
+
+
+def band_long(n=2048, seed=303, min_len=10000, max_len=100000, band_w=256):
+    st = Stream(seed, 3)
+    L = st.integers(min_len, max_len, n)
+    qs, rs = [], []
+    for p in range(n):
+        ref = random_codes(st, int(L[p]), 4)
+        qry = mutate(ref, 0.12, 3, 5, 4, 4, st)
+        qs.append(qry)
+        rs.append(ref)
+    b = pack_pairs(qs, rs, dna_matrix(1, -2), -2, -1, GLOBAL, BAND, band_w=band_w,
+                   want_cigar=True, name="band_long")
+    b.meta = dict(seed=seed)
+    return b
+
+
+def xdrop_ext(n=200000, seed=404, min_len=150, max_len=5000, xdrop=100, seed_len=31):
+    """2n extension problems: entries [0, n) are left sides, [n, 2n) right
+    sides of the same n seeds.  meta['seed_score'] is the exact seed's score."""
+    st = Stream(seed, 4)
+    qs, rs = [], []
+    sides = []
+    for side in range(2):
+        L = st.integers(min_len, max_len, n)
+        div = 0.05 + 0.20 * st.uniform(n)
+        for p in range(n):
+            ext = random_codes(st, int(L[p]), 4)
+            flank_len = int(np.ceil(0.1 * L[p]))
+            rflank = random_codes(st, flank_len, 4)
+            qext = mutate(ext, float(div[p]), 2, 1, 1, 4, st)
+            qflank = random_codes(st, flank_len, 4)
+            rs.append(np.concatenate([ext, rflank]))
+            qs.append(np.concatenate([qext, qflank]))
+        sides.append(dict(L=L, div=div))
+    seeds = random_codes(st, n * seed_len, 4).reshape(n, seed_len)
+    b = pack_pairs(qs, rs, dna_matrix(2, -4), -4, -2, EXTEND, XDROP, xdrop=xdrop,
+                   name="xdrop_ext")
+    b.meta = dict(seed=seed, n_ext=n, seed_len=seed_len, seed_score=2 * seed_len,
+                  seeds=seeds, sides=sides)
+    return b
+
+
+WORKLOADS = {
+    "nw_dna_1k": nw_dna_1k,
+    "sw_protein": sw_protein,
+    "band_long": band_long,
+    "xdrop_ext": xdrop_ext,
+}
+
+
+def serving_requests(n_req, qps, seed=505, mix=(0.4, 0.3, 0.1, 0.2),
+                     scale_long=1.0):
+    """Poisson arrivals (exponential gaps) of single-pair requests drawn from the
+    four workloads above in proportions ``mix``.  Returns (arrival_s, kinds,
+    batches) where batches[k] is a Batch holding that kind's requests in order.
+    ``scale_long`` < 1 shortens band_long requests (for small test runs)."""
+    st = Stream(seed, 5)
+    gaps = -np.log(np.maximum(st.uniform(n_req), 1e-300)) / float(qps)
+    arrival = np.cumsum(gaps)
+    u = st.uniform(n_req)
+    cum = np.cumsum(np.asarray(mix, dtype=np.float64))
+    kinds = np.searchsorted(cum / cum[-1], u, side="right").astype(np.int64)
+    kinds = np.minimum(kinds, 3)
+    counts = [int((kinds == k).sum()) for k in range(4)]
+    batches = [
+        nw_dna_1k(n=max(counts[0], 1), seed=seed + 1),
+        sw_protein(n=max(counts[1], 1), seed=seed + 2),
+        band_long(n=max(counts[2], 1), seed=seed + 3,
+                  min_len=max(64, int(10000 * scale_long)),
+                  max_len=max(128, int(100000 * scale_long))),
+        xdrop_ext(n=max((counts[3] + 1) // 2, 1), seed=seed + 4),
+    ]
+    return arrival, kinds, batches
