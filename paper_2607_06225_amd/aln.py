@@ -1,0 +1,259 @@
+"""Thin ctypes binding of libaln_hip.so (include/aln.h).
+
+Argument marshalling only: every alignment step runs in the HIP library.
+PyTorch supplies device memory (tensors) and streams.  Importing this module
+does not touch the GPU; the first Context() loads the library and raises if
+it has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libaln_hip.so")
+
+GLOBAL, LOCAL, EXTEND = 0, 1, 2
+FULL, BAND, XDROP = 0, 1, 2
+W_AUTO, W_I16, W_I32 = 0, 1, 2
+R_OK, R_UNREACHABLE, R_CIGAR_CAP, R_BAD_SYMBOL = 0, 1, 2, 3
+F_I16_RERUN, F_WIDENED = 1, 2
+OP_I, OP_D, OP_EQ, OP_X = 1, 2, 7, 8
+
+RESULT_DTYPE = np.dtype([
+    ("score", "<i4"), ("q_end", "<i4"), ("r_end", "<i4"), ("q_begin", "<i4"),
+    ("r_begin", "<i4"), ("status", "<i4"), ("flags", "<i4"), ("cigar_len", "<i4"),
+    ("cells", "<i8"), ("cigar_off", "<i8")])
+assert RESULT_DTYPE.itemsize == 48
+
+
+class AlnError(RuntimeError):
+    pass
+
+
+class _Scoring(ctypes.Structure):
+    _fields_ = [("alphabet", ctypes.c_int32), ("matrix", ctypes.c_void_p),
+                ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("prune", ctypes.c_int32),
+                ("band_w", ctypes.c_int32), ("xdrop", ctypes.c_int32),
+                ("width", ctypes.c_int32), ("want_cigar", ctypes.c_int32)]
+
+
+class _Batch(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("q", ctypes.c_void_p), ("q_off", ctypes.c_void_p),
+                ("q_len", ctypes.c_void_p), ("r", ctypes.c_void_p),
+                ("r_off", ctypes.c_void_p), ("r_len", ctypes.c_void_p)]
+
+
+class _Footprint(ctypes.Structure):
+    _fields_ = [("workspace_bytes", ctypes.c_uint64), ("traceback_bytes", ctypes.c_uint64),
+                ("cigar_words", ctypes.c_uint64), ("cells", ctypes.c_int64)]
+
+
+_lib = None
+
+# every symbol include/aln.h declares
+EXPORTS = [
+    "aln_abi_version", "aln_create", "aln_destroy", "aln_last_error",
+    "aln_set_scoring", "aln_plan_create", "aln_plan_destroy", "aln_execute",
+    "aln_execute_per_pair", "aln_graph_capture", "aln_graph_launch",
+]
+
+
+def load_library(path=LIB_PATH):
+    """Load libaln_hip.so and declare its signatures (no GPU call)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise AlnError(f"{path} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    P, I32, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64
+    sig = {
+        "aln_abi_version": ([], I32),
+        "aln_create": ([P, I32], I32),
+        "aln_destroy": ([P], None),
+        "aln_last_error": ([P], ctypes.c_char_p),
+        "aln_set_scoring": ([P, P, P], I32),
+        "aln_plan_create": ([P, I32, P, I32, P, P, P, P], I32),
+        "aln_plan_destroy": ([P], None),
+        "aln_execute": ([P, P, P, P, U64, P, P, U64, P], I32),
+        "aln_execute_per_pair": ([P, P, P, P, U64, P, P, U64, P], I32),
+        "aln_graph_capture": ([P, P, P, P, U64, P, P, U64, P], I32),
+        "aln_graph_launch": ([P, P, P], I32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    def __init__(self, ctx, handle, fp, n, params):
+        self.ctx = ctx
+        self.handle = handle
+        self.workspace_bytes = int(fp.workspace_bytes)
+        self.traceback_bytes = int(fp.traceback_bytes)
+        self.cigar_words = int(fp.cigar_words)
+        self.cells = int(fp.cells)
+        self.n = n
+        self.params = params
+
+    def close(self):
+        if self.handle is not None:
+            self.ctx.lib.aln_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DeviceBatch:
+    """A workloads.Batch copied to device tensors, in the layout aln_batch names."""
+
+    def __init__(self, batch, device="cuda"):
+        import torch
+        self.src = batch
+        self.n = batch.n
+        self.q = torch.from_numpy(np.ascontiguousarray(batch.q)).to(device)
+        self.q_off = torch.from_numpy(np.ascontiguousarray(batch.q_off)).to(device)
+        self.q_len = torch.from_numpy(np.ascontiguousarray(batch.q_len)).to(device)
+        self.r = torch.from_numpy(np.ascontiguousarray(batch.r)).to(device)
+        self.r_off = torch.from_numpy(np.ascontiguousarray(batch.r_off)).to(device)
+        self.r_len = torch.from_numpy(np.ascontiguousarray(batch.r_len)).to(device)
+        self.q_len_host = np.ascontiguousarray(batch.q_len, dtype=np.int32)
+        self.r_len_host = np.ascontiguousarray(batch.r_len, dtype=np.int32)
+        self.c = _Batch(self.n, self.q.data_ptr(), self.q_off.data_ptr(), self.q_len.data_ptr(),
+                        self.r.data_ptr(), self.r_off.data_ptr(), self.r_len.data_ptr())
+
+
+class Context:
+    def __init__(self, device=0):
+        self.lib = load_library()
+        self.device = device
+        h = ctypes.c_void_p()
+        self._check(self.lib.aln_create(ctypes.byref(h), int(device)), None)
+        self.handle = h
+
+    def _check(self, rc, handle="self"):
+        if rc != 0:
+            msg = b""
+            if handle is not None and getattr(self, "handle", None) is not None:
+                msg = self.lib.aln_last_error(self.handle) or b""
+            raise AlnError(f"aln call failed ({rc}): {msg.decode(errors='replace')}")
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            self.lib.aln_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_scoring(self, matrix, gap_open, gap_extend):
+        mat = np.ascontiguousarray(np.asarray(matrix, dtype=np.int32))
+        A = int(mat.shape[0])
+        sc = _Scoring(A, mat.ctypes.data, int(gap_open), int(gap_extend))
+        sid = ctypes.c_int32()
+        self._check(self.lib.aln_set_scoring(self.handle, ctypes.byref(sc), ctypes.byref(sid)))
+        return int(sid.value)
+
+    def plan(self, scoring_id, q_len_host, r_len_host, mode, prune=FULL, band_w=0, xdrop=0,
+             width=W_AUTO, want_cigar=False):
+        ql = np.ascontiguousarray(q_len_host, dtype=np.int32)
+        rl = np.ascontiguousarray(r_len_host, dtype=np.int32)
+        params = _Params(int(mode), int(prune), int(band_w), int(xdrop), int(width),
+                         1 if want_cigar else 0)
+        h = ctypes.c_void_p()
+        fp = _Footprint()
+        self._check(self.lib.aln_plan_create(self.handle, int(scoring_id), ctypes.byref(params),
+                                             int(ql.size), ql.ctypes.data, rl.ctypes.data,
+                                             ctypes.byref(h), ctypes.byref(fp)))
+        return Plan(self, h, fp, int(ql.size), params)
+
+    def _exec(self, fn, plan, dbatch, ws, res, cigar, stream):
+        self._check(fn(self.handle, plan.handle, ctypes.byref(dbatch.c), _ptr(ws),
+                       int(ws.numel()) if ws is not None else 0, _ptr(res), _ptr(cigar),
+                       int(cigar.numel()) if cigar is not None else 0, _stream_handle(stream)))
+
+    def execute(self, plan, dbatch, ws, res, cigar=None, stream=None):
+        self._exec(self.lib.aln_execute, plan, dbatch, ws, res, cigar, stream)
+
+    def execute_per_pair(self, plan, dbatch, ws, res, cigar=None, stream=None):
+        self._exec(self.lib.aln_execute_per_pair, plan, dbatch, ws, res, cigar, stream)
+
+    def graph_capture(self, plan, dbatch, ws, res, cigar=None, stream=None):
+        self._exec(self.lib.aln_graph_capture, plan, dbatch, ws, res, cigar, stream)
+
+    def graph_launch(self, plan, stream=None):
+        self._check(self.lib.aln_graph_launch(self.handle, plan.handle, _stream_handle(stream)))
+
+
+class Buffers:
+    """Device buffers for one plan: workspace (uint8), results, CIGAR words."""
+
+    def __init__(self, plan, device="cuda"):
+        import torch
+        self.ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device=device)
+        self.res = torch.zeros(max(plan.n, 1) * RESULT_DTYPE.itemsize, dtype=torch.uint8,
+                               device=device)
+        self.cigar = (torch.zeros(max(plan.cigar_words, 1), dtype=torch.int32, device=device)
+                      if plan.params.want_cigar else None)
+
+    def results(self, n):
+        raw = self.res.cpu().numpy()
+        return np.frombuffer(raw.tobytes(), dtype=RESULT_DTYPE, count=n).copy()
+
+    def cigars(self, res):
+        if self.cigar is None:
+            return None
+        words = self.cigar.cpu().numpy().view(np.uint32)
+        return [words[int(r["cigar_off"]): int(r["cigar_off"]) + int(r["cigar_len"])].copy()
+                for r in res]
+
+
+def align(ctx, batch, scoring_id=None, width=W_AUTO, mode=None, per_pair=False, graph=False,
+          stream=None, dbatch=None):
+    """Plan and run one workloads.Batch; returns (results ndarray, cigars or None)."""
+    import torch
+    if scoring_id is None:
+        scoring_id = ctx.set_scoring(batch.matrix, batch.gap_open, batch.gap_extend)
+    plan = ctx.plan(scoring_id, batch.q_len, batch.r_len, batch.mode if mode is None else mode,
+                    batch.prune, batch.band_w, batch.xdrop, width, batch.want_cigar)
+    db = dbatch if dbatch is not None else DeviceBatch(batch)
+    buf = Buffers(plan)
+    if graph:
+        s = stream or torch.cuda.Stream()
+        ctx.graph_capture(plan, db, buf.ws, buf.res, buf.cigar, stream=s)
+        s.synchronize()
+    elif per_pair:
+        ctx.execute_per_pair(plan, db, buf.ws, buf.res, buf.cigar, stream=stream)
+    else:
+        ctx.execute(plan, db, buf.ws, buf.res, buf.cigar, stream=stream)
+    torch.cuda.synchronize()
+    res = buf.results(batch.n)
+    cig = buf.cigars(res)
+    plan.close()
+    return res, cig

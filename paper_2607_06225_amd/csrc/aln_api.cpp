@@ -1,0 +1,441 @@
+// aln_api.cpp -- host runtime behind include/aln.h.
+//
+// Planning happens on the host from the pairs' lengths: each pair gets a
+// kernel and a tile shape, pairs of one shape are ordered longest first
+// (largest cell count first, so the tail of a launch is short work), and the
+// workspace is laid out as [task lists | traceback codes].  Executing a plan
+// uploads the task lists from pinned memory and enqueues the kernels on the
+// caller's stream; nothing is allocated on that path.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using alnk::DevScoring;
+using alnk::PairTask;
+
+struct aln_ctx {
+  int device = 0;
+  std::string err;
+  std::vector<DevScoring *> dsc; // device copies, owned
+  std::vector<DevScoring> hsc;   // host mirrors
+};
+
+namespace {
+
+enum Kind { K_STRIP = 0 };
+
+struct LaunchDesc {
+  int kind;
+  int rows;
+  int mode;
+  bool tb;
+  bool small;
+  int32_t first; // first task of this launch
+  int32_t count;
+  int32_t lds_bnd;
+  int32_t lds_prof;
+};
+
+constexpr uint64_t kAlign = 256;
+uint64_t align_up(uint64_t v, uint64_t a = kAlign) { return (v + a - 1) / a * a; }
+
+aln_status fail(aln_ctx *ctx, aln_status st, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return st;
+}
+
+#define HIP_TRY(ctx, call)                                                       \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess)                                                        \
+      return fail((ctx), ALN_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+// Rows per lane for the strip kernel: fewest padded cells plus a per-step
+// overhead of about eight cells per lane.
+int choose_strip_rows(int32_t M, int32_t N) {
+  static const int cand[] = {8, 16, 24, 32};
+  int best = 16;
+  double best_cost = 1e300;
+  for (int R : cand) {
+    const int64_t HS = 64LL * R;
+    const int64_t ns = (M + HS - 1) / HS;
+    const double cost = (double)ns * (double)(N + 63) * 64.0 * (double)(R + 8);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = R;
+    }
+  }
+  return best;
+}
+
+} // namespace
+
+struct aln_plan {
+  aln_ctx *ctx = nullptr;
+  int32_t scoring_id = 0;
+  aln_params p{};
+  int32_t n = 0;
+  std::vector<int32_t> qlen, rlen;
+  std::vector<PairTask> tasks;
+  std::vector<LaunchDesc> launches;
+  uint64_t tasks_bytes = 0;
+  uint64_t tb_base = 0;
+  uint64_t tb_bytes = 0;
+  uint64_t ws_bytes = 0;
+  uint64_t cigar_words = 0;
+  int64_t cells = 0;
+  void *pinned = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+};
+
+extern "C" {
+
+int32_t aln_abi_version(void) { return ALN_ABI_VERSION; }
+
+aln_status aln_create(aln_ctx **ctx, int32_t device) {
+  if (!ctx) return ALN_E_INVAL;
+  *ctx = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return ALN_E_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return ALN_E_DEVICE;
+  aln_ctx *c = new (std::nothrow) aln_ctx;
+  if (!c) return ALN_E_NOMEM;
+  c->device = device;
+  *ctx = c;
+  return ALN_OK;
+}
+
+void aln_destroy(aln_ctx *ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  for (DevScoring *d : ctx->dsc) hipFree(d);
+  delete ctx;
+}
+
+const char *aln_last_error(const aln_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+aln_status aln_set_scoring(aln_ctx *ctx, const aln_scoring *sc, int32_t *scoring_id) {
+  if (!ctx || !sc || !scoring_id || !sc->matrix) return fail(ctx, ALN_E_INVAL, "null argument");
+  const int A = sc->alphabet;
+  if (A < 1 || A > alnk::kMaxAlphabet)
+    return fail(ctx, ALN_E_INVAL, "alphabet %d outside 1..%d", A, alnk::kMaxAlphabet);
+  if (sc->gap_open > 0 || sc->gap_extend > 0 || sc->gap_open < -1024 || sc->gap_extend < -1024)
+    return fail(ctx, ALN_E_INVAL, "gap penalties must lie in [-1024, 0]");
+  DevScoring h;
+  memset(&h, 0, sizeof h);
+  h.alphabet = A;
+  h.gap_open = sc->gap_open;
+  h.gap_extend = sc->gap_extend;
+  h.max_s = -1 << 30;
+  h.min_s = 1 << 30;
+  bool mm = true;
+  for (int a = 0; a < A; ++a)
+    for (int b = 0; b < A; ++b) {
+      const int v = sc->matrix[a * A + b];
+      if (v < -127 || v > 127)
+        return fail(ctx, ALN_E_INVAL, "substitution score %d outside [-127, 127]", v);
+      h.mat[a * alnk::kMaxAlphabet + b] = v;
+      h.max_s = std::max(h.max_s, v);
+      h.min_s = std::min(h.min_s, v);
+      const int ref = (a == b) ? sc->matrix[0] : (A > 1 ? sc->matrix[1] : 0);
+      if (v != ref) mm = false;
+    }
+  h.match_mismatch = mm ? 1 : 0;
+  h.match = sc->matrix[0];
+  h.mismatch = A > 1 ? sc->matrix[1] : 0;
+  for (int a = 0; a < A; ++a) {
+    uint32_t w = 0;
+    for (int b = 0; b < 4; ++b) {
+      const int v = (b < A) ? h.mat[a * alnk::kMaxAlphabet + b] : -128;
+      w |= ((uint32_t)(v & 0xff)) << (8 * b);
+    }
+    h.rowtab[a] = w;
+  }
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  DevScoring *d = nullptr;
+  HIP_TRY(ctx, hipMalloc(&d, sizeof(DevScoring)));
+  hipError_t e = hipMemcpy(d, &h, sizeof h, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(d);
+    return fail(ctx, ALN_E_DEVICE, "hipMemcpy scoring: %s", hipGetErrorString(e));
+  }
+  ctx->dsc.push_back(d);
+  ctx->hsc.push_back(h);
+  *scoring_id = (int32_t)ctx->dsc.size() - 1;
+  return ALN_OK;
+}
+
+aln_status aln_plan_create(aln_ctx *ctx, int32_t scoring_id, const aln_params *params, int32_t n,
+                           const int32_t *q_len_host, const int32_t *r_len_host, aln_plan **plan,
+                           aln_footprint *fp) {
+  if (!ctx || !params || !plan || n < 0 || (n > 0 && (!q_len_host || !r_len_host)))
+    return fail(ctx, ALN_E_INVAL, "null argument or negative n");
+  *plan = nullptr;
+  if (scoring_id < 0 || scoring_id >= (int32_t)ctx->dsc.size())
+    return fail(ctx, ALN_E_INVAL, "unknown scoring id %d", scoring_id);
+  const aln_params &p = *params;
+  if (p.mode < ALN_GLOBAL || p.mode > ALN_EXTEND) return fail(ctx, ALN_E_INVAL, "bad mode");
+  if (p.prune < ALN_FULL || p.prune > ALN_XDROP) return fail(ctx, ALN_E_INVAL, "bad prune");
+  if (p.prune == ALN_BAND && p.band_w < 0) return fail(ctx, ALN_E_INVAL, "band_w < 0");
+  if (p.prune == ALN_XDROP && (p.xdrop < 0 || p.mode != ALN_EXTEND))
+    return fail(ctx, ALN_E_INVAL, "XDROP needs mode EXTEND and xdrop >= 0");
+  if (p.prune == ALN_XDROP && p.want_cigar)
+    return fail(ctx, ALN_E_UNSUPPORTED, "CIGAR is not produced under XDROP");
+  if (p.width < ALN_W_AUTO || p.width > ALN_W_I32) return fail(ctx, ALN_E_INVAL, "bad width");
+  if (p.prune != ALN_FULL)
+    return fail(ctx, ALN_E_UNSUPPORTED, "pruning rule %d not available in this build", p.prune);
+  const DevScoring &hs = ctx->hsc[scoring_id];
+  const int64_t per_step = (int64_t)std::abs(hs.gap_open) + std::abs(hs.gap_extend) + 128;
+
+  aln_plan *pl = new (std::nothrow) aln_plan;
+  if (!pl) return fail(ctx, ALN_E_NOMEM, "plan allocation");
+  pl->ctx = ctx;
+  pl->scoring_id = scoring_id;
+  pl->p = p;
+  pl->n = n;
+  pl->qlen.assign(q_len_host, q_len_host + n);
+  pl->rlen.assign(r_len_host, r_len_host + n);
+  const bool small = hs.alphabet <= 4;
+
+  // group pairs by rows-per-lane
+  std::vector<std::vector<int32_t>> groups(33);
+  int32_t maxN[33] = {0};
+  bool multi[33] = {false};
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t M = pl->qlen[i], N = pl->rlen[i];
+    if (M < 0 || N < 0) {
+      delete pl;
+      return fail(ctx, ALN_E_INVAL, "negative length at pair %d", i);
+    }
+    if ((int64_t)(M + (int64_t)N) * per_step >= (1LL << 29)) {
+      delete pl;
+      return fail(ctx, ALN_E_UNSUPPORTED, "pair %d too long for int32 scores", i);
+    }
+    const int R = choose_strip_rows(M, N);
+    groups[R].push_back(i);
+    maxN[R] = std::max(maxN[R], N);
+    if (M > 64 * R) multi[R] = true;
+    pl->cells += (int64_t)M * N;
+  }
+  uint64_t tb_off = 0, cg_off = 0;
+  for (int R = 1; R <= 32; ++R) {
+    auto &g = groups[R];
+    if (g.empty()) continue;
+    std::stable_sort(g.begin(), g.end(), [&](int32_t a, int32_t b) {
+      return (int64_t)pl->qlen[a] * pl->rlen[a] > (int64_t)pl->qlen[b] * pl->rlen[b];
+    });
+    LaunchDesc L;
+    L.kind = K_STRIP;
+    L.rows = R;
+    L.mode = p.mode;
+    L.tb = p.want_cigar != 0;
+    L.small = small;
+    L.first = (int32_t)pl->tasks.size();
+    L.count = (int32_t)g.size();
+    L.lds_bnd = multi[R] ? (int32_t)align_up((uint64_t)(maxN[R] + 1) * 8, 16) : 0;
+    L.lds_prof = small ? 0 : (int32_t)align_up((uint64_t)hs.alphabet * 64 * R, 16);
+    if (4LL * (L.lds_bnd + L.lds_prof) > 160 * 1024) {
+      delete pl;
+      return fail(ctx, ALN_E_UNSUPPORTED,
+                  "full-matrix pairs with N = %d and M > %d need more LDS than a CU has", maxN[R],
+                  64 * R);
+    }
+    for (int32_t i : g) {
+      PairTask t;
+      memset(&t, 0, sizeof t);
+      t.pair = i;
+      t.rows = R;
+      t.tb_off = -1;
+      const int32_t M = pl->qlen[i], N = pl->rlen[i];
+      if (p.want_cigar) {
+        const int64_t ns = (M + 64LL * R - 1) / (64LL * R);
+        const uint64_t bytes = (uint64_t)ns * (uint64_t)(N + 63) * 64ULL * (uint64_t)(R / 2);
+        t.tb_off = (int64_t)tb_off;
+        tb_off += align_up(bytes);
+        t.cigar_off = (int64_t)cg_off;
+        t.cigar_cap = M + N + 1;
+        cg_off += (uint64_t)(M + N + 1);
+      }
+      pl->tasks.push_back(t);
+    }
+    pl->launches.push_back(L);
+  }
+  pl->tasks_bytes = align_up(sizeof(PairTask) * std::max<size_t>(pl->tasks.size(), 1));
+  pl->tb_base = pl->tasks_bytes;
+  pl->tb_bytes = tb_off;
+  pl->ws_bytes = pl->tb_base + pl->tb_bytes;
+  pl->cigar_words = cg_off;
+  if (hipHostMalloc(&pl->pinned, pl->tasks_bytes, hipHostMallocDefault) != hipSuccess) {
+    delete pl;
+    return fail(ctx, ALN_E_NOMEM, "pinned staging for %llu bytes",
+                (unsigned long long)pl->tasks_bytes);
+  }
+  if (!pl->tasks.empty()) memcpy(pl->pinned, pl->tasks.data(), sizeof(PairTask) * pl->tasks.size());
+  if (fp) {
+    fp->workspace_bytes = pl->ws_bytes;
+    fp->traceback_bytes = pl->tb_bytes;
+    fp->cigar_words = pl->cigar_words;
+    fp->cells = pl->cells;
+  }
+  *plan = pl;
+  return ALN_OK;
+}
+
+void aln_plan_destroy(aln_plan *plan) {
+  if (!plan) return;
+  if (plan->gexec) hipGraphExecDestroy(plan->gexec);
+  if (plan->graph) hipGraphDestroy(plan->graph);
+  if (plan->pinned) hipHostFree(plan->pinned);
+  delete plan;
+}
+
+static aln_status check_exec(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, void *d_ws,
+                             uint64_t ws_bytes, aln_result *d_res, uint32_t *d_cigar,
+                             uint64_t cigar_words) {
+  if (!ctx || !plan || !b || plan->ctx != ctx) return fail(ctx, ALN_E_INVAL, "bad context or plan");
+  if (b->n != plan->n) return fail(ctx, ALN_E_INVAL, "batch has %d pairs, plan %d", b->n, plan->n);
+  if (plan->n == 0) return ALN_OK;
+  if (!d_res || !b->q_off || !b->q_len || !b->r_off || !b->r_len)
+    return fail(ctx, ALN_E_INVAL, "null device pointer");
+  if (!d_ws || ws_bytes < plan->ws_bytes)
+    return fail(ctx, ALN_E_CAPACITY, "workspace %llu < %llu bytes", (unsigned long long)ws_bytes,
+                (unsigned long long)plan->ws_bytes);
+  if (plan->p.want_cigar && (!d_cigar || cigar_words < plan->cigar_words))
+    return fail(ctx, ALN_E_CAPACITY, "CIGAR buffer %llu < %llu words",
+                (unsigned long long)cigar_words, (unsigned long long)plan->cigar_words);
+  return ALN_OK;
+}
+
+static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, void *d_ws,
+                           aln_result *d_res, uint32_t *d_cigar, hipStream_t st, bool per_pair) {
+  if (plan->n == 0) return ALN_OK;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  uint8_t *ws = static_cast<uint8_t *>(d_ws);
+  PairTask *dtasks = reinterpret_cast<PairTask *>(ws);
+  HIP_TRY(ctx, hipMemcpyAsync(dtasks, plan->pinned, sizeof(PairTask) * plan->tasks.size(),
+                              hipMemcpyHostToDevice, st));
+  alnk::BatchPtrs bp{b->q, b->q_off, b->q_len, b->r, b->r_off, b->r_len};
+  const DevScoring *dsc = ctx->dsc[plan->scoring_id];
+  const DevScoring &hsc = ctx->hsc[plan->scoring_id];
+
+  alnk::ValidateArgs va{bp, plan->n, hsc.alphabet, d_res};
+  HIP_TRY(ctx, alnk::launch_validate(va, st));
+
+  for (const LaunchDesc &L : plan->launches) {
+    alnk::StripArgs sa;
+    sa.b = bp;
+    sa.mode = L.mode;
+    sa.sc = dsc;
+    sa.tb = ws + plan->tb_base;
+    sa.res = d_res;
+    sa.lds_bnd = L.lds_bnd;
+    sa.lds_prof = L.lds_prof;
+    if (!per_pair) {
+      sa.tasks = dtasks + L.first;
+      sa.ntasks = L.count;
+      HIP_TRY(ctx, alnk::launch_strip(L.rows, L.mode, L.tb, L.small, sa, st));
+    } else {
+      for (int32_t k = 0; k < L.count; ++k) {
+        sa.tasks = dtasks + L.first + k;
+        sa.ntasks = 1;
+        HIP_TRY(ctx, alnk::launch_strip(L.rows, L.mode, L.tb, L.small, sa, st));
+      }
+    }
+  }
+  if (plan->p.want_cigar) {
+    alnk::WalkArgs wa;
+    wa.b = bp;
+    wa.mode = plan->p.mode;
+    wa.layout = 0;
+    wa.sc = dsc;
+    wa.tb = ws + plan->tb_base;
+    wa.res = d_res;
+    wa.cigar = d_cigar;
+    if (!per_pair) {
+      wa.tasks = dtasks;
+      wa.ntasks = (int32_t)plan->tasks.size();
+      HIP_TRY(ctx, alnk::launch_walk(0, wa, st));
+    } else {
+      for (size_t k = 0; k < plan->tasks.size(); ++k) {
+        wa.tasks = dtasks + k;
+        wa.ntasks = 1;
+        HIP_TRY(ctx, alnk::launch_walk(0, wa, st));
+      }
+    }
+  }
+  return ALN_OK;
+}
+
+aln_status aln_execute(aln_ctx *ctx, aln_plan *plan, const aln_batch *batch, void *d_ws,
+                       uint64_t ws_bytes, aln_result *d_res, uint32_t *d_cigar,
+                       uint64_t cigar_words, void *stream) {
+  aln_status st = check_exec(ctx, plan, batch, d_ws, ws_bytes, d_res, d_cigar, cigar_words);
+  if (st != ALN_OK) return st;
+  return run_plan(ctx, plan, batch, d_ws, d_res, d_cigar, (hipStream_t)stream, false);
+}
+
+aln_status aln_execute_per_pair(aln_ctx *ctx, aln_plan *plan, const aln_batch *batch, void *d_ws,
+                                uint64_t ws_bytes, aln_result *d_res, uint32_t *d_cigar,
+                                uint64_t cigar_words, void *stream) {
+  aln_status st = check_exec(ctx, plan, batch, d_ws, ws_bytes, d_res, d_cigar, cigar_words);
+  if (st != ALN_OK) return st;
+  return run_plan(ctx, plan, batch, d_ws, d_res, d_cigar, (hipStream_t)stream, true);
+}
+
+aln_status aln_graph_capture(aln_ctx *ctx, aln_plan *plan, const aln_batch *batch, void *d_ws,
+                             uint64_t ws_bytes, aln_result *d_res, uint32_t *d_cigar,
+                             uint64_t cigar_words, void *stream) {
+  aln_status st = check_exec(ctx, plan, batch, d_ws, ws_bytes, d_res, d_cigar, cigar_words);
+  if (st != ALN_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (s == nullptr) return fail(ctx, ALN_E_INVAL, "graph capture needs a non-default stream");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (plan->gexec) {
+    hipGraphExecDestroy(plan->gexec);
+    plan->gexec = nullptr;
+  }
+  if (plan->graph) {
+    hipGraphDestroy(plan->graph);
+    plan->graph = nullptr;
+  }
+  HIP_TRY(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  st = run_plan(ctx, plan, batch, d_ws, d_res, d_cigar, s, false);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  if (st != ALN_OK) {
+    if (g) hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(ctx, ALN_E_DEVICE, "end capture: %s", hipGetErrorString(e));
+  plan->graph = g;
+  HIP_TRY(ctx, hipGraphInstantiate(&plan->gexec, g, nullptr, nullptr, 0));
+  HIP_TRY(ctx, hipGraphLaunch(plan->gexec, s));
+  return ALN_OK;
+}
+
+aln_status aln_graph_launch(aln_ctx *ctx, aln_plan *plan, void *stream) {
+  if (!ctx || !plan || !plan->gexec) return fail(ctx, ALN_E_INVAL, "no captured graph");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipGraphLaunch(plan->gexec, (hipStream_t)stream));
+  return ALN_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,87 @@
+// internal.h -- declarations shared by the host runtime (aln_api.cpp) and the
+// gfx950 kernels.  Not part of the public ABI (include/aln.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "aln.h"
+
+namespace alnk {
+
+// Minus infinity in int32 kernels.  Far enough from INT32_MIN that sums of a
+// few "minus infinity" terms with scores and gap penalties cannot wrap.
+constexpr int32_t NEG32 = -(1 << 30);
+constexpr int kMaxAlphabet = 32;
+
+// Scoring scheme resident on the device (one per aln_set_scoring call).
+struct DevScoring {
+  int32_t alphabet;
+  int32_t gap_open;
+  int32_t gap_extend;
+  int32_t max_s;        // largest substitution score
+  int32_t min_s;        // smallest substitution score
+  int32_t match_mismatch; // 1: diagonal all equal, off-diagonal all equal
+  int32_t match, mismatch;
+  int32_t mat[kMaxAlphabet * kMaxAlphabet]; // s(a,b) = mat[a*32+b]
+  // rowtab[a]: bytes s(a,0..3) packed little-endian (alphabet <= 4)
+  uint32_t rowtab[kMaxAlphabet];
+};
+
+// One pair's entry in a launch's work list (uploaded into the workspace).
+struct PairTask {
+  int32_t pair;      // index into the batch
+  int32_t rows;      // rows per lane (strip kernel) / window elements per lane
+  int64_t tb_off;    // byte offset of the pair's traceback codes (-1: none)
+  int64_t cigar_off; // first word of the pair's CIGAR slot
+  int32_t cigar_cap; // words in the slot
+  int32_t aux;       // kernel-specific
+};
+
+struct BatchPtrs {
+  const uint8_t *q;
+  const int64_t *q_off;
+  const int32_t *q_len;
+  const uint8_t *r;
+  const int64_t *r_off;
+  const int32_t *r_len;
+};
+
+struct StripArgs {
+  BatchPtrs b;
+  const PairTask *tasks;
+  int32_t ntasks;
+  int32_t mode;
+  const DevScoring *sc;
+  uint8_t *tb;        // traceback base (workspace)
+  aln_result *res;
+  int32_t lds_bnd;    // bytes of LDS per wave for the inter-strip row (0: none)
+  int32_t lds_prof;   // bytes of LDS per wave for the query profile (0: none)
+};
+
+struct WalkArgs {
+  BatchPtrs b;
+  const PairTask *tasks;
+  int32_t ntasks;
+  int32_t mode;
+  int32_t layout;     // 0: strip layout, 1: diagonal-band layout
+  const DevScoring *sc;
+  const uint8_t *tb;
+  aln_result *res;
+  uint32_t *cigar;
+};
+
+struct ValidateArgs {
+  BatchPtrs b;
+  int32_t n;
+  int32_t alphabet;
+  aln_result *res;
+};
+
+// Launchers (defined in the kernel translation units).
+hipError_t launch_validate(const ValidateArgs &a, hipStream_t s);
+hipError_t launch_strip(int rows, int mode, bool tb, bool small_alphabet,
+                        const StripArgs &a, hipStream_t s);
+hipError_t launch_walk(int layout, const WalkArgs &a, hipStream_t s);
+
+} // namespace alnk
