@@ -196,6 +196,16 @@ aln_status aln_graph_capture(aln_ctx *ctx, aln_plan *plan,
                              void *stream);
 aln_status aln_graph_launch(aln_ctx *ctx, aln_plan *plan, void *stream);
 
+/* Kernel timing for measurement tools.  While enabled (enable = 1), every
+ * kernel launch of aln_execute is bracketed by HIP events on the launch
+ * stream; aln_kernel_times() synchronises those events and returns, for each
+ * kernel family, the summed milliseconds and launch count since the last
+ * call (then resets).  names[k] receives a static string.  Returns the number
+ * of families written (<= max).  Not for use during graph capture. */
+aln_status aln_set_profiling(aln_ctx *ctx, int32_t enable);
+int32_t aln_kernel_times(aln_ctx *ctx, const char **names, double *ms,
+                         int64_t *launches, int32_t max);
+
 #ifdef __cplusplus
 }
 #endif

@@ -60,6 +60,7 @@ EXPORTS = [
     "aln_abi_version", "aln_create", "aln_destroy", "aln_last_error",
     "aln_set_scoring", "aln_plan_create", "aln_plan_destroy", "aln_execute",
     "aln_execute_per_pair", "aln_graph_capture", "aln_graph_launch",
+    "aln_set_profiling", "aln_kernel_times",
 ]
 
 
@@ -84,6 +85,8 @@ def load_library(path=LIB_PATH):
         "aln_execute_per_pair": ([P, P, P, P, U64, P, P, U64, P], I32),
         "aln_graph_capture": ([P, P, P, P, U64, P, P, U64, P], I32),
         "aln_graph_launch": ([P, P, P], I32),
+        "aln_set_profiling": ([P, I32], I32),
+        "aln_kernel_times": ([P, P, P, P, I32], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -209,6 +212,19 @@ class Context:
 
     def graph_launch(self, plan, stream=None):
         self._check(self.lib.aln_graph_launch(self.handle, plan.handle, _stream_handle(stream)))
+
+    def set_profiling(self, enable):
+        self._check(self.lib.aln_set_profiling(self.handle, 1 if enable else 0))
+
+    def kernel_times(self, max_families=16):
+        """{family: (total_ms, launches)} since the last call (profiling on)."""
+        names = (ctypes.c_char_p * max_families)()
+        ms = (ctypes.c_double * max_families)()
+        cnt = (ctypes.c_int64 * max_families)()
+        k = self.lib.aln_kernel_times(self.handle, names, ms, cnt, max_families)
+        if k < 0:
+            raise AlnError(f"aln_kernel_times failed ({k})")
+        return {names[i].decode(): (float(ms[i]), int(cnt[i])) for i in range(k)}
 
 
 class Buffers:

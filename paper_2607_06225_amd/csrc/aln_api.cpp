@@ -26,6 +26,14 @@ struct aln_ctx {
   std::string err;
   std::vector<DevScoring *> dsc; // device copies, owned
   std::vector<DevScoring> hsc;   // host mirrors
+  // kernel timing (aln_set_profiling)
+  bool profiling = false;
+  struct TimedLaunch {
+    const char *name;
+    hipEvent_t a, b;
+  };
+  std::vector<TimedLaunch> timed;
+  std::vector<hipEvent_t> event_pool;
 };
 
 namespace {
@@ -84,6 +92,31 @@ int choose_strip_rows(int32_t M, int32_t N) {
   return best;
 }
 
+hipEvent_t pool_event(aln_ctx *ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Run `launch` (which enqueues one kernel on `st`); with profiling on, the
+// launch is bracketed by events recorded on the same stream.
+template <class F>
+hipError_t timed_launch(aln_ctx *ctx, const char *name, hipStream_t st, F &&launch) {
+  if (!ctx->profiling) return launch();
+  hipEvent_t a = pool_event(ctx), b = pool_event(ctx);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipEventRecord(a, st);
+  hipError_t e = launch();
+  hipEventRecord(b, st);
+  ctx->timed.push_back({name, a, b});
+  return e;
+}
+
 } // namespace
 
 struct aln_plan {
@@ -127,7 +160,45 @@ void aln_destroy(aln_ctx *ctx) {
   if (!ctx) return;
   hipSetDevice(ctx->device);
   for (DevScoring *d : ctx->dsc) hipFree(d);
+  for (auto &t : ctx->timed) {
+    hipEventDestroy(t.a);
+    hipEventDestroy(t.b);
+  }
+  for (hipEvent_t e : ctx->event_pool) hipEventDestroy(e);
   delete ctx;
+}
+
+aln_status aln_set_profiling(aln_ctx *ctx, int32_t enable) {
+  if (!ctx) return ALN_E_INVAL;
+  ctx->profiling = enable != 0;
+  return ALN_OK;
+}
+
+int32_t aln_kernel_times(aln_ctx *ctx, const char **names, double *ms, int64_t *launches,
+                         int32_t max) {
+  if (!ctx || max < 0 || (max > 0 && (!names || !ms || !launches))) return ALN_E_INVAL;
+  hipSetDevice(ctx->device);
+  int32_t nout = 0;
+  for (auto &t : ctx->timed) {
+    float el = 0.f;
+    hipEventSynchronize(t.b);
+    hipEventElapsedTime(&el, t.a, t.b);
+    int32_t k = 0;
+    while (k < nout && strcmp(names[k], t.name) != 0) ++k;
+    if (k == nout) {
+      if (nout == max) continue;
+      names[nout] = t.name;
+      ms[nout] = 0.0;
+      launches[nout] = 0;
+      ++nout;
+    }
+    ms[k] += el;
+    launches[k] += 1;
+    ctx->event_pool.push_back(t.a);
+    ctx->event_pool.push_back(t.b);
+  }
+  ctx->timed.clear();
+  return nout;
 }
 
 const char *aln_last_error(const aln_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
@@ -337,7 +408,7 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
   const DevScoring &hsc = ctx->hsc[plan->scoring_id];
 
   alnk::ValidateArgs va{bp, plan->n, hsc.alphabet, d_res};
-  HIP_TRY(ctx, alnk::launch_validate(va, st));
+  HIP_TRY(ctx, timed_launch(ctx, "validate", st, [&] { return alnk::launch_validate(va, st); }));
 
   for (const LaunchDesc &L : plan->launches) {
     alnk::StripArgs sa;
@@ -351,7 +422,9 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
     if (!per_pair) {
       sa.tasks = dtasks + L.first;
       sa.ntasks = L.count;
-      HIP_TRY(ctx, alnk::launch_strip(L.rows, L.mode, L.tb, L.small, sa, st));
+      HIP_TRY(ctx, timed_launch(ctx, "strip_i32", st, [&] {
+                return alnk::launch_strip(L.rows, L.mode, L.tb, L.small, sa, st);
+              }));
     } else {
       for (int32_t k = 0; k < L.count; ++k) {
         sa.tasks = dtasks + L.first + k;
@@ -372,7 +445,7 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
     if (!per_pair) {
       wa.tasks = dtasks;
       wa.ntasks = (int32_t)plan->tasks.size();
-      HIP_TRY(ctx, alnk::launch_walk(0, wa, st));
+      HIP_TRY(ctx, timed_launch(ctx, "walk", st, [&] { return alnk::launch_walk(0, wa, st); }));
     } else {
       for (size_t k = 0; k < plan->tasks.size(); ++k) {
         wa.tasks = dtasks + k;
