@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -38,7 +39,7 @@ struct aln_ctx {
 
 namespace {
 
-enum Kind { K_STRIP = 0 };
+enum Kind { K_STRIP = 0, K_SW16 = 1, K_RERUN = 2 };
 
 struct LaunchDesc {
   int kind;
@@ -110,9 +111,9 @@ hipError_t timed_launch(aln_ctx *ctx, const char *name, hipStream_t st, F &&laun
   if (!ctx->profiling) return launch();
   hipEvent_t a = pool_event(ctx), b = pool_event(ctx);
   if (!a || !b) return hipErrorOutOfMemory;
-  hipEventRecord(a, st);
+  (void)hipEventRecord(a, st);
   hipError_t e = launch();
-  hipEventRecord(b, st);
+  (void)hipEventRecord(b, st);
   ctx->timed.push_back({name, a, b});
   return e;
 }
@@ -127,6 +128,13 @@ struct aln_plan {
   std::vector<int32_t> qlen, rlen;
   std::vector<PairTask> tasks;
   std::vector<LaunchDesc> launches;
+  // packed int16 path
+  std::vector<alnk::Sw16Task> sw16_tasks;    // two pairs per task
+  std::vector<alnk::Sw16Task> sw16_single;   // one pair per task (per-pair runs)
+  int sw16_rows = 16;
+  uint64_t sw16_off = 0, sw16_single_off = 0, rerun_cnt_off = 0, rerun_off = 0;
+  LaunchDesc rerun{};
+  uint64_t upload_bytes = 0;
   uint64_t tasks_bytes = 0;
   uint64_t tb_base = 0;
   uint64_t tb_bytes = 0;
@@ -158,13 +166,13 @@ aln_status aln_create(aln_ctx **ctx, int32_t device) {
 
 void aln_destroy(aln_ctx *ctx) {
   if (!ctx) return;
-  hipSetDevice(ctx->device);
-  for (DevScoring *d : ctx->dsc) hipFree(d);
+  (void)hipSetDevice(ctx->device);
+  for (DevScoring *d : ctx->dsc) (void)hipFree(d);
   for (auto &t : ctx->timed) {
-    hipEventDestroy(t.a);
-    hipEventDestroy(t.b);
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
   }
-  for (hipEvent_t e : ctx->event_pool) hipEventDestroy(e);
+  for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -177,12 +185,12 @@ aln_status aln_set_profiling(aln_ctx *ctx, int32_t enable) {
 int32_t aln_kernel_times(aln_ctx *ctx, const char **names, double *ms, int64_t *launches,
                          int32_t max) {
   if (!ctx || max < 0 || (max > 0 && (!names || !ms || !launches))) return ALN_E_INVAL;
-  hipSetDevice(ctx->device);
+  (void)hipSetDevice(ctx->device);
   int32_t nout = 0;
   for (auto &t : ctx->timed) {
     float el = 0.f;
-    hipEventSynchronize(t.b);
-    hipEventElapsedTime(&el, t.a, t.b);
+    (void)hipEventSynchronize(t.b);
+    (void)hipEventElapsedTime(&el, t.a, t.b);
     int32_t k = 0;
     while (k < nout && strcmp(names[k], t.name) != 0) ++k;
     if (k == nout) {
@@ -215,7 +223,7 @@ aln_status aln_set_scoring(aln_ctx *ctx, const aln_scoring *sc, int32_t *scoring
   h.alphabet = A;
   h.gap_open = sc->gap_open;
   h.gap_extend = sc->gap_extend;
-  h.max_s = -1 << 30;
+  h.max_s = -(1 << 30);
   h.min_s = 1 << 30;
   bool mm = true;
   for (int a = 0; a < A; ++a)
@@ -245,7 +253,7 @@ aln_status aln_set_scoring(aln_ctx *ctx, const aln_scoring *sc, int32_t *scoring
   HIP_TRY(ctx, hipMalloc(&d, sizeof(DevScoring)));
   hipError_t e = hipMemcpy(d, &h, sizeof h, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
-    hipFree(d);
+    (void)hipFree(d);
     return fail(ctx, ALN_E_DEVICE, "hipMemcpy scoring: %s", hipGetErrorString(e));
   }
   ctx->dsc.push_back(d);
@@ -286,9 +294,119 @@ aln_status aln_plan_create(aln_ctx *ctx, int32_t scoring_id, const aln_params *p
   pl->rlen.assign(r_len_host, r_len_host + n);
   const bool small = hs.alphabet <= 4;
 
+  int32_t maxM = 0, maxN = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    maxM = std::max(maxM, pl->qlen[i]);
+    maxN = std::max(maxN, pl->rlen[i]);
+  }
+  // packed int16 Smith-Waterman: LOCAL, full matrix, score + end cell
+  const int rerun_rows = 16;
+  const int32_t rerun_bnd = (int32_t)align_up((uint64_t)(maxN + 1) * 8, 16);
+  const int32_t rerun_prof = small ? 0 : (int32_t)align_up((uint64_t)hs.alphabet * 64 * rerun_rows, 16);
+  const bool use_sw16 = p.mode == ALN_LOCAL && p.prune == ALN_FULL && !p.want_cigar &&
+                        p.width != ALN_W_I32 && n > 0 && hs.alphabet < alnk::kMaxAlphabet &&
+                        maxN <= 65534 && maxM < (1 << 20) &&
+                        4LL * (rerun_bnd + rerun_prof) <= 160 * 1024;
+  if (use_sw16) {
+    if (const char *ev = getenv("ALN_SW16_ROWS")) {
+      const int r = atoi(ev);
+      if (r == 4 || r == 8 || r == 12 || r == 16) pl->sw16_rows = r;
+    }
+    const int R = pl->sw16_rows;
+    const int HS = 16 * R;
+    std::vector<int32_t> order(n);
+    for (int32_t i = 0; i < n; ++i) order[i] = i;
+    auto nstr = [&](int32_t i) { return (pl->qlen[i] + HS - 1) / HS; };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+      const int sa = nstr(a), sb = nstr(b);
+      if (sa != sb) return sa > sb;
+      return pl->rlen[a] > pl->rlen[b];
+    });
+    uint64_t bnd_bytes = 0;
+    std::vector<uint64_t> bnd_rel;
+    for (int32_t k = 0; k < n; k += 2) {
+      alnk::Sw16Task t;
+      t.pa = order[k];
+      t.pb = (k + 1 < n) ? order[k + 1] : -1;
+      t.nstrips = nstr(t.pa);
+      t.nmax = pl->rlen[t.pa];
+      if (t.pb >= 0) {
+        t.nstrips = std::max(t.nstrips, nstr(t.pb));
+        t.nmax = std::max(t.nmax, pl->rlen[t.pb]);
+      }
+      t.bnd_off = 0;
+      bnd_rel.push_back(t.nstrips > 1 ? bnd_bytes : ~0ULL);
+      if (t.nstrips > 1) bnd_bytes += align_up((uint64_t)(t.nmax + 1) * 8);
+      pl->sw16_tasks.push_back(t);
+    }
+    for (int32_t k = 0; k < n; ++k) {
+      alnk::Sw16Task t;
+      t.pa = order[k];
+      t.pb = -1;
+      t.nstrips = nstr(t.pa);
+      t.nmax = pl->rlen[t.pa];
+      t.bnd_off = 0;
+      pl->sw16_single.push_back(t);
+    }
+    // workspace: [sw16 tasks | single tasks | rerun counter | rerun queue | boundary rows]
+    pl->sw16_off = 0;
+    pl->sw16_single_off = align_up(sizeof(alnk::Sw16Task) * pl->sw16_tasks.size());
+    pl->rerun_cnt_off = pl->sw16_single_off + align_up(sizeof(alnk::Sw16Task) * pl->sw16_single.size());
+    pl->rerun_off = pl->rerun_cnt_off + kAlign;
+    const uint64_t bnd_base = pl->rerun_off + align_up(sizeof(PairTask) * (size_t)n);
+    for (size_t k = 0; k < pl->sw16_tasks.size(); ++k)
+      pl->sw16_tasks[k].bnd_off = bnd_rel[k] == ~0ULL ? 0 : (int64_t)(bnd_base + bnd_rel[k]);
+    // single-pair tasks reuse the boundary row of their pair's packed task
+    for (size_t k = 0; k < pl->sw16_tasks.size(); ++k) {
+      const int64_t off = pl->sw16_tasks[k].bnd_off;
+      pl->sw16_single[2 * k].bnd_off = off;
+      if (2 * k + 1 < pl->sw16_single.size()) pl->sw16_single[2 * k + 1].bnd_off = off;
+    }
+    LaunchDesc L{};
+    L.kind = K_SW16;
+    L.rows = R;
+    L.mode = ALN_LOCAL;
+    L.first = 0;
+    L.count = (int32_t)pl->sw16_tasks.size();
+    pl->launches.push_back(L);
+    pl->rerun.kind = K_RERUN;
+    pl->rerun.rows = rerun_rows;
+    pl->rerun.mode = ALN_LOCAL;
+    pl->rerun.tb = false;
+    pl->rerun.small = small;
+    pl->rerun.first = 0;
+    pl->rerun.count = n;
+    pl->rerun.lds_bnd = rerun_bnd;
+    pl->rerun.lds_prof = rerun_prof;
+    for (int32_t i = 0; i < n; ++i) pl->cells += (int64_t)pl->qlen[i] * pl->rlen[i];
+    pl->upload_bytes = pl->rerun_cnt_off;
+    pl->tasks_bytes = bnd_base + bnd_bytes;
+    pl->tb_base = pl->tasks_bytes;
+    pl->tb_bytes = 0;
+    pl->ws_bytes = pl->tasks_bytes;
+    pl->cigar_words = 0;
+    if (hipHostMalloc(&pl->pinned, std::max<uint64_t>(pl->upload_bytes, 1), hipHostMallocDefault) !=
+        hipSuccess) {
+      delete pl;
+      return fail(ctx, ALN_E_NOMEM, "pinned staging");
+    }
+    memcpy((uint8_t *)pl->pinned + pl->sw16_off, pl->sw16_tasks.data(),
+           sizeof(alnk::Sw16Task) * pl->sw16_tasks.size());
+    memcpy((uint8_t *)pl->pinned + pl->sw16_single_off, pl->sw16_single.data(),
+           sizeof(alnk::Sw16Task) * pl->sw16_single.size());
+    if (fp) {
+      fp->workspace_bytes = pl->ws_bytes;
+      fp->traceback_bytes = 0;
+      fp->cigar_words = 0;
+      fp->cells = pl->cells;
+    }
+    *plan = pl;
+    return ALN_OK;
+  }
+
   // group pairs by rows-per-lane
   std::vector<std::vector<int32_t>> groups(33);
-  int32_t maxN[33] = {0};
+  int32_t grpN[33] = {0};
   bool multi[33] = {false};
   for (int32_t i = 0; i < n; ++i) {
     const int32_t M = pl->qlen[i], N = pl->rlen[i];
@@ -302,7 +420,7 @@ aln_status aln_plan_create(aln_ctx *ctx, int32_t scoring_id, const aln_params *p
     }
     const int R = choose_strip_rows(M, N);
     groups[R].push_back(i);
-    maxN[R] = std::max(maxN[R], N);
+    grpN[R] = std::max(grpN[R], N);
     if (M > 64 * R) multi[R] = true;
     pl->cells += (int64_t)M * N;
   }
@@ -321,12 +439,12 @@ aln_status aln_plan_create(aln_ctx *ctx, int32_t scoring_id, const aln_params *p
     L.small = small;
     L.first = (int32_t)pl->tasks.size();
     L.count = (int32_t)g.size();
-    L.lds_bnd = multi[R] ? (int32_t)align_up((uint64_t)(maxN[R] + 1) * 8, 16) : 0;
+    L.lds_bnd = multi[R] ? (int32_t)align_up((uint64_t)(grpN[R] + 1) * 8, 16) : 0;
     L.lds_prof = small ? 0 : (int32_t)align_up((uint64_t)hs.alphabet * 64 * R, 16);
     if (4LL * (L.lds_bnd + L.lds_prof) > 160 * 1024) {
       delete pl;
       return fail(ctx, ALN_E_UNSUPPORTED,
-                  "full-matrix pairs with N = %d and M > %d need more LDS than a CU has", maxN[R],
+                  "full-matrix pairs with N = %d and M > %d need more LDS than a CU has", grpN[R],
                   64 * R);
     }
     for (int32_t i : g) {
@@ -350,6 +468,7 @@ aln_status aln_plan_create(aln_ctx *ctx, int32_t scoring_id, const aln_params *p
     pl->launches.push_back(L);
   }
   pl->tasks_bytes = align_up(sizeof(PairTask) * std::max<size_t>(pl->tasks.size(), 1));
+  pl->upload_bytes = sizeof(PairTask) * pl->tasks.size();
   pl->tb_base = pl->tasks_bytes;
   pl->tb_bytes = tb_off;
   pl->ws_bytes = pl->tb_base + pl->tb_bytes;
@@ -372,9 +491,9 @@ aln_status aln_plan_create(aln_ctx *ctx, int32_t scoring_id, const aln_params *p
 
 void aln_plan_destroy(aln_plan *plan) {
   if (!plan) return;
-  if (plan->gexec) hipGraphExecDestroy(plan->gexec);
-  if (plan->graph) hipGraphDestroy(plan->graph);
-  if (plan->pinned) hipHostFree(plan->pinned);
+  if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  if (plan->pinned) (void)hipHostFree(plan->pinned);
   delete plan;
 }
 
@@ -401,18 +520,63 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   uint8_t *ws = static_cast<uint8_t *>(d_ws);
   PairTask *dtasks = reinterpret_cast<PairTask *>(ws);
-  HIP_TRY(ctx, hipMemcpyAsync(dtasks, plan->pinned, sizeof(PairTask) * plan->tasks.size(),
-                              hipMemcpyHostToDevice, st));
+  if (plan->upload_bytes)
+    HIP_TRY(ctx, hipMemcpyAsync(ws, plan->pinned, plan->upload_bytes, hipMemcpyHostToDevice, st));
   alnk::BatchPtrs bp{b->q, b->q_off, b->q_len, b->r, b->r_off, b->r_len};
   const DevScoring *dsc = ctx->dsc[plan->scoring_id];
   const DevScoring &hsc = ctx->hsc[plan->scoring_id];
+  const bool sw16 = !plan->sw16_tasks.empty();
+  int32_t *rerun_cnt = sw16 ? reinterpret_cast<int32_t *>(ws + plan->rerun_cnt_off) : nullptr;
+  PairTask *rerun_q = sw16 ? reinterpret_cast<PairTask *>(ws + plan->rerun_off) : nullptr;
 
-  alnk::ValidateArgs va{bp, plan->n, hsc.alphabet, d_res};
+  alnk::ValidateArgs va{bp, plan->n, hsc.alphabet, d_res, rerun_cnt};
   HIP_TRY(ctx, timed_launch(ctx, "validate", st, [&] { return alnk::launch_validate(va, st); }));
+
+  if (sw16) {
+    alnk::Sw16Args a16;
+    a16.b = bp;
+    a16.sc = dsc;
+    a16.sc_alphabet = hsc.alphabet;
+    a16.ws = ws;
+    a16.res = d_res;
+    a16.rerun_count = rerun_cnt;
+    a16.rerun = rerun_q;
+    a16.rerun_threshold = 32767 - std::max(hsc.max_s, 0);
+    if (!per_pair) {
+      a16.tasks = reinterpret_cast<const alnk::Sw16Task *>(ws + plan->sw16_off);
+      a16.ntasks = (int32_t)plan->sw16_tasks.size();
+      HIP_TRY(ctx, timed_launch(ctx, "sw16", st, [&] {
+                return alnk::launch_sw16(plan->sw16_rows, a16, st);
+              }));
+    } else {
+      for (size_t k = 0; k < plan->sw16_single.size(); ++k) {
+        a16.tasks = reinterpret_cast<const alnk::Sw16Task *>(ws + plan->sw16_single_off) + k;
+        a16.ntasks = 1;
+        HIP_TRY(ctx, alnk::launch_sw16(plan->sw16_rows, a16, st));
+      }
+    }
+    const LaunchDesc &L = plan->rerun;
+    alnk::StripArgs sa;
+    sa.b = bp;
+    sa.tasks = rerun_q;
+    sa.ntasks = L.count;
+    sa.dyn_ntasks = rerun_cnt;
+    sa.mode = L.mode;
+    sa.sc = dsc;
+    sa.tb = nullptr;
+    sa.res = d_res;
+    sa.lds_bnd = L.lds_bnd;
+    sa.lds_prof = L.lds_prof;
+    HIP_TRY(ctx, timed_launch(ctx, "strip_i32_rerun", st, [&] {
+              return alnk::launch_strip(L.rows, L.mode, false, L.small, sa, st);
+            }));
+    return ALN_OK;
+  }
 
   for (const LaunchDesc &L : plan->launches) {
     alnk::StripArgs sa;
     sa.b = bp;
+    sa.dyn_ntasks = nullptr;
     sa.mode = L.mode;
     sa.sc = dsc;
     sa.tb = ws + plan->tb_base;
@@ -482,11 +646,11 @@ aln_status aln_graph_capture(aln_ctx *ctx, aln_plan *plan, const aln_batch *batc
   if (s == nullptr) return fail(ctx, ALN_E_INVAL, "graph capture needs a non-default stream");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   if (plan->gexec) {
-    hipGraphExecDestroy(plan->gexec);
+    (void)hipGraphExecDestroy(plan->gexec);
     plan->gexec = nullptr;
   }
   if (plan->graph) {
-    hipGraphDestroy(plan->graph);
+    (void)hipGraphDestroy(plan->graph);
     plan->graph = nullptr;
   }
   HIP_TRY(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -494,7 +658,7 @@ aln_status aln_graph_capture(aln_ctx *ctx, aln_plan *plan, const aln_batch *batc
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(s, &g);
   if (st != ALN_OK) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return st;
   }
   if (e != hipSuccess) return fail(ctx, ALN_E_DEVICE, "end capture: %s", hipGetErrorString(e));

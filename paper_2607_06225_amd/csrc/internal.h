@@ -50,7 +50,8 @@ struct BatchPtrs {
 struct StripArgs {
   BatchPtrs b;
   const PairTask *tasks;
-  int32_t ntasks;
+  int32_t ntasks;            // upper bound when dyn_ntasks is set
+  const int32_t *dyn_ntasks; // device-side task count (re-run queues), or null
   int32_t mode;
   const DevScoring *sc;
   uint8_t *tb;        // traceback base (workspace)
@@ -76,6 +77,28 @@ struct ValidateArgs {
   int32_t n;
   int32_t alphabet;
   aln_result *res;
+  int32_t *reset_counter; // zeroed by the first block (re-run queue), or null
+};
+
+// Two pairs aligned by one 16-lane group of the packed int16 kernel.
+struct Sw16Task {
+  int32_t pa, pb;    // pair indices (pb = -1: none)
+  int32_t nstrips;   // 16*R-row strips of the taller pair
+  int32_t nmax;      // max(N_a, N_b)
+  int64_t bnd_off;   // byte offset of the group's strip-boundary row in ws
+};
+
+struct Sw16Args {
+  BatchPtrs b;
+  const Sw16Task *tasks;
+  int32_t ntasks;
+  const DevScoring *sc;
+  int32_t sc_alphabet;     // host copy of the alphabet (LDS sizing)
+  uint8_t *ws;
+  aln_result *res;
+  int32_t *rerun_count;    // queue of pairs to recompute in int32
+  PairTask *rerun;
+  int32_t rerun_threshold; // best >= this: may have saturated
 };
 
 // Launchers (defined in the kernel translation units).
@@ -83,5 +106,6 @@ hipError_t launch_validate(const ValidateArgs &a, hipStream_t s);
 hipError_t launch_strip(int rows, int mode, bool tb, bool small_alphabet,
                         const StripArgs &a, hipStream_t s);
 hipError_t launch_walk(int layout, const WalkArgs &a, hipStream_t s);
+hipError_t launch_sw16(int rows, const Sw16Args &a, hipStream_t s);
 
 } // namespace alnk

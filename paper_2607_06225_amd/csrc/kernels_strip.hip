@@ -34,12 +34,22 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 template <int R, int MODE, bool TB, bool SMALLA>
+__device__ void strip_task(const StripArgs &a, int task, int wave, int lane, uint8_t *smem);
+
+// One wavefront per task; waves stride over the task list so that a grid
+// smaller than the list (device-side counts) still covers it.
+template <int R, int MODE, bool TB, bool SMALLA>
 __global__ __launch_bounds__(256) void strip_kernel(StripArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int task = blockIdx.x * 4 + wave;
-  if (task >= a.ntasks) return;
+  const int ntasks = a.dyn_ntasks ? min(*a.dyn_ntasks, a.ntasks) : a.ntasks;
+  for (int task = blockIdx.x * 4 + wave; task < ntasks; task += gridDim.x * 4)
+    strip_task<R, MODE, TB, SMALLA>(a, task, wave, lane, smem);
+}
+
+template <int R, int MODE, bool TB, bool SMALLA>
+__device__ void strip_task(const StripArgs &a, int task, int wave, int lane, uint8_t *smem) {
   const PairTask tk = a.tasks[task];
   const int p = tk.pair;
   const int M = a.b.q_len[p];
@@ -394,6 +404,7 @@ __global__ __launch_bounds__(256) void validate_kernel(ValidateArgs a) {
   for (int k = threadIdx.x; k < N; k += blockDim.x) mine |= (Rs[k] >= a.alphabet);
   if (mine) atomicOr(&bad, 1);
   __syncthreads();
+  if (p == 0 && threadIdx.x == 0 && a.reset_counter) *a.reset_counter = 0;
   if (threadIdx.x == 0) {
     aln_result *r = a.res + p;
     r->score = 0;
@@ -425,7 +436,9 @@ static hipError_t launch_strip_t(const StripArgs &a, hipStream_t s) {
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(kern, dim3((a.ntasks + 3) / 4), dim3(256), lds, s, a);
+  int blocks = (a.ntasks + 3) / 4;
+  if (a.dyn_ntasks) blocks = min(blocks, 1024);
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 
