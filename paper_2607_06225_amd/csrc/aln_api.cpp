@@ -39,7 +39,7 @@ struct aln_ctx {
 
 namespace {
 
-enum Kind { K_STRIP = 0, K_SW16 = 1, K_RERUN = 2 };
+enum Kind { K_STRIP = 0, K_SW16 = 1, K_RERUN = 2, K_DIAG = 3 };
 
 struct LaunchDesc {
   int kind;
@@ -134,6 +134,10 @@ struct aln_plan {
   int sw16_rows = 16;
   uint64_t sw16_off = 0, sw16_single_off = 0, rerun_cnt_off = 0, rerun_off = 0;
   LaunchDesc rerun{};
+  // X-drop widening queues: counters (ws offset) and two queues of n tasks
+  uint64_t widen_cnt_off = 0, widen_off[2] = {0, 0};
+  bool xdrop = false;
+  int32_t n_strip_tb = 0, first_diag_tb = 0, n_diag_tb = 0; // walk ranges
   uint64_t upload_bytes = 0;
   uint64_t tasks_bytes = 0;
   uint64_t tb_base = 0;
@@ -279,8 +283,6 @@ aln_status aln_plan_create(aln_ctx *ctx, int32_t scoring_id, const aln_params *p
   if (p.prune == ALN_XDROP && p.want_cigar)
     return fail(ctx, ALN_E_UNSUPPORTED, "CIGAR is not produced under XDROP");
   if (p.width < ALN_W_AUTO || p.width > ALN_W_I32) return fail(ctx, ALN_E_INVAL, "bad width");
-  if (p.prune != ALN_FULL)
-    return fail(ctx, ALN_E_UNSUPPORTED, "pruning rule %d not available in this build", p.prune);
   const DevScoring &hs = ctx->hsc[scoring_id];
   const int64_t per_step = (int64_t)std::abs(hs.gap_open) + std::abs(hs.gap_extend) + 128;
 
@@ -404,10 +406,17 @@ aln_status aln_plan_create(aln_ctx *ctx, int32_t scoring_id, const aln_params *p
     return ALN_OK;
   }
 
-  // group pairs by rows-per-lane
-  std::vector<std::vector<int32_t>> groups(33);
-  int32_t grpN[33] = {0};
-  bool multi[33] = {false};
+  // ---- per-pair kernel choice: full-matrix strips, or the antidiagonal
+  // kernel (band, X-drop) with a window of 64*RD diagonals
+  struct Item {
+    int32_t pair;
+    int kind;
+    int rows;
+    double cost;
+  };
+  std::vector<Item> items;
+  items.reserve(n);
+  static const int kDiagRows[] = {2, 4, 8, 10, 16, 32};
   for (int32_t i = 0; i < n; ++i) {
     const int32_t M = pl->qlen[i], N = pl->rlen[i];
     if (M < 0 || N < 0) {
@@ -418,45 +427,88 @@ aln_status aln_plan_create(aln_ctx *ctx, int32_t scoring_id, const aln_params *p
       delete pl;
       return fail(ctx, ALN_E_UNSUPPORTED, "pair %d too long for int32 scores", i);
     }
-    const int R = choose_strip_rows(M, N);
-    groups[R].push_back(i);
-    grpN[R] = std::max(grpN[R], N);
-    if (M > 64 * R) multi[R] = true;
-    pl->cells += (int64_t)M * N;
+    Item it{i, K_STRIP, 0, 0.0};
+    const bool band_is_full = p.prune == ALN_BAND && (M == 0 || p.band_w >= std::max(M, N));
+    if (p.prune == ALN_FULL || band_is_full) {
+      it.rows = choose_strip_rows(M, N);
+      it.cost = (double)M * N;
+      pl->cells += (int64_t)M * N;
+    } else {
+      it.kind = K_DIAG;
+      if (p.mode != ALN_GLOBAL && (int64_t)std::max(hs.max_s, 1) * std::min(M, N) >= (1 << 20)) {
+        delete pl;
+        return fail(ctx, ALN_E_UNSUPPORTED, "pair %d: best score may exceed 2^20", i);
+      }
+      if (p.prune == ALN_BAND) {
+        const int64_t w = p.band_w;
+        int64_t width = 2 * w + 6 + ((2 * w + 2) * std::abs((int64_t)N - M) + M - 1) / std::max(M, 1);
+        width = std::min<int64_t>(width, 2LL * std::min(M, N) + 6);
+        it.rows = 0;
+        for (int r : kDiagRows)
+          if (64LL * r - 6 >= width && (!p.want_cigar || r <= 16)) { it.rows = r; break; }
+        if (it.rows == 0) {
+          delete pl;
+          return fail(ctx, ALN_E_UNSUPPORTED, "pair %d: band of %lld diagonals exceeds the window",
+                      i, (long long)width);
+        }
+        it.cost = (double)(M + N) * it.rows;
+      } else {
+        it.rows = 4;
+        it.cost = (double)(M + N);
+      }
+    }
+    items.push_back(it);
   }
+  std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
+    if (a.kind != b.kind) return a.kind < b.kind;
+    if (a.rows != b.rows) return a.rows < b.rows;
+    return a.cost > b.cost;
+  });
   uint64_t tb_off = 0, cg_off = 0;
-  for (int R = 1; R <= 32; ++R) {
-    auto &g = groups[R];
-    if (g.empty()) continue;
-    std::stable_sort(g.begin(), g.end(), [&](int32_t a, int32_t b) {
-      return (int64_t)pl->qlen[a] * pl->rlen[a] > (int64_t)pl->qlen[b] * pl->rlen[b];
-    });
-    LaunchDesc L;
-    L.kind = K_STRIP;
-    L.rows = R;
+  for (size_t k = 0; k < items.size();) {
+    size_t e = k;
+    int32_t grpN = 0;
+    bool multi = false;
+    while (e < items.size() && items[e].kind == items[k].kind && items[e].rows == items[k].rows) {
+      grpN = std::max(grpN, pl->rlen[items[e].pair]);
+      if (items[e].kind == K_STRIP && pl->qlen[items[e].pair] > 64 * items[e].rows) multi = true;
+      ++e;
+    }
+    LaunchDesc L{};
+    L.kind = items[k].kind;
+    L.rows = items[k].rows;
     L.mode = p.mode;
     L.tb = p.want_cigar != 0;
     L.small = small;
     L.first = (int32_t)pl->tasks.size();
-    L.count = (int32_t)g.size();
-    L.lds_bnd = multi[R] ? (int32_t)align_up((uint64_t)(grpN[R] + 1) * 8, 16) : 0;
-    L.lds_prof = small ? 0 : (int32_t)align_up((uint64_t)hs.alphabet * 64 * R, 16);
-    if (4LL * (L.lds_bnd + L.lds_prof) > 160 * 1024) {
-      delete pl;
-      return fail(ctx, ALN_E_UNSUPPORTED,
-                  "full-matrix pairs with N = %d and M > %d need more LDS than a CU has", grpN[R],
-                  64 * R);
+    L.count = (int32_t)(e - k);
+    if (L.kind == K_STRIP) {
+      L.lds_bnd = multi ? (int32_t)align_up((uint64_t)(grpN + 1) * 8, 16) : 0;
+      L.lds_prof = small ? 0 : (int32_t)align_up((uint64_t)hs.alphabet * 64 * L.rows, 16);
+      if (4LL * (L.lds_bnd + L.lds_prof) > 160 * 1024) {
+        delete pl;
+        return fail(ctx, ALN_E_UNSUPPORTED,
+                    "full-matrix pairs with N = %d and M > %d need more LDS than a CU has", grpN,
+                    64 * L.rows);
+      }
     }
-    for (int32_t i : g) {
+    for (size_t q = k; q < e; ++q) {
+      const int32_t i = items[q].pair;
+      const int32_t M = pl->qlen[i], N = pl->rlen[i];
       PairTask t;
       memset(&t, 0, sizeof t);
       t.pair = i;
-      t.rows = R;
+      t.rows = L.rows;
       t.tb_off = -1;
-      const int32_t M = pl->qlen[i], N = pl->rlen[i];
       if (p.want_cigar) {
-        const int64_t ns = (M + 64LL * R - 1) / (64LL * R);
-        const uint64_t bytes = (uint64_t)ns * (uint64_t)(N + 63) * 64ULL * (uint64_t)(R / 2);
+        uint64_t bytes;
+        if (L.kind == K_STRIP) {
+          const int64_t ns = (M + 64LL * L.rows - 1) / (64LL * L.rows);
+          bytes = (uint64_t)ns * (uint64_t)(N + 63) * 64ULL * (uint64_t)(L.rows / 2);
+        } else {
+          const uint64_t nk = (uint64_t)M + N + 1;
+          bytes = (nk + 63) / 64 * 64 * 4 + ((uint64_t)(M + N) / 2 + 1) * 64 * 8;
+        }
         t.tb_off = (int64_t)tb_off;
         tb_off += align_up(bytes);
         t.cigar_off = (int64_t)cg_off;
@@ -466,17 +518,36 @@ aln_status aln_plan_create(aln_ctx *ctx, int32_t scoring_id, const aln_params *p
       pl->tasks.push_back(t);
     }
     pl->launches.push_back(L);
+    k = e;
   }
+  // walk ranges: strip tasks come first (kind order), then antidiagonal tasks
+  if (p.want_cigar) {
+    for (const LaunchDesc &L : pl->launches) {
+      if (L.kind == K_STRIP) pl->n_strip_tb += L.count;
+      if (L.kind == K_DIAG) {
+        if (pl->n_diag_tb == 0) pl->first_diag_tb = L.first;
+        pl->n_diag_tb += L.count;
+      }
+    }
+  }
+  pl->xdrop = p.prune == ALN_XDROP;
   pl->tasks_bytes = align_up(sizeof(PairTask) * std::max<size_t>(pl->tasks.size(), 1));
   pl->upload_bytes = sizeof(PairTask) * pl->tasks.size();
+  if (pl->xdrop) {
+    pl->widen_cnt_off = pl->tasks_bytes;
+    pl->widen_off[0] = pl->widen_cnt_off + kAlign;
+    pl->widen_off[1] = pl->widen_off[0] + align_up(sizeof(PairTask) * (size_t)std::max(n, 1));
+    pl->tasks_bytes = pl->widen_off[1] + align_up(sizeof(PairTask) * (size_t)std::max(n, 1));
+  }
   pl->tb_base = pl->tasks_bytes;
   pl->tb_bytes = tb_off;
   pl->ws_bytes = pl->tb_base + pl->tb_bytes;
   pl->cigar_words = cg_off;
-  if (hipHostMalloc(&pl->pinned, pl->tasks_bytes, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc(&pl->pinned, std::max<uint64_t>(pl->upload_bytes, 1), hipHostMallocDefault) !=
+      hipSuccess) {
     delete pl;
     return fail(ctx, ALN_E_NOMEM, "pinned staging for %llu bytes",
-                (unsigned long long)pl->tasks_bytes);
+                (unsigned long long)pl->upload_bytes);
   }
   if (!pl->tasks.empty()) memcpy(pl->pinned, pl->tasks.data(), sizeof(PairTask) * pl->tasks.size());
   if (fp) {
@@ -529,7 +600,9 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
   int32_t *rerun_cnt = sw16 ? reinterpret_cast<int32_t *>(ws + plan->rerun_cnt_off) : nullptr;
   PairTask *rerun_q = sw16 ? reinterpret_cast<PairTask *>(ws + plan->rerun_off) : nullptr;
 
-  alnk::ValidateArgs va{bp, plan->n, hsc.alphabet, d_res, rerun_cnt};
+  int32_t *widen_cnt = plan->xdrop ? reinterpret_cast<int32_t *>(ws + plan->widen_cnt_off) : nullptr;
+  alnk::ValidateArgs va{bp, plan->n, hsc.alphabet, d_res, sw16 ? rerun_cnt : widen_cnt,
+                        sw16 ? 1 : (plan->xdrop ? 2 : 0)};
   HIP_TRY(ctx, timed_launch(ctx, "validate", st, [&] { return alnk::launch_validate(va, st); }));
 
   if (sw16) {
@@ -573,7 +646,41 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
     return ALN_OK;
   }
 
+  auto diag_args = [&](const PairTask *tasks, int32_t ntasks, const int32_t *dyn, int widen_rows,
+                       int32_t *wcnt, PairTask *wq) {
+    alnk::DiagArgs da;
+    da.b = bp;
+    da.tasks = tasks;
+    da.ntasks = ntasks;
+    da.dyn_ntasks = dyn;
+    da.band_w = plan->p.band_w;
+    da.xdrop = plan->p.xdrop;
+    da.sc = dsc;
+    da.tb = ws + plan->tb_base;
+    da.res = d_res;
+    da.widen_count = wcnt;
+    da.widen = wq;
+    da.widen_rows = widen_rows;
+    return da;
+  };
+  PairTask *wq0 = plan->xdrop ? reinterpret_cast<PairTask *>(ws + plan->widen_off[0]) : nullptr;
+  PairTask *wq1 = plan->xdrop ? reinterpret_cast<PairTask *>(ws + plan->widen_off[1]) : nullptr;
   for (const LaunchDesc &L : plan->launches) {
+    if (L.kind == K_DIAG) {
+      const int widen_rows = plan->xdrop ? 16 : 0;
+      if (!per_pair) {
+        alnk::DiagArgs da = diag_args(dtasks + L.first, L.count, nullptr, widen_rows, widen_cnt, wq0);
+        HIP_TRY(ctx, timed_launch(ctx, plan->xdrop ? "xdrop" : "diag_band", st, [&] {
+                  return alnk::launch_diag(L.rows, L.mode, plan->p.prune, L.tb, da, st);
+                }));
+      } else {
+        for (int32_t k = 0; k < L.count; ++k) {
+          alnk::DiagArgs da = diag_args(dtasks + L.first + k, 1, nullptr, widen_rows, widen_cnt, wq0);
+          HIP_TRY(ctx, alnk::launch_diag(L.rows, L.mode, plan->p.prune, L.tb, da, st));
+        }
+      }
+      continue;
+    }
     alnk::StripArgs sa;
     sa.b = bp;
     sa.dyn_ntasks = nullptr;
@@ -597,6 +704,17 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
       }
     }
   }
+  if (plan->xdrop) {
+    // pairs whose surviving region outgrew 256 diagonals, then 1024
+    alnk::DiagArgs d1 = diag_args(wq0, plan->n, widen_cnt, 32, widen_cnt + 1, wq1);
+    HIP_TRY(ctx, timed_launch(ctx, "xdrop_wide", st, [&] {
+              return alnk::launch_diag(16, ALN_EXTEND, ALN_XDROP, false, d1, st);
+            }));
+    alnk::DiagArgs d2 = diag_args(wq1, plan->n, widen_cnt + 1, 0, nullptr, nullptr);
+    HIP_TRY(ctx, timed_launch(ctx, "xdrop_wide", st, [&] {
+              return alnk::launch_diag(32, ALN_EXTEND, ALN_XDROP, false, d2, st);
+            }));
+  }
   if (plan->p.want_cigar) {
     alnk::WalkArgs wa;
     wa.b = bp;
@@ -606,16 +724,21 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
     wa.tb = ws + plan->tb_base;
     wa.res = d_res;
     wa.cigar = d_cigar;
+    auto walk = [&](int layout, const PairTask *tasks, int32_t nt) -> hipError_t {
+      wa.tasks = tasks;
+      wa.ntasks = nt;
+      wa.layout = layout;
+      return layout == 0 ? alnk::launch_walk(0, wa, st) : alnk::launch_walk_diag(wa, st);
+    };
     if (!per_pair) {
-      wa.tasks = dtasks;
-      wa.ntasks = (int32_t)plan->tasks.size();
-      HIP_TRY(ctx, timed_launch(ctx, "walk", st, [&] { return alnk::launch_walk(0, wa, st); }));
+      HIP_TRY(ctx, timed_launch(ctx, "walk", st, [&] { return walk(0, dtasks, plan->n_strip_tb); }));
+      HIP_TRY(ctx, timed_launch(ctx, "walk", st, [&] {
+                return walk(1, dtasks + plan->first_diag_tb, plan->n_diag_tb);
+              }));
     } else {
-      for (size_t k = 0; k < plan->tasks.size(); ++k) {
-        wa.tasks = dtasks + k;
-        wa.ntasks = 1;
-        HIP_TRY(ctx, alnk::launch_walk(0, wa, st));
-      }
+      for (int32_t k = 0; k < plan->n_strip_tb; ++k) HIP_TRY(ctx, walk(0, dtasks + k, 1));
+      for (int32_t k = 0; k < plan->n_diag_tb; ++k)
+        HIP_TRY(ctx, walk(1, dtasks + plan->first_diag_tb + k, 1));
     }
   }
   return ALN_OK;

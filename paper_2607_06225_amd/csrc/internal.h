@@ -77,7 +77,8 @@ struct ValidateArgs {
   int32_t n;
   int32_t alphabet;
   aln_result *res;
-  int32_t *reset_counter; // zeroed by the first block (re-run queue), or null
+  int32_t *reset_counter; // counters zeroed by the first block (re-run queues)
+  int32_t n_reset;
 };
 
 // Two pairs aligned by one 16-lane group of the packed int16 kernel.
@@ -101,11 +102,29 @@ struct Sw16Args {
   int32_t rerun_threshold; // best >= this: may have saturated
 };
 
+// Antidiagonal kernel (BAND and XDROP).
+struct DiagArgs {
+  BatchPtrs b;
+  const PairTask *tasks;      // rows = window elements per lane (RD)
+  int32_t ntasks;
+  const int32_t *dyn_ntasks;  // device-side count (widening queues), or null
+  int32_t band_w;
+  int32_t xdrop;
+  const DevScoring *sc;
+  uint8_t *tb;                // traceback codes + per-antidiagonal window base
+  aln_result *res;
+  int32_t *widen_count;       // XDROP pairs whose region outgrew the window
+  PairTask *widen;
+  int32_t widen_rows;         // RD of the next wider kernel (0: none)
+};
+
 // Launchers (defined in the kernel translation units).
 hipError_t launch_validate(const ValidateArgs &a, hipStream_t s);
 hipError_t launch_strip(int rows, int mode, bool tb, bool small_alphabet,
                         const StripArgs &a, hipStream_t s);
 hipError_t launch_walk(int layout, const WalkArgs &a, hipStream_t s);
 hipError_t launch_sw16(int rows, const Sw16Args &a, hipStream_t s);
+hipError_t launch_diag(int rows, int mode, int prune, bool tb, const DiagArgs &a, hipStream_t s);
+hipError_t launch_walk_diag(const WalkArgs &a, hipStream_t s);
 
 } // namespace alnk

@@ -1,0 +1,543 @@
+// kernels_diag.hip -- banded and X-drop Gotoh H/E/F on gfx950 (int32),
+// evaluated antidiagonal by antidiagonal in sheared coordinates.
+//
+// Coordinates (Sec. 6.2): antidiagonal k = i + j and diagonal d = j - i; the
+// cells of antidiagonal k are those with d = k (mod 2).  Every dependency of
+// cell (k, d) lies on earlier antidiagonals:
+//   E(i,j) comes from (k-1, d-1),  F(i,j) from (k-1, d+1),  H(i-1,j-1) from
+//   (k-2, d).
+// So one register per diagonal holds that diagonal's latest H, the E value
+// it passes right (EN = max(E + e, H + o + e)) and the F value it passes down
+// (FN = max(F + e, H + o + e)); a step updates the diagonals of one parity
+// in place.  One wavefront per pair; lane l owns RD consecutive diagonals of a
+// 64*RD-wide window [dbase, dbase + 64*RD) that slides two diagonals at a time
+// to follow the active region.  The only cross-lane traffic is one DPP
+// (wave_shr or wave_shl) per step for the diagonal at a lane boundary.
+//
+// Domain per antidiagonal (Sec. 7): a contiguous range of diagonals
+//   BAND  the static prune axis, centred on the rectangle's diagonal: row i
+//         keeps floor(i*N/M) - w <= j <= floor(i*N/M) + w; on antidiagonal k
+//         this is one interval of j, tracked incrementally;
+//   XDROP the candidates [lo - 1, hi + 1] around the previous antidiagonal's
+//         first and last surviving cells; a candidate is pruned (H = E = F =
+//         minus infinity) when it scores more than X below the best score of
+//         the earlier antidiagonals.
+// Cells outside the domain read as minus infinity.
+//
+// Traceback (BAND): per cell a 4-bit code -- bits 0-1 the term that gave H
+// (0 diagonal, 1 E, 2 F, 3 LOCAL zero), bit 2 set when E(i,j+1) opens from
+// H(i,j), bit 3 when F(i+1,j) opens from H(i,j) -- stored per lane and
+// antidiagonal pair, with the window base of every antidiagonal.
+#include "internal.h"
+
+namespace alnk {
+
+constexpr int kSeqBuf = 2048; // circular LDS staging of sequence codes (per wave)
+
+__device__ __forceinline__ int dpp_wshr1(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int dpp_wshl1(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, 0x130, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ int wave_max_i32(int v) {
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// end order: higher score, then smaller i, then smaller j
+__device__ __forceinline__ bool better_end(int s, int i, int j, int bs, int bi, int bj) {
+  if (s != bs) return s > bs;
+  if (i != bi) return i < bi;
+  return j < bj;
+}
+
+// Incremental tracker of the band's j-interval on antidiagonal k: the cells
+// (k - j, j) inside the matrix with c(i) - w <= j <= c(i) + w, c(i) =
+// floor(i*N/M).  As j grows, i = k - j shrinks and c(i) cannot grow, so both
+// conditions cut the antidiagonal at one point each; as k grows both ends move
+// right.  c(i) is stepped with a remainder (N = qn*M + rn), no division.
+struct BandTrack {
+  int M, N, w, qn, rn;
+  int jl, cl, rl; // lower end j and c(k - j), (k - j)*N mod M
+  int ju, cu, ru; // upper end
+  __device__ void init(int M_, int N_, int w_) {
+    M = M_; N = N_; w = w_;
+    qn = N / M; rn = N % M;
+    jl = cl = rl = 0;
+    ju = cu = ru = 0;
+  }
+  __device__ void inc(int &c, int &r) const { r += rn; c += qn; if (r >= M) { r -= M; c += 1; } }
+  __device__ void dec(int &c, int &r) const { r -= rn; c -= qn; if (r < 0) { r += M; c -= 1; } }
+  // advance to antidiagonal k (called for k = 1, 2, ... in order)
+  __device__ void step(int k) {
+    inc(cl, rl); // i = k - jl grew by one
+    inc(cu, ru);
+    const int jmax = min(N, k);
+    // lower end: smallest j >= k - M with j >= c(k - j) - w
+    while (jl <= jmax && (jl < k - M || jl < cl - w)) { ++jl; dec(cl, rl); }
+    // upper end: largest j <= min(N, k) with j <= c(k - j) + w
+    for (;;) {
+      if (ju + 1 > jmax) break;
+      int c2 = cu, r2 = ru;
+      dec(c2, r2);
+      if (ju + 1 > c2 + w) break;
+      ++ju; cu = c2; ru = r2;
+    }
+  }
+};
+
+template <int RD, int MODE, int PRUNE, bool TB>
+__device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8_t *smem,
+                          const int8_t *smat) {
+  constexpr int W = 64 * RD;
+  constexpr int HALF = RD / 2;
+  const PairTask tk = a.tasks[task];
+  const int p = tk.pair;
+  aln_result *res = a.res + p;
+  const int M = a.b.q_len[p];
+  const int N = a.b.r_len[p];
+  const uint8_t *Q = a.b.q + a.b.q_off[p];
+  const uint8_t *Rs = a.b.r + a.b.r_off[p];
+  const int go = a.sc->gap_open, ge = a.sc->gap_extend, goe = go + ge;
+  const int A = a.sc->alphabet;
+
+  if (M == 0 || N == 0) {
+    if (lane == 0) {
+      if (MODE == ALN_GLOBAL) {
+        res->score = (M + N == 0) ? 0 : go + (M + N) * ge;
+        res->q_end = M;
+        res->r_end = N;
+      } else {
+        res->score = 0;
+        res->q_end = 0;
+        res->r_end = 0;
+      }
+      res->cells = 0;
+    }
+    return;
+  }
+
+  uint8_t *qbuf = smem + (size_t)wave * 2 * kSeqBuf;
+  uint8_t *rbuf = qbuf + kSeqBuf;
+  int qtop = 0, rtop = 0; // codes [0, top) staged (modulo kSeqBuf)
+  auto stage = [&](const uint8_t *src, int len, uint8_t *buf, int &top, int need) {
+    while (top < len && top <= need) {
+      const int base = top + lane * 4;
+      uint32_t w4 = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int idx = base + b;
+        const uint32_t c = (idx < len) ? (uint32_t)min((int)src[idx], A) : (uint32_t)A;
+        w4 |= c << (8 * b);
+      }
+      *reinterpret_cast<uint32_t *>(buf + (base & (kSeqBuf - 1))) = w4;
+      top += 256;
+    }
+  };
+
+  // window state: element e = lane*RD + x  <->  diagonal dbase + e
+  int H[RD], EN[RD], FN[RD];
+#pragma unroll
+  for (int x = 0; x < RD; ++x) { H[x] = NEG32; EN[x] = NEG32; FN[x] = NEG32; }
+  int dbase = -(W / 2);
+  const int e0 = lane * RD;
+
+  // write values into the element holding diagonal d (wave-uniform d)
+  auto set_elem = [&](int d, int h, int en, int fn) {
+    const int e = d - dbase;
+    if (e < 0 || e >= W) return;
+    const int ln = e / RD, x = e - ln * RD;
+#pragma unroll
+    for (int y = 0; y < RD; ++y)
+      if (y == x && lane == ln) { H[y] = h; EN[y] = en; FN[y] = fn; }
+  };
+  auto get_h = [&](int d) -> int {
+    const int e = d - dbase;
+    if (e < 0 || e >= W) return NEG32;
+    const int ln = e / RD, x = e - ln * RD;
+    int v = NEG32;
+#pragma unroll
+    for (int y = 0; y < RD; ++y)
+      if (y == x) v = H[y];
+    return __builtin_amdgcn_readlane(v, ln);
+  };
+  auto shift_right2 = [&]() { // dbase += 2
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+      const int h0 = dpp_wshl1(NEG32, H[0]), en0 = dpp_wshl1(NEG32, EN[0]), fn0 = dpp_wshl1(NEG32, FN[0]);
+#pragma unroll
+      for (int x = 0; x < RD - 1; ++x) { H[x] = H[x + 1]; EN[x] = EN[x + 1]; FN[x] = FN[x + 1]; }
+      H[RD - 1] = h0; EN[RD - 1] = en0; FN[RD - 1] = fn0;
+    }
+    dbase += 2;
+  };
+  auto shift_left2 = [&]() { // dbase -= 2
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+      const int hl = dpp_wshr1(NEG32, H[RD - 1]), enl = dpp_wshr1(NEG32, EN[RD - 1]),
+                fnl = dpp_wshr1(NEG32, FN[RD - 1]);
+#pragma unroll
+      for (int x = RD - 1; x > 0; --x) { H[x] = H[x - 1]; EN[x] = EN[x - 1]; FN[x] = FN[x - 1]; }
+      H[0] = hl; EN[0] = enl; FN[0] = fnl;
+    }
+    dbase -= 2;
+  };
+
+  // k = 0: the cell (0,0)
+  set_elem(0, 0, goe, goe);
+  int best = 0, best_i = 0, best_j = 0; // running best through the last antidiagonal
+  int lo = 0, hi = 0;                   // domain (XDROP: survivors) of the last antidiagonal
+  long long cells = 0;
+  BandTrack bt;
+  const bool band_full = (PRUNE == ALN_BAND) && M == 0;
+  if (PRUNE == ALN_BAND) bt.init(M, N, a.band_w);
+  bool overflow = false;
+
+  // traceback output
+  uint32_t *tbw = nullptr;
+  int *dbh = nullptr;
+  uint32_t code_lo = 0, code_hi = 0;
+  int dbase_acc = 0;
+  if (TB) {
+    const int nk = M + N + 1;
+    dbh = reinterpret_cast<int *>(a.tb + tk.tb_off);
+    tbw = reinterpret_cast<uint32_t *>(a.tb + tk.tb_off + (size_t)((nk + 63) / 64) * 64 * 4);
+  }
+  int gh = NEG32; // GLOBAL: H(M, N)
+
+  const int KMAX = M + N;
+  for (int k = 1; k <= KMAX; ++k) {
+    // ---- domain of antidiagonal k (in d), clipped to the matrix
+    int dlo, dhi;
+    const int mlo = max(-k, k - 2 * M), mhi = min(k, 2 * N - k);
+    if (PRUNE == ALN_BAND) {
+      if (band_full) {
+        dlo = mlo; dhi = mhi;
+      } else {
+        bt.step(k);
+        dlo = 2 * bt.jl - k;
+        dhi = 2 * bt.ju - k;
+      }
+    } else {
+      dlo = max(lo - 1, mlo);
+      dhi = min(hi + 1, mhi);
+      if (dlo > dhi) break;
+    }
+    // ---- keep the domain inside the window
+    if (dlo <= dhi) {
+      if (dhi - dlo > W - 6) { overflow = true; break; }
+      while (dhi > dbase + W - 3) shift_right2();
+      while (dlo < dbase + 2) shift_left2();
+    }
+    const int par = k & 1;
+    // ---- stage sequence codes for this step's window
+    {
+      const int needq = ((k - dbase) >> 1) + 64; // largest i on the window, plus slack
+      const int needr = ((k + dbase + W) >> 1) + 64;
+      stage(Q, M, qbuf, qtop, min(needq, M + 64));
+      stage(Rs, N, rbuf, rtop, min(needr, N + 64));
+    }
+    if (TB) {
+      if (lane == (k & 63)) dbase_acc = dbase;
+      if ((k & 63) == 63 || k == KMAX) {
+        const int blk = k >> 6;
+        if (lane <= (k & 63)) dbh[blk * 64 + lane] = dbase_acc;
+      }
+    }
+    // ---- neighbour values across the lane boundary
+    int left_x = NEG32, right_x = NEG32;
+    if (par == 0) left_x = dpp_wshr1(NEG32, EN[RD - 1]);
+    else right_x = dpp_wshl1(NEG32, FN[0]);
+    // ---- SIMD update of this parity's diagonals
+    const int elo = dlo - dbase, ehi = dhi - dbase; // domain in element index
+    const int thr = (PRUNE == ALN_XDROP) ? max(best - a.xdrop, NEG32 / 2 + 1) : NEG32;
+    int kkey = -1;                                  // (H << 11) | e of the best survivor
+    const int d0 = dbase + e0 + par;
+    const int i0 = (k - d0) >> 1, j0 = (k + d0) >> 1;
+    uint32_t cw = 0;
+#pragma unroll
+    for (int m = 0; m < HALF; ++m) {
+      const int x = 2 * m + par;
+      const int e = e0 + x;
+      const int left = (x == 0) ? left_x : EN[(x + RD - 1) % RD];
+      const int right = (x == RD - 1) ? right_x : FN[(x + 1) % RD];
+      const int i = i0 - m, j = j0 + m;
+      const int qc = qbuf[(i - 1) & (kSeqBuf - 1)];
+      const int rc = rbuf[(j - 1) & (kSeqBuf - 1)];
+      const int sv = smat[qc * kMaxAlphabet + rc];
+      const int hd = H[x] + sv;
+      int h = max(max(hd, left), right);
+      if (MODE == ALN_LOCAL) h = max(h, 0);
+      const int t = h + goe;
+      const int en = max(left + ge, t);
+      const int fn = max(right + ge, t);
+      bool keep = (unsigned)(e - elo) <= (unsigned)(ehi - elo) && elo <= ehi;
+      if (PRUNE == ALN_XDROP) keep = keep && h >= thr;
+      if (TB) {
+        uint32_t hs = (h == hd) ? 0u : ((h == left) ? 1u : 2u);
+        if (MODE == ALN_LOCAL && h == 0) hs = 3u;
+        const uint32_t nib = hs | ((en == t) ? 4u : 0u) | ((fn == t) ? 8u : 0u);
+        cw |= nib << (4 * m);
+      }
+      H[x] = keep ? h : NEG32;
+      EN[x] = keep ? en : NEG32;
+      FN[x] = keep ? fn : NEG32;
+      if (MODE != ALN_GLOBAL) {
+        const int key = keep ? ((max(h, -1) << 11) | e) : -1;
+        kkey = max(kkey, key);
+      }
+    }
+    // ---- boundary cells (i = 0 at d = k, j = 0 at d = -k) by formula
+    if (k <= dhi + 1 || -k >= dlo - 1) {
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        const int d = side ? -k : k;
+        if (d < dlo || d > dhi) continue;
+        const int hb = (MODE == ALN_LOCAL) ? 0 : go + k * ge;
+        const bool kb = !(PRUNE == ALN_XDROP && hb < thr);
+        set_elem(d, kb ? hb : NEG32, kb ? hb + goe : NEG32, kb ? hb + goe : NEG32);
+        if (TB) {
+          const int e = d - dbase, ln = e / RD, x = e - ln * RD;
+          if (lane == ln) cw = (cw & ~(0xfu << (4 * (x >> 1)))) | (0xcu << (4 * (x >> 1)));
+        }
+        if (MODE != ALN_GLOBAL && kb) {
+          const int key = (max(hb, -1) << 11) | (d - dbase);
+          if (lane == 0) kkey = max(kkey, key);
+        }
+      }
+    }
+    if (TB) {
+      if (par == 0) code_lo = cw;
+      else code_hi = cw;
+      if (par == 1 || k == KMAX) {
+        const uint32_t lo32 = code_lo | (HALF < 8 ? (code_hi << (4 * HALF)) : 0u);
+        const uint32_t hi32 = (HALF < 8) ? (code_hi >> (32 - 4 * HALF)) : code_hi;
+        *reinterpret_cast<uint2 *>(tbw + ((size_t)(k >> 1) * 64 + lane) * 2) = make_uint2(lo32, hi32);
+        code_lo = code_hi = 0;
+      }
+    }
+    // ---- cells evaluated on this antidiagonal (i >= 1 and j >= 1)
+    {
+      const int c_lo = max(dlo, 2 - k), c_hi = min(dhi, k - 2);
+      if (c_lo <= c_hi) cells += (c_hi - c_lo) / 2 + 1;
+    }
+    // ---- best cell of this antidiagonal, next domain
+    if (MODE != ALN_GLOBAL) {
+      const int kb = wave_max_i32(kkey);
+      if (kb >= 0) {
+        const int sc = kb >> 11;
+        const int d = dbase + (kb & 2047);
+        const int bi = (k - d) >> 1, bj = (k + d) >> 1;
+        if (better_end(sc, bi, bj, best, best_i, best_j)) { best = sc; best_i = bi; best_j = bj; }
+      }
+    }
+    if (PRUNE == ALN_XDROP) {
+      // first and last surviving diagonals
+      int slo = 1 << 30, shi = -(1 << 30);
+#pragma unroll
+      for (int m = 0; m < HALF; ++m) {
+        const int x = 2 * m + par;
+        const unsigned long long bal = __ballot(H[x] > NEG32 / 2);
+        if (bal) {
+          const int lf = __ffsll((long long)bal) - 1;
+          const int ll = 63 - __clzll((long long)bal);
+          slo = min(slo, dbase + lf * RD + x);
+          shi = max(shi, dbase + ll * RD + x);
+        }
+      }
+      if (slo > shi) break; // every candidate pruned: the extension stops
+      lo = slo;
+      hi = shi;
+    } else {
+      lo = dlo;
+      hi = dhi;
+    }
+    if (MODE == ALN_GLOBAL && k == KMAX) gh = get_h(N - M);
+  }
+
+  if (lane == 0) {
+    if (overflow) {
+      res->flags |= ALN_F_WIDENED;
+      if (a.widen_rows > 0) {
+        const int slot = atomicAdd(a.widen_count, 1);
+        PairTask t = tk;
+        t.rows = a.widen_rows;
+        a.widen[slot] = t;
+      } else {
+        res->status = ALN_R_TOO_WIDE; // region wider than the widest window
+      }
+    } else if (MODE == ALN_GLOBAL) {
+      if (gh <= NEG32 / 2) {
+        res->score = INT32_MIN;
+        res->status = ALN_R_UNREACHABLE;
+      } else {
+        res->score = gh;
+      }
+      res->q_end = M;
+      res->r_end = N;
+    } else {
+      res->score = best;
+      res->q_end = best_i;
+      res->r_end = best_j;
+    }
+    if (!overflow) res->cells = cells;
+  }
+}
+
+template <int RD, int MODE, int PRUNE, bool TB>
+__global__ __launch_bounds__(256) void diag_kernel(DiagArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  int8_t *smat = reinterpret_cast<int8_t *>(smem + 4 * 2 * kSeqBuf);
+  const int A = a.sc->alphabet;
+  for (int k = threadIdx.x; k < kMaxAlphabet * kMaxAlphabet; k += blockDim.x) {
+    const int qa = k / kMaxAlphabet, rc = k % kMaxAlphabet;
+    smat[k] = (qa < A && rc < A) ? (int8_t)a.sc->mat[k] : (int8_t)-128;
+  }
+  __syncthreads();
+  const int ntasks = a.dyn_ntasks ? min(*a.dyn_ntasks, a.ntasks) : a.ntasks;
+  for (int task = blockIdx.x * 4 + wave; task < ntasks; task += gridDim.x * 4)
+    diag_task<RD, MODE, PRUNE, TB>(a, task, wave, lane, smem, smat);
+}
+
+// ---------------------------------------------------------------- walk
+// Code of cell (i, j) in the sheared layout: antidiagonal k = i + j, window
+// base dbase(k), element e = (j - i) - dbase(k) in lane e / RD.
+__device__ __forceinline__ int diag_code(const uint8_t *tbp, int i, int j, int RD, int nk) {
+  const int k = i + j, d = j - i;
+  const int *dbh = reinterpret_cast<const int *>(tbp);
+  const uint8_t *codes = tbp + (size_t)((nk + 63) / 64) * 64 * 4;
+  const int e = d - dbh[k];
+  const int ln = e / RD, x = e - ln * RD;
+  const int pos = (k & 1) * (RD / 2) + (x >> 1);
+  const uint8_t b = codes[((size_t)(k >> 1) * 64 + ln) * 8 + (pos >> 1)];
+  return (b >> ((pos & 1) * 4)) & 15;
+}
+
+struct CigarOut {
+  uint32_t *out;
+  int w, cur, run;
+  bool overflow;
+  __device__ void emit(int op) {
+    if (op == cur) { ++run; return; }
+    flush();
+    cur = op;
+    run = 1;
+  }
+  __device__ void flush() {
+    if (cur >= 0) {
+      if (w > 0) out[--w] = ((uint32_t)run << 4) | (uint32_t)cur;
+      else overflow = true;
+    }
+  }
+};
+
+// One thread per pair; in state E the opening bit is read from the cell to
+// the left, in state F from the cell above (the codes store, for each cell,
+// whether the gaps it passes right and down open there).
+__global__ __launch_bounds__(64) void walk_diag_kernel(WalkArgs a) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.ntasks) return;
+  const PairTask tk = a.tasks[k];
+  const int p = tk.pair;
+  aln_result *res = a.res + p;
+  res->cigar_off = tk.cigar_off;
+  res->cigar_len = 0;
+  if (res->status != ALN_R_OK) return;
+  const int M = a.b.q_len[p], N = a.b.r_len[p];
+  const uint8_t *Q = a.b.q + a.b.q_off[p];
+  const uint8_t *Rs = a.b.r + a.b.r_off[p];
+  const uint8_t *tbp = a.tb + tk.tb_off;
+  const int RD = tk.rows, nk = M + N + 1;
+  const bool local = a.mode == ALN_LOCAL;
+  int i = res->q_end, j = res->r_end;
+  CigarOut cw{a.cigar + tk.cigar_off, tk.cigar_cap, -1, 0, false};
+  int state = 0;
+  bool corrupt = false;
+  for (long guard = 2L * (i + j) + 2; guard > 0; --guard) {
+    if ((state == 1 && j < 1) || (state == 2 && i < 1) || i < 0 || j < 0) { corrupt = true; break; }
+    if (state == 0) {
+      if (i == 0 && j == 0) break;
+      if (local && (i == 0 || j == 0)) break;
+      if (i == 0) { cw.emit(ALN_OP_D); --j; continue; }
+      if (j == 0) { cw.emit(ALN_OP_I); --i; continue; }
+      const int hs = diag_code(tbp, i, j, RD, nk) & 3;
+      if (local && hs == 3) break;
+      if (hs == 0) {
+        cw.emit(Q[i - 1] == Rs[j - 1] ? ALN_OP_EQ : ALN_OP_X);
+        --i;
+        --j;
+      } else {
+        state = hs;
+      }
+    } else if (state == 1) {
+      cw.emit(ALN_OP_D);
+      if (diag_code(tbp, i, j - 1, RD, nk) & 4) state = 0;
+      --j;
+    } else {
+      cw.emit(ALN_OP_I);
+      if (diag_code(tbp, i - 1, j, RD, nk) & 8) state = 0;
+      --i;
+    }
+  }
+  cw.flush();
+  res->q_begin = i;
+  res->r_begin = j;
+  if (corrupt || cw.overflow) {
+    res->status = ALN_R_CIGAR_CAP;
+  } else {
+    res->cigar_len = tk.cigar_cap - cw.w;
+    res->cigar_off = tk.cigar_off + cw.w;
+  }
+  (void)M;
+  (void)N;
+}
+
+hipError_t launch_walk_diag(const WalkArgs &a, hipStream_t s) {
+  if (a.ntasks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(walk_diag_kernel, dim3((a.ntasks + 63) / 64), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int RD, int MODE, int PRUNE, bool TB>
+static hipError_t launch_diag_t(const DiagArgs &a, hipStream_t s) {
+  const size_t lds = (size_t)4 * 2 * kSeqBuf + kMaxAlphabet * kMaxAlphabet;
+  int blocks = (a.ntasks + 3) / 4;
+  if (a.dyn_ntasks) blocks = min(blocks, 2048);
+  hipLaunchKernelGGL((diag_kernel<RD, MODE, PRUNE, TB>), dim3(blocks), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int RD>
+static hipError_t launch_diag_r(int mode, int prune, bool tb, const DiagArgs &a, hipStream_t s) {
+  if (prune == ALN_XDROP) return launch_diag_t<RD, ALN_EXTEND, ALN_XDROP, false>(a, s);
+  switch (mode) {
+  case ALN_GLOBAL:
+    return tb ? launch_diag_t<RD, ALN_GLOBAL, ALN_BAND, true>(a, s)
+              : launch_diag_t<RD, ALN_GLOBAL, ALN_BAND, false>(a, s);
+  case ALN_LOCAL:
+    return tb ? launch_diag_t<RD, ALN_LOCAL, ALN_BAND, true>(a, s)
+              : launch_diag_t<RD, ALN_LOCAL, ALN_BAND, false>(a, s);
+  default:
+    return tb ? launch_diag_t<RD, ALN_EXTEND, ALN_BAND, true>(a, s)
+              : launch_diag_t<RD, ALN_EXTEND, ALN_BAND, false>(a, s);
+  }
+}
+
+hipError_t launch_diag(int rows, int mode, int prune, bool tb, const DiagArgs &a, hipStream_t s) {
+  if (a.ntasks <= 0) return hipSuccess;
+  switch (rows) {
+  case 2: return launch_diag_r<2>(mode, prune, tb, a, s);
+  case 4: return launch_diag_r<4>(mode, prune, tb, a, s);
+  case 8: return launch_diag_r<8>(mode, prune, tb, a, s);
+  case 10: return launch_diag_r<10>(mode, prune, tb, a, s);
+  case 16: return launch_diag_r<16>(mode, prune, tb, a, s);
+  case 32: return launch_diag_r<32>(mode, prune, tb, a, s);
+  default: return hipErrorInvalidValue;
+  }
+}
+
+} // namespace alnk

@@ -404,7 +404,7 @@ __global__ __launch_bounds__(256) void validate_kernel(ValidateArgs a) {
   for (int k = threadIdx.x; k < N; k += blockDim.x) mine |= (Rs[k] >= a.alphabet);
   if (mine) atomicOr(&bad, 1);
   __syncthreads();
-  if (p == 0 && threadIdx.x == 0 && a.reset_counter) *a.reset_counter = 0;
+  if (p == 0 && a.reset_counter && (int)threadIdx.x < a.n_reset) a.reset_counter[threadIdx.x] = 0;
   if (threadIdx.x == 0) {
     aln_result *r = a.res + p;
     r->score = 0;
