@@ -64,6 +64,12 @@ class Stream:
         with np.errstate(over="ignore"):
             return _mix(self.key + idx * _GAMMA)
 
+    def u64_at(self, start, n):
+        """Draws start .. start+n-1 of the stream (does not move the counter)."""
+        idx = np.arange(start + 1, start + 1 + n, dtype=np.uint64)
+        with np.errstate(over="ignore"):
+            return _mix(self.key + idx * _GAMMA)
+
     def uniform(self, n):
         return (self.u64(n) >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))
 
@@ -254,17 +260,110 @@ def sw_protein(n=65536, seed=202, sigma=0.6, homolog_frac=0.3, identity=0.4):
     return b
 
 
+def _segments(lengths):
+    """Start offsets of consecutive segments with the given lengths."""
+    off = np.zeros(len(lengths), dtype=np.int64)
+    if len(lengths) > 1:
+        off[1:] = np.cumsum(lengths[:-1])
+    return off
+
+
+def _dna_sides_chunk(x, y, L, rate, flank, w_sub, w_ins, w_del):
+    """One chunk of _dna_sides: x holds one draw per reference base, y one per
+    flank base; returns (q, q_len, r, r_len) for these sides, concatenated."""
+    ns = L.size
+    ref = (x & np.uint64(3)).astype(np.uint8)
+    u_edit = (x >> np.uint64(40)).astype(np.float64) * (1.0 / (1 << 24))
+    u_type = ((x >> np.uint64(2)) & np.uint64(0xFFFFFF)).astype(np.float64) * (1.0 / (1 << 24))
+    ins_code = ((x >> np.uint64(26)) & np.uint64(3)).astype(np.uint8)
+    u_sub = ((x >> np.uint64(28)) & np.uint64(0xFFF)).astype(np.float64) * (1.0 / (1 << 12))
+    tot = float(w_sub + w_ins + w_del)
+    edit = u_edit < np.repeat(rate, L)
+    t = u_type * tot
+    is_sub = edit & (t < w_sub)
+    is_ins = edit & (t >= w_sub) & (t < w_sub + w_ins)
+    is_del = edit & (t >= w_sub + w_ins)
+    first = ref.copy()
+    shift = (1 + np.floor(u_sub * 3)).astype(np.uint8)
+    first[is_sub] = (first[is_sub] + shift[is_sub]) % 4
+    cnt = np.ones(ref.size, dtype=np.int64)
+    cnt[is_ins] = 2
+    cnt[is_del] = 0
+    starts = np.cumsum(cnt) - cnt
+    qext = np.empty(int(cnt.sum()), dtype=np.uint8)
+    keep = cnt >= 1
+    qext[starts[keep]] = first[keep]
+    qext[starts[is_ins] + 1] = ins_code[is_ins]
+    seg = _segments(L)
+    ccnt = np.concatenate([[0], np.cumsum(cnt)])
+    qlen_ext = ccnt[seg + L] - ccnt[seg]
+    rfl = (y & np.uint64(3)).astype(np.uint8)
+    qfl = ((y >> np.uint64(2)) & np.uint64(3)).astype(np.uint8)
+
+    def join(a, a_len, f, f_len):
+        out_len = a_len + f_len
+        out = np.empty(int(out_len.sum()), dtype=np.uint8)
+        o = _segments(out_len)
+        ia = np.arange(a.size, dtype=np.int64) - np.repeat(_segments(a_len), a_len)
+        out[np.repeat(o, a_len) + ia] = a
+        jf = np.arange(f.size, dtype=np.int64) - np.repeat(_segments(f_len), f_len)
+        out[np.repeat(o + a_len, f_len) + jf] = f
+        return out, out_len
+
+    r, r_len = join(ref, L, rfl, flank)
+    q, q_len = join(qext, qlen_ext, qfl, flank)
+    return q, q_len, r, r_len
+
+
+def _dna_sides(seed, stream_id, L, rate, w_sub, w_ins, w_del, flank=None,
+               chunk_bases=1 << 22, threads=8):
+    """DNA pairs with random reference r_p (length L[p]) and query q_p = r_p
+    edited per base with probability rate[p] (types weighted sub:ins:del as in
+    mutate()), each followed by an unrelated random flank of flank[p] bases.
+
+    One 64-bit draw per reference base from stream (seed, stream_id) fixes the
+    base (bits 0-1), the edit type (bits 2-25 as a uniform), the inserted base
+    (bits 26-27), the substitution offset 1 + floor(3u) (bits 28-39) and the
+    edit decision (bits 40-63 as a uniform); one draw per flank position from
+    stream (seed, stream_id + 1) gives the reference (bits 0-1) and query
+    (bits 2-3) flank bases.  Draws are indexed by absolute base position, so
+    the output does not depend on chunking or threads."""
+    from concurrent.futures import ThreadPoolExecutor
+    L = np.asarray(L, dtype=np.int64)
+    ns = L.size
+    rate = np.broadcast_to(np.asarray(rate, dtype=np.float64), (ns,))
+    flank = np.zeros(ns, np.int64) if flank is None else np.asarray(flank, np.int64)
+    cumL = np.concatenate([[0], np.cumsum(L)])
+    cumF = np.concatenate([[0], np.cumsum(flank)])
+    bounds = [0]
+    while bounds[-1] < ns:
+        s0 = bounds[-1]
+        s1 = int(np.searchsorted(cumL, cumL[s0] + chunk_bases, side="right")) - 1
+        bounds.append(min(ns, max(s1, s0 + 1)))
+    sx, sy = Stream(seed, stream_id), Stream(seed, stream_id + 1)
+
+    def work(c):
+        s0, s1 = bounds[c], bounds[c + 1]
+        x = sx.u64_at(int(cumL[s0]), int(cumL[s1] - cumL[s0]))
+        y = sy.u64_at(int(cumF[s0]), int(cumF[s1] - cumF[s0]))
+        return _dna_sides_chunk(x, y, L[s0:s1], rate[s0:s1], flank[s0:s1],
+                                w_sub, w_ins, w_del)
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        parts = list(ex.map(work, range(len(bounds) - 1)))
+    q = np.concatenate([p[0] for p in parts]) if parts else np.zeros(0, np.uint8)
+    q_len = np.concatenate([p[1] for p in parts]) if parts else np.zeros(0, np.int64)
+    r = np.concatenate([p[2] for p in parts]) if parts else np.zeros(0, np.uint8)
+    r_len = np.concatenate([p[3] for p in parts]) if parts else np.zeros(0, np.int64)
+    return q, _segments(q_len), q_len.astype(np.int32), r, _segments(r_len), r_len.astype(np.int32)
+
+
 def band_long(n=2048, seed=303, min_len=10000, max_len=100000, band_w=256):
     st = Stream(seed, 3)
     L = st.integers(min_len, max_len, n)
-    qs, rs = [], []
-    for p in range(n):
-        ref = random_codes(st, int(L[p]), 4)
-        qry = mutate(ref, 0.12, 3, 5, 4, 4, st)
-        qs.append(qry)
-        rs.append(ref)
-    b = pack_pairs(qs, rs, dna_matrix(1, -2), -2, -1, GLOBAL, BAND, band_w=band_w,
-                   want_cigar=True, name="band_long")
+    q, qo, ql, r, ro, rl = _dna_sides(seed, 30, L, 0.12, 3, 5, 4)
+    b = Batch("band_long", q, qo, ql, r, ro, rl, dna_matrix(1, -2), -2, -1, GLOBAL, BAND,
+              band_w=band_w, want_cigar=True)
     b.meta = dict(seed=seed)
     return b
 
@@ -273,25 +372,16 @@ def xdrop_ext(n=200000, seed=404, min_len=150, max_len=5000, xdrop=100, seed_len
     """2n extension problems: entries [0, n) are left sides, [n, 2n) right
     sides of the same n seeds.  meta['seed_score'] is the exact seed's score."""
     st = Stream(seed, 4)
-    qs, rs = [], []
-    sides = []
-    for side in range(2):
-        L = st.integers(min_len, max_len, n)
-        div = 0.05 + 0.20 * st.uniform(n)
-        for p in range(n):
-            ext = random_codes(st, int(L[p]), 4)
-            flank_len = int(np.ceil(0.1 * L[p]))
-            rflank = random_codes(st, flank_len, 4)
-            qext = mutate(ext, float(div[p]), 2, 1, 1, 4, st)
-            qflank = random_codes(st, flank_len, 4)
-            rs.append(np.concatenate([ext, rflank]))
-            qs.append(np.concatenate([qext, qflank]))
-        sides.append(dict(L=L, div=div))
+    ns = 2 * n
+    L = st.integers(min_len, max_len, ns)
+    div = 0.05 + 0.20 * st.uniform(ns)
+    flank = np.ceil(0.1 * L).astype(np.int64)
     seeds = random_codes(st, n * seed_len, 4).reshape(n, seed_len)
-    b = pack_pairs(qs, rs, dna_matrix(2, -4), -4, -2, EXTEND, XDROP, xdrop=xdrop,
-                   name="xdrop_ext")
+    q, qo, ql, r, ro, rl = _dna_sides(seed, 40, L, div, 2, 1, 1, flank=flank)
+    b = Batch("xdrop_ext", q, qo, ql, r, ro, rl, dna_matrix(2, -4), -4, -2, EXTEND, XDROP,
+              xdrop=xdrop)
     b.meta = dict(seed=seed, n_ext=n, seed_len=seed_len, seed_score=2 * seed_len,
-                  seeds=seeds, sides=sides)
+                  seeds=seeds, L=L, div=div)
     return b
 
 
