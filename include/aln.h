@@ -208,6 +208,98 @@ aln_status aln_set_profiling(aln_ctx *ctx, int32_t enable);
 int32_t aln_kernel_times(aln_ctx *ctx, const char **names, double *ms,
                          int64_t *launches, int32_t max);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of single-pair requests on one device.
+ *
+ * A server owns a worker thread, `streams` HIP streams (default priority)
+ * and one device allocation of `hbm_budget` bytes made at creation.  Each
+ * submitted request is copied to host memory owned by the server.  Whenever
+ * a stream is idle, the worker takes the oldest pending request together
+ * with later pending requests of the same scoring and parameters (up to
+ * max_batch_pairs pairs and max_batch_cells cells), plans them as one batch
+ * (same planner and kernels as aln_execute) and admits the micro-batch once
+ * the budget has a free block for its footprint: sequences + workspace
+ * (traceback codes dominate) + results + CIGAR words.  Requests that arrive
+ * while micro-batches run wait for the next free stream and memory;
+ * micro-batches on different streams overlap on the device.  A pair's
+ * result does not depend on which requests share its micro-batch.
+ * Scorings must be set on the context before aln_server_create; the server
+ * keeps its own device copies.  All aln_server_* calls are thread-safe.
+ * ---------------------------------------------------------------------- */
+typedef struct aln_server aln_server;
+
+typedef struct {
+  int32_t streams;         /* micro-batches in flight at once, 1..16          */
+  int32_t max_batch_pairs; /* pairs per micro-batch, >= 1                     */
+  uint64_t hbm_budget;     /* device bytes for admitted work; 0: half of the
+                              free device memory at creation                 */
+  int64_t max_batch_cells; /* M*N cap per micro-batch (0: none); the oldest
+                              request is always taken                        */
+} aln_server_cfg;
+
+typedef struct {
+  int32_t scoring_id;   /* from aln_set_scoring, before aln_server_create     */
+  aln_params params;    /* as for aln_plan_create                            */
+  const uint8_t *q;     /* host memory, copied by aln_server_submit          */
+  int32_t q_len;
+  const uint8_t *r;
+  int32_t r_len;
+  uint64_t tag;         /* returned unchanged in the completion              */
+} aln_request;
+
+typedef struct {
+  uint64_t id;          /* from aln_server_submit                            */
+  uint64_t tag;
+  aln_result result;    /* cigar_off indexes the `cigar` buffer of the poll
+                           that returned this completion                     */
+  int32_t error;        /* ALN_OK, or why the request was not run
+                           (ALN_E_DEVICE, ALN_E_NOMEM, ALN_E_CAPACITY)       */
+  int32_t batch_pairs;  /* pairs in the micro-batch that carried it          */
+  uint64_t batch_id;
+  double t_submit;      /* seconds on the server clock (aln_server_clock)   */
+  double t_launch;      /* its micro-batch was enqueued                      */
+  double t_done;        /* the worker saw the micro-batch finish             */
+} aln_completion;       /* 104 bytes */
+
+typedef struct {
+  uint64_t submitted, completed, batches;
+  uint64_t admission_waits;  /* times a ready micro-batch waited for memory   */
+  uint64_t arena_bytes;      /* device budget in use by the server            */
+  uint64_t peak_arena_bytes; /* most bytes held by micro-batches at once      */
+  int64_t cells;             /* cells evaluated by completed requests         */
+  int32_t peak_inflight;     /* most micro-batches on the device at once      */
+  int32_t streams;
+} aln_server_stats;          /* 64 bytes */
+
+/* Create a server on ctx's device.  Errors: ALN_E_INVAL (configuration),
+ * ALN_E_NOMEM (the budget cannot be reserved), ALN_E_DEVICE. */
+aln_status aln_server_create(aln_ctx *ctx, const aln_server_cfg *cfg,
+                             aln_server **srv);
+/* Finish every submitted request, then release the server's resources.
+ * Completions not yet polled are discarded. */
+void aln_server_destroy(aln_server *srv);
+/* Queue one pair.  The request is planned alone first: ALN_E_INVAL or
+ * ALN_E_UNSUPPORTED for what aln_plan_create would reject, ALN_E_CAPACITY if
+ * its footprint exceeds the whole budget.  *id receives the request id. */
+aln_status aln_server_submit(aln_server *srv, const aln_request *req,
+                             uint64_t *id);
+/* Move up to `max` finished requests into out[], oldest first, waiting up to
+ * wait_us microseconds if none is ready.  CIGAR words go to the caller's
+ * host buffer cigar[0 .. cigar_cap); *cigar_used receives the words written.
+ * Returns the number of completions, or ALN_E_CAPACITY if the next
+ * completion's CIGAR alone does not fit in cigar_cap. */
+int32_t aln_server_poll(aln_server *srv, aln_completion *out, int32_t max,
+                        uint32_t *cigar, uint64_t cigar_cap,
+                        uint64_t *cigar_used, int32_t wait_us);
+/* Wait until every submitted request has finished (timeout_ms < 0: no limit).
+ * ALN_E_CAPACITY if the time ran out. */
+aln_status aln_server_drain(aln_server *srv, int32_t timeout_ms);
+/* Seconds since the server was created (the clock of the completion times). */
+double aln_server_clock(const aln_server *srv);
+aln_status aln_server_get_stats(aln_server *srv, aln_server_stats *stats);
+/* Message of the last failed call or worker error (empty string if none). */
+const char *aln_server_last_error(aln_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

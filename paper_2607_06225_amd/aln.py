@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(HERE, "libaln_hip.so")
 GLOBAL, LOCAL, EXTEND = 0, 1, 2
 FULL, BAND, XDROP = 0, 1, 2
 W_AUTO, W_I16, W_I32 = 0, 1, 2
-R_OK, R_UNREACHABLE, R_CIGAR_CAP, R_BAD_SYMBOL = 0, 1, 2, 3
+R_OK, R_UNREACHABLE, R_CIGAR_CAP, R_BAD_SYMBOL, R_TOO_WIDE = 0, 1, 2, 3, 4
+E_INVAL, E_NOMEM, E_DEVICE, E_CAPACITY, E_UNSUPPORTED = -1, -2, -3, -4, -5
 F_I16_RERUN, F_WIDENED = 1, 2
 OP_I, OP_D, OP_EQ, OP_X = 1, 2, 7, 8
 
@@ -53,6 +54,32 @@ class _Footprint(ctypes.Structure):
                 ("cigar_words", ctypes.c_uint64), ("cells", ctypes.c_int64)]
 
 
+class _ServerCfg(ctypes.Structure):
+    _fields_ = [("streams", ctypes.c_int32), ("max_batch_pairs", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_uint64), ("max_batch_cells", ctypes.c_int64)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("scoring_id", ctypes.c_int32), ("params", _Params),
+                ("q", ctypes.c_void_p), ("q_len", ctypes.c_int32),
+                ("r", ctypes.c_void_p), ("r_len", ctypes.c_int32),
+                ("tag", ctypes.c_uint64)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("admission_waits", ctypes.c_uint64),
+                ("arena_bytes", ctypes.c_uint64), ("peak_arena_bytes", ctypes.c_uint64),
+                ("cells", ctypes.c_int64), ("peak_inflight", ctypes.c_int32),
+                ("streams", ctypes.c_int32)]
+
+
+COMPLETION_DTYPE = np.dtype(
+    [("id", "<u8"), ("tag", "<u8")] + [(n, RESULT_DTYPE.fields[n][0]) for n in RESULT_DTYPE.names]
+    + [("error", "<i4"), ("batch_pairs", "<i4"), ("batch_id", "<u8"),
+       ("t_submit", "<f8"), ("t_launch", "<f8"), ("t_done", "<f8")])
+assert COMPLETION_DTYPE.itemsize == 104
+
 _lib = None
 
 # every symbol include/aln.h declares
@@ -61,6 +88,8 @@ EXPORTS = [
     "aln_set_scoring", "aln_plan_create", "aln_plan_destroy", "aln_execute",
     "aln_execute_per_pair", "aln_graph_capture", "aln_graph_launch",
     "aln_set_profiling", "aln_kernel_times",
+    "aln_server_create", "aln_server_destroy", "aln_server_submit", "aln_server_poll",
+    "aln_server_drain", "aln_server_clock", "aln_server_get_stats", "aln_server_last_error",
 ]
 
 
@@ -87,6 +116,14 @@ def load_library(path=LIB_PATH):
         "aln_graph_launch": ([P, P, P], I32),
         "aln_set_profiling": ([P, I32], I32),
         "aln_kernel_times": ([P, P, P, P, I32], I32),
+        "aln_server_create": ([P, P, P], I32),
+        "aln_server_destroy": ([P], None),
+        "aln_server_submit": ([P, P, P], I32),
+        "aln_server_poll": ([P, P, I32, P, U64, P, I32], I32),
+        "aln_server_drain": ([P, I32], I32),
+        "aln_server_clock": ([P], ctypes.c_double),
+        "aln_server_get_stats": ([P, P], I32),
+        "aln_server_last_error": ([P], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -273,3 +310,87 @@ def align(ctx, batch, scoring_id=None, width=W_AUTO, mode=None, per_pair=False, 
     cig = buf.cigars(res)
     plan.close()
     return res, cig
+
+
+class Server:
+    """Continuous-batching request server (include/aln.h, aln_server_*).
+
+    Scorings must be set on ``ctx`` before the server is created.  submit()
+    copies the sequences; poll() returns (completions ndarray of
+    COMPLETION_DTYPE, list of CIGAR arrays or None per completion)."""
+
+    def __init__(self, ctx, streams=4, max_batch_pairs=1024, hbm_budget=0, max_batch_cells=0):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        cfg = _ServerCfg(int(streams), int(max_batch_pairs), int(hbm_budget),
+                         int(max_batch_cells))
+        h = ctypes.c_void_p()
+        ctx._check(self.lib.aln_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self._max_cigar = 1
+        self._comp = (ctypes.c_uint8 * (COMPLETION_DTYPE.itemsize * 256))()
+        self._cig = np.zeros(1 << 16, dtype=np.uint32)
+
+    def _err(self, rc):
+        msg = self.lib.aln_server_last_error(self.handle) or b""
+        return AlnError(f"aln_server call failed ({rc}): {msg.decode(errors='replace')}")
+
+    def submit(self, scoring_id, q, r, mode, prune=FULL, band_w=0, xdrop=0, width=W_AUTO,
+               want_cigar=False, tag=0):
+        qa = np.ascontiguousarray(q, dtype=np.uint8)
+        ra = np.ascontiguousarray(r, dtype=np.uint8)
+        req = _Request(int(scoring_id),
+                       _Params(int(mode), int(prune), int(band_w), int(xdrop), int(width),
+                               1 if want_cigar else 0),
+                       qa.ctypes.data if qa.size else None, int(qa.size),
+                       ra.ctypes.data if ra.size else None, int(ra.size), int(tag))
+        rid = ctypes.c_uint64()
+        rc = self.lib.aln_server_submit(self.handle, ctypes.byref(req), ctypes.byref(rid))
+        if rc != 0:
+            raise self._err(rc)
+        if want_cigar:
+            self._max_cigar = max(self._max_cigar, qa.size + ra.size + 1)
+        return int(rid.value)
+
+    def poll(self, max_n=256, wait_us=0):
+        max_n = min(int(max_n), 256)
+        need = self._max_cigar * max_n
+        if self._cig.size < need:
+            self._cig = np.zeros(need, dtype=np.uint32)
+        used = ctypes.c_uint64()
+        k = self.lib.aln_server_poll(self.handle, self._comp, max_n, self._cig.ctypes.data,
+                                     int(self._cig.size), ctypes.byref(used), int(wait_us))
+        if k < 0:
+            raise self._err(k)
+        comp = np.frombuffer(bytes(self._comp)[: k * COMPLETION_DTYPE.itemsize],
+                             dtype=COMPLETION_DTYPE).copy()
+        cigs = [self._cig[int(c["cigar_off"]): int(c["cigar_off"]) + int(c["cigar_len"])].copy()
+                if c["cigar_len"] > 0 else None for c in comp]
+        return comp, cigs
+
+    def drain(self, timeout_ms=-1):
+        rc = self.lib.aln_server_drain(self.handle, int(timeout_ms))
+        if rc != 0:
+            raise self._err(rc)
+
+    def clock(self):
+        return float(self.lib.aln_server_clock(self.handle))
+
+    def stats(self):
+        st = _ServerStats()
+        rc = self.lib.aln_server_get_stats(self.handle, ctypes.byref(st))
+        if rc != 0:
+            raise self._err(rc)
+        return {n: int(getattr(st, n)) for n, _ in _ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            self.lib.aln_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

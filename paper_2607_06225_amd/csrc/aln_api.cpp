@@ -18,55 +18,15 @@
 #include <vector>
 
 #include "internal.h"
+#include "runtime.h"
 
 using alnk::DevScoring;
 using alnk::PairTask;
+using namespace alnrt;
 
-struct aln_ctx {
-  int device = 0;
-  std::string err;
-  std::vector<DevScoring *> dsc; // device copies, owned
-  std::vector<DevScoring> hsc;   // host mirrors
-  // kernel timing (aln_set_profiling)
-  bool profiling = false;
-  struct TimedLaunch {
-    const char *name;
-    hipEvent_t a, b;
-  };
-  std::vector<TimedLaunch> timed;
-  std::vector<hipEvent_t> event_pool;
-};
 
 namespace {
 
-enum Kind { K_STRIP = 0, K_SW16 = 1, K_RERUN = 2, K_DIAG = 3 };
-
-struct LaunchDesc {
-  int kind;
-  int rows;
-  int mode;
-  bool tb;
-  bool small;
-  int32_t first; // first task of this launch
-  int32_t count;
-  int32_t lds_bnd;
-  int32_t lds_prof;
-};
-
-constexpr uint64_t kAlign = 256;
-uint64_t align_up(uint64_t v, uint64_t a = kAlign) { return (v + a - 1) / a * a; }
-
-aln_status fail(aln_ctx *ctx, aln_status st, const char *fmt, ...) {
-  if (ctx) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    ctx->err = buf;
-  }
-  return st;
-}
 
 #define HIP_TRY(ctx, call)                                                       \
   do {                                                                           \
@@ -120,35 +80,17 @@ hipError_t timed_launch(aln_ctx *ctx, const char *name, hipStream_t st, F &&laun
 
 } // namespace
 
-struct aln_plan {
-  aln_ctx *ctx = nullptr;
-  int32_t scoring_id = 0;
-  aln_params p{};
-  int32_t n = 0;
-  std::vector<int32_t> qlen, rlen;
-  std::vector<PairTask> tasks;
-  std::vector<LaunchDesc> launches;
-  // packed int16 path
-  std::vector<alnk::Sw16Task> sw16_tasks;    // two pairs per task
-  std::vector<alnk::Sw16Task> sw16_single;   // one pair per task (per-pair runs)
-  int sw16_rows = 16;
-  uint64_t sw16_off = 0, sw16_single_off = 0, rerun_cnt_off = 0, rerun_off = 0;
-  LaunchDesc rerun{};
-  // X-drop widening queues: counters (ws offset) and two queues of n tasks
-  uint64_t widen_cnt_off = 0, widen_off[2] = {0, 0};
-  bool xdrop = false;
-  int32_t n_strip_tb = 0, first_diag_tb = 0, n_diag_tb = 0; // walk ranges
-  uint64_t upload_bytes = 0;
-  uint64_t tasks_bytes = 0;
-  uint64_t tb_base = 0;
-  uint64_t tb_bytes = 0;
-  uint64_t ws_bytes = 0;
-  uint64_t cigar_words = 0;
-  int64_t cells = 0;
-  void *pinned = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-};
+aln_status alnrt::fail(aln_ctx *ctx, aln_status st, const char *fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return st;
+}
 
 extern "C" {
 
@@ -266,9 +208,11 @@ aln_status aln_set_scoring(aln_ctx *ctx, const aln_scoring *sc, int32_t *scoring
   return ALN_OK;
 }
 
-aln_status aln_plan_create(aln_ctx *ctx, int32_t scoring_id, const aln_params *params, int32_t n,
-                           const int32_t *q_len_host, const int32_t *r_len_host, aln_plan **plan,
-                           aln_footprint *fp) {
+} // extern "C"
+
+aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params *params, int32_t n,
+                             const int32_t *q_len_host, const int32_t *r_len_host,
+                             aln_plan **plan) {
   if (!ctx || !params || !plan || n < 0 || (n > 0 && (!q_len_host || !r_len_host)))
     return fail(ctx, ALN_E_INVAL, "null argument or negative n");
   *plan = nullptr;
@@ -387,21 +331,6 @@ aln_status aln_plan_create(aln_ctx *ctx, int32_t scoring_id, const aln_params *p
     pl->tb_bytes = 0;
     pl->ws_bytes = pl->tasks_bytes;
     pl->cigar_words = 0;
-    if (hipHostMalloc(&pl->pinned, std::max<uint64_t>(pl->upload_bytes, 1), hipHostMallocDefault) !=
-        hipSuccess) {
-      delete pl;
-      return fail(ctx, ALN_E_NOMEM, "pinned staging");
-    }
-    memcpy((uint8_t *)pl->pinned + pl->sw16_off, pl->sw16_tasks.data(),
-           sizeof(alnk::Sw16Task) * pl->sw16_tasks.size());
-    memcpy((uint8_t *)pl->pinned + pl->sw16_single_off, pl->sw16_single.data(),
-           sizeof(alnk::Sw16Task) * pl->sw16_single.size());
-    if (fp) {
-      fp->workspace_bytes = pl->ws_bytes;
-      fp->traceback_bytes = 0;
-      fp->cigar_words = 0;
-      fp->cells = pl->cells;
-    }
     *plan = pl;
     return ALN_OK;
   }
@@ -543,13 +472,36 @@ aln_status aln_plan_create(aln_ctx *ctx, int32_t scoring_id, const aln_params *p
   pl->tb_bytes = tb_off;
   pl->ws_bytes = pl->tb_base + pl->tb_bytes;
   pl->cigar_words = cg_off;
+  *plan = pl;
+  return ALN_OK;
+}
+
+void alnrt::plan_stage(const aln_plan *pl, void *dst) {
+  uint8_t *d = static_cast<uint8_t *>(dst);
+  if (!pl->sw16_tasks.empty()) {
+    memcpy(d + pl->sw16_off, pl->sw16_tasks.data(), sizeof(alnk::Sw16Task) * pl->sw16_tasks.size());
+    memcpy(d + pl->sw16_single_off, pl->sw16_single.data(),
+           sizeof(alnk::Sw16Task) * pl->sw16_single.size());
+  } else if (!pl->tasks.empty()) {
+    memcpy(d, pl->tasks.data(), sizeof(PairTask) * pl->tasks.size());
+  }
+}
+
+extern "C" {
+
+aln_status aln_plan_create(aln_ctx *ctx, int32_t scoring_id, const aln_params *params, int32_t n,
+                           const int32_t *q_len_host, const int32_t *r_len_host, aln_plan **plan,
+                           aln_footprint *fp) {
+  aln_plan *pl = nullptr;
+  aln_status st = plan_build(ctx, scoring_id, params, n, q_len_host, r_len_host, &pl);
+  if (st != ALN_OK) return st;
   if (hipHostMalloc(&pl->pinned, std::max<uint64_t>(pl->upload_bytes, 1), hipHostMallocDefault) !=
       hipSuccess) {
     delete pl;
     return fail(ctx, ALN_E_NOMEM, "pinned staging for %llu bytes",
                 (unsigned long long)pl->upload_bytes);
   }
-  if (!pl->tasks.empty()) memcpy(pl->pinned, pl->tasks.data(), sizeof(PairTask) * pl->tasks.size());
+  plan_stage(pl, pl->pinned);
   if (fp) {
     fp->workspace_bytes = pl->ws_bytes;
     fp->traceback_bytes = pl->tb_bytes;
@@ -564,7 +516,7 @@ void aln_plan_destroy(aln_plan *plan) {
   if (!plan) return;
   if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
   if (plan->graph) (void)hipGraphDestroy(plan->graph);
-  if (plan->pinned) (void)hipHostFree(plan->pinned);
+  if (plan->pinned && plan->own_pinned) (void)hipHostFree(plan->pinned);
   delete plan;
 }
 
@@ -799,3 +751,8 @@ aln_status aln_graph_launch(aln_ctx *ctx, aln_plan *plan, void *stream) {
 }
 
 } // extern "C"
+
+aln_status alnrt::plan_run(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, void *d_ws,
+                           aln_result *d_res, uint32_t *d_cigar, hipStream_t st, bool per_pair) {
+  return run_plan(ctx, plan, b, d_ws, d_res, d_cigar, st, per_pair);
+}

@@ -1,0 +1,95 @@
+// runtime.h -- host-side state shared by the execution API (aln_api.cpp) and
+// the request server (server.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "aln.h"
+#include "internal.h"
+
+struct aln_ctx {
+  int device = 0;
+  std::string err;
+  std::vector<alnk::DevScoring *> dsc; // device copies, owned
+  std::vector<alnk::DevScoring> hsc;   // host mirrors
+  // kernel timing (aln_set_profiling)
+  bool profiling = false;
+  struct TimedLaunch {
+    const char *name;
+    hipEvent_t a, b;
+  };
+  std::vector<TimedLaunch> timed;
+  std::vector<hipEvent_t> event_pool;
+};
+
+namespace alnrt {
+
+enum Kind { K_STRIP = 0, K_SW16 = 1, K_RERUN = 2, K_DIAG = 3 };
+
+struct LaunchDesc {
+  int kind;
+  int rows;
+  int mode;
+  bool tb;
+  bool small;
+  int32_t first; // first task of this launch
+  int32_t count;
+  int32_t lds_bnd;
+  int32_t lds_prof;
+};
+
+constexpr uint64_t kAlign = 256;
+inline uint64_t align_up(uint64_t v, uint64_t a = kAlign) { return (v + a - 1) / a * a; }
+
+// Record a formatted message as ctx's last error and return st.
+aln_status fail(aln_ctx *ctx, aln_status st, const char *fmt, ...);
+
+} // namespace alnrt
+
+struct aln_plan {
+  aln_ctx *ctx = nullptr;
+  int32_t scoring_id = 0;
+  aln_params p{};
+  int32_t n = 0;
+  std::vector<int32_t> qlen, rlen;
+  std::vector<alnk::PairTask> tasks;
+  std::vector<alnrt::LaunchDesc> launches;
+  // packed int16 path
+  std::vector<alnk::Sw16Task> sw16_tasks;    // two pairs per task
+  std::vector<alnk::Sw16Task> sw16_single;   // one pair per task (per-pair runs)
+  int sw16_rows = 16;
+  uint64_t sw16_off = 0, sw16_single_off = 0, rerun_cnt_off = 0, rerun_off = 0;
+  alnrt::LaunchDesc rerun{};
+  // X-drop widening queues: counters (ws offset) and two queues of n tasks
+  uint64_t widen_cnt_off = 0, widen_off[2] = {0, 0};
+  bool xdrop = false;
+  int32_t n_strip_tb = 0, first_diag_tb = 0, n_diag_tb = 0; // walk ranges
+  uint64_t upload_bytes = 0; // task lists copied to the front of the workspace
+  uint64_t tasks_bytes = 0;
+  uint64_t tb_base = 0;
+  uint64_t tb_bytes = 0;
+  uint64_t ws_bytes = 0;
+  uint64_t cigar_words = 0;
+  int64_t cells = 0;
+  void *pinned = nullptr;   // host staging of the task lists
+  bool own_pinned = true;   // false: staging belongs to the server slot
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+};
+
+namespace alnrt {
+
+// Plan a batch from host lengths (kernel choice, buckets, workspace layout).
+// Host work only; no pinned staging is allocated (pl->pinned stays null).
+aln_status plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params *params, int32_t n,
+                      const int32_t *q_len_host, const int32_t *r_len_host, aln_plan **out);
+// Write the plan's upload image (plan->upload_bytes bytes) to dst.
+void plan_stage(const aln_plan *pl, void *dst);
+// Enqueue the plan on `st` (upload from pl->pinned, then the kernels).
+aln_status plan_run(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, void *d_ws,
+                    aln_result *d_res, uint32_t *d_cigar, hipStream_t st, bool per_pair);
+
+} // namespace alnrt

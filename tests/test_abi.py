@@ -4,6 +4,7 @@ No compute call is made (there may be no GPU)."""
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -37,6 +38,53 @@ def test_struct_layouts():
     assert ctypes.sizeof(aln._Footprint) == 32
     assert ctypes.sizeof(aln._Batch) == 56
     assert ctypes.sizeof(aln._Scoring) == 24
+    assert ctypes.sizeof(aln._ServerCfg) == 24
+    assert ctypes.sizeof(aln._Request) == 72
+    assert ctypes.sizeof(aln._ServerStats) == 64
+    assert aln.COMPLETION_DTYPE.itemsize == 104
+
+
+STRUCTS = {
+    "aln_scoring": aln._Scoring, "aln_params": aln._Params, "aln_batch": aln._Batch,
+    "aln_footprint": aln._Footprint, "aln_server_cfg": aln._ServerCfg,
+    "aln_request": aln._Request, "aln_server_stats": aln._ServerStats,
+}
+NUMPY_STRUCTS = {"aln_result": aln.RESULT_DTYPE, "aln_completion": aln.COMPLETION_DTYPE}
+
+
+def test_header_layouts_match_the_binding(tmp_path):
+    """Compile a probe against include/aln.h with the host C compiler and
+    compare every struct's size and field offsets with the binding's."""
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "aln.h"', "int main(void) {"]
+    expect = {}
+    for cname, cls in STRUCTS.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        expect[cname] = ctypes.sizeof(cls)
+        for fname, _ in cls._fields_:
+            key = f"{cname}.{fname}"
+            lines.append(f'printf("{key} %zu\\n", offsetof({cname}, {fname}));')
+            expect[key] = getattr(cls, fname).offset
+    for cname, dt in NUMPY_STRUCTS.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        expect[cname] = dt.itemsize
+        for fname in dt.names:
+            if cname == "aln_completion" and fname in aln.RESULT_DTYPE.names:
+                key = f"{cname}.result.{fname}"
+                expr = f"offsetof(aln_completion, result) + offsetof(aln_result, {fname})"
+            else:
+                key = f"{cname}.{fname}"
+                expr = f"offsetof({cname}, {fname})"
+            lines.append(f'printf("{key} %zu\\n", (size_t)({expr}));')
+            expect[key] = dt.fields[fname][1]
+    lines.append("return 0; }")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-I", os.path.join(ROOT, "include"), str(src),
+                    "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {k: int(v) for k, v in (ln.split() for ln in out.strip().splitlines())}
+    assert got == expect
 
 
 def test_missing_library_fails_loudly(tmp_path):
