@@ -12,7 +12,9 @@ cells for X-drop), exactly the `cells` field the oracle reports.
 The headline workload (the JSON line's `value`) is the protein
 Smith-Waterman batch: 65,536 pairs, lognormal lengths, score + end cell.
 The other workloads (global DNA with CIGAR, banded long reads with CIGAR,
-X-drop seed extension) are measured the same way under "configs".
+X-drop seed extension) are measured the same way under "configs", and the
+serving mix of all four (Poisson arrivals through the request server) under
+"serving" with p50/p99 latency.
 
 For each: per-kernel times from HIP events recorded on the launch stream
 during the timed steps (roofline of the dominant kernel), the same kernels
@@ -230,6 +232,69 @@ def run_workload(name, batch, args, cpu_seconds, pp_cap):
     return out
 
 
+def run_serving(args):
+    """Serving mix: requests drawn from the four workloads (40/30/10/20) at
+    full size; saturation = burst throughput, then Poisson arrivals at 0.5x
+    and 0.8x of it.  Latency is arrival to completion on the server clock."""
+    import torch
+    from paper_2607_06225_amd import aln, serving
+    from paper_2607_06225_amd import workloads as W
+    from tests.parity import compare, oracle_batch
+
+    n = args.serving_requests
+    log(f"[bench] serving: generating {n} requests")
+    arrival1, kinds, batches = W.serving_requests(n, qps=1.0, seed=505)
+    ctx = aln.Context(0)
+    sids = [ctx.set_scoring(b.matrix, b.gap_open, b.gap_extend) for b in batches]
+    reqs = serving.mixed_requests(batches, kinds, sids)
+    cfg = dict(streams=args.serving_streams, max_batch_pairs=1024, hbm_budget=64 << 30,
+               class_streams=args.serving_class_streams)
+    out = dict(requests=n, mix="40/30/10/20 of nw_dna_1k/sw_protein/band_long/xdrop_ext "
+                              "(one pair or one extension side per request)",
+               streams=cfg["streams"], hbm_budget_bytes=cfg["hbm_budget"], levels=[])
+
+    def level(name, arrival):
+        srv = aln.Server(ctx, **cfg)
+        comps, cigs, wall, lat = serving.replay(srv, reqs, arrival)
+        st = srv.stats()
+        srv.close()
+        rec = dict(level=name, wall_s=round(wall, 3), qps_achieved=round(n / wall, 1),
+                   gcups=round(st["cells"] / wall / 1e9, 3), batches=st["batches"],
+                   mean_batch_pairs=round(n / max(st["batches"], 1), 2),
+                   peak_inflight=st["peak_inflight"], admission_waits=st["admission_waits"],
+                   errors=int((comps["error"] != 0).sum()), **serving.percentiles(lat))
+        log(f"[bench] serving {name}: {json.dumps(rec)}")
+        return rec, comps, cigs
+
+    log("[bench] serving: burst (saturation)")
+    sat, comps, cigs = level("burst", None)
+    out["levels"].append(sat)
+    out["saturation_qps"] = sat["qps_achieved"]
+    for frac in (0.5, 0.8):
+        qps = frac * sat["qps_achieved"]
+        rec, _, _ = level(f"{frac}x", arrival1 / qps)
+        rec["qps_offered"] = round(qps, 1)
+        out["levels"].append(rec)
+
+    # bit-exact check of the burst level against the oracle on the first k requests
+    k = min(n, args.serving_check)
+    bad = 0
+    first = []
+    for kind, b in enumerate(batches):
+        idx = [i for i in range(k) if reqs[i]["kind"] == kind]
+        if not idx:
+            continue
+        sub = b.subset([reqs[i]["pair"] for i in idx])
+        ores = oracle_batch(sub)
+        gc = [cigs[i] if cigs[i] is not None else np.zeros(0, np.uint32) for i in idx]
+        mism = compare(sub, comps[idx], gc if b.want_cigar else None, ores)
+        bad += len(mism)
+        first += mism[:2]
+    out["bit_exact_check"] = dict(requests=k, mismatches=bad, first=first[:3])
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,6 +310,15 @@ def main():
     ap.add_argument("--extra-cpu-seconds", type=float, default=6.0)
     ap.add_argument("--per-pair-cap", type=int, default=2048,
                     help="largest number of pairs launched one by one")
+    ap.add_argument("--serving-requests", type=int, default=2000,
+                    help="requests per serving level (0: skip the serving mix)")
+    ap.add_argument("--serving-streams", type=int, default=4)
+    ap.add_argument("--serving-class-streams", type=int, default=0,
+                    help="streams one request class may hold (0: the server default, streams/4)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="measure only the serving mix (no headline line)")
+    ap.add_argument("--serving-check", type=int, default=600,
+                    help="requests of the burst level checked against the oracle")
     ap.add_argument("--per-pair-cells", type=float, default=1e9,
                     help="cell budget of the one-launch-per-pair sample")
     args = ap.parse_args()
@@ -264,6 +338,9 @@ def main():
             ap.error(f"unknown workload {c}")
     pp_cap = 0 if args.no_per_pair else args.per_pair_cap
 
+    if args.serving_only:
+        print(json.dumps({"serving": run_serving(args)}), flush=True)
+        return 0
     log(f"[bench] generating {args.workload}")
     head = run_workload(args.workload, W.WORKLOADS[args.workload](), args,
                         0 if args.no_cpu_baseline else args.cpu_seconds, pp_cap)
@@ -278,6 +355,7 @@ def main():
         configs[c] = run_workload(c, b, args, 0 if args.no_cpu_baseline
                                   else args.extra_cpu_seconds, pp_cap)
         del b
+    serving_out = run_serving(args) if args.serving_requests > 0 else None
 
     out = {
         "metric": METRIC,
@@ -304,6 +382,7 @@ def main():
         "step_ms_median": head["step_ms_median"],
         "plan_ms": head["plan_ms"],
         "configs": configs,
+        "serving": serving_out,
     }
     for k in ("int32_reruns", "statuses"):
         if k in head:

@@ -214,8 +214,9 @@ int32_t aln_kernel_times(aln_ctx *ctx, const char **names, double *ms,
  * A server owns a worker thread, `streams` HIP streams (default priority)
  * and one device allocation of `hbm_budget` bytes made at creation.  Each
  * submitted request is copied to host memory owned by the server.  Whenever
- * a stream is idle, the worker takes the oldest pending request together
- * with later pending requests of the same scoring and parameters (up to
+ * a stream is idle, the worker takes the oldest pending request whose class
+ * (scoring and parameters) holds fewer than class_streams streams, together
+ * with later pending requests of the same class (up to
  * max_batch_pairs pairs and max_batch_cells cells), plans them as one batch
  * (same planner and kernels as aln_execute) and admits the micro-batch once
  * the budget has a free block for its footprint: sequences + workspace
@@ -235,6 +236,10 @@ typedef struct {
                               free device memory at creation                 */
   int64_t max_batch_cells; /* M*N cap per micro-batch (0: none); the oldest
                               request is always taken                        */
+  int32_t class_streams;   /* most streams one parameter class may hold at
+                              once, so long jobs of one kind cannot starve
+                              the others (0: streams / 4, at least 1)      */
+  int32_t reserved;        /* 0                                              */
 } aln_server_cfg;
 
 typedef struct {

@@ -56,7 +56,8 @@ class _Footprint(ctypes.Structure):
 
 class _ServerCfg(ctypes.Structure):
     _fields_ = [("streams", ctypes.c_int32), ("max_batch_pairs", ctypes.c_int32),
-                ("hbm_budget", ctypes.c_uint64), ("max_batch_cells", ctypes.c_int64)]
+                ("hbm_budget", ctypes.c_uint64), ("max_batch_cells", ctypes.c_int64),
+                ("class_streams", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _Request(ctypes.Structure):
@@ -319,11 +320,12 @@ class Server:
     copies the sequences; poll() returns (completions ndarray of
     COMPLETION_DTYPE, list of CIGAR arrays or None per completion)."""
 
-    def __init__(self, ctx, streams=4, max_batch_pairs=1024, hbm_budget=0, max_batch_cells=0):
+    def __init__(self, ctx, streams=4, max_batch_pairs=1024, hbm_budget=0, max_batch_cells=0,
+                 class_streams=0):
         self.ctx = ctx
         self.lib = ctx.lib
         cfg = _ServerCfg(int(streams), int(max_batch_pairs), int(hbm_budget),
-                         int(max_batch_cells))
+                         int(max_batch_cells), int(class_streams), 0)
         h = ctypes.c_void_p()
         ctx._check(self.lib.aln_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h

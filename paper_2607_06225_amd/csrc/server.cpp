@@ -9,9 +9,10 @@
 //     results, CIGAR words).  A micro-batch is admitted when a slot is free
 //     and the arena has a block for its footprint; otherwise it waits for a
 //     running micro-batch to retire and release its block.
-// Whenever a slot is free the worker takes the oldest pending request and
-// every later pending request with the same scoring and parameters (up to the
-// configured pair and cell caps), plans them as one batch with the same
+// Whenever a slot is free the worker takes the oldest pending request whose
+// class (scoring and parameters) holds fewer slots than its quota, and every
+// later pending request of that class (up to the configured pair and cell
+// caps), plans them as one batch with the same
 // planner and kernels as aln_execute, and enqueues upload, kernels and result
 // download on the slot's stream.  Requests arriving while other micro-batches
 // run join the next one; micro-batches on different streams overlap on the
@@ -213,12 +214,13 @@ void retire(aln_server *s, Slot &sl) {
 // Try to start a micro-batch on `sl`.  Returns 1 when launched, 0 when the
 // head batch must wait for memory, -1 when requests were completed with an
 // error instead.
-int launch_next(aln_server *s, Slot &sl, bool any_busy) {
-  const Request &head = s->pending.front();
+int launch_next(aln_server *s, Slot &sl, size_t head_idx, bool any_busy) {
+  const Request &head = s->pending[head_idx];
   std::vector<size_t> pick;
   int64_t cells = 0;
-  const size_t scan = std::min<size_t>(s->pending.size(), 4 * (size_t)s->cfg.max_batch_pairs + 64);
-  for (size_t k = 0; k < scan && (int32_t)pick.size() < s->cfg.max_batch_pairs; ++k) {
+  const size_t scan =
+      std::min<size_t>(s->pending.size(), head_idx + 4 * (size_t)s->cfg.max_batch_pairs + 64);
+  for (size_t k = head_idx; k < scan && (int32_t)pick.size() < s->cfg.max_batch_pairs; ++k) {
     const Request &r = s->pending[k];
     if (!same_class(r, head)) continue;
     const int64_t c = (int64_t)r.q.size() * (int64_t)r.r.size();
@@ -408,7 +410,17 @@ void worker_main(aln_server *s) {
         else if (!free_slot) free_slot = &sl;
       }
       if (!free_slot) break;
-      const int r = launch_next(s, *free_slot, any_busy);
+      // oldest pending request whose class is under its stream quota
+      size_t h = 0;
+      const size_t look = std::min<size_t>(s->pending.size(), 4096);
+      for (; h < look; ++h) {
+        int32_t held = 0;
+        for (const Slot &sl : s->slots)
+          if (sl.busy && same_class(sl.reqs.front(), s->pending[h])) ++held;
+        if (held < s->cfg.class_streams) break;
+      }
+      if (h == look) break;
+      const int r = launch_next(s, *free_slot, h, any_busy);
       if (r == 0) break;
       progressed = true;
     }
@@ -473,6 +485,8 @@ aln_status aln_server_create(aln_ctx *ctx, const aln_server_cfg *cfg, aln_server
   if (!s) return alnrt::fail(ctx, ALN_E_NOMEM, "server allocation");
   s->cfg = *cfg;
   s->cfg.hbm_budget = budget;
+  if (s->cfg.class_streams <= 0) s->cfg.class_streams = std::max(1, cfg->streams / 4);
+  s->cfg.class_streams = std::min(s->cfg.class_streams, cfg->streams);
   s->device = ctx->device;
   s->t0 = Clock::now();
   aln_status st = aln_create(&s->ctx, ctx->device);

@@ -38,7 +38,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(aln._Footprint) == 32
     assert ctypes.sizeof(aln._Batch) == 56
     assert ctypes.sizeof(aln._Scoring) == 24
-    assert ctypes.sizeof(aln._ServerCfg) == 24
+    assert ctypes.sizeof(aln._ServerCfg) == 32
     assert ctypes.sizeof(aln._Request) == 72
     assert ctypes.sizeof(aln._ServerStats) == 64
     assert aln.COMPLETION_DTYPE.itemsize == 104
