@@ -315,6 +315,9 @@ def main():
     ap.add_argument("--serving-streams", type=int, default=4)
     ap.add_argument("--serving-class-streams", type=int, default=0,
                     help="streams one request class may hold (0: the server default, streams/4)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device 5 times (calibrates HBM "
+                         "byte counters against a transfer of known size)")
     ap.add_argument("--serving-only", action="store_true",
                     help="measure only the serving mix (no headline line)")
     ap.add_argument("--serving-check", type=int, default=600,
@@ -338,6 +341,16 @@ def main():
             ap.error(f"unknown workload {c}")
     pp_cap = 0 if args.no_per_pair else args.per_pair_cap
 
+    if args.copy_calibration:
+        n = args.copy_calibration << 20
+        src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n, "copies": 5}), flush=True)
+        return 0
     if args.serving_only:
         print(json.dumps({"serving": run_serving(args)}), flush=True)
         return 0

@@ -403,105 +403,6 @@ __global__ __launch_bounds__(256) void diag_kernel(DiagArgs a) {
     diag_task<RD, MODE, PRUNE, TB>(a, task, wave, lane, smem, smat);
 }
 
-// ---------------------------------------------------------------- walk
-// Code of cell (i, j) in the sheared layout: antidiagonal k = i + j, window
-// base dbase(k), element e = (j - i) - dbase(k) in lane e / RD.
-__device__ __forceinline__ int diag_code(const uint8_t *tbp, int i, int j, int RD, int nk) {
-  const int k = i + j, d = j - i;
-  const int *dbh = reinterpret_cast<const int *>(tbp);
-  const uint8_t *codes = tbp + (size_t)((nk + 63) / 64) * 64 * 4;
-  const int e = d - dbh[k];
-  const int ln = e / RD, x = e - ln * RD;
-  const int pos = (k & 1) * (RD / 2) + (x >> 1);
-  const uint8_t b = codes[((size_t)(k >> 1) * 64 + ln) * 8 + (pos >> 1)];
-  return (b >> ((pos & 1) * 4)) & 15;
-}
-
-struct CigarOut {
-  uint32_t *out;
-  int w, cur, run;
-  bool overflow;
-  __device__ void emit(int op) {
-    if (op == cur) { ++run; return; }
-    flush();
-    cur = op;
-    run = 1;
-  }
-  __device__ void flush() {
-    if (cur >= 0) {
-      if (w > 0) out[--w] = ((uint32_t)run << 4) | (uint32_t)cur;
-      else overflow = true;
-    }
-  }
-};
-
-// One thread per pair; in state E the opening bit is read from the cell to
-// the left, in state F from the cell above (the codes store, for each cell,
-// whether the gaps it passes right and down open there).
-__global__ __launch_bounds__(64) void walk_diag_kernel(WalkArgs a) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= a.ntasks) return;
-  const PairTask tk = a.tasks[k];
-  const int p = tk.pair;
-  aln_result *res = a.res + p;
-  res->cigar_off = tk.cigar_off;
-  res->cigar_len = 0;
-  if (res->status != ALN_R_OK) return;
-  const int M = a.b.q_len[p], N = a.b.r_len[p];
-  const uint8_t *Q = a.b.q + a.b.q_off[p];
-  const uint8_t *Rs = a.b.r + a.b.r_off[p];
-  const uint8_t *tbp = a.tb + tk.tb_off;
-  const int RD = tk.rows, nk = M + N + 1;
-  const bool local = a.mode == ALN_LOCAL;
-  int i = res->q_end, j = res->r_end;
-  CigarOut cw{a.cigar + tk.cigar_off, tk.cigar_cap, -1, 0, false};
-  int state = 0;
-  bool corrupt = false;
-  for (long guard = 2L * (i + j) + 2; guard > 0; --guard) {
-    if ((state == 1 && j < 1) || (state == 2 && i < 1) || i < 0 || j < 0) { corrupt = true; break; }
-    if (state == 0) {
-      if (i == 0 && j == 0) break;
-      if (local && (i == 0 || j == 0)) break;
-      if (i == 0) { cw.emit(ALN_OP_D); --j; continue; }
-      if (j == 0) { cw.emit(ALN_OP_I); --i; continue; }
-      const int hs = diag_code(tbp, i, j, RD, nk) & 3;
-      if (local && hs == 3) break;
-      if (hs == 0) {
-        cw.emit(Q[i - 1] == Rs[j - 1] ? ALN_OP_EQ : ALN_OP_X);
-        --i;
-        --j;
-      } else {
-        state = hs;
-      }
-    } else if (state == 1) {
-      cw.emit(ALN_OP_D);
-      if (diag_code(tbp, i, j - 1, RD, nk) & 4) state = 0;
-      --j;
-    } else {
-      cw.emit(ALN_OP_I);
-      if (diag_code(tbp, i - 1, j, RD, nk) & 8) state = 0;
-      --i;
-    }
-  }
-  cw.flush();
-  res->q_begin = i;
-  res->r_begin = j;
-  if (corrupt || cw.overflow) {
-    res->status = ALN_R_CIGAR_CAP;
-  } else {
-    res->cigar_len = tk.cigar_cap - cw.w;
-    res->cigar_off = tk.cigar_off + cw.w;
-  }
-  (void)M;
-  (void)N;
-}
-
-hipError_t launch_walk_diag(const WalkArgs &a, hipStream_t s) {
-  if (a.ntasks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(walk_diag_kernel, dim3((a.ntasks + 63) / 64), dim3(64), 0, s, a);
-  return hipGetLastError();
-}
-
 template <int RD, int MODE, int PRUNE, bool TB>
 static hipError_t launch_diag_t(const DiagArgs &a, hipStream_t s) {
   const size_t lds = (size_t)4 * 2 * kSeqBuf + kMaxAlphabet * kMaxAlphabet;

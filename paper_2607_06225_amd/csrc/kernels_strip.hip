@@ -283,111 +283,6 @@ __device__ void strip_task(const StripArgs &a, int task, int wave, int lane, uin
   }
 }
 
-// ---------------------------------------------------------------- walk
-// One thread per pair follows the stored codes back from the end cell, with
-// the same preferences the codes encode, and run-length encodes the path.
-// Words are written backwards from the end of the pair's CIGAR slot, so the
-// finished CIGAR reads start to end from res.cigar_off.
-struct CigarWriter {
-  uint32_t *out;
-  int w;
-  int cur;
-  int run;
-  bool overflow;
-  __device__ void emit(int op) {
-    if (op == cur) {
-      ++run;
-      return;
-    }
-    flush();
-    cur = op;
-    run = 1;
-  }
-  __device__ void flush() {
-    if (cur >= 0) {
-      if (w > 0) out[--w] = ((uint32_t)run << 4) | (uint32_t)cur;
-      else overflow = true;
-    }
-  }
-};
-
-__device__ __forceinline__ int strip_code(const uint8_t *tb, int i, int j, int R, int T) {
-  const int HS = 64 * R;
-  const int s = (i - 1) / HS;
-  const int within = (i - 1) - s * HS;
-  const int l = within / R;
-  const int r = within - l * R;
-  const int t = (j - 1) + l;
-  const size_t byte = ((size_t)(s * T + t) * 64 + l) * (R / 2) + (r >> 1);
-  return (tb[byte] >> ((r & 1) * 4)) & 15;
-}
-
-__global__ __launch_bounds__(64) void walk_strip_kernel(WalkArgs a) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= a.ntasks) return;
-  const PairTask tk = a.tasks[k];
-  const int p = tk.pair;
-  aln_result *res = a.res + p;
-  res->cigar_off = tk.cigar_off;
-  res->cigar_len = 0;
-  if (res->status != ALN_R_OK) return;
-  const int N = a.b.r_len[p];
-  const uint8_t *Q = a.b.q + a.b.q_off[p];
-  const uint8_t *Rs = a.b.r + a.b.r_off[p];
-  const uint8_t *tb = a.tb + tk.tb_off;
-  const int R = tk.rows;
-  const int T = N + 63;
-  const bool local = a.mode == ALN_LOCAL;
-  int i = res->q_end, j = res->r_end;
-  CigarWriter cw{a.cigar + tk.cigar_off, tk.cigar_cap, -1, 0, false};
-  int state = 0;
-  bool corrupt = false;
-  // every iteration either moves or switches H -> E/F, so 2(M+N)+2 bounds it
-  for (long guard = 2L * (res->q_end + res->r_end) + 2; guard > 0; --guard) {
-    if ((state == 1 && j < 1) || (state == 2 && i < 1) || i < 0 || j < 0) {
-      corrupt = true;
-      break;
-    }
-    if (state == 0) {
-      if (i == 0 && j == 0) break;
-      if (local && (i == 0 || j == 0)) break;
-      if (i == 0) { cw.emit(ALN_OP_D); --j; continue; }
-      if (j == 0) { cw.emit(ALN_OP_I); --i; continue; }
-      const int c = strip_code(tb, i, j, R, T);
-      const int hs = c & 3;
-      if (local && hs == 3) break;
-      if (hs == 0) {
-        cw.emit(Q[i - 1] == Rs[j - 1] ? ALN_OP_EQ : ALN_OP_X);
-        --i;
-        --j;
-      } else {
-        state = hs;
-      }
-    } else if (state == 1) {
-      const int c = strip_code(tb, i, j, R, T);
-      cw.emit(ALN_OP_D);
-      if (c & 4) state = 0;
-      --j;
-    } else {
-      const int c = strip_code(tb, i, j, R, T);
-      cw.emit(ALN_OP_I);
-      if (c & 8) state = 0;
-      --i;
-    }
-  }
-  cw.flush();
-  res->q_begin = i;
-  res->r_begin = j;
-  if (corrupt) {
-    res->status = ALN_R_CIGAR_CAP;
-  } else if (cw.overflow) {
-    res->status = ALN_R_CIGAR_CAP;
-  } else {
-    res->cigar_len = tk.cigar_cap - cw.w;
-    res->cigar_off = tk.cigar_off + cw.w;
-  }
-}
-
 // ---------------------------------------------------------------- validate
 // Initialises every result and flags pairs holding a code >= alphabet.
 __global__ __launch_bounds__(256) void validate_kernel(ValidateArgs a) {
@@ -469,11 +364,5 @@ hipError_t launch_strip(int rows, int mode, bool tb, bool small_alphabet, const 
   }
 }
 
-hipError_t launch_walk(int layout, const WalkArgs &a, hipStream_t s) {
-  if (a.ntasks <= 0) return hipSuccess;
-  if (layout != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(walk_strip_kernel, dim3((a.ntasks + 63) / 64), dim3(64), 0, s, a);
-  return hipGetLastError();
-}
 
 } // namespace alnk

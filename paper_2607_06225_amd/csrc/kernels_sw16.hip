@@ -29,6 +29,8 @@
 // Overflow.  A pair whose best score reaches 32767 - max(s) may have
 // saturated; it is flagged and appended to a queue that the int32 kernel
 // recomputes.  Below that bound no intermediate value can leave int16.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace alnk {
@@ -48,20 +50,21 @@ __device__ __forceinline__ uint32_t pk_subsat_u16(uint32_t a, uint32_t b) {
                                                                     __builtin_bit_cast(us2, b)));
 }
 
-// hd + (sext(byte K of pa), sext(byte K of pb)) per 16-bit half.  Each SDWA
-// add reads and writes the same register (the other half is preserved), so
-// no copy of hd is needed.
+// hd + (sext(byte K of pa), sext(byte K of pb)) per 16-bit half, into a new
+// register: the first SDWA add writes the low half and zero-fills the high
+// one, the second writes the high half and preserves the low one.  hd is
+// only read, so it needs no copy.
 #define ALN_SDWA_ADD_BYTES(K)                                                                   \
-  asm("v_add_u16_sdwa %0, %0, sext(%1) dst_sel:WORD_0 dst_unused:UNUSED_PRESERVE "             \
+  asm("v_add_u16_sdwa %0, %1, sext(%2) dst_sel:WORD_0 dst_unused:UNUSED_PAD "                  \
       "src0_sel:WORD_0 src1_sel:BYTE_" #K                                                      \
-      : "+v"(out) : "v"(pa));                                                                  \
-  asm("v_add_u16_sdwa %0, %0, sext(%1) dst_sel:WORD_1 dst_unused:UNUSED_PRESERVE "             \
+      : "=v"(out) : "v"(hd), "v"(pa));                                                         \
+  asm("v_add_u16_sdwa %0, %1, sext(%2) dst_sel:WORD_1 dst_unused:UNUSED_PRESERVE "             \
       "src0_sel:WORD_1 src1_sel:BYTE_" #K                                                      \
-      : "+v"(out) : "v"(pb))
+      : "+v"(out) : "v"(hd), "v"(pb))
 
 template <int K>
 __device__ __forceinline__ uint32_t add_score_bytes(uint32_t hd, uint32_t pa, uint32_t pb) {
-  uint32_t out = hd;
+  uint32_t out;
   if constexpr (K == 0) { ALN_SDWA_ADD_BYTES(0); }
   else if constexpr (K == 1) { ALN_SDWA_ADD_BYTES(1); }
   else if constexpr (K == 2) { ALN_SDWA_ADD_BYTES(2); }
@@ -232,10 +235,19 @@ __global__ __launch_bounds__(64) void sw16_kernel(Sw16Args a) {
         for (int k = 0; k < NWD; ++k) { wa[k] = pa[k]; wb[k] = pb[k]; }
       };
       uint32_t cur_c = dpp_row_shr1(ring_c, padc2);
-      uint32_t wa[NWD], wb[NWD];
+      uint32_t wa[NWD], wb[NWD], wa2[NWD], wb2[NWD];
       prof_words(cur_c, wa, wb);
 
-      for (int t = 0; t < T_w; ++t) {
+      // One column step.  (wc, wbc) hold this step's profile words, (wn, wbn)
+      // receive the next step's; the loop below alternates the two buffers.
+      // End-cell keys of an even step are parked in (pA, pB) and folded in
+      // with the odd step's keys by one three-input max.
+      uint32_t pA[R], pB[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) { pA[r] = 0; pB[r] = 0; }
+      auto step = [&](int t, auto odd_tag, const uint32_t (&wc)[NWD], const uint32_t (&wbc)[NWD],
+                      uint32_t (&wn)[NWD], uint32_t (&wbn)[NWD]) {
+        constexpr bool odd = decltype(odd_tag)::value;
         const int k16 = t & 15;
         if (k16 == 0 && t > 0) {
           flush(t - 1, 16);
@@ -248,32 +260,40 @@ __global__ __launch_bounds__(64) void sw16_kernel(Sw16Args a) {
         ring_c = dpp_row_shl1(ring_c);
         const uint32_t lane0_next = (k16 == 15) ? n1_c : ring_c;
         const uint32_t next_c = dpp_row_shr1(lane0_next, cur_c);
-        uint32_t wa_n[NWD], wb_n[NWD];
-        prof_words(next_c, wa_n, wb_n);
+        prof_words(next_c, wn, wbn);
         const int j = t + 1 - gl;
         if (gact && j >= 1 && j <= my_nmax) {
+          // diagonal inputs of every row first, from H(i-1, j-1) before any
+          // row overwrites its H(i, j-1)
+          uint32_t hdg[R];
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const uint32_t hd = r == 0 ? hd_top : Hl[r - 1];
+            switch (r & 3) {
+            case 0: hdg[r] = add_score_bytes<0>(hd, wc[r >> 2], wbc[r >> 2]); break;
+            case 1: hdg[r] = add_score_bytes<1>(hd, wc[r >> 2], wbc[r >> 2]); break;
+            case 2: hdg[r] = add_score_bytes<2>(hd, wc[r >> 2], wbc[r >> 2]); break;
+            default: hdg[r] = add_score_bytes<3>(hd, wc[r >> 2], wbc[r >> 2]); break;
+            }
+          }
           uint32_t tu = pk_subsat_u16(in_h, goe2);
           uint32_t fu = in_f;
-          uint32_t hd = hd_top;
           const uint32_t jinv = 0xffffu - (uint32_t)j;
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             const uint32_t f = pk_max_i16(pk_add_16(fu, ge2), tu);
-            uint32_t hdiag;
-            switch (r & 3) {
-            case 0: hdiag = add_score_bytes<0>(hd, wa[r >> 2], wb[r >> 2]); break;
-            case 1: hdiag = add_score_bytes<1>(hd, wa[r >> 2], wb[r >> 2]); break;
-            case 2: hdiag = add_score_bytes<2>(hd, wa[r >> 2], wb[r >> 2]); break;
-            default: hdiag = add_score_bytes<3>(hd, wa[r >> 2], wb[r >> 2]); break;
-            }
-            const uint32_t h = pk_max_i16(pk_max_i16(hdiag, EN[r]), f);
+            const uint32_t h = pk_max_i16(pk_max_i16(hdg[r], EN[r]), f);
             const uint32_t tt = pk_subsat_u16(h, goe2);
             const uint32_t en = pk_max_i16(pk_add_16(EN[r], ge2), tt);
-            const int keyA = (int)((h << 16) | jinv);
-            const int keyB = (int)((h & 0xffff0000u) | jinv);
-            kA[r] = (uint32_t)max((int)kA[r], keyA);
-            kB[r] = (uint32_t)max((int)kB[r], keyB);
-            hd = Hl[r];
+            const uint32_t keyA = (h << 16) | jinv;
+            const uint32_t keyB = (h & 0xffff0000u) | jinv;
+            if constexpr (odd) {
+              kA[r] = max(kA[r], max(pA[r], keyA));
+              kB[r] = max(kB[r], max(pB[r], keyB));
+            } else {
+              pA[r] = keyA;
+              pB[r] = keyB;
+            }
             Hl[r] = h;
             EN[r] = en;
             tu = tt;
@@ -282,12 +302,32 @@ __global__ __launch_bounds__(64) void sw16_kernel(Sw16Args a) {
           hd_top = in_h;
           out_h = Hl[R - 1];
           out_f = fu;
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            if constexpr (odd) {
+              kA[r] = max(kA[r], pA[r]);
+              kB[r] = max(kB[r], pB[r]);
+            } else {
+              pA[r] = 0;
+              pB[r] = 0;
+            }
+          }
         }
         ring_h = dpp_insert_shl1(out_h, ring_h);
         ring_f = dpp_insert_shl1(out_f, ring_f);
         cur_c = next_c;
+      };
+      int t = 0;
+      for (; t + 1 < T_w; t += 2) {
+        step(t, std::false_type{}, wa, wb, wa2, wb2);
+        step(t + 1, std::true_type{}, wa2, wb2, wa, wb);
+      }
+      if (t < T_w) step(t, std::false_type{}, wa, wb, wa2, wb2);
 #pragma unroll
-        for (int k = 0; k < NWD; ++k) { wa[k] = wa_n[k]; wb[k] = wb_n[k]; }
+      for (int r = 0; r < R; ++r) { // keys still parked by a final even step
+        kA[r] = max(kA[r], pA[r]);
+        kB[r] = max(kB[r], pB[r]);
       }
       flush(T_w - 1, ((T_w - 1) & 15) + 1);
       if (s + 1 < ns_w) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");

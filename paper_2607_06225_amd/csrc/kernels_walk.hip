@@ -1,0 +1,354 @@
+// kernels_walk.hip -- traceback walks on gfx950: stored 4-bit codes -> CIGAR.
+//
+// One wavefront per pair.  The path from the end cell back to the start is
+// inherently serial, so every lane runs the same walk (all control flow is
+// wave-uniform) and lane 0 writes the CIGAR words.  What the wave adds is
+// memory parallelism: the codes are read in an order that never goes
+// forward -- the antidiagonal k = i + j never grows along the path, and in the
+// strip layout neither does the skewed step t = j - 1 + lane -- so the codes
+// are consumed block by block.  The wave copies the current block from HBM
+// into LDS with coalesced 16-byte loads while the next block's loads are
+// already in flight in registers; each step is then one LDS read instead of a
+// dependent HBM read.  The sequence bytes needed for '=' / 'X' come from
+// 256-byte LDS windows that slide down as i and j fall.
+//
+// Preferences are the ones the codes encode (traceback of Sec. 2): in state H
+// (LOCAL: stop on a zero) diagonal, then E, then F; in E and F the opening
+// bit decides between returning to H and extending the gap.
+#include "internal.h"
+
+namespace alnk {
+
+namespace {
+
+constexpr int kBlockBytes = 16384;  // one LDS code block
+
+// The walk's state is the same in every lane; reading it through
+// readfirstlane keeps it in scalar registers and its branches scalar.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+constexpr int kPre = kBlockBytes / 16 / 64; // uint4 per lane per block
+
+// Run-length CIGAR written backwards from the end of the pair's slot.  The
+// state is wave-uniform; lane 0 stores.
+struct WaveCigar {
+  uint32_t *out;
+  int w, cur, run;
+  bool overflow;
+  __device__ void emit(int op, int lane) {
+    if (op == cur) {
+      ++run;
+      return;
+    }
+    flush(lane);
+    cur = op;
+    run = 1;
+  }
+  __device__ void flush(int lane) {
+    if (cur < 0) return;
+    if (w > 0) {
+      --w;
+      if (lane == 0) out[w] = ((uint32_t)run << 4) | (uint32_t)cur;
+    } else {
+      overflow = true;
+    }
+  }
+};
+
+// A 256-byte LDS window over a sequence that only moves towards its start.
+struct SeqWindow {
+  const uint8_t *src;
+  int len;
+  int base;
+  uint8_t *lds;
+  __device__ int get(int idx, int lane) { // 0 <= idx < len, wave-uniform
+    if (idx < base || idx >= base + 256) {
+      base = max(0, idx - 255);
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int p = base + lane * 4 + b;
+        lds[lane * 4 + b] = p < len ? src[p] : 0;
+      }
+      __syncthreads();
+    }
+    return uni(lds[idx - base]);
+  }
+};
+
+// Copies of one code block: `pre` holds the block being prefetched.
+struct BlockCache {
+  uint4 pre[kPre];
+  int pre_key = -1;
+  int pre_aux = 0;
+  int cur_key = -1;
+  int cur_aux = 0; // lane l: per-block value l (window base of antidiagonal l)
+  __device__ void install(uint4 *lds4, int lane) {
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kPre; ++m) lds4[lane + 64 * m] = pre[m];
+    cur_aux = pre_aux;
+    __syncthreads();
+    cur_key = pre_key;
+  }
+};
+
+__device__ __forceinline__ void load_block(BlockCache &c, const uint4 *src, int n4, int key,
+                                           int aux, int lane) {
+#pragma unroll
+  for (int m = 0; m < kPre; ++m) {
+    const int u = lane + 64 * m;
+    c.pre[m] = u < n4 ? src[u] : make_uint4(0u, 0u, 0u, 0u);
+  }
+  c.pre_key = key;
+  c.pre_aux = aux;
+}
+
+} // namespace
+
+// ------------------------------------------------------------ strip layout
+// Codes of strip s: step t (0..N+62), lane l, rows r = 0..R-1 packed two per
+// byte at ((s*T + t)*64 + l)*(R/2) + r/2.  Cell (i, j) lives in strip
+// (i-1)/(64R), lane ((i-1) mod 64R)/R, row (i-1) mod R, step t = j-1+lane.
+// A block is TBK consecutive steps of one strip (TBK*32R <= 16 KB bytes).
+// The walk keeps (s, l, r) of its row and steps them as i falls.
+__global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
+  __shared__ __align__(16) uint4 codes4[kBlockBytes / 16];
+  __shared__ uint8_t qwin[256], rwin[256];
+  const int lane = threadIdx.x;
+  const int task = blockIdx.x;
+  if (task >= a.ntasks) return;
+  const PairTask tk = a.tasks[task];
+  const int p = tk.pair;
+  aln_result *res = a.res + p;
+  const int status = uni(res->status);
+  const int i_end = uni(res->q_end), j_end = uni(res->r_end);
+  __syncthreads();
+  if (lane == 0) {
+    res->cigar_off = tk.cigar_off;
+    res->cigar_len = 0;
+  }
+  if (status != ALN_R_OK) return;
+  const int M = uni(a.b.q_len[p]), N = uni(a.b.r_len[p]);
+  SeqWindow qw{a.b.q + a.b.q_off[p], M, 1 << 30, qwin};
+  SeqWindow rw{a.b.r + a.b.r_off[p], N, 1 << 30, rwin};
+  const uint8_t *tb = a.tb + tk.tb_off;
+  const int R = uni(tk.rows), HB = R / 2, T = N + 63;
+  const int LTB = R <= 16 ? 5 : 4; // log2 of the block's steps
+  const int TBK = 1 << LTB;
+  const int NTB = (T + TBK - 1) >> LTB;
+  const bool local = a.mode == ALN_LOCAL;
+  const uint8_t *codes = reinterpret_cast<const uint8_t *>(codes4);
+  BlockCache bc;
+
+  auto fetch = [&](int s, int b) {
+    const int steps = min(TBK, T - b * TBK);
+    const uint4 *src = reinterpret_cast<const uint4 *>(
+        tb + ((size_t)s * T + (size_t)b * TBK) * 64 * HB);
+    load_block(bc, src, steps * 64 * HB / 16, s * NTB + b, 0, lane);
+  };
+  // row position of i (valid while i >= 1)
+  int i = i_end, j = j_end;
+  int rs = 0, rl = 0, rr = 0;
+  if (i >= 1) {
+    const int within = (i - 1) % (64 * R);
+    rs = (i - 1) / (64 * R);
+    rl = within / R;
+    rr = within - rl * R;
+  }
+  auto up = [&]() { // i -> i - 1
+    --i;
+    if (--rr < 0) {
+      rr = R - 1;
+      if (--rl < 0) {
+        rl = 63;
+        --rs;
+      }
+    }
+  };
+  bool bad = false;
+  auto code = [&](int jj) -> int { // code of (i, jj)
+    const int t = (jj - 1) + rl;
+    const int b = t >> LTB;
+    const int key = rs * NTB + b;
+    if (key != bc.cur_key) {
+      if (key != bc.pre_key) fetch(rs, b);
+      bc.install(codes4, lane);
+      if (b > 0) fetch(rs, b - 1);
+    }
+    const int byte = ((t - (b << LTB)) * 64 + rl) * HB + (rr >> 1);
+    if ((unsigned)byte >= (unsigned)kBlockBytes) {
+      bad = true;
+      return 0;
+    }
+    return uni((codes[byte] >> ((rr & 1) * 4)) & 15);
+  };
+
+  WaveCigar cw{a.cigar + tk.cigar_off, tk.cigar_cap, -1, 0, false};
+  int state = 0;
+  // every iteration moves or switches H -> E/F, so 2(M+N)+2 bounds the walk
+  for (int guard = 2 * (i_end + j_end) + 2; guard > 0 && !bad; --guard) {
+    if ((state == 1 && j < 1) || (state == 2 && i < 1) || i < 0 || j < 0) {
+      bad = true;
+      break;
+    }
+    if (state == 0) {
+      if (i == 0 && j == 0) break;
+      if (local && (i == 0 || j == 0)) break;
+      if (i == 0) { cw.emit(ALN_OP_D, lane); --j; continue; }
+      if (j == 0) { cw.emit(ALN_OP_I, lane); up(); continue; }
+      const int hs = code(j) & 3;
+      if (local && hs == 3) break;
+      if (hs == 0) {
+        cw.emit(qw.get(i - 1, lane) == rw.get(j - 1, lane) ? ALN_OP_EQ : ALN_OP_X, lane);
+        up();
+        --j;
+      } else {
+        state = hs;
+      }
+    } else if (state == 1) {
+      const int c = code(j);
+      cw.emit(ALN_OP_D, lane);
+      if (c & 4) state = 0;
+      --j;
+    } else {
+      const int c = code(j);
+      cw.emit(ALN_OP_I, lane);
+      if (c & 8) state = 0;
+      up();
+    }
+  }
+  cw.flush(lane);
+  if (lane == 0) {
+    res->q_begin = i;
+    res->r_begin = j;
+    if (bad || cw.overflow) {
+      res->status = ALN_R_CIGAR_CAP;
+    } else {
+      res->cigar_len = tk.cigar_cap - cw.w;
+      res->cigar_off = tk.cigar_off + cw.w;
+    }
+  }
+}
+
+// ---------------------------------------------------------- diagonal layout
+// Per antidiagonal k the window base dbase(k) (ints, rounded up to 64), then
+// per antidiagonal pair k/2 and lane 8 bytes: the RD/2 cells of the even
+// antidiagonal in the low nibbles, then those of the odd one.  Cell (i, j):
+// element e = (j - i) - dbase(k), lane e / RD, slot e mod RD.  A block is 64
+// antidiagonals: 16 KB of codes plus 64 window bases.
+__global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
+  __shared__ __align__(16) uint4 codes4[kBlockBytes / 16];
+  __shared__ uint8_t qwin[256], rwin[256];
+  const int lane = threadIdx.x;
+  const int task = blockIdx.x;
+  if (task >= a.ntasks) return;
+  const PairTask tk = a.tasks[task];
+  const int p = tk.pair;
+  aln_result *res = a.res + p;
+  const int status = uni(res->status);
+  const int i_end = uni(res->q_end), j_end = uni(res->r_end);
+  __syncthreads();
+  if (lane == 0) {
+    res->cigar_off = tk.cigar_off;
+    res->cigar_len = 0;
+  }
+  if (status != ALN_R_OK) return;
+  const int M = uni(a.b.q_len[p]), N = uni(a.b.r_len[p]);
+  SeqWindow qw{a.b.q + a.b.q_off[p], M, 1 << 30, qwin};
+  SeqWindow rw{a.b.r + a.b.r_off[p], N, 1 << 30, rwin};
+  const int RD = uni(tk.rows);
+  const int inv = (65536 + RD - 1) / RD; // e / RD = (e * inv) >> 16 for 0 <= e < 64*RD
+  const int nk = M + N + 1;
+  const int nks = (M + N) / 2 + 1; // antidiagonal pairs stored
+  const uint8_t *tbp = a.tb + tk.tb_off;
+  const int *dbh = reinterpret_cast<const int *>(tbp);
+  const uint4 *cod = reinterpret_cast<const uint4 *>(tbp + (size_t)((nk + 63) / 64) * 64 * 4);
+  const bool local = a.mode == ALN_LOCAL;
+  const uint8_t *codes = reinterpret_cast<const uint8_t *>(codes4);
+  BlockCache bc;
+
+  auto fetch = [&](int b) {
+    const int pairs = min(32, nks - b * 32); // antidiagonal pairs of this block
+    load_block(bc, cod + (size_t)b * (kBlockBytes / 16), pairs * 32, b, dbh[b * 64 + lane], lane);
+  };
+  bool bad = false;
+  auto code = [&](int i, int j) -> int {
+    const int k = i + j;
+    const int b = k >> 6;
+    if (b != bc.cur_key) {
+      if (b != bc.pre_key) fetch(b);
+      bc.install(codes4, lane);
+      if (b > 0) fetch(b - 1);
+    }
+    const int e = (j - i) - __builtin_amdgcn_readlane(bc.cur_aux, k & 63);
+    if ((unsigned)e >= (unsigned)(64 * RD)) {
+      bad = true;
+      return 0;
+    }
+    const int ln = (e * inv) >> 16;
+    const int x = e - ln * RD;
+    const int pos = (k & 1) * (RD >> 1) + (x >> 1);
+    const int byte = ((k >> 1) & 31) * 512 + ln * 8 + (pos >> 1);
+    return uni((codes[byte] >> ((pos & 1) * 4)) & 15);
+  };
+
+  int i = i_end, j = j_end;
+  WaveCigar cw{a.cigar + tk.cigar_off, tk.cigar_cap, -1, 0, false};
+  int state = 0;
+  for (int guard = 2 * (i_end + j_end) + 2; guard > 0 && !bad; --guard) {
+    if ((state == 1 && j < 1) || (state == 2 && i < 1) || i < 0 || j < 0) {
+      bad = true;
+      break;
+    }
+    if (state == 0) {
+      if (i == 0 && j == 0) break;
+      if (local && (i == 0 || j == 0)) break;
+      if (i == 0) { cw.emit(ALN_OP_D, lane); --j; continue; }
+      if (j == 0) { cw.emit(ALN_OP_I, lane); --i; continue; }
+      const int hs = code(i, j) & 3;
+      if (local && hs == 3) break;
+      if (hs == 0) {
+        cw.emit(qw.get(i - 1, lane) == rw.get(j - 1, lane) ? ALN_OP_EQ : ALN_OP_X, lane);
+        --i;
+        --j;
+      } else {
+        state = hs;
+      }
+    } else if (state == 1) {
+      // the code of (i, j-1) says whether E(i, j) opened from H(i, j-1)
+      cw.emit(ALN_OP_D, lane);
+      if (code(i, j - 1) & 4) state = 0;
+      --j;
+    } else {
+      cw.emit(ALN_OP_I, lane);
+      if (code(i - 1, j) & 8) state = 0;
+      --i;
+    }
+  }
+  cw.flush(lane);
+  if (lane == 0) {
+    res->q_begin = i;
+    res->r_begin = j;
+    if (bad || cw.overflow) {
+      res->status = ALN_R_CIGAR_CAP;
+    } else {
+      res->cigar_len = tk.cigar_cap - cw.w;
+      res->cigar_off = tk.cigar_off + cw.w;
+    }
+  }
+}
+
+hipError_t launch_walk(int layout, const WalkArgs &a, hipStream_t s) {
+  (void)layout;
+  if (a.ntasks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(walk_strip_wave, dim3(a.ntasks), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_walk_diag(const WalkArgs &a, hipStream_t s) {
+  if (a.ntasks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(walk_diag_wave, dim3(a.ntasks), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+} // namespace alnk

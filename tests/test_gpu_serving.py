@@ -79,14 +79,16 @@ def test_results_identical_alone_and_in_mix(mix):
 
 
 def test_admission_waits_for_memory(mix):
-    """A budget that holds only a few long-read micro-batches: ready work
-    waits for memory, the budget is never exceeded, results stay exact."""
+    """Long-read requests only (1-10 kbp, band 256, CIGAR: up to ~5 MB of
+    traceback codes each) against a 12 MiB budget with four streams for the
+    class: ready micro-batches must wait for memory, the budget is never
+    exceeded and the results stay exact."""
     from paper_2607_06225_amd import aln, serving
     arrival, kinds, batches = mix
     ctx, sids = make_ctx(batches)
-    reqs = [rq for rq in serving.mixed_requests(batches, kinds, sids) if rq["kind"] in (0, 2)]
-    budget = 24 << 20
-    srv = aln.Server(ctx, streams=4, max_batch_pairs=8, hbm_budget=budget)
+    reqs = [rq for rq in serving.mixed_requests(batches, kinds, sids) if rq["kind"] == 2] * 3
+    budget = 12 << 20
+    srv = aln.Server(ctx, streams=4, max_batch_pairs=4, hbm_budget=budget, class_streams=4)
     comps, cigs, _, _ = serving.replay(srv, reqs)
     st = srv.stats()
     srv.close()
@@ -95,7 +97,11 @@ def test_admission_waits_for_memory(mix):
     assert st["admission_waits"] > 0
     assert st["peak_arena_bytes"] <= budget
     assert np.all(comps["error"] == 0)
-    oracle_check(reqs, comps, cigs, batches)
+    n = len(reqs) // 3
+    for f in FIELDS:  # the three copies of each request agree
+        assert np.array_equal(comps[f][:n], comps[f][n:2 * n]), f
+        assert np.array_equal(comps[f][:n], comps[f][2 * n:]), f
+    oracle_check(reqs[:n], comps[:n], cigs[:n], batches)
     ctx.close()
 
 
