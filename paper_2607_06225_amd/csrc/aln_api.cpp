@@ -613,6 +613,7 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
     da.widen_count = wcnt;
     da.widen = wq;
     da.widen_rows = widen_rows;
+    da.match_mismatch = hsc.match_mismatch;
     return da;
   };
   PairTask *wq0 = plan->xdrop ? reinterpret_cast<PairTask *>(ws + plan->widen_off[0]) : nullptr;

@@ -116,6 +116,7 @@ struct DiagArgs {
   int32_t *widen_count;       // XDROP pairs whose region outgrew the window
   PairTask *widen;
   int32_t widen_rows;         // RD of the next wider kernel (0: none)
+  int32_t match_mismatch;     // 1: the scoring is one match and one mismatch score
 };
 
 // Launchers (defined in the kernel translation units).

@@ -28,6 +28,8 @@
 // (0 diagonal, 1 E, 2 F, 3 LOCAL zero), bit 2 set when E(i,j+1) opens from
 // H(i,j), bit 3 when F(i+1,j) opens from H(i,j) -- stored per lane and
 // antidiagonal pair, with the window base of every antidiagonal.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace alnk {
@@ -41,9 +43,18 @@ __device__ __forceinline__ int dpp_wshl1(int old, int v) {
   return __builtin_amdgcn_update_dpp(old, v, 0x130, 0xf, 0xf, false);
 }
 
+// Maximum over the wave by DPP: prefix maxima within each 16-lane row
+// (row_shr 1, 2, 4, 8), then across rows (row_bcast 15 and 31); lane 63 ends
+// with the maximum of all lanes.  Lanes without a source read INT32_MIN.
 __device__ __forceinline__ int wave_max_i32(int v) {
-  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  return v;
+  constexpr int lo = INT32_MIN;
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x111, 0xf, 0xf, false)); // row_shr:1
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x112, 0xf, 0xf, false)); // row_shr:2
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x114, 0xf, 0xf, false)); // row_shr:4
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x118, 0xf, 0xf, false)); // row_shr:8
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x142, 0xa, 0xf, false)); // row_bcast:15
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x143, 0xc, 0xf, false)); // row_bcast:31
+  return __builtin_amdgcn_readlane(v, 63);
 }
 
 // end order: higher score, then smaller i, then smaller j
@@ -88,9 +99,10 @@ struct BandTrack {
   }
 };
 
-template <int RD, int MODE, int PRUNE, bool TB>
+template <int RD, int MODE, int PRUNE, bool TB, bool MM>
 __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8_t *smem,
                           const int8_t *smat) {
+  static_assert(RD % 2 == 0, "a lane must hold whole diagonal pairs");
   constexpr int W = 64 * RD;
   constexpr int HALF = RD / 2;
   const PairTask tk = a.tasks[task];
@@ -102,6 +114,7 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
   const uint8_t *Rs = a.b.r + a.b.r_off[p];
   const int go = a.sc->gap_open, ge = a.sc->gap_extend, goe = go + ge;
   const int A = a.sc->alphabet;
+  const int s_match = a.sc->match, s_mismatch = a.sc->mismatch; // MM: all that scores
 
   if (M == 0 || N == 0) {
     if (lane == 0) {
@@ -208,7 +221,11 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
   int gh = NEG32; // GLOBAL: H(M, N)
 
   const int KMAX = M + N;
-  for (int k = 1; k <= KMAX; ++k) {
+  // One antidiagonal.  The window base and RD are even, so element x holds a
+  // cell of antidiagonal k exactly when x = k (mod 2): with the parity a
+  // compile-time constant every register index below is static.
+  auto step = [&](auto par_tag, const int k) -> bool {
+    constexpr int par = decltype(par_tag)::value;
     // ---- domain of antidiagonal k (in d), clipped to the matrix
     int dlo, dhi;
     const int mlo = max(-k, k - 2 * M), mhi = min(k, 2 * N - k);
@@ -223,15 +240,14 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
     } else {
       dlo = max(lo - 1, mlo);
       dhi = min(hi + 1, mhi);
-      if (dlo > dhi) break;
+      if (dlo > dhi) return false;
     }
     // ---- keep the domain inside the window
     if (dlo <= dhi) {
-      if (dhi - dlo > W - 6) { overflow = true; break; }
+      if (dhi - dlo > W - 6) { overflow = true; return false; }
       while (dhi > dbase + W - 3) shift_right2();
       while (dlo < dbase + 2) shift_left2();
     }
-    const int par = k & 1;
     // ---- stage sequence codes for this step's window
     {
       const int needq = ((k - dbase) >> 1) + 64; // largest i on the window, plus slack
@@ -248,7 +264,7 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
     }
     // ---- neighbour values across the lane boundary
     int left_x = NEG32, right_x = NEG32;
-    if (par == 0) left_x = dpp_wshr1(NEG32, EN[RD - 1]);
+    if constexpr (par == 0) left_x = dpp_wshr1(NEG32, EN[RD - 1]);
     else right_x = dpp_wshl1(NEG32, FN[0]);
     // ---- SIMD update of this parity's diagonals
     const int elo = dlo - dbase, ehi = dhi - dbase; // domain in element index
@@ -266,7 +282,7 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
       const int i = i0 - m, j = j0 + m;
       const int qc = qbuf[(i - 1) & (kSeqBuf - 1)];
       const int rc = rbuf[(j - 1) & (kSeqBuf - 1)];
-      const int sv = smat[qc * kMaxAlphabet + rc];
+      const int sv = MM ? (qc == rc ? s_match : s_mismatch) : smat[qc * kMaxAlphabet + rc];
       const int hd = H[x] + sv;
       int h = max(max(hd, left), right);
       if (MODE == ALN_LOCAL) h = max(h, 0);
@@ -347,7 +363,7 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
           shi = max(shi, dbase + ll * RD + x);
         }
       }
-      if (slo > shi) break; // every candidate pruned: the extension stops
+      if (slo > shi) return false; // every candidate pruned: the extension stops
       lo = slo;
       hi = shi;
     } else {
@@ -355,6 +371,11 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
       hi = dhi;
     }
     if (MODE == ALN_GLOBAL && k == KMAX) gh = get_h(N - M);
+    return true;
+  };
+  for (int k = 1; k <= KMAX; k += 2) {
+    if (!step(std::integral_constant<int, 1>{}, k)) break;
+    if (k + 1 > KMAX || !step(std::integral_constant<int, 0>{}, k + 1)) break;
   }
 
   if (lane == 0) {
@@ -386,10 +407,12 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
   }
 }
 
-template <int RD, int MODE, int PRUNE, bool TB>
+template <int RD, int MODE, int PRUNE, bool TB, bool MM>
 __global__ __launch_bounds__(256) void diag_kernel(DiagArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
-  const int wave = threadIdx.x >> 6;
+  // wave-uniform by construction; saying so keeps every per-pair and
+  // per-antidiagonal quantity (task, lengths, domain, window base) scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   int8_t *smat = reinterpret_cast<int8_t *>(smem + 4 * 2 * kSeqBuf);
   const int A = a.sc->alphabet;
@@ -400,15 +423,17 @@ __global__ __launch_bounds__(256) void diag_kernel(DiagArgs a) {
   __syncthreads();
   const int ntasks = a.dyn_ntasks ? min(*a.dyn_ntasks, a.ntasks) : a.ntasks;
   for (int task = blockIdx.x * 4 + wave; task < ntasks; task += gridDim.x * 4)
-    diag_task<RD, MODE, PRUNE, TB>(a, task, wave, lane, smem, smat);
+    diag_task<RD, MODE, PRUNE, TB, MM>(a, task, wave, lane, smem, smat);
 }
 
 template <int RD, int MODE, int PRUNE, bool TB>
 static hipError_t launch_diag_t(const DiagArgs &a, hipStream_t s) {
+  const bool mm = a.match_mismatch != 0;
   const size_t lds = (size_t)4 * 2 * kSeqBuf + kMaxAlphabet * kMaxAlphabet;
   int blocks = (a.ntasks + 3) / 4;
   if (a.dyn_ntasks) blocks = min(blocks, 2048);
-  hipLaunchKernelGGL((diag_kernel<RD, MODE, PRUNE, TB>), dim3(blocks), dim3(256), lds, s, a);
+  if (mm) hipLaunchKernelGGL((diag_kernel<RD, MODE, PRUNE, TB, true>), dim3(blocks), dim3(256), lds, s, a);
+  else hipLaunchKernelGGL((diag_kernel<RD, MODE, PRUNE, TB, false>), dim3(blocks), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 
