@@ -112,11 +112,22 @@ def run_workload(name, batch, args, cpu_seconds, pp_cap):
     mode_name = MODE_NAME[batch.mode]
     ctx = aln.Context(0)
     sid = ctx.set_scoring(batch.matrix, batch.gap_open, batch.gap_extend)
+    tuning = None
+    db = aln.DeviceBatch(batch)
+    if not args.no_autotune:
+        # tune on the batch itself, or on its first 65,536 pairs
+        tb = batch if batch.n <= 65536 else batch.subset(np.arange(65536))
+        tdb = db if tb is batch else aln.DeviceBatch(tb)
+        t0 = time.perf_counter()
+        tuning = ctx.autotune(sid, tdb, batch.mode, batch.prune, batch.band_w, batch.xdrop,
+                              want_cigar=batch.want_cigar)
+        tuning = dict(ms=round((time.perf_counter() - t0) * 1e3, 1), sample_pairs=tb.n,
+                      **{k: v for k, v in tuning.items() if k != "valid"})
+        del tdb
     t0 = time.perf_counter()
     plan = ctx.plan(sid, batch.q_len, batch.r_len, batch.mode, batch.prune, batch.band_w,
                     batch.xdrop, aln.W_AUTO, batch.want_cigar)
     plan_ms = (time.perf_counter() - t0) * 1e3
-    db = aln.DeviceBatch(batch)
     buf = aln.Buffers(plan)
     stream = torch.cuda.current_stream()
 
@@ -217,7 +228,7 @@ def run_workload(name, batch, args, cpu_seconds, pp_cap):
         step_ms_median=round(float(np.median(per_step)), 4),
         kernel_ms_per_step={k: round(v, 4) for k, v in kernel_ms.items()},
         roofline=roof, per_pair=per_pair, cpu_baseline=cpu, bit_exact_check=verified,
-        plan_ms=round(plan_ms, 2),
+        plan_ms=round(plan_ms, 2), autotune=tuning,
         statuses={int(s): int(c) for s, c in zip(*np.unique(res["status"], return_counts=True))},
     )
     if batch.prune == 2:
@@ -305,6 +316,8 @@ def main():
     ap.add_argument("--configs", default="nw_dna_1k,band_long,xdrop_ext",
                     help="comma list of further workloads to measure, or 'none'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="plan with built-in tile costs instead of measured ones")
     ap.add_argument("--no-per-pair", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--extra-cpu-seconds", type=float, default=6.0)
@@ -394,6 +407,7 @@ def main():
         "step_ms_trimmed_mean": head["step_ms_trimmed_mean"],
         "step_ms_median": head["step_ms_median"],
         "plan_ms": head["plan_ms"],
+        "autotune": head["autotune"],
         "configs": configs,
         "serving": serving_out,
     }

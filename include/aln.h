@@ -148,6 +148,24 @@ typedef struct {
   int64_t cells;        /* interior cells the plan will evaluate (FULL, BAND) */
 } aln_footprint;
 
+/* Tile choices found by the autotuner (aln_autotune) for the three kernel
+ * families whose tiling is free: rows per lane of the packed int16
+ * Smith-Waterman kernel, rows per lane of the int32 full-matrix strips (0:
+ * the planner's per-pair choice) and the starting window of the X-drop
+ * kernel (diagonals per lane).  Each ms[] entry is the measured time of one
+ * candidate on the tuning batch (0: not measured, negative: not runnable).
+ * While `valid`, aln_plan_create uses the chosen tiles.  Tiles never change
+ * results. */
+typedef struct {
+  int32_t valid;
+  int32_t sw16_rows;      /* 4, 8, 12 or 16                                   */
+  int32_t strip_rows;     /* 0 (per pair), 8, 16, 24 or 32                    */
+  int32_t xdrop_rows;     /* 2, 4 or 8                                        */
+  double sw16_ms[4];      /* candidates 16, 12, 8, 4                          */
+  double strip_ms[5];     /* candidates 0, 8, 16, 24, 32                      */
+  double xdrop_ms[3];     /* candidates 4, 2, 8                               */
+} aln_tuning;             /* 112 bytes */
+
 /* ABI version of the loaded library (ALN_ABI_VERSION). */
 int32_t aln_abi_version(void);
 
@@ -197,6 +215,20 @@ aln_status aln_graph_capture(aln_ctx *ctx, aln_plan *plan,
                              uint32_t *d_cigar, uint64_t cigar_words,
                              void *stream);
 aln_status aln_graph_launch(aln_ctx *ctx, aln_plan *plan, void *stream);
+
+/* Autotuner: run every candidate tile of the kernel family this batch uses
+ * (packed int16 SW, int32 strips or X-drop) on the batch itself -- pass a
+ * sample of a large workload -- and keep the fastest in the context's
+ * tuning (the other families' choices are kept).  Same arguments as
+ * aln_plan_create plus the device batch; allocates and frees its own device
+ * memory and synchronises `stream`.  Bands have nothing to tune (ALN_OK). */
+aln_status aln_autotune(aln_ctx *ctx, int32_t scoring_id, const aln_params *params,
+                        const aln_batch *batch, const int32_t *q_len_host,
+                        const int32_t *r_len_host, void *stream);
+/* Read or replace the context's tile choices (for example ones saved from
+ * an earlier aln_autotune on the same device). */
+aln_status aln_get_tuning(const aln_ctx *ctx, aln_tuning *tuning);
+aln_status aln_set_tuning(aln_ctx *ctx, const aln_tuning *tuning);
 
 /* Kernel timing for measurement tools.  While enabled (enable = 1), every
  * kernel launch of aln_execute is bracketed by HIP events on the launch

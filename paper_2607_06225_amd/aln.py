@@ -81,6 +81,16 @@ COMPLETION_DTYPE = np.dtype(
        ("t_submit", "<f8"), ("t_launch", "<f8"), ("t_done", "<f8")])
 assert COMPLETION_DTYPE.itemsize == 104
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("valid", ctypes.c_int32), ("sw16_rows", ctypes.c_int32),
+                ("strip_rows", ctypes.c_int32), ("xdrop_rows", ctypes.c_int32),
+                ("sw16_ms", ctypes.c_double * 4), ("strip_ms", ctypes.c_double * 5),
+                ("xdrop_ms", ctypes.c_double * 3)]
+
+
+SW16_TILES, STRIP_TILES, XDROP_TILES = (16, 12, 8, 4), (0, 8, 16, 24, 32), (4, 2, 8)
+
+
 _lib = None
 
 # every symbol include/aln.h declares
@@ -88,7 +98,7 @@ EXPORTS = [
     "aln_abi_version", "aln_create", "aln_destroy", "aln_last_error",
     "aln_set_scoring", "aln_plan_create", "aln_plan_destroy", "aln_execute",
     "aln_execute_per_pair", "aln_graph_capture", "aln_graph_launch",
-    "aln_set_profiling", "aln_kernel_times",
+    "aln_set_profiling", "aln_kernel_times", "aln_autotune", "aln_get_tuning", "aln_set_tuning",
     "aln_server_create", "aln_server_destroy", "aln_server_submit", "aln_server_poll",
     "aln_server_drain", "aln_server_clock", "aln_server_get_stats", "aln_server_last_error",
 ]
@@ -117,6 +127,9 @@ def load_library(path=LIB_PATH):
         "aln_graph_launch": ([P, P, P], I32),
         "aln_set_profiling": ([P, I32], I32),
         "aln_kernel_times": ([P, P, P, P, I32], I32),
+        "aln_autotune": ([P, I32, P, P, P, P, P], I32),
+        "aln_get_tuning": ([P, P], I32),
+        "aln_set_tuning": ([P, P], I32),
         "aln_server_create": ([P, P, P], I32),
         "aln_server_destroy": ([P], None),
         "aln_server_submit": ([P, P, P], I32),
@@ -250,6 +263,37 @@ class Context:
 
     def graph_launch(self, plan, stream=None):
         self._check(self.lib.aln_graph_launch(self.handle, plan.handle, _stream_handle(stream)))
+
+    def autotune(self, scoring_id, dbatch, mode, prune=FULL, band_w=0, xdrop=0, width=W_AUTO,
+                 want_cigar=False, stream=None):
+        """Time every candidate tile of the kernel family this batch uses on
+        the batch itself (a DeviceBatch; pass a sample of a large workload)
+        and keep the fastest for later plans of this context."""
+        params = _Params(int(mode), int(prune), int(band_w), int(xdrop), int(width),
+                         1 if want_cigar else 0)
+        ql = dbatch.q_len_host
+        rl = dbatch.r_len_host
+        self._check(self.lib.aln_autotune(self.handle, int(scoring_id), ctypes.byref(params),
+                                          ctypes.byref(dbatch.c), ql.ctypes.data, rl.ctypes.data,
+                                          _stream_handle(stream)))
+        return self.tuning()
+
+    def tuning(self):
+        t = _Tuning()
+        self._check(self.lib.aln_get_tuning(self.handle, ctypes.byref(t)))
+        return {"valid": bool(t.valid), "sw16_rows": int(t.sw16_rows),
+                "strip_rows": int(t.strip_rows), "xdrop_rows": int(t.xdrop_rows),
+                "sw16_ms": dict(zip(SW16_TILES, map(float, t.sw16_ms))),
+                "strip_ms": dict(zip(STRIP_TILES, map(float, t.strip_ms))),
+                "xdrop_ms": dict(zip(XDROP_TILES, map(float, t.xdrop_ms)))}
+
+    def set_tuning(self, tuning):
+        t = _Tuning()
+        t.valid = 1 if tuning.get("valid", True) else 0
+        t.sw16_rows = int(tuning.get("sw16_rows", 16))
+        t.strip_rows = int(tuning.get("strip_rows", 0))
+        t.xdrop_rows = int(tuning.get("xdrop_rows", 4))
+        self._check(self.lib.aln_set_tuning(self.handle, ctypes.byref(t)))
 
     def set_profiling(self, enable):
         self._check(self.lib.aln_set_profiling(self.handle, 1 if enable else 0))

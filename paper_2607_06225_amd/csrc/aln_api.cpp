@@ -254,45 +254,69 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
                         maxN <= 65534 && maxM < (1 << 20) &&
                         4LL * (rerun_bnd + rerun_prof) <= 160 * 1024;
   if (use_sw16) {
+    // rows per lane: forced while the autotuner measures, else the
+    // ALN_SW16_ROWS override, else the autotuner's choice, else 16
+    int tile = 16;
+    if (ctx->tuning.valid) tile = ctx->tuning.sw16_rows;
     if (const char *ev = getenv("ALN_SW16_ROWS")) {
       const int r = atoi(ev);
-      if (r == 4 || r == 8 || r == 12 || r == 16) pl->sw16_rows = r;
+      if (r == 4 || r == 8 || r == 12 || r == 16) tile = r;
     }
-    const int R = pl->sw16_rows;
-    const int HS = 16 * R;
+    if (ctx->force_sw16_rows) tile = ctx->force_sw16_rows;
+    std::vector<int> prow(n, tile);
+    pl->sw16_rows = prow.empty() ? 16 : prow[0];
     std::vector<int32_t> order(n);
     for (int32_t i = 0; i < n; ++i) order[i] = i;
-    auto nstr = [&](int32_t i) { return (pl->qlen[i] + HS - 1) / HS; };
+    auto nstr = [&](int32_t i) { return (pl->qlen[i] + 16 * prow[i] - 1) / (16 * prow[i]); };
+    // buckets by tile (largest tile first), longest work first inside one
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+      if (prow[a] != prow[b]) return prow[a] > prow[b];
       const int sa = nstr(a), sb = nstr(b);
       if (sa != sb) return sa > sb;
       return pl->rlen[a] > pl->rlen[b];
     });
     uint64_t bnd_bytes = 0;
     std::vector<uint64_t> bnd_rel;
-    for (int32_t k = 0; k < n; k += 2) {
-      alnk::Sw16Task t;
-      t.pa = order[k];
-      t.pb = (k + 1 < n) ? order[k + 1] : -1;
-      t.nstrips = nstr(t.pa);
-      t.nmax = pl->rlen[t.pa];
-      if (t.pb >= 0) {
-        t.nstrips = std::max(t.nstrips, nstr(t.pb));
-        t.nmax = std::max(t.nmax, pl->rlen[t.pb]);
+    for (int32_t k = 0; k < n;) {
+      const int R = prow[order[k]];
+      LaunchDesc L{};
+      L.kind = K_SW16;
+      L.rows = R;
+      L.mode = ALN_LOCAL;
+      L.first = (int32_t)pl->sw16_tasks.size();
+      int32_t e = k;
+      while (e < n && prow[order[e]] == R) ++e;
+      for (int32_t q = k; q < e; q += 2) {
+        alnk::Sw16Task t;
+        t.pa = order[q];
+        t.pb = (q + 1 < e) ? order[q + 1] : -1;
+        t.nstrips = nstr(t.pa);
+        t.nmax = pl->rlen[t.pa];
+        if (t.pb >= 0) {
+          t.nstrips = std::max(t.nstrips, nstr(t.pb));
+          t.nmax = std::max(t.nmax, pl->rlen[t.pb]);
+        }
+        t.bnd_off = 0;
+        bnd_rel.push_back(t.nstrips > 1 ? bnd_bytes : ~0ULL);
+        if (t.nstrips > 1) bnd_bytes += align_up((uint64_t)(t.nmax + 1) * 8);
+        pl->sw16_tasks.push_back(t);
+        // the same pairs one by one (per-pair runs), sharing the boundary row
+        for (int h = 0; h < 2; ++h) {
+          const int32_t pp = h ? t.pb : t.pa;
+          if (pp < 0) continue;
+          alnk::Sw16Task u;
+          u.pa = pp;
+          u.pb = -1;
+          u.nstrips = nstr(pp);
+          u.nmax = pl->rlen[pp];
+          u.bnd_off = (int64_t)(pl->sw16_tasks.size() - 1); // task index, resolved below
+          pl->sw16_single.push_back(u);
+          pl->sw16_single_rows.push_back(R);
+        }
       }
-      t.bnd_off = 0;
-      bnd_rel.push_back(t.nstrips > 1 ? bnd_bytes : ~0ULL);
-      if (t.nstrips > 1) bnd_bytes += align_up((uint64_t)(t.nmax + 1) * 8);
-      pl->sw16_tasks.push_back(t);
-    }
-    for (int32_t k = 0; k < n; ++k) {
-      alnk::Sw16Task t;
-      t.pa = order[k];
-      t.pb = -1;
-      t.nstrips = nstr(t.pa);
-      t.nmax = pl->rlen[t.pa];
-      t.bnd_off = 0;
-      pl->sw16_single.push_back(t);
+      L.count = (int32_t)pl->sw16_tasks.size() - L.first;
+      pl->launches.push_back(L);
+      k = e;
     }
     // workspace: [sw16 tasks | single tasks | rerun counter | rerun queue | boundary rows]
     pl->sw16_off = 0;
@@ -302,19 +326,7 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     const uint64_t bnd_base = pl->rerun_off + align_up(sizeof(PairTask) * (size_t)n);
     for (size_t k = 0; k < pl->sw16_tasks.size(); ++k)
       pl->sw16_tasks[k].bnd_off = bnd_rel[k] == ~0ULL ? 0 : (int64_t)(bnd_base + bnd_rel[k]);
-    // single-pair tasks reuse the boundary row of their pair's packed task
-    for (size_t k = 0; k < pl->sw16_tasks.size(); ++k) {
-      const int64_t off = pl->sw16_tasks[k].bnd_off;
-      pl->sw16_single[2 * k].bnd_off = off;
-      if (2 * k + 1 < pl->sw16_single.size()) pl->sw16_single[2 * k + 1].bnd_off = off;
-    }
-    LaunchDesc L{};
-    L.kind = K_SW16;
-    L.rows = R;
-    L.mode = ALN_LOCAL;
-    L.first = 0;
-    L.count = (int32_t)pl->sw16_tasks.size();
-    pl->launches.push_back(L);
+    for (alnk::Sw16Task &u : pl->sw16_single) u.bnd_off = pl->sw16_tasks[(size_t)u.bnd_off].bnd_off;
     pl->rerun.kind = K_RERUN;
     pl->rerun.rows = rerun_rows;
     pl->rerun.mode = ALN_LOCAL;
@@ -359,7 +371,9 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     Item it{i, K_STRIP, 0, 0.0};
     const bool band_is_full = p.prune == ALN_BAND && (M == 0 || p.band_w >= std::max(M, N));
     if (p.prune == ALN_FULL || band_is_full) {
-      it.rows = choose_strip_rows(M, N);
+      int srows = ctx->tuning.valid ? ctx->tuning.strip_rows : 0;
+      if (ctx->force_strip_rows >= 0) srows = ctx->force_strip_rows;
+      it.rows = srows ? srows : choose_strip_rows(M, N);
       it.cost = (double)M * N;
       pl->cells += (int64_t)M * N;
     } else {
@@ -382,7 +396,8 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
         }
         it.cost = (double)(M + N) * it.rows;
       } else {
-        it.rows = 4;
+        it.rows = ctx->tuning.valid ? ctx->tuning.xdrop_rows : 4;
+        if (ctx->force_xdrop_rows) it.rows = ctx->force_xdrop_rows;
         it.cost = (double)(M + N);
       }
     }
@@ -568,16 +583,19 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
     a16.rerun = rerun_q;
     a16.rerun_threshold = 32767 - std::max(hsc.max_s, 0);
     if (!per_pair) {
-      a16.tasks = reinterpret_cast<const alnk::Sw16Task *>(ws + plan->sw16_off);
-      a16.ntasks = (int32_t)plan->sw16_tasks.size();
-      HIP_TRY(ctx, timed_launch(ctx, "sw16", st, [&] {
-                return alnk::launch_sw16(plan->sw16_rows, a16, st);
-              }));
+      for (const LaunchDesc &L : plan->launches) {
+        if (L.kind != K_SW16) continue;
+        a16.tasks = reinterpret_cast<const alnk::Sw16Task *>(ws + plan->sw16_off) + L.first;
+        a16.ntasks = L.count;
+        HIP_TRY(ctx, timed_launch(ctx, "sw16", st, [&] {
+                  return alnk::launch_sw16(L.rows, a16, st);
+                }));
+      }
     } else {
       for (size_t k = 0; k < plan->sw16_single.size(); ++k) {
         a16.tasks = reinterpret_cast<const alnk::Sw16Task *>(ws + plan->sw16_single_off) + k;
         a16.ntasks = 1;
-        HIP_TRY(ctx, alnk::launch_sw16(plan->sw16_rows, a16, st));
+        HIP_TRY(ctx, alnk::launch_sw16(plan->sw16_single_rows[k], a16, st));
       }
     }
     const LaunchDesc &L = plan->rerun;

@@ -178,7 +178,7 @@ __global__ __launch_bounds__(64) void sw16_kernel(Sw16Args a) {
           for (int k = 0; k < NWD; ++k) { da[k] = wa[k]; db[k] = wb[k]; }
         }
       }
-      if (s > 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (s > 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 
       // ---- state: H(i, j-1), E+(i, j), per-row keys
       uint32_t Hl[R], EN[R], kA[R], kB[R];
@@ -330,7 +330,10 @@ __global__ __launch_bounds__(64) void sw16_kernel(Sw16Args a) {
         kB[r] = max(kB[r], pB[r]);
       }
       flush(T_w - 1, ((T_w - 1) & 15) + 1);
-      if (s + 1 < ns_w) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      // The strip's bottom row is written to HBM and read back by the next
+      // strip of this same one-wave workgroup: workgroup-scope ordering
+      // (all of its lanes share one L1) is all the hand-over needs.
+      if (s + 1 < ns_w) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
 
       // ---- fold this strip's row maxima into the pair's end-cell key
       unsigned long long la = 0, lb = 0;

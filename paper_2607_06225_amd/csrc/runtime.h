@@ -23,6 +23,12 @@ struct aln_ctx {
   };
   std::vector<TimedLaunch> timed;
   std::vector<hipEvent_t> event_pool;
+  // autotuning: the tiles chosen by aln_autotune, and the tile the tuner
+  // forces while it measures a candidate (sw16/xdrop 0, strips -1: none)
+  aln_tuning tuning{};
+  int force_sw16_rows = 0;
+  int force_strip_rows = -1;
+  int force_xdrop_rows = 0;
 };
 
 namespace alnrt {
@@ -60,6 +66,7 @@ struct aln_plan {
   // packed int16 path
   std::vector<alnk::Sw16Task> sw16_tasks;    // two pairs per task
   std::vector<alnk::Sw16Task> sw16_single;   // one pair per task (per-pair runs)
+  std::vector<int> sw16_single_rows;         // tile of each single task
   int sw16_rows = 16;
   uint64_t sw16_off = 0, sw16_single_off = 0, rerun_cnt_off = 0, rerun_off = 0;
   alnrt::LaunchDesc rerun{};

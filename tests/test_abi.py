@@ -48,6 +48,7 @@ STRUCTS = {
     "aln_scoring": aln._Scoring, "aln_params": aln._Params, "aln_batch": aln._Batch,
     "aln_footprint": aln._Footprint, "aln_server_cfg": aln._ServerCfg,
     "aln_request": aln._Request, "aln_server_stats": aln._ServerStats,
+    "aln_tuning": aln._Tuning,
 }
 NUMPY_STRUCTS = {"aln_result": aln.RESULT_DTYPE, "aln_completion": aln.COMPLETION_DTYPE}
 

@@ -1,0 +1,77 @@
+"""GPU tests of the autotuner: it times every candidate tile of the kernel
+family a batch uses, keeps the fastest, and plans built with any tile stay
+bit-exact against the oracle."""
+import numpy as np
+import pytest
+
+from paper_2607_06225_amd import workloads as W
+from tests.parity import compare, oracle_batch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture()
+def ctx():
+    import torch
+    from paper_2607_06225_amd import aln
+    assert torch.cuda.is_available()
+    c = aln.Context(0)
+    yield c
+    c.close()
+
+
+def tune_and_check(ctx, b, family, tiles):
+    from paper_2607_06225_amd import aln
+    sid = ctx.set_scoring(b.matrix, b.gap_open, b.gap_extend)
+    db = aln.DeviceBatch(b)
+    t = ctx.autotune(sid, db, b.mode, b.prune, b.band_w, b.xdrop, want_cigar=b.want_cigar)
+    print(f"[gpu] {b.name}: {t}", flush=True)
+    assert t["valid"]
+    assert t[f"{family}_rows"] in tiles
+    assert all(ms != 0.0 for ms in t[f"{family}_ms"].values())
+    assert max(t[f"{family}_ms"].values()) > 0
+    res, cig = aln.align(ctx, b, scoring_id=sid, dbatch=db)
+    assert compare(b, res, cig, oracle_batch(b)) == []
+    return t
+
+
+def test_autotune_packed_sw(ctx):
+    tune_and_check(ctx, W.sw_protein(n=3000, seed=61), "sw16", (4, 8, 12, 16))
+
+
+def test_autotune_strips_with_cigar(ctx):
+    tune_and_check(ctx, W.nw_dna_1k(n=64, seed=62), "strip", (0, 8, 16, 24, 32))
+
+
+def test_autotune_xdrop(ctx):
+    tune_and_check(ctx, W.xdrop_ext(n=3000, seed=63), "xdrop", (2, 4, 8))
+
+
+@pytest.mark.parametrize("tile", [2, 8])
+def test_every_xdrop_start_window_is_bit_exact(ctx, tile):
+    from paper_2607_06225_amd import aln
+    b = W.xdrop_ext(n=1500, seed=70 + tile)
+    sid = ctx.set_scoring(b.matrix, b.gap_open, b.gap_extend)
+    ctx.set_tuning({"sw16_rows": 16, "strip_rows": 0, "xdrop_rows": tile})
+    res, _ = aln.align(ctx, b, scoring_id=sid)
+    assert compare(b, res, None, oracle_batch(b)) == []
+
+
+@pytest.mark.parametrize("tile", [8, 24])
+def test_every_fixed_strip_tile_is_bit_exact(ctx, tile):
+    from paper_2607_06225_amd import aln
+    b = W.nw_dna_1k(n=24, seed=80 + tile)
+    sid = ctx.set_scoring(b.matrix, b.gap_open, b.gap_extend)
+    ctx.set_tuning({"sw16_rows": 16, "strip_rows": tile, "xdrop_rows": 4})
+    res, cig = aln.align(ctx, b, scoring_id=sid)
+    assert compare(b, res, cig, oracle_batch(b)) == []
+
+
+def test_set_tuning_round_trip_and_validation(ctx):
+    from paper_2607_06225_amd import aln
+    ctx.set_tuning({"sw16_rows": 8, "strip_rows": 24, "xdrop_rows": 2})
+    got = ctx.tuning()
+    assert got["valid"] and (got["sw16_rows"], got["strip_rows"], got["xdrop_rows"]) == (8, 24, 2)
+    for bad in ({"sw16_rows": 5}, {"strip_rows": 12}, {"xdrop_rows": 16}):
+        with pytest.raises(aln.AlnError):
+            ctx.set_tuning(dict({"sw16_rows": 16, "strip_rows": 0, "xdrop_rows": 4}, **bad))
