@@ -104,6 +104,26 @@ def cpu_baseline(batch, work, target_s):
                        f"{dt:.1f} s on {cores} host threads"), ores, k
 
 
+def measured_traffic(family, workload):
+    """HBM bytes per launch of a kernel family on a workload, from the
+    rocprofv3 FETCH_SIZE / WRITE_SIZE passes summarised in
+    profiles/traffic.json (scaled by a copy of known size).  None when the
+    kernel's source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        table = json.load(f)
+    for e in table.get("kernels", []):
+        if e["family"] == family and e["workload"] == workload:
+            with open(os.path.join(ROOT, e["source"]), "rb") as src:
+                if hashlib.sha256(src.read()).hexdigest()[:16] != e["source_sha256_16"]:
+                    return None
+            return int(e["hbm_bytes_per_launch"])
+    return None
+
+
 def run_workload(name, batch, args, cpu_seconds, pp_cap):
     import torch
     from paper_2607_06225_amd import aln
@@ -172,7 +192,7 @@ def run_workload(name, batch, args, cpu_seconds, pp_cap):
     cells_per_launch = cells / dom_launches
     achieved = cells_per_launch * ops / (dom_launch_ms * 1e-3) / 1e12
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=round(peak, 2), unit="TOP/s",
-                frac=round(achieved / peak, 4), traffic=None,
+                frac=round(achieved / peak, 4), traffic=measured_traffic(dom, name),
                 kernel=dom, ops_per_cell=ops, op_width=width,
                 cells_per_launch=int(cells_per_launch), launches_per_step=dom_launches,
                 avg_launch_ms=round(dom_launch_ms, 4))
