@@ -151,20 +151,23 @@ typedef struct {
 /* Tile choices found by the autotuner (aln_autotune) for the three kernel
  * families whose tiling is free: rows per lane of the packed int16
  * Smith-Waterman kernel, rows per lane of the int32 full-matrix strips (0:
- * the planner's per-pair choice) and the starting window of the X-drop
- * kernel (diagonals per lane).  Each ms[] entry is the measured time of one
- * candidate on the tuning batch (0: not measured, negative: not runnable).
- * While `valid`, aln_plan_create uses the chosen tiles.  Tiles never change
- * results. */
+ * the planner's per-pair choice) and the X-drop kernel's starting window
+ * (diagonals per lane, and extension sides per wavefront: 1 side over all
+ * 64 lanes, or 4 sides of 16 lanes each).  Each ms[] entry is the measured
+ * time of one candidate on the tuning batch (0: not measured, negative: not
+ * runnable).  While `valid`, aln_plan_create uses the chosen tiles.  Tiles
+ * never change results. */
 typedef struct {
   int32_t valid;
   int32_t sw16_rows;      /* 4, 8, 12 or 16                                   */
   int32_t strip_rows;     /* 0 (per pair), 8, 16, 24 or 32                    */
   int32_t xdrop_rows;     /* 2, 4 or 8                                        */
+  int32_t xdrop_sides;    /* 1, or 4 (with xdrop_rows 8)                      */
+  int32_t reserved;
   double sw16_ms[4];      /* candidates 16, 12, 8, 4                          */
   double strip_ms[5];     /* candidates 0, 8, 16, 24, 32                      */
-  double xdrop_ms[3];     /* candidates 4, 2, 8                               */
-} aln_tuning;             /* 112 bytes */
+  double xdrop_ms[4];     /* candidates 4x1, 2x1, 8x1, 8x4 (rows x sides)     */
+} aln_tuning;             /* 128 bytes */
 
 /* ABI version of the loaded library (ALN_ABI_VERSION). */
 int32_t aln_abi_version(void);

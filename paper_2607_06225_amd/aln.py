@@ -84,11 +84,13 @@ assert COMPLETION_DTYPE.itemsize == 104
 class _Tuning(ctypes.Structure):
     _fields_ = [("valid", ctypes.c_int32), ("sw16_rows", ctypes.c_int32),
                 ("strip_rows", ctypes.c_int32), ("xdrop_rows", ctypes.c_int32),
+                ("xdrop_sides", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("sw16_ms", ctypes.c_double * 4), ("strip_ms", ctypes.c_double * 5),
-                ("xdrop_ms", ctypes.c_double * 3)]
+                ("xdrop_ms", ctypes.c_double * 4)]
 
 
-SW16_TILES, STRIP_TILES, XDROP_TILES = (16, 12, 8, 4), (0, 8, 16, 24, 32), (4, 2, 8)
+SW16_TILES, STRIP_TILES = (16, 12, 8, 4), (0, 8, 16, 24, 32)
+XDROP_TILES = ("4x1", "2x1", "8x1", "8x4")  # diagonals per lane x sides per wavefront
 
 
 _lib = None
@@ -283,6 +285,7 @@ class Context:
         self._check(self.lib.aln_get_tuning(self.handle, ctypes.byref(t)))
         return {"valid": bool(t.valid), "sw16_rows": int(t.sw16_rows),
                 "strip_rows": int(t.strip_rows), "xdrop_rows": int(t.xdrop_rows),
+                "xdrop_sides": int(t.xdrop_sides),
                 "sw16_ms": dict(zip(SW16_TILES, map(float, t.sw16_ms))),
                 "strip_ms": dict(zip(STRIP_TILES, map(float, t.strip_ms))),
                 "xdrop_ms": dict(zip(XDROP_TILES, map(float, t.xdrop_ms)))}
@@ -293,6 +296,7 @@ class Context:
         t.sw16_rows = int(tuning.get("sw16_rows", 16))
         t.strip_rows = int(tuning.get("strip_rows", 0))
         t.xdrop_rows = int(tuning.get("xdrop_rows", 4))
+        t.xdrop_sides = int(tuning.get("xdrop_sides", 1))
         self._check(self.lib.aln_set_tuning(self.handle, ctypes.byref(t)))
 
     def set_profiling(self, enable):

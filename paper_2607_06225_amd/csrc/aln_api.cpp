@@ -422,6 +422,11 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     L.kind = items[k].kind;
     L.rows = items[k].rows;
     L.mode = p.mode;
+    if (L.kind == K_DIAG && p.prune == ALN_XDROP) {
+      L.sides = ctx->tuning.valid ? ctx->tuning.xdrop_sides : 1;
+      if (ctx->force_xdrop_sides) L.sides = ctx->force_xdrop_sides;
+      if (L.sides != 1 && L.rows != 8) L.sides = 1;
+    }
     L.tb = p.want_cigar != 0;
     L.small = small;
     L.first = (int32_t)pl->tasks.size();
@@ -639,15 +644,17 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
   for (const LaunchDesc &L : plan->launches) {
     if (L.kind == K_DIAG) {
       const int widen_rows = plan->xdrop ? 16 : 0;
+      auto go = [&](const alnk::DiagArgs &da) {
+        return L.sides == 4 ? alnk::launch_xdrop_group(da, st)
+                            : alnk::launch_diag(L.rows, L.mode, plan->p.prune, L.tb, da, st);
+      };
       if (!per_pair) {
         alnk::DiagArgs da = diag_args(dtasks + L.first, L.count, nullptr, widen_rows, widen_cnt, wq0);
-        HIP_TRY(ctx, timed_launch(ctx, plan->xdrop ? "xdrop" : "diag_band", st, [&] {
-                  return alnk::launch_diag(L.rows, L.mode, plan->p.prune, L.tb, da, st);
-                }));
+        HIP_TRY(ctx, timed_launch(ctx, plan->xdrop ? "xdrop" : "diag_band", st, [&] { return go(da); }));
       } else {
         for (int32_t k = 0; k < L.count; ++k) {
           alnk::DiagArgs da = diag_args(dtasks + L.first + k, 1, nullptr, widen_rows, widen_cnt, wq0);
-          HIP_TRY(ctx, alnk::launch_diag(L.rows, L.mode, plan->p.prune, L.tb, da, st));
+          HIP_TRY(ctx, go(da));
         }
       }
       continue;

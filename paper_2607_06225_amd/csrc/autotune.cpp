@@ -107,6 +107,7 @@ aln_status aln_autotune(aln_ctx *ctx, int32_t scoring_id, const aln_params *para
     t.sw16_rows = 16;
     t.strip_rows = 0;
     t.xdrop_rows = 4;
+    t.xdrop_sides = 1;
   }
   aln_status err = ALN_OK;
   auto run = [&]() {
@@ -115,13 +116,18 @@ aln_status aln_autotune(aln_ctx *ctx, int32_t scoring_id, const aln_params *para
   const bool local_full = p.mode == ALN_LOCAL && p.prune == ALN_FULL && !p.want_cigar &&
                           p.width != ALN_W_I32;
   if (p.prune == ALN_XDROP) {
-    static const int c[3] = {4, 2, 8};
-    t.xdrop_rows = pick(c, 3, t.xdrop_ms, 4, [&](int r) {
-      ctx->force_xdrop_rows = r;
+    // candidates rows x sides: 4x1, 2x1, 8x1, 8x4 (encoded rows + 100*(sides-1))
+    static const int c[4] = {4, 2, 8, 308};
+    const int best = pick(c, 4, t.xdrop_ms, 4, [&](int code) {
+      ctx->force_xdrop_rows = code % 100;
+      ctx->force_xdrop_sides = code / 100 + 1;
       const double ms = run();
       ctx->force_xdrop_rows = 0;
+      ctx->force_xdrop_sides = 0;
       return ms;
     });
+    t.xdrop_rows = best % 100;
+    t.xdrop_sides = best / 100 + 1;
   } else if (local_full) {
     static const int c[4] = {16, 12, 8, 4};
     t.sw16_rows = pick(c, 4, t.sw16_ms, 16, [&](int r) {
@@ -157,8 +163,10 @@ aln_status aln_set_tuning(aln_ctx *ctx, const aln_tuning *tuning) {
   if (!ctx || !tuning) return ALN_E_INVAL;
   if (tuning->valid) {
     const int s = tuning->sw16_rows, r = tuning->strip_rows, x = tuning->xdrop_rows;
+    const int xs = tuning->xdrop_sides;
     if (!(s == 4 || s == 8 || s == 12 || s == 16) ||
-        !(r == 0 || r == 8 || r == 16 || r == 24 || r == 32) || !(x == 2 || x == 4 || x == 8))
+        !(r == 0 || r == 8 || r == 16 || r == 24 || r == 32) || !(x == 2 || x == 4 || x == 8) ||
+        !(xs == 1 || (xs == 4 && x == 8)))
       return alnrt::fail(ctx, ALN_E_INVAL, "tile choice outside the kernels' tiles");
   }
   ctx->tuning = *tuning;

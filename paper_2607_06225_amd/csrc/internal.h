@@ -126,6 +126,8 @@ hipError_t launch_strip(int rows, int mode, bool tb, bool small_alphabet,
 hipError_t launch_walk(int layout, const WalkArgs &a, hipStream_t s);
 hipError_t launch_sw16(int rows, const Sw16Args &a, hipStream_t s);
 hipError_t launch_diag(int rows, int mode, int prune, bool tb, const DiagArgs &a, hipStream_t s);
+// X-drop (EXTEND), four sides per wavefront, 8 diagonals per lane
+hipError_t launch_xdrop_group(const DiagArgs &a, hipStream_t s);
 hipError_t launch_walk_diag(const WalkArgs &a, hipStream_t s);
 
 } // namespace alnk

@@ -426,6 +426,279 @@ __global__ __launch_bounds__(256) void diag_kernel(DiagArgs a) {
     diag_task<RD, MODE, PRUNE, TB, MM>(a, task, wave, lane, smem, smat);
 }
 
+// ------------------------------------------------------------------
+// X-drop extension, four sides per wavefront.  Each 16-lane DPP row holds
+// one side's window of 16*RD diagonals (with RD = 8 the same 128 diagonals a
+// whole wavefront holds at two per lane), so a wavefront advances four sides
+// per antidiagonal and every lane evaluates RD/2 cells per step.  The step is
+// diag_task's for mode EXTEND with X-drop pruning; what that kernel keeps in
+// scalar registers per pair (window base, domain, best cell, survivors) is
+// here per row, in vector registers equal across the row's lanes.  Cross-lane
+// moves use row_shr / row_shl; row reductions a DPP butterfly.
+constexpr int kGroupSeq = 512; // LDS ring per sequence per side (bytes)
+
+__device__ __forceinline__ int dpp_rshr1(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, 0x111, 0xf, 0xf, false); // row_shr:1
+}
+__device__ __forceinline__ int dpp_rshl1(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, 0x101, 0xf, 0xf, false); // row_shl:1
+}
+// maximum over the 16 lanes of each row, in every lane of the row
+__device__ __forceinline__ int row_max_all(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xf, 0xf, false));  // quad_perm 1,0,3,2
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xf, 0xf, false));  // quad_perm 2,3,0,1
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xf, 0xf, false)); // row_ror:4
+  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xf, 0xf, false)); // row_ror:8
+  return v;
+}
+
+template <int RD, bool MM>
+__device__ void xdrop_group(const DiagArgs &a, int task4, int ntasks, int lane, uint8_t *smem,
+                            const int8_t *smat) {
+  static_assert(RD % 2 == 0, "a lane must hold whole diagonal pairs");
+  constexpr int G = 16;
+  constexpr int W = G * RD;
+  constexpr int HALF = RD / 2;
+  const int g = lane >> 4, gl = lane & 15;
+  const int task = task4 + g;
+  const bool has = task < ntasks;
+  const int p = has ? a.tasks[task].pair : -1;
+  const int M = has ? a.b.q_len[p] : 0;
+  const int N = has ? a.b.r_len[p] : 0;
+  const uint8_t *Q = has ? a.b.q + a.b.q_off[p] : nullptr;
+  const uint8_t *Rs = has ? a.b.r + a.b.r_off[p] : nullptr;
+  const int go = a.sc->gap_open, ge = a.sc->gap_extend, goe = go + ge;
+  const int A = a.sc->alphabet;
+  const int s_match = a.sc->match, s_mismatch = a.sc->mismatch;
+  aln_result *res = has ? a.res + p : nullptr;
+
+  bool alive = has && M > 0 && N > 0;
+  if (has && !alive && gl == 0) {
+    res->score = 0;
+    res->q_end = 0;
+    res->r_end = 0;
+    res->cells = 0;
+  }
+
+  uint8_t *qbuf = smem + (size_t)g * 2 * kGroupSeq;
+  uint8_t *rbuf = qbuf + kGroupSeq;
+  int qtop = 0, rtop = 0;
+  // each row's 16 lanes stage 64 codes per pass
+  auto stage = [&](const uint8_t *src, int len, uint8_t *buf, int &top, int need) {
+    while (alive && top < len && top <= need) {
+      const int base = top + gl * 4;
+      uint32_t w4 = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int idx = base + b;
+        const uint32_t c = (idx < len) ? (uint32_t)min((int)src[idx], A) : (uint32_t)A;
+        w4 |= c << (8 * b);
+      }
+      *reinterpret_cast<uint32_t *>(buf + (base & (kGroupSeq - 1))) = w4;
+      top += 64;
+    }
+  };
+
+  int H[RD], EN[RD], FN[RD];
+#pragma unroll
+  for (int x = 0; x < RD; ++x) { H[x] = NEG32; EN[x] = NEG32; FN[x] = NEG32; }
+  int dbase = -(W / 2);
+  const int e0 = gl * RD;
+  // write into the element of this row's window holding diagonal d
+  auto set_elem = [&](bool on, int d, int h, int en, int fn) {
+    const int e = d - dbase;
+    const bool in = on && e >= 0 && e < W && gl == e / RD;
+    const int x = e - gl * RD;
+#pragma unroll
+    for (int y = 0; y < RD; ++y)
+      if (in && y == x) { H[y] = h; EN[y] = en; FN[y] = fn; }
+  };
+  // window moves by two diagonals in the rows where `on`
+  auto shift_right2 = [&](bool on) { // dbase += 2
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+      const int h0 = dpp_rshl1(NEG32, H[0]), en0 = dpp_rshl1(NEG32, EN[0]), fn0 = dpp_rshl1(NEG32, FN[0]);
+      if (on) {
+#pragma unroll
+        for (int x = 0; x < RD - 1; ++x) { H[x] = H[x + 1]; EN[x] = EN[x + 1]; FN[x] = FN[x + 1]; }
+        H[RD - 1] = h0; EN[RD - 1] = en0; FN[RD - 1] = fn0;
+      }
+    }
+    if (on) dbase += 2;
+  };
+  auto shift_left2 = [&](bool on) { // dbase -= 2
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+      const int hl = dpp_rshr1(NEG32, H[RD - 1]), enl = dpp_rshr1(NEG32, EN[RD - 1]),
+                fnl = dpp_rshr1(NEG32, FN[RD - 1]);
+      if (on) {
+#pragma unroll
+        for (int x = RD - 1; x > 0; --x) { H[x] = H[x - 1]; EN[x] = EN[x - 1]; FN[x] = FN[x - 1]; }
+        H[0] = hl; EN[0] = enl; FN[0] = fnl;
+      }
+    }
+    if (on) dbase -= 2;
+  };
+
+  set_elem(alive, 0, 0, goe, goe);
+  int best = 0, best_i = 0, best_j = 0;
+  int lo = 0, hi = 0;
+  long long cells = 0;
+  bool overflow = false;
+  const int KMAX = M + N;
+  int kmax_w = KMAX; // longest side of the wavefront
+#pragma unroll
+  for (int q = 0; q < 4; ++q) kmax_w = max(kmax_w, __builtin_amdgcn_readlane(KMAX, q * 16));
+
+  auto step = [&](auto par_tag, const int k) {
+    constexpr int par = decltype(par_tag)::value;
+    if (k > KMAX) alive = false;
+    // ---- domain: one step around the last antidiagonal's survivors
+    const int mlo = max(-k, k - 2 * M), mhi = min(k, 2 * N - k);
+    const int dlo = max(lo - 1, mlo), dhi = min(hi + 1, mhi);
+    if (dlo > dhi) alive = false;
+    if (alive && dhi - dlo > W - 6) {
+      overflow = true;
+      alive = false;
+    }
+    // ---- keep the domain inside the window (rows needing it shift together)
+    while (__ballot(alive && dhi > dbase + W - 3)) shift_right2(alive && dhi > dbase + W - 3);
+    while (__ballot(alive && dlo < dbase + 2)) shift_left2(alive && dlo < dbase + 2);
+    // ---- stage codes
+    {
+      const int needq = ((k - dbase) >> 1) + 64;
+      const int needr = ((k + dbase + W) >> 1) + 64;
+      stage(Q, M, qbuf, qtop, min(needq, M + 64));
+      stage(Rs, N, rbuf, rtop, min(needr, N + 64));
+    }
+    int left_x = NEG32, right_x = NEG32;
+    if constexpr (par == 0) left_x = dpp_rshr1(NEG32, EN[RD - 1]);
+    else right_x = dpp_rshl1(NEG32, FN[0]);
+    const int elo = dlo - dbase, ehi = dhi - dbase;
+    const int thr = max(best - a.xdrop, NEG32 / 2 + 1);
+    int kkey = -1;
+    const int d0 = dbase + e0 + par;
+    const int i0 = (k - d0) >> 1, j0 = (k + d0) >> 1;
+#pragma unroll
+    for (int m = 0; m < HALF; ++m) {
+      const int x = 2 * m + par;
+      const int e = e0 + x;
+      const int left = (x == 0) ? left_x : EN[(x + RD - 1) % RD];
+      const int right = (x == RD - 1) ? right_x : FN[(x + 1) % RD];
+      const int i = i0 - m, j = j0 + m;
+      const int qc = qbuf[(i - 1) & (kGroupSeq - 1)];
+      const int rc = rbuf[(j - 1) & (kGroupSeq - 1)];
+      const int sv = MM ? (qc == rc ? s_match : s_mismatch) : smat[qc * kMaxAlphabet + rc];
+      const int hd = H[x] + sv;
+      const int h = max(max(hd, left), right);
+      const int t = h + goe;
+      const int en = max(left + ge, t);
+      const int fn = max(right + ge, t);
+      const bool keep = alive && (unsigned)(e - elo) <= (unsigned)(ehi - elo) && h >= thr;
+      H[x] = keep ? h : NEG32;
+      EN[x] = keep ? en : NEG32;
+      FN[x] = keep ? fn : NEG32;
+      const int key = keep ? ((max(h, -1) << 11) | e) : -1;
+      kkey = max(kkey, key);
+    }
+    // ---- boundary cells (i = 0 at d = k, j = 0 at d = -k)
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int d = side ? -k : k;
+      const bool inb = alive && d >= dlo && d <= dhi;
+      const int hb = go + k * ge;
+      const bool kb = hb >= thr;
+      set_elem(inb, d, kb ? hb : NEG32, kb ? hb + goe : NEG32, kb ? hb + goe : NEG32);
+      if (inb && kb && gl == 0) kkey = max(kkey, (max(hb, -1) << 11) | (d - dbase));
+    }
+    // ---- cells evaluated on this antidiagonal (i >= 1 and j >= 1)
+    if (alive) {
+      const int c_lo = max(dlo, 2 - k), c_hi = min(dhi, k - 2);
+      if (c_lo <= c_hi) cells += (c_hi - c_lo) / 2 + 1;
+    }
+    // ---- best cell of the antidiagonal (per row)
+    const int kb = row_max_all(kkey);
+    if (alive && kb >= 0) {
+      const int sc = kb >> 11;
+      const int d = dbase + (kb & 2047);
+      const int bi = (k - d) >> 1, bj = (k + d) >> 1;
+      if (better_end(sc, bi, bj, best, best_i, best_j)) { best = sc; best_i = bi; best_j = bj; }
+    }
+    // ---- first and last surviving diagonals of each row's window
+    int slo = 1 << 30, shi = -(1 << 30);
+#pragma unroll
+    for (int m = 0; m < HALF; ++m) {
+      const int x = 2 * m + par;
+      const unsigned long long bal = __ballot(H[x] > NEG32 / 2);
+      const uint32_t gb = (uint32_t)(bal >> (16 * g)) & 0xffffu;
+      if (gb) {
+        const int lf = __ffs((int)gb) - 1;
+        const int ll = 31 - __clz((int)gb);
+        slo = min(slo, dbase + lf * RD + x);
+        shi = max(shi, dbase + ll * RD + x);
+      }
+    }
+    if (slo > shi) alive = false; // every candidate pruned: the extension stops
+    if (alive) {
+      lo = slo;
+      hi = shi;
+    }
+  };
+  for (int k = 1; k <= kmax_w; k += 2) {
+    if (!__ballot(alive)) break;
+    step(std::integral_constant<int, 1>{}, k);
+    if (k + 1 > kmax_w || !__ballot(alive)) break;
+    step(std::integral_constant<int, 0>{}, k + 1);
+  }
+
+  if (has && gl == 0 && (M > 0 && N > 0)) {
+    if (overflow) {
+      res->flags |= ALN_F_WIDENED;
+      if (a.widen_rows > 0) {
+        const int slot = atomicAdd(a.widen_count, 1);
+        PairTask t = a.tasks[task];
+        t.rows = a.widen_rows;
+        a.widen[slot] = t;
+      } else {
+        res->status = ALN_R_TOO_WIDE;
+      }
+    } else {
+      res->score = best;
+      res->q_end = best_i;
+      res->r_end = best_j;
+      res->cells = cells;
+    }
+  }
+}
+
+template <int RD, bool MM>
+__global__ __launch_bounds__(256) void xdrop_group_kernel(DiagArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  int8_t *smat = reinterpret_cast<int8_t *>(smem + 4 * 4 * 2 * kGroupSeq);
+  const int A = a.sc->alphabet;
+  for (int k = threadIdx.x; k < kMaxAlphabet * kMaxAlphabet; k += blockDim.x) {
+    const int qa = k / kMaxAlphabet, rc = k % kMaxAlphabet;
+    smat[k] = (qa < A && rc < A) ? (int8_t)a.sc->mat[k] : (int8_t)-128;
+  }
+  __syncthreads();
+  const int ntasks = a.ntasks;
+  for (int t4 = (blockIdx.x * 4 + wave) * 4; t4 < ntasks; t4 += gridDim.x * 16)
+    xdrop_group<RD, MM>(a, t4, ntasks, lane, smem + (size_t)wave * 4 * 2 * kGroupSeq, smat);
+}
+
+hipError_t launch_xdrop_group(const DiagArgs &a, hipStream_t s) {
+  if (a.ntasks <= 0) return hipSuccess;
+  const size_t lds = (size_t)4 * 4 * 2 * kGroupSeq + kMaxAlphabet * kMaxAlphabet;
+  const int blocks = (a.ntasks + 15) / 16;
+  if (a.match_mismatch)
+    hipLaunchKernelGGL((xdrop_group_kernel<8, true>), dim3(blocks), dim3(256), lds, s, a);
+  else
+    hipLaunchKernelGGL((xdrop_group_kernel<8, false>), dim3(blocks), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
 template <int RD, int MODE, int PRUNE, bool TB>
 static hipError_t launch_diag_t(const DiagArgs &a, hipStream_t s) {
   const bool mm = a.match_mismatch != 0;

@@ -29,6 +29,7 @@ struct aln_ctx {
   int force_sw16_rows = 0;
   int force_strip_rows = -1;
   int force_xdrop_rows = 0;
+  int force_xdrop_sides = 0;
 };
 
 namespace alnrt {
@@ -45,6 +46,7 @@ struct LaunchDesc {
   int32_t count;
   int32_t lds_bnd;
   int32_t lds_prof;
+  int sides = 1; // X-drop: extension sides per wavefront
 };
 
 constexpr uint64_t kAlign = 256;

@@ -88,8 +88,18 @@ def xdrop_batch(rng, lengths, X, div=0.15, name="xd"):
                         name=name)
 
 
+XDROP_TILES = [(4, 1), (8, 4)]  # (diagonals per lane, extension sides per wavefront)
+
+
+def with_xdrop_tile(ctx, tile):
+    ctx.set_tuning({"sw16_rows": 16, "strip_rows": 0, "xdrop_rows": tile[0],
+                    "xdrop_sides": tile[1]})
+
+
+@pytest.mark.parametrize("tile", XDROP_TILES)
 @pytest.mark.parametrize("X", [0, 5, 20, 100, 400])
-def test_xdrop_edge_shapes(ctx, X):
+def test_xdrop_edge_shapes(ctx, X, tile):
+    with_xdrop_tile(ctx, tile)
     rng = np.random.default_rng(500 + X)
     lengths = [(0, 0), (0, 5), (5, 0), (1, 1), (3, 50), (50, 3)] + \
               [(int(rng.integers(1, 800)), int(rng.integers(1, 800))) for _ in range(60)]
@@ -98,7 +108,9 @@ def test_xdrop_edge_shapes(ctx, X):
     assert compare(b, res, None, oracle_batch(b)) == []
 
 
-def test_xdrop_identical_and_unrelated(ctx):
+@pytest.mark.parametrize("tile", XDROP_TILES)
+def test_xdrop_identical_and_unrelated(ctx, tile):
+    with_xdrop_tile(ctx, tile)
     rng = np.random.default_rng(9)
     qs, rs = [], []
     for L in (10, 200, 1000, 3000):
@@ -113,10 +125,13 @@ def test_xdrop_identical_and_unrelated(ctx):
     assert compare(b, res, None, oracle_batch(b)) == []
 
 
-def test_xdrop_widening_chain(ctx):
-    """A huge X keeps whole antidiagonals alive: regions wider than 256 and
-    1024 diagonals are recomputed with wider windows (flag WIDENED)."""
+@pytest.mark.parametrize("tile", XDROP_TILES)
+def test_xdrop_widening_chain(ctx, tile):
+    """A huge X keeps whole antidiagonals alive: regions wider than the first
+    window, then 1024 diagonals, are recomputed with wider windows (flag
+    WIDENED)."""
     from paper_2607_06225_amd import aln
+    with_xdrop_tile(ctx, tile)
     rng = np.random.default_rng(10)
     lengths = [(100, 100), (400, 420), (900, 880), (60, 700)]
     b = xdrop_batch(rng, lengths, 10 ** 6, name="xd_wide")
@@ -127,7 +142,9 @@ def test_xdrop_widening_chain(ctx):
     assert int(res["flags"][2]) & aln.F_WIDENED
 
 
-def test_xdrop_extension_workload_sample(ctx):
+@pytest.mark.parametrize("tile", XDROP_TILES)
+def test_xdrop_extension_workload_sample(ctx, tile):
+    with_xdrop_tile(ctx, tile)
     b = W.xdrop_ext(n=1500, seed=4040)
     res, _ = run(ctx, b)
     assert compare(b, res, None, oracle_batch(b)) == []

@@ -44,17 +44,21 @@ def test_autotune_strips_with_cigar(ctx):
 
 
 def test_autotune_xdrop(ctx):
-    tune_and_check(ctx, W.xdrop_ext(n=3000, seed=63), "xdrop", (2, 4, 8))
+    t = tune_and_check(ctx, W.xdrop_ext(n=3000, seed=63), "xdrop", (2, 4, 8))
+    assert t["xdrop_sides"] in (1, 4)
 
 
-@pytest.mark.parametrize("tile", [2, 8])
-def test_every_xdrop_start_window_is_bit_exact(ctx, tile):
+@pytest.mark.parametrize("tile,sides", [(2, 1), (8, 1), (8, 4)])
+def test_every_xdrop_start_window_is_bit_exact(ctx, tile, sides):
     from paper_2607_06225_amd import aln
-    b = W.xdrop_ext(n=1500, seed=70 + tile)
+    b = W.xdrop_ext(n=1500, seed=70 + tile + sides)
     sid = ctx.set_scoring(b.matrix, b.gap_open, b.gap_extend)
-    ctx.set_tuning({"sw16_rows": 16, "strip_rows": 0, "xdrop_rows": tile})
+    ctx.set_tuning({"sw16_rows": 16, "strip_rows": 0, "xdrop_rows": tile, "xdrop_sides": sides})
     res, _ = aln.align(ctx, b, scoring_id=sid)
     assert compare(b, res, None, oracle_batch(b)) == []
+    rp, _ = aln.align(ctx, b.subset(np.arange(0, b.n, 37)), scoring_id=sid, per_pair=True)
+    rb, _ = aln.align(ctx, b.subset(np.arange(0, b.n, 37)), scoring_id=sid)
+    assert np.array_equal(rp, rb)
 
 
 @pytest.mark.parametrize("tile", [8, 24])
@@ -72,6 +76,8 @@ def test_set_tuning_round_trip_and_validation(ctx):
     ctx.set_tuning({"sw16_rows": 8, "strip_rows": 24, "xdrop_rows": 2})
     got = ctx.tuning()
     assert got["valid"] and (got["sw16_rows"], got["strip_rows"], got["xdrop_rows"]) == (8, 24, 2)
-    for bad in ({"sw16_rows": 5}, {"strip_rows": 12}, {"xdrop_rows": 16}):
+    for bad in ({"sw16_rows": 5}, {"strip_rows": 12}, {"xdrop_rows": 16},
+                {"xdrop_rows": 4, "xdrop_sides": 4}, {"xdrop_sides": 2}):
         with pytest.raises(aln.AlnError):
-            ctx.set_tuning(dict({"sw16_rows": 16, "strip_rows": 0, "xdrop_rows": 4}, **bad))
+            ctx.set_tuning(dict({"sw16_rows": 16, "strip_rows": 0, "xdrop_rows": 8,
+                                 "xdrop_sides": 1}, **bad))
