@@ -236,8 +236,26 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
 // antidiagonal in the low nibbles, then those of the odd one.  Cell (i, j):
 // element e = (j - i) - dbase(k), lane e / RD, slot e mod RD.  A block is 64
 // antidiagonals: 16 KB of codes plus 64 window bases.
+//
+// The walk advances by whole runs.  The two most recent blocks (the one
+// holding the walk's antidiagonal and the one before) stay in two LDS slots,
+// and the next older block is in flight in registers.  Every lane m < 32
+// reads, in parallel, the code of the m-th cell ahead along the current move:
+//   state H  cells (i-m, j-m): the diagonal run ends at the first cell whose
+//            code does not choose the diagonal (one ballot); the run's '='
+//            and 'X' come from a second ballot of sequence comparisons;
+//   state E  cells (i, j-1-m): the gap ends at the first one whose code says
+//            E(i, j-m) opened there;
+//   state F  cells (i-1-m, j): likewise for the vertical gap.
+// All those cells lie within 63 antidiagonals of the current one, so within
+// the two resident blocks.
+constexpr int kLook = 32;
+
+__device__ __forceinline__ int ctz64(unsigned long long v) { return v ? __ffsll((long long)v) - 1 : 64; }
+
 __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
-  __shared__ __align__(16) uint4 codes4[kBlockBytes / 16];
+  __shared__ __align__(16) uint4 codes4[2][kBlockBytes / 16];
+  __shared__ int dbl[2][64];
   __shared__ uint8_t qwin[256], rwin[256];
   const int lane = threadIdx.x;
   const int task = blockIdx.x;
@@ -254,8 +272,8 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
   }
   if (status != ALN_R_OK) return;
   const int M = uni(a.b.q_len[p]), N = uni(a.b.r_len[p]);
-  SeqWindow qw{a.b.q + a.b.q_off[p], M, 1 << 30, qwin};
-  SeqWindow rw{a.b.r + a.b.r_off[p], N, 1 << 30, rwin};
+  const uint8_t *Qs = a.b.q + a.b.q_off[p];
+  const uint8_t *Rs = a.b.r + a.b.r_off[p];
   const int RD = uni(tk.rows);
   const int inv = (65536 + RD - 1) / RD; // e / RD = (e * inv) >> 16 for 0 <= e < 64*RD
   const int nk = M + N + 1;
@@ -264,37 +282,89 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
   const int *dbh = reinterpret_cast<const int *>(tbp);
   const uint4 *cod = reinterpret_cast<const uint4 *>(tbp + (size_t)((nk + 63) / 64) * 64 * 4);
   const bool local = a.mode == ALN_LOCAL;
-  const uint8_t *codes = reinterpret_cast<const uint8_t *>(codes4);
-  BlockCache bc;
 
+  // block cache: slots hold blocks cur and cur - 1; `pre` holds cur - 2
+  uint4 pre[kPre];
+  int pre_aux = 0, pre_blk = -1, cur = -1;
   auto fetch = [&](int b) {
-    const int pairs = min(32, nks - b * 32); // antidiagonal pairs of this block
-    load_block(bc, cod + (size_t)b * (kBlockBytes / 16), pairs * 32, b, dbh[b * 64 + lane], lane);
-  };
-  bool bad = false;
-  auto code = [&](int i, int j) -> int {
-    const int k = i + j;
-    const int b = k >> 6;
-    if (b != bc.cur_key) {
-      if (b != bc.pre_key) fetch(b);
-      bc.install(codes4, lane);
-      if (b > 0) fetch(b - 1);
+    const int pairs = min(32, nks - b * 32);
+    const uint4 *src = cod + (size_t)b * (kBlockBytes / 16);
+#pragma unroll
+    for (int m = 0; m < kPre; ++m) {
+      const int u = lane + 64 * m;
+      pre[m] = u < pairs * 32 ? src[u] : make_uint4(0u, 0u, 0u, 0u);
     }
-    const int e = (j - i) - __builtin_amdgcn_readlane(bc.cur_aux, k & 63);
+    pre_aux = dbh[b * 64 + lane];
+    pre_blk = b;
+  };
+  auto install = [&](int b) { // put block b (already fetched) into its slot
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kPre; ++m) codes4[b & 1][lane + 64 * m] = pre[m];
+    dbl[b & 1][lane] = pre_aux;
+    __syncthreads();
+  };
+  auto make_resident = [&](int b) { // blocks b and b - 1 resident, b - 2 in flight
+    if (b == cur) return;
+    if (b == cur - 1 && b >= 1) { // the common step: one block older
+      if (pre_blk != b - 1) fetch(b - 1);
+      install(b - 1);
+    } else { // first use, or a jump
+      fetch(b);
+      install(b);
+      if (b >= 1) {
+        fetch(b - 1);
+        install(b - 1);
+      }
+    }
+    cur = b;
+    if (b >= 2) fetch(b - 2);
+  };
+  const uint8_t *codes0 = reinterpret_cast<const uint8_t *>(codes4[0]);
+  // code of (ii, jj), any lane; the cell must lie in a resident block
+  auto code_at = [&](int ii, int jj, bool &bad_lane) -> int {
+    const int kk = ii + jj;
+    const int slot = (kk >> 6) & 1;
+    const int e = (jj - ii) - dbl[slot][kk & 63];
     if ((unsigned)e >= (unsigned)(64 * RD)) {
-      bad = true;
+      bad_lane = true;
       return 0;
     }
     const int ln = (e * inv) >> 16;
     const int x = e - ln * RD;
-    const int pos = (k & 1) * (RD >> 1) + (x >> 1);
-    const int byte = ((k >> 1) & 31) * 512 + ln * 8 + (pos >> 1);
-    return uni((codes[byte] >> ((pos & 1) * 4)) & 15);
+    const int pos = (kk & 1) * (RD >> 1) + (x >> 1);
+    const int byte = slot * kBlockBytes + ((kk >> 1) & 31) * 512 + ln * 8 + (pos >> 1);
+    return (codes0[byte] >> ((pos & 1) * 4)) & 15;
+  };
+  // sequence windows covering the next kLook + 1 positions below i and j
+  int qbase = 1 << 30, rbase = 1 << 30;
+  auto cover = [&](const uint8_t *src, int len, uint8_t *win, int &base, int lo, int hi) {
+    if (lo >= base && hi < base + 256) return;
+    base = max(0, hi - 255);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int pidx = base + lane * 4 + t;
+      win[lane * 4 + t] = pidx < len ? src[pidx] : 0;
+    }
+    __syncthreads();
   };
 
   int i = i_end, j = j_end;
   WaveCigar cw{a.cigar + tk.cigar_off, tk.cigar_cap, -1, 0, false};
+  auto emit_n = [&](int op, int n) {
+    if (n <= 0) return;
+    if (op == cw.cur) {
+      cw.run += n;
+      return;
+    }
+    cw.flush(lane);
+    cw.cur = op;
+    cw.run = n;
+  };
   int state = 0;
+  bool bad = false;
+  const unsigned long long look_mask = (1ull << kLook) - 1;
   for (int guard = 2 * (i_end + j_end) + 2; guard > 0 && !bad; --guard) {
     if ((state == 1 && j < 1) || (state == 2 && i < 1) || i < 0 || j < 0) {
       bad = true;
@@ -303,26 +373,91 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
     if (state == 0) {
       if (i == 0 && j == 0) break;
       if (local && (i == 0 || j == 0)) break;
-      if (i == 0) { cw.emit(ALN_OP_D, lane); --j; continue; }
-      if (j == 0) { cw.emit(ALN_OP_I, lane); --i; continue; }
-      const int hs = code(i, j) & 3;
-      if (local && hs == 3) break;
-      if (hs == 0) {
-        cw.emit(qw.get(i - 1, lane) == rw.get(j - 1, lane) ? ALN_OP_EQ : ALN_OP_X, lane);
-        --i;
-        --j;
-      } else {
-        state = hs;
+      if (i == 0) { emit_n(ALN_OP_D, j); j = 0; continue; }
+      if (j == 0) { emit_n(ALN_OP_I, i); i = 0; continue; }
+      make_resident((i + j) >> 6);
+      cover(Qs, M, qwin, qbase, max(0, i - 1 - kLook), i - 1);
+      cover(Rs, N, rwin, rbase, max(0, j - 1 - kLook), j - 1);
+      // lanes m < kLook: the cell m steps up the diagonal
+      const int ii = i - lane, jj = j - lane;
+      const bool valid = lane < kLook && ii >= 1 && jj >= 1;
+      bool bl = false;
+      const int c = valid ? code_at(ii, jj, bl) : 0;
+      const int hs = c & 3;
+      const bool diag = valid && !bl && hs == 0;
+      const unsigned long long badm = __ballot(valid && bl);
+      if (badm & 1ull) { bad = true; break; }
+      const int L = min(ctz64(~__ballot(diag) & look_mask), kLook); // diagonal run length
+      if (L == 0) {
+        const int hs0 = uni(hs);
+        if (local && hs0 == 3) break;
+        state = hs0; // 1: E, 2: F
+        continue;
       }
+      if (badm & ((1ull << L) - 1)) { bad = true; break; }
+      // '=' / 'X' of the run, first step of the walk first
+      const bool mism = lane < L && qwin[ii - 1 - qbase] != rwin[jj - 1 - rbase];
+      unsigned long long mm = __ballot(mism) & ((1ull << L) - 1);
+      int pos = 0;
+      while (pos < L) {
+        const bool x = (mm >> pos) & 1ull;
+        const unsigned long long rest = (x ? ~mm : mm) >> pos;
+        const int run = min(ctz64(rest), L - pos);
+        emit_n(x ? ALN_OP_X : ALN_OP_EQ, run);
+        pos += run;
+      }
+      i -= L;
+      j -= L;
     } else if (state == 1) {
-      // the code of (i, j-1) says whether E(i, j) opened from H(i, j-1)
-      cw.emit(ALN_OP_D, lane);
-      if (code(i, j - 1) & 4) state = 0;
-      --j;
+      // D moves from (i, j): E(i, j-m) opened from H(i, j-1-m) per code(i, j-1-m)
+      make_resident((i + j) >> 6);
+      const int jj = j - 1 - lane;
+      const bool valid = lane < kLook && jj >= 0;
+      bool bl = false;
+      const int c = valid ? code_at(i, jj, bl) : 0;
+      const bool open = valid && !bl && (c & 4);
+      if (__ballot(valid && bl)) {
+        // a bad code ahead: only a concern if the gap reaches it
+        const int first_bad = ctz64(__ballot(valid && bl));
+        const int first_open = ctz64(__ballot(open));
+        if (first_bad <= first_open) { bad = true; break; }
+      }
+      const unsigned long long om = __ballot(open) & look_mask;
+      if (om) {
+        const int n = ctz64(om) + 1;
+        emit_n(ALN_OP_D, n);
+        j -= n;
+        state = 0;
+      } else {
+        const int n = min(kLook, j);
+        if (n < kLook) { bad = true; break; } // the gap must open by column 0
+        emit_n(ALN_OP_D, n);
+        j -= n;
+      }
     } else {
-      cw.emit(ALN_OP_I, lane);
-      if (code(i - 1, j) & 8) state = 0;
-      --i;
+      make_resident((i + j) >> 6);
+      const int ii = i - 1 - lane;
+      const bool valid = lane < kLook && ii >= 0;
+      bool bl = false;
+      const int c = valid ? code_at(ii, j, bl) : 0;
+      const bool open = valid && !bl && (c & 8);
+      if (__ballot(valid && bl)) {
+        const int first_bad = ctz64(__ballot(valid && bl));
+        const int first_open = ctz64(__ballot(open));
+        if (first_bad <= first_open) { bad = true; break; }
+      }
+      const unsigned long long om = __ballot(open) & look_mask;
+      if (om) {
+        const int n = ctz64(om) + 1;
+        emit_n(ALN_OP_I, n);
+        i -= n;
+        state = 0;
+      } else {
+        const int n = min(kLook, i);
+        if (n < kLook) { bad = true; break; }
+        emit_n(ALN_OP_I, n);
+        i -= n;
+      }
     }
   }
   cw.flush(lane);
