@@ -155,16 +155,21 @@ typedef struct {
  * (diagonals per lane, and extension sides per wavefront: 1 side over all
  * 64 lanes, or 4 sides of 16 lanes each).  Each ms[] entry is the measured
  * time of one candidate on the tuning batch (0: not measured, negative: not
- * runnable).  While `valid`, aln_plan_create uses the chosen tiles.  Tiles
- * never change results. */
+ * runnable).  While `valid`, aln_plan_create uses the chosen tiles.
+ * sw16_wide_pct sets when the packed kernel gives a pair-of-pairs a whole
+ * 64-lane wavefront (64*R-row strips) instead of a 16-lane group: when the
+ * task's serial column steps exceed that percent of the launch's balanced
+ * load per wavefront slot (0: the default, 80; -1: never).  Tiles never
+ * change results. */
 typedef struct {
   int32_t valid;
   int32_t sw16_rows;      /* 4, 8, 12 or 16                                   */
   int32_t strip_rows;     /* 0 (per pair), 8, 16, 24 or 32                    */
   int32_t xdrop_rows;     /* 2, 4 or 8                                        */
   int32_t xdrop_sides;    /* 1, or 4 (with xdrop_rows 8)                      */
-  int32_t reserved;
-  double sw16_ms[4];      /* candidates 16, 12, 8, 4                          */
+  int32_t sw16_wide_pct;  /* 0 (default 80), -1 (never) or 1..10000          */
+  double sw16_ms[4];      /* candidates 16, 12, 8, 4 (each: best of the wide
+                             thresholds 25, 40, 60, 80 it was timed with)    */
   double strip_ms[5];     /* candidates 0, 8, 16, 24, 32                      */
   double xdrop_ms[4];     /* candidates 4x1, 2x1, 8x1, 8x4 (rows x sides)     */
 } aln_tuning;             /* 128 bytes */

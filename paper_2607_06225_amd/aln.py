@@ -84,7 +84,7 @@ assert COMPLETION_DTYPE.itemsize == 104
 class _Tuning(ctypes.Structure):
     _fields_ = [("valid", ctypes.c_int32), ("sw16_rows", ctypes.c_int32),
                 ("strip_rows", ctypes.c_int32), ("xdrop_rows", ctypes.c_int32),
-                ("xdrop_sides", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("xdrop_sides", ctypes.c_int32), ("sw16_wide_pct", ctypes.c_int32),
                 ("sw16_ms", ctypes.c_double * 4), ("strip_ms", ctypes.c_double * 5),
                 ("xdrop_ms", ctypes.c_double * 4)]
 
@@ -285,7 +285,7 @@ class Context:
         self._check(self.lib.aln_get_tuning(self.handle, ctypes.byref(t)))
         return {"valid": bool(t.valid), "sw16_rows": int(t.sw16_rows),
                 "strip_rows": int(t.strip_rows), "xdrop_rows": int(t.xdrop_rows),
-                "xdrop_sides": int(t.xdrop_sides),
+                "xdrop_sides": int(t.xdrop_sides), "sw16_wide_pct": int(t.sw16_wide_pct),
                 "sw16_ms": dict(zip(SW16_TILES, map(float, t.sw16_ms))),
                 "strip_ms": dict(zip(STRIP_TILES, map(float, t.strip_ms))),
                 "xdrop_ms": dict(zip(XDROP_TILES, map(float, t.xdrop_ms)))}
@@ -297,6 +297,7 @@ class Context:
         t.strip_rows = int(tuning.get("strip_rows", 0))
         t.xdrop_rows = int(tuning.get("xdrop_rows", 4))
         t.xdrop_sides = int(tuning.get("xdrop_sides", 1))
+        t.sw16_wide_pct = int(tuning.get("sw16_wide_pct", 0))
         self._check(self.lib.aln_set_tuning(self.handle, ctypes.byref(t)))
 
     def set_profiling(self, enable):

@@ -106,6 +106,12 @@ aln_status aln_create(aln_ctx **ctx, int32_t device) {
   aln_ctx *c = new (std::nothrow) aln_ctx;
   if (!c) return ALN_E_NOMEM;
   c->device = device;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && v > 0)
+    c->cus = v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) ==
+          hipSuccess && v > 0)
+    c->lds_per_cu = v;
   *ctx = c;
   return ALN_OK;
 }
@@ -251,7 +257,7 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
   const int32_t rerun_prof = small ? 0 : (int32_t)align_up((uint64_t)hs.alphabet * 64 * rerun_rows, 16);
   const bool use_sw16 = p.mode == ALN_LOCAL && p.prune == ALN_FULL && !p.want_cigar &&
                         p.width != ALN_W_I32 && n > 0 && hs.alphabet < alnk::kMaxAlphabet &&
-                        maxN <= 65534 && maxM < (1 << 20) &&
+                        maxN <= 65535 - 63 && maxM < (1 << 20) &&
                         4LL * (rerun_bnd + rerun_prof) <= 160 * 1024;
   if (use_sw16) {
     // rows per lane: forced while the autotuner measures, else the
@@ -263,64 +269,135 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
       if (r == 4 || r == 8 || r == 12 || r == 16) tile = r;
     }
     if (ctx->force_sw16_rows) tile = ctx->force_sw16_rows;
-    std::vector<int> prow(n, tile);
-    pl->sw16_rows = prow.empty() ? 16 : prow[0];
+    const int R = tile;
+    pl->sw16_rows = R;
+    const int32_t HS = 16 * R, HW = 64 * R; // strip heights: 16-lane group, wide item
+    auto nstr = [](int32_t m, int32_t hs) { return (m + hs - 1) / hs; };
+    // pairs sorted by strips, then columns, longest first; consecutive
+    // pairs share a task (the two 16-bit halves), so the halves match
     std::vector<int32_t> order(n);
     for (int32_t i = 0; i < n; ++i) order[i] = i;
-    auto nstr = [&](int32_t i) { return (pl->qlen[i] + 16 * prow[i] - 1) / (16 * prow[i]); };
-    // buckets by tile (largest tile first), longest work first inside one
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-      if (prow[a] != prow[b]) return prow[a] > prow[b];
-      const int sa = nstr(a), sb = nstr(b);
+      const int sa = nstr(pl->qlen[a], HS), sb = nstr(pl->qlen[b], HS);
       if (sa != sb) return sa > sb;
       return pl->rlen[a] > pl->rlen[b];
     });
+    struct TaskDim {
+      int32_t pa, pb, mmax, nmax;
+    };
+    std::vector<TaskDim> td;
+    for (int32_t q = 0; q < n; q += 2) {
+      TaskDim t{order[q], q + 1 < n ? order[q + 1] : -1, pl->qlen[order[q]], pl->rlen[order[q]]};
+      if (t.pb >= 0) {
+        t.mmax = std::max(t.mmax, pl->qlen[t.pb]);
+        t.nmax = std::max(t.nmax, pl->rlen[t.pb]);
+      }
+      td.push_back(t);
+    }
+    const int32_t nt = (int32_t)td.size();
+    // Serial column steps of one wavefront: a group of four tasks on 16-lane
+    // groups runs the largest strip count times the widest reference (plus
+    // the lane skew); a wide item runs one task in 64*R-row strips.
+    auto steps_narrow = [&](const std::vector<int32_t> &grp) {
+      int32_t ns = 0, nm = 0;
+      for (int32_t k : grp) {
+        ns = std::max(ns, nstr(td[k].mmax, HS));
+        nm = std::max(nm, td[k].nmax);
+      }
+      return (int64_t)ns * (nm + 15);
+    };
+    auto steps_wide = [&](int32_t k) { return (int64_t)nstr(td[k].mmax, HW) * (td[k].nmax + 63); };
+    // Load model: one wavefront per item; LDS bounds the wavefronts per CU.
+    // A lone wavefront keeps its SIMD about 4/5 busy, so a second one on the
+    // same SIMD adds about a quarter of a wavefront's rate.
+    const size_t lds16 = alnk::sw16_lds_bytes(R, hs.alphabet);
+    const int wpc = (int)std::max<size_t>(1, std::min<size_t>(16, (size_t)ctx->lds_per_cu / lds16));
+    const double capacity =
+        (double)ctx->cus * (std::min(wpc, 4) + 0.25 * std::min(std::max(wpc - 4, 0), 4));
+    int64_t total = 0;
+    for (int32_t k = 0; k < nt; k += 4) {
+      std::vector<int32_t> grp;
+      for (int32_t q = k; q < std::min(nt, k + 4); ++q) grp.push_back(q);
+      total += steps_narrow(grp);
+    }
+    // A task whose own strips take longer than most of a wave slot's share
+    // of the launch would finish last: it runs wide.
+    int wide_pct = ctx->tuning.valid && ctx->tuning.sw16_wide_pct ? ctx->tuning.sw16_wide_pct : 80;
+    if (ctx->force_sw16_wide_pct) wide_pct = ctx->force_sw16_wide_pct;
+    const double wide_above =
+        wide_pct < 0 ? 1e300 : wide_pct / 100.0 * (double)total / capacity;
+    struct Item {
+      int64_t steps;
+      std::vector<int32_t> tasks;
+      bool wide;
+    };
+    std::vector<Item> items;
+    std::vector<int32_t> grp;
+    auto close_group = [&] {
+      if (grp.empty()) return;
+      items.push_back(Item{steps_narrow(grp), grp, false});
+      grp.clear();
+    };
+    for (int32_t k = 0; k < nt; ++k) {
+      if ((double)nstr(td[k].mmax, HS) * (td[k].nmax + 15) > wide_above) {
+        items.push_back(Item{steps_wide(k), {k}, true});
+        continue;
+      }
+      grp.push_back(k);
+      if (grp.size() == 4) close_group();
+    }
+    close_group();
+    // longest item first: workgroups are dispatched in index order
+    std::stable_sort(items.begin(), items.end(),
+                     [](const Item &a, const Item &b) { return a.steps > b.steps; });
+    pl->sw16_wide = 0;
     uint64_t bnd_bytes = 0;
     std::vector<uint64_t> bnd_rel;
-    for (int32_t k = 0; k < n;) {
-      const int R = prow[order[k]];
-      LaunchDesc L{};
-      L.kind = K_SW16;
-      L.rows = R;
-      L.mode = ALN_LOCAL;
-      L.first = (int32_t)pl->sw16_tasks.size();
-      int32_t e = k;
-      while (e < n && prow[order[e]] == R) ++e;
-      for (int32_t q = k; q < e; q += 2) {
+    LaunchDesc L{};
+    L.kind = K_SW16;
+    L.rows = R;
+    L.mode = ALN_LOCAL;
+    L.first = 0;
+    for (const Item &it : items) {
+      pl->sw16_items.push_back(
+          alnk::Sw16Item{(int32_t)pl->sw16_tasks.size(), it.wide ? -1 : (int32_t)it.tasks.size()});
+      pl->sw16_wide += it.wide;
+      for (int32_t k : it.tasks) {
+        const TaskDim &d = td[k];
         alnk::Sw16Task t;
-        t.pa = order[q];
-        t.pb = (q + 1 < e) ? order[q + 1] : -1;
-        t.nstrips = nstr(t.pa);
-        t.nmax = pl->rlen[t.pa];
-        if (t.pb >= 0) {
-          t.nstrips = std::max(t.nstrips, nstr(t.pb));
-          t.nmax = std::max(t.nmax, pl->rlen[t.pb]);
-        }
+        t.pa = d.pa;
+        t.pb = d.pb;
+        t.nstrips = nstr(d.mmax, it.wide ? HW : HS);
+        t.nmax = d.nmax;
         t.bnd_off = 0;
         bnd_rel.push_back(t.nstrips > 1 ? bnd_bytes : ~0ULL);
         if (t.nstrips > 1) bnd_bytes += align_up((uint64_t)(t.nmax + 1) * 8);
         pl->sw16_tasks.push_back(t);
-        // the same pairs one by one (per-pair runs), sharing the boundary row
+        // the same pairs one by one (per-pair runs, always wide), sharing the
+        // task's boundary row: a pair alone never has more strips, nor more
+        // columns, than its task
         for (int h = 0; h < 2; ++h) {
           const int32_t pp = h ? t.pb : t.pa;
           if (pp < 0) continue;
           alnk::Sw16Task u;
           u.pa = pp;
           u.pb = -1;
-          u.nstrips = nstr(pp);
+          u.nstrips = nstr(pl->qlen[pp], HW);
           u.nmax = pl->rlen[pp];
           u.bnd_off = (int64_t)(pl->sw16_tasks.size() - 1); // task index, resolved below
           pl->sw16_single.push_back(u);
           pl->sw16_single_rows.push_back(R);
         }
       }
-      L.count = (int32_t)pl->sw16_tasks.size() - L.first;
-      pl->launches.push_back(L);
-      k = e;
     }
-    // workspace: [sw16 tasks | single tasks | rerun counter | rerun queue | boundary rows]
+    L.count = (int32_t)pl->sw16_tasks.size();
+    pl->launches.push_back(L);
+    // workspace: [sw16 tasks | items | single tasks | rerun counter | rerun queue |
+    //             boundary rows]
     pl->sw16_off = 0;
-    pl->sw16_single_off = align_up(sizeof(alnk::Sw16Task) * pl->sw16_tasks.size());
+    pl->sw16_items_off = align_up(sizeof(alnk::Sw16Task) * pl->sw16_tasks.size());
+    pl->sw16_single_off =
+        pl->sw16_items_off + align_up(sizeof(alnk::Sw16Item) * pl->sw16_items.size());
     pl->rerun_cnt_off = pl->sw16_single_off + align_up(sizeof(alnk::Sw16Task) * pl->sw16_single.size());
     pl->rerun_off = pl->rerun_cnt_off + kAlign;
     const uint64_t bnd_base = pl->rerun_off + align_up(sizeof(PairTask) * (size_t)n);
@@ -500,6 +577,8 @@ void alnrt::plan_stage(const aln_plan *pl, void *dst) {
   uint8_t *d = static_cast<uint8_t *>(dst);
   if (!pl->sw16_tasks.empty()) {
     memcpy(d + pl->sw16_off, pl->sw16_tasks.data(), sizeof(alnk::Sw16Task) * pl->sw16_tasks.size());
+    memcpy(d + pl->sw16_items_off, pl->sw16_items.data(),
+           sizeof(alnk::Sw16Item) * pl->sw16_items.size());
     memcpy(d + pl->sw16_single_off, pl->sw16_single.data(),
            sizeof(alnk::Sw16Task) * pl->sw16_single.size());
   } else if (!pl->tasks.empty()) {
@@ -592,6 +671,8 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
         if (L.kind != K_SW16) continue;
         a16.tasks = reinterpret_cast<const alnk::Sw16Task *>(ws + plan->sw16_off) + L.first;
         a16.ntasks = L.count;
+        a16.items = reinterpret_cast<const alnk::Sw16Item *>(ws + plan->sw16_items_off);
+        a16.nitems = (int32_t)plan->sw16_items.size();
         HIP_TRY(ctx, timed_launch(ctx, "sw16", st, [&] {
                   return alnk::launch_sw16(L.rows, a16, st);
                 }));
@@ -600,6 +681,8 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
       for (size_t k = 0; k < plan->sw16_single.size(); ++k) {
         a16.tasks = reinterpret_cast<const alnk::Sw16Task *>(ws + plan->sw16_single_off) + k;
         a16.ntasks = 1;
+        a16.items = nullptr;
+        a16.nitems = 0;
         HIP_TRY(ctx, alnk::launch_sw16(plan->sw16_single_rows[k], a16, st));
       }
     }

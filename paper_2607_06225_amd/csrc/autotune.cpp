@@ -129,13 +129,27 @@ aln_status aln_autotune(aln_ctx *ctx, int32_t scoring_id, const aln_params *para
     t.xdrop_rows = best % 100;
     t.xdrop_sides = best / 100 + 1;
   } else if (local_full) {
+    // rows per lane x the wide-item threshold; sw16_ms keeps each tile's
+    // best time over the thresholds
     static const int c[4] = {16, 12, 8, 4};
+    static const int wp[4] = {25, 40, 60, 80};
+    int wide_of[17] = {0};
     t.sw16_rows = pick(c, 4, t.sw16_ms, 16, [&](int r) {
+      double wms[4];
       ctx->force_sw16_rows = r;
-      const double ms = run();
+      wide_of[r] = pick(wp, 4, wms, 80, [&](int pct) {
+        ctx->force_sw16_wide_pct = pct;
+        const double ms = run();
+        ctx->force_sw16_wide_pct = 0;
+        return ms;
+      });
       ctx->force_sw16_rows = 0;
+      double ms = -1.0;
+      for (double x : wms)
+        if (x > 0 && (ms < 0 || x < ms)) ms = x;
       return ms;
     });
+    t.sw16_wide_pct = wide_of[t.sw16_rows] ? wide_of[t.sw16_rows] : 80;
   } else if (p.prune == ALN_FULL) {
     static const int c[5] = {0, 8, 16, 24, 32};
     t.strip_rows = pick(c, 5, t.strip_ms, 0, [&](int r) {
@@ -163,10 +177,10 @@ aln_status aln_set_tuning(aln_ctx *ctx, const aln_tuning *tuning) {
   if (!ctx || !tuning) return ALN_E_INVAL;
   if (tuning->valid) {
     const int s = tuning->sw16_rows, r = tuning->strip_rows, x = tuning->xdrop_rows;
-    const int xs = tuning->xdrop_sides;
+    const int xs = tuning->xdrop_sides, w = tuning->sw16_wide_pct;
     if (!(s == 4 || s == 8 || s == 12 || s == 16) ||
         !(r == 0 || r == 8 || r == 16 || r == 24 || r == 32) || !(x == 2 || x == 4 || x == 8) ||
-        !(xs == 1 || (xs == 4 && x == 8)))
+        !(xs == 1 || (xs == 4 && x == 8)) || w < -1 || w > 10000)
       return alnrt::fail(ctx, ALN_E_INVAL, "tile choice outside the kernels' tiles");
   }
   ctx->tuning = *tuning;

@@ -84,15 +84,31 @@ struct ValidateArgs {
 // Two pairs aligned by one 16-lane group of the packed int16 kernel.
 struct Sw16Task {
   int32_t pa, pb;    // pair indices (pb = -1: none)
-  int32_t nstrips;   // 16*R-row strips of the taller pair
+  int32_t nstrips;   // strips of the taller pair (16*R or, in a wide item, 64*R rows)
   int32_t nmax;      // max(N_a, N_b)
   int64_t bnd_off;   // byte offset of the group's strip-boundary row in ws
 };
+
+// One wavefront's work in the packed kernel: `count` (1..4) tasks on 16-lane
+// groups, or (count < 0) the single task `first` on all 64 lanes.
+struct Sw16Item {
+  int32_t first;
+  int32_t count;
+};
+
+// LDS of one packed-kernel workgroup: eight pairs' int8 profiles of
+// (alphabet + 1) letters x 16 lanes x R rows (equally two pairs x 64 lanes),
+// then the 32x32 int8 substitution matrix.
+inline size_t sw16_lds_bytes(int rows, int alphabet) {
+  return (size_t)8 * (alphabet + 1) * 16 * rows + kMaxAlphabet * kMaxAlphabet;
+}
 
 struct Sw16Args {
   BatchPtrs b;
   const Sw16Task *tasks;
   int32_t ntasks;
+  const Sw16Item *items;   // work items, one per workgroup; null: every task wide
+  int32_t nitems;
   const DevScoring *sc;
   int32_t sc_alphabet;     // host copy of the alphabet (LDS sizing)
   uint8_t *ws;

@@ -12,6 +12,8 @@
 
 struct aln_ctx {
   int device = 0;
+  int cus = 256;                // compute units, and LDS bytes per CU (planner's load model)
+  int lds_per_cu = 160 * 1024;
   std::string err;
   std::vector<alnk::DevScoring *> dsc; // device copies, owned
   std::vector<alnk::DevScoring> hsc;   // host mirrors
@@ -30,6 +32,7 @@ struct aln_ctx {
   int force_strip_rows = -1;
   int force_xdrop_rows = 0;
   int force_xdrop_sides = 0;
+  int force_sw16_wide_pct = 0;
 };
 
 namespace alnrt {
@@ -69,8 +72,10 @@ struct aln_plan {
   std::vector<alnk::Sw16Task> sw16_tasks;    // two pairs per task
   std::vector<alnk::Sw16Task> sw16_single;   // one pair per task (per-pair runs)
   std::vector<int> sw16_single_rows;         // tile of each single task
+  std::vector<alnk::Sw16Item> sw16_items;    // one wavefront each, longest first
+  int32_t sw16_wide = 0;                     // items running one task on 64 lanes
   int sw16_rows = 16;
-  uint64_t sw16_off = 0, sw16_single_off = 0, rerun_cnt_off = 0, rerun_off = 0;
+  uint64_t sw16_off = 0, sw16_items_off = 0, sw16_single_off = 0, rerun_cnt_off = 0, rerun_off = 0;
   alnrt::LaunchDesc rerun{};
   // X-drop widening queues: counters (ws offset) and two queues of n tasks
   uint64_t widen_cnt_off = 0, widen_off[2] = {0, 0};

@@ -145,3 +145,30 @@ def test_sw16_every_row_tile_is_bit_exact(ctx, rows, monkeypatch):
     res, _ = run(ctx, b)
     ores = oracle_batch(b)
     assert compare(b, res, None, ores) == []
+
+
+EDGE_W = [1, 63, 64, 65, 255, 256, 257, 700, 1023, 1024, 1025, 1536, 2000]
+
+
+@pytest.mark.parametrize("rows", [4, 16])
+@pytest.mark.parametrize("wide_pct", [-1, 1, 0])
+def test_sw16_narrow_and_wide_items_are_bit_exact(ctx, rows, wide_pct):
+    """Work items on four 16-lane groups (wide_pct -1: every item), on one
+    64-lane wavefront (wide_pct 1: every long task) and the planner's mix
+    give the oracle's results, over lengths at and around the strip heights
+    of both forms; per-pair launches (always wide) agree."""
+    rng = np.random.default_rng(900 + rows)
+    lengths = [(int(rng.choice(EDGE_W)), int(rng.choice(EDGE_W))) for _ in range(61)]
+    lengths += [(2000, 2000), (1025, 3), (3, 1025), (1, 1), (0, 7)]
+    b = local_batch(W.protein_matrix(11), -11, -1, lengths, 20, 950 + rows, name="sw16_items")
+    ctx.set_tuning({"sw16_rows": rows, "strip_rows": 0, "xdrop_rows": 4, "sw16_wide_pct": wide_pct})
+    try:
+        res, _ = run(ctx, b)
+        assert compare(b, res, None, oracle_batch(b)) == []
+        sub = b.subset(np.arange(0, b.n, 5))
+        rpp, _ = run(ctx, sub, per_pair=True)
+        rb, _ = run(ctx, sub)
+        for k in ("score", "q_end", "r_end", "cells", "status"):
+            assert np.array_equal(rpp[k], rb[k]), k
+    finally:
+        ctx.set_tuning({"valid": False})

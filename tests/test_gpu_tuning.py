@@ -36,7 +36,8 @@ def tune_and_check(ctx, b, family, tiles):
 
 
 def test_autotune_packed_sw(ctx):
-    tune_and_check(ctx, W.sw_protein(n=3000, seed=61), "sw16", (4, 8, 12, 16))
+    t = tune_and_check(ctx, W.sw_protein(n=3000, seed=61), "sw16", (4, 8, 12, 16))
+    assert t["sw16_wide_pct"] in (25, 40, 60, 80)
 
 
 def test_autotune_strips_with_cigar(ctx):
@@ -73,11 +74,13 @@ def test_every_fixed_strip_tile_is_bit_exact(ctx, tile):
 
 def test_set_tuning_round_trip_and_validation(ctx):
     from paper_2607_06225_amd import aln
-    ctx.set_tuning({"sw16_rows": 8, "strip_rows": 24, "xdrop_rows": 2})
+    ctx.set_tuning({"sw16_rows": 8, "strip_rows": 24, "xdrop_rows": 2, "sw16_wide_pct": 150})
     got = ctx.tuning()
-    assert got["valid"] and (got["sw16_rows"], got["strip_rows"], got["xdrop_rows"]) == (8, 24, 2)
+    assert got["valid"] and (got["sw16_rows"], got["strip_rows"], got["xdrop_rows"],
+                             got["sw16_wide_pct"]) == (8, 24, 2, 150)
     for bad in ({"sw16_rows": 5}, {"strip_rows": 12}, {"xdrop_rows": 16},
-                {"xdrop_rows": 4, "xdrop_sides": 4}, {"xdrop_sides": 2}):
+                {"xdrop_rows": 4, "xdrop_sides": 4}, {"xdrop_sides": 2},
+                {"sw16_wide_pct": -2}, {"sw16_wide_pct": 10001}):
         with pytest.raises(aln.AlnError):
             ctx.set_tuning(dict({"sw16_rows": 16, "strip_rows": 0, "xdrop_rows": 8,
                                  "xdrop_sides": 1}, **bad))
