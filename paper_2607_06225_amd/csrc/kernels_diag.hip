@@ -35,6 +35,10 @@
 namespace alnk {
 
 constexpr int kSeqBuf = 2048; // circular LDS staging of sequence codes (per wave)
+// Each ring is followed by a copy of its first kSeqMirror bytes, so a window
+// of a few dwords read at any 4-aligned ring position never wraps.
+constexpr int kSeqMirror = 32;
+constexpr int kSeqStride = kSeqBuf + kSeqMirror;
 
 __device__ __forceinline__ int dpp_wshr1(int old, int v) {
   return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xf, 0xf, false);
@@ -132,8 +136,8 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
     return;
   }
 
-  uint8_t *qbuf = smem + (size_t)wave * 2 * kSeqBuf;
-  uint8_t *rbuf = qbuf + kSeqBuf;
+  uint8_t *qbuf = smem + (size_t)wave * 2 * kSeqStride;
+  uint8_t *rbuf = qbuf + kSeqStride;
   int qtop = 0, rtop = 0; // codes [0, top) staged (modulo kSeqBuf)
   auto stage = [&](const uint8_t *src, int len, uint8_t *buf, int &top, int need) {
     while (top < len && top <= need) {
@@ -145,9 +149,28 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
         const uint32_t c = (idx < len) ? (uint32_t)min((int)src[idx], A) : (uint32_t)A;
         w4 |= c << (8 * b);
       }
-      *reinterpret_cast<uint32_t *>(buf + (base & (kSeqBuf - 1))) = w4;
+      const int at = base & (kSeqBuf - 1);
+      *reinterpret_cast<uint32_t *>(buf + at) = w4;
+      if (at < kSeqMirror) *reinterpret_cast<uint32_t *>(buf + kSeqBuf + at) = w4;
       top += 256;
     }
+  };
+  // This lane's codes for one antidiagonal: the query codes q[i0-HALF ..
+  // i0-1] and reference codes r[j0-1 .. j0+HALF-2] of its HALF cells, as
+  // packed bytes (window byte b of the query belongs to cell HALF-1-b, byte
+  // b of the reference to cell b).  One aligned read of NQW dwords and a
+  // byte-align per register, instead of two byte reads per cell.
+  constexpr int NWB = (HALF + 3) / 4;   // registers per window
+  constexpr int NQW = (HALF + 3 + 3) / 4; // aligned dwords covering it
+  static_assert(4 * NQW <= kSeqMirror, "window read beyond the ring's mirror");
+  auto window = [&](const uint8_t *buf, int first, uint32_t (&w)[NWB]) {
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(buf + (first & (kSeqBuf - 4)));
+    uint32_t d[NQW];
+#pragma unroll
+    for (int k = 0; k < NQW; ++k) d[k] = src[k];
+#pragma unroll
+    for (int k = 0; k < NWB; ++k)
+      w[k] = __builtin_amdgcn_alignbyte(k + 1 < NQW ? d[k + 1] : 0u, d[k], (uint32_t)first & 3u);
   };
 
   // window state: element e = lane*RD + x  <->  diagonal dbase + e
@@ -273,33 +296,43 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
     const int d0 = dbase + e0 + par;
     const int i0 = (k - d0) >> 1, j0 = (k + d0) >> 1;
     uint32_t cw = 0;
+    uint32_t qw[NWB], rw[NWB];
+    window(qbuf, i0 - HALF, qw);
+    window(rbuf, j0 - 1, rw);
 #pragma unroll
     for (int m = 0; m < HALF; ++m) {
       const int x = 2 * m + par;
       const int e = e0 + x;
       const int left = (x == 0) ? left_x : EN[(x + RD - 1) % RD];
       const int right = (x == RD - 1) ? right_x : FN[(x + 1) % RD];
-      const int i = i0 - m, j = j0 + m;
-      const int qc = qbuf[(i - 1) & (kSeqBuf - 1)];
-      const int rc = rbuf[(j - 1) & (kSeqBuf - 1)];
+      const int qb = HALF - 1 - m;
+      const int qc = (int)((qw[qb >> 2] >> (8 * (qb & 3))) & 0xffu);
+      const int rc = (int)((rw[m >> 2] >> (8 * (m & 3))) & 0xffu);
       const int sv = MM ? (qc == rc ? s_match : s_mismatch) : smat[qc * kMaxAlphabet + rc];
       const int hd = H[x] + sv;
       int h = max(max(hd, left), right);
       if (MODE == ALN_LOCAL) h = max(h, 0);
-      const int t = h + goe;
-      const int en = max(left + ge, t);
-      const int fn = max(right + ge, t);
       bool keep = (unsigned)(e - elo) <= (unsigned)(ehi - elo) && elo <= ehi;
       if (PRUNE == ALN_XDROP) keep = keep && h >= thr;
+      // Outside a band only H needs the mask, with the open term formed
+      // from the masked H: an E carries a real value only to the right of
+      // the band and an F only to its left, and the band's edges move by
+      // at most one diagonal per antidiagonal, so neither flows back in;
+      // every other E and F stays at or below NEG + o + e.  X-drop prunes
+      // inside its range, so there all three are masked.
+      const int hk = keep ? h : NEG32;
+      const int t = (PRUNE == ALN_BAND ? hk : h) + goe;
+      const int en = max(left + ge, t);
+      const int fn = max(right + ge, t);
       if (TB) {
         uint32_t hs = (h == hd) ? 0u : ((h == left) ? 1u : 2u);
         if (MODE == ALN_LOCAL && h == 0) hs = 3u;
         const uint32_t nib = hs | ((en == t) ? 4u : 0u) | ((fn == t) ? 8u : 0u);
         cw |= nib << (4 * m);
       }
-      H[x] = keep ? h : NEG32;
-      EN[x] = keep ? en : NEG32;
-      FN[x] = keep ? fn : NEG32;
+      H[x] = hk;
+      EN[x] = (PRUNE == ALN_BAND || keep) ? en : NEG32;
+      FN[x] = (PRUNE == ALN_BAND || keep) ? fn : NEG32;
       if (MODE != ALN_GLOBAL) {
         const int key = keep ? ((max(h, -1) << 11) | e) : -1;
         kkey = max(kkey, key);
@@ -414,7 +447,7 @@ __global__ __launch_bounds__(256) void diag_kernel(DiagArgs a) {
   // per-antidiagonal quantity (task, lengths, domain, window base) scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  int8_t *smat = reinterpret_cast<int8_t *>(smem + 4 * 2 * kSeqBuf);
+  int8_t *smat = reinterpret_cast<int8_t *>(smem + 4 * 2 * kSeqStride);
   const int A = a.sc->alphabet;
   for (int k = threadIdx.x; k < kMaxAlphabet * kMaxAlphabet; k += blockDim.x) {
     const int qa = k / kMaxAlphabet, rc = k % kMaxAlphabet;
@@ -702,7 +735,7 @@ hipError_t launch_xdrop_group(const DiagArgs &a, hipStream_t s) {
 template <int RD, int MODE, int PRUNE, bool TB>
 static hipError_t launch_diag_t(const DiagArgs &a, hipStream_t s) {
   const bool mm = a.match_mismatch != 0;
-  const size_t lds = (size_t)4 * 2 * kSeqBuf + kMaxAlphabet * kMaxAlphabet;
+  const size_t lds = (size_t)4 * 2 * kSeqStride + kMaxAlphabet * kMaxAlphabet;
   int blocks = (a.ntasks + 3) / 4;
   if (a.dyn_ntasks) blocks = min(blocks, 2048);
   if (mm) hipLaunchKernelGGL((diag_kernel<RD, MODE, PRUNE, TB, true>), dim3(blocks), dim3(256), lds, s, a);
