@@ -27,6 +27,9 @@ constexpr int kBlockBytes = 16384;  // one LDS code block
 // readfirstlane keeps it in scalar registers and its branches scalar.
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 constexpr int kPre = kBlockBytes / 16 / 64; // uint4 per lane per block
+constexpr int kLook = 32;                   // cells a walk step looks ahead
+
+__device__ __forceinline__ int ctz64(unsigned long long v) { return v ? __ffsll((long long)v) - 1 : 64; }
 
 // Run-length CIGAR written backwards from the end of the pair's slot.  The
 // state is wave-uniform; lane 0 stores.
@@ -34,15 +37,6 @@ struct WaveCigar {
   uint32_t *out;
   int w, cur, run;
   bool overflow;
-  __device__ void emit(int op, int lane) {
-    if (op == cur) {
-      ++run;
-      return;
-    }
-    flush(lane);
-    cur = op;
-    run = 1;
-  }
   __device__ void flush(int lane) {
     if (cur < 0) return;
     if (w > 0) {
@@ -54,65 +48,24 @@ struct WaveCigar {
   }
 };
 
-// A 256-byte LDS window over a sequence that only moves towards its start.
-struct SeqWindow {
-  const uint8_t *src;
-  int len;
-  int base;
-  uint8_t *lds;
-  __device__ int get(int idx, int lane) { // 0 <= idx < len, wave-uniform
-    if (idx < base || idx >= base + 256) {
-      base = max(0, idx - 255);
-      __syncthreads();
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int p = base + lane * 4 + b;
-        lds[lane * 4 + b] = p < len ? src[p] : 0;
-      }
-      __syncthreads();
-    }
-    return uni(lds[idx - base]);
-  }
-};
-
-// Copies of one code block: `pre` holds the block being prefetched.
-struct BlockCache {
-  uint4 pre[kPre];
-  int pre_key = -1;
-  int pre_aux = 0;
-  int cur_key = -1;
-  int cur_aux = 0; // lane l: per-block value l (window base of antidiagonal l)
-  __device__ void install(uint4 *lds4, int lane) {
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < kPre; ++m) lds4[lane + 64 * m] = pre[m];
-    cur_aux = pre_aux;
-    __syncthreads();
-    cur_key = pre_key;
-  }
-};
-
-__device__ __forceinline__ void load_block(BlockCache &c, const uint4 *src, int n4, int key,
-                                           int aux, int lane) {
-#pragma unroll
-  for (int m = 0; m < kPre; ++m) {
-    const int u = lane + 64 * m;
-    c.pre[m] = u < n4 ? src[u] : make_uint4(0u, 0u, 0u, 0u);
-  }
-  c.pre_key = key;
-  c.pre_aux = aux;
-}
-
 } // namespace
 
 // ------------------------------------------------------------ strip layout
 // Codes of strip s: step t (0..N+62), lane l, rows r = 0..R-1 packed two per
 // byte at ((s*T + t)*64 + l)*(R/2) + r/2.  Cell (i, j) lives in strip
-// (i-1)/(64R), lane ((i-1) mod 64R)/R, row (i-1) mod R, step t = j-1+lane.
-// A block is TBK consecutive steps of one strip (TBK*32R <= 16 KB bytes).
-// The walk keeps (s, l, r) of its row and steps them as i falls.
+// (i-1)/(64R), lane ((i-1) mod 64R)/R, row (i-1) mod R, step t = j-1+lane;
+// bit 2 of its code says E(i, j) opened from H(i, j-1), bit 3 that F(i, j)
+// opened from H(i-1, j).  A block is TBK consecutive steps of one strip
+// (TBK*32R <= 16 KB).  Blocks are numbered s*NTB + b; the walk never moves to
+// a higher number.
+//
+// Like the diagonal-layout walk below, it advances by whole runs: lanes
+// m < 32 read the codes of the m-th cell ahead (H: (i-m, j-m), E: (i, j-m),
+// F: (i-m, j)) from the two resident blocks (the walk's block and the one
+// before in the same strip), and a run also ends at the first cell outside
+// them; the next iteration makes that cell's block resident.
 __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
-  __shared__ __align__(16) uint4 codes4[kBlockBytes / 16];
+  __shared__ __align__(16) uint4 codes4[2][kBlockBytes / 16];
   __shared__ uint8_t qwin[256], rwin[256];
   const int lane = threadIdx.x;
   const int task = blockIdx.x;
@@ -129,24 +82,59 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
   }
   if (status != ALN_R_OK) return;
   const int M = uni(a.b.q_len[p]), N = uni(a.b.r_len[p]);
-  SeqWindow qw{a.b.q + a.b.q_off[p], M, 1 << 30, qwin};
-  SeqWindow rw{a.b.r + a.b.r_off[p], N, 1 << 30, rwin};
+  const uint8_t *Qs = a.b.q + a.b.q_off[p];
+  const uint8_t *Rs = a.b.r + a.b.r_off[p];
   const uint8_t *tb = a.tb + tk.tb_off;
   const int R = uni(tk.rows), HB = R / 2, T = N + 63;
-  const int LTB = R <= 16 ? 5 : 4; // log2 of the block's steps
+  const int invR = (65536 + R - 1) / R; // v / R = (v * invR) >> 16 for 0 <= v < 64
+  const int LTB = R <= 16 ? 5 : 4;      // log2 of the block's steps
   const int TBK = 1 << LTB;
   const int NTB = (T + TBK - 1) >> LTB;
   const bool local = a.mode == ALN_LOCAL;
-  const uint8_t *codes = reinterpret_cast<const uint8_t *>(codes4);
-  BlockCache bc;
+  const uint8_t *codes0 = reinterpret_cast<const uint8_t *>(codes4[0]);
 
+  // block cache: slots hold (cs, cb) and (cs, cb - 1); `pre` holds (cs, cb - 2)
+  uint4 pre[kPre];
+  int pre_key = -1, cs = -1, cb = -1;
   auto fetch = [&](int s, int b) {
     const int steps = min(TBK, T - b * TBK);
     const uint4 *src = reinterpret_cast<const uint4 *>(
         tb + ((size_t)s * T + (size_t)b * TBK) * 64 * HB);
-    load_block(bc, src, steps * 64 * HB / 16, s * NTB + b, 0, lane);
+    const int n4 = steps * 64 * HB / 16;
+#pragma unroll
+    for (int m = 0; m < kPre; ++m) {
+      const int u = lane + 64 * m;
+      pre[m] = u < n4 ? src[u] : make_uint4(0u, 0u, 0u, 0u);
+    }
+    pre_key = s * NTB + b;
   };
-  // row position of i (valid while i >= 1)
+  auto install = [&](int key) {
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kPre; ++m) codes4[key & 1][lane + 64 * m] = pre[m];
+    __syncthreads();
+  };
+  auto make_resident = [&](int s, int b) {
+    if (s == cs && b == cb) return;
+    const int key = s * NTB + b;
+    if (s == cs && b == cb - 1) { // the common step: one block older
+      if (b >= 1) {
+        if (pre_key != key - 1) fetch(s, b - 1);
+        install(key - 1);
+      }
+    } else { // first use, or a new strip
+      fetch(s, b);
+      install(key);
+      if (b >= 1) {
+        fetch(s, b - 1);
+        install(key - 1);
+      }
+    }
+    cs = s;
+    cb = b;
+    if (b >= 2) fetch(s, b - 2);
+  };
+  // position of row i (while i >= 1): strip rs, lane rl, row rr
   int i = i_end, j = j_end;
   int rs = 0, rl = 0, rr = 0;
   if (i >= 1) {
@@ -155,37 +143,67 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
     rl = within / R;
     rr = within - rl * R;
   }
-  auto up = [&]() { // i -> i - 1
-    --i;
-    if (--rr < 0) {
-      rr = R - 1;
-      if (--rl < 0) {
-        rl = 63;
-        --rs;
+  // position of row i - m, 0 <= m <= 32 (one strip boundary at most)
+  auto rowpos = [&](int m, int &s2, int &l2, int &r2) {
+    const int x = rr - m;
+    s2 = rs;
+    l2 = rl;
+    r2 = x;
+    if (x < 0) {
+      const int dl = ((R - 1 - x) * invR) >> 16; // ceil(-x / R)
+      l2 = rl - dl;
+      r2 = x + dl * R;
+      if (l2 < 0) {
+        l2 += 64;
+        s2 -= 1;
       }
     }
   };
-  bool bad = false;
-  auto code = [&](int jj) -> int { // code of (i, jj)
-    const int t = (jj - 1) + rl;
+  auto up_by = [&](int n) {
+    int s2, l2, r2;
+    rowpos(n, s2, l2, r2);
+    rs = s2;
+    rl = l2;
+    rr = r2;
+    i -= n;
+  };
+  // code of the cell at (strip s2, lane l2, row r2, column jj), or -1 when
+  // its block is not resident
+  auto code_at = [&](int s2, int l2, int r2, int jj) -> int {
+    const int t = jj - 1 + l2;
     const int b = t >> LTB;
-    const int key = rs * NTB + b;
-    if (key != bc.cur_key) {
-      if (key != bc.pre_key) fetch(rs, b);
-      bc.install(codes4, lane);
-      if (b > 0) fetch(rs, b - 1);
+    if (s2 != cs || t < 0 || b > cb || b < cb - 1) return -1;
+    const int slot = (s2 * NTB + b) & 1;
+    const int byte = slot * kBlockBytes + ((t - (b << LTB)) * 64 + l2) * HB + (r2 >> 1);
+    return (codes0[byte] >> ((r2 & 1) * 4)) & 15;
+  };
+  int qbase = 1 << 30, rbase = 1 << 30;
+  auto cover = [&](const uint8_t *src, int len, uint8_t *win, int &base, int lo, int hi) {
+    if (lo >= base && hi < base + 256) return;
+    base = max(0, hi - 255);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int pidx = base + lane * 4 + t;
+      win[lane * 4 + t] = pidx < len ? src[pidx] : 0;
     }
-    const int byte = ((t - (b << LTB)) * 64 + rl) * HB + (rr >> 1);
-    if ((unsigned)byte >= (unsigned)kBlockBytes) {
-      bad = true;
-      return 0;
-    }
-    return uni((codes[byte] >> ((rr & 1) * 4)) & 15);
+    __syncthreads();
   };
 
   WaveCigar cw{a.cigar + tk.cigar_off, tk.cigar_cap, -1, 0, false};
+  auto emit_n = [&](int op, int n) {
+    if (n <= 0) return;
+    if (op == cw.cur) {
+      cw.run += n;
+      return;
+    }
+    cw.flush(lane);
+    cw.cur = op;
+    cw.run = n;
+  };
   int state = 0;
-  // every iteration moves or switches H -> E/F, so 2(M+N)+2 bounds the walk
+  bool bad = false;
+  const unsigned long long look_mask = (1ull << kLook) - 1;
   for (int guard = 2 * (i_end + j_end) + 2; guard > 0 && !bad; --guard) {
     if ((state == 1 && j < 1) || (state == 2 && i < 1) || i < 0 || j < 0) {
       bad = true;
@@ -194,27 +212,84 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
     if (state == 0) {
       if (i == 0 && j == 0) break;
       if (local && (i == 0 || j == 0)) break;
-      if (i == 0) { cw.emit(ALN_OP_D, lane); --j; continue; }
-      if (j == 0) { cw.emit(ALN_OP_I, lane); up(); continue; }
-      const int hs = code(j) & 3;
-      if (local && hs == 3) break;
-      if (hs == 0) {
-        cw.emit(qw.get(i - 1, lane) == rw.get(j - 1, lane) ? ALN_OP_EQ : ALN_OP_X, lane);
-        up();
-        --j;
-      } else {
-        state = hs;
+      if (i == 0) { emit_n(ALN_OP_D, j); j = 0; continue; }
+      if (j == 0) { emit_n(ALN_OP_I, i); i = 0; continue; }
+      make_resident(rs, (j - 1 + rl) >> LTB);
+      cover(Qs, M, qwin, qbase, max(0, i - 1 - kLook), i - 1);
+      cover(Rs, N, rwin, rbase, max(0, j - 1 - kLook), j - 1);
+      // lanes m < kLook: the cell m steps up the diagonal
+      const int m = lane;
+      const int ii = i - m, jj = j - m;
+      int c = -1;
+      if (m < kLook && ii >= 1 && jj >= 1) {
+        int s2, l2, r2;
+        rowpos(m, s2, l2, r2);
+        c = code_at(s2, l2, r2, jj);
       }
+      const bool diag = c >= 0 && (c & 3) == 0;
+      const int L = min(ctz64(~__ballot(diag) & look_mask), kLook); // diagonal run length
+      if (L == 0) {
+        const int hs0 = uni(c) & 3; // lane 0: the walk's own cell, always resident
+        if (local && hs0 == 3) break;
+        state = hs0; // 1: E, 2: F
+        continue;
+      }
+      // '=' / 'X' of the run, first step of the walk first
+      const bool mism = lane < L && qwin[ii - 1 - qbase] != rwin[jj - 1 - rbase];
+      const unsigned long long mm = __ballot(mism) & ((1ull << L) - 1);
+      int pos = 0;
+      while (pos < L) {
+        const bool x = (mm >> pos) & 1ull;
+        const unsigned long long rest = (x ? ~mm : mm) >> pos;
+        const int run = min(ctz64(rest), L - pos);
+        emit_n(x ? ALN_OP_X : ALN_OP_EQ, run);
+        pos += run;
+      }
+      up_by(L);
+      j -= L;
     } else if (state == 1) {
-      const int c = code(j);
-      cw.emit(ALN_OP_D, lane);
-      if (c & 4) state = 0;
-      --j;
+      // D moves: E(i, j-m) opened from H(i, j-m-1) per the code of (i, j-m)
+      make_resident(rs, (j - 1 + rl) >> LTB);
+      const int jj = j - lane;
+      const bool in = lane < kLook && jj >= 1;
+      const int c = in ? code_at(rs, rl, rr, jj) : -1;
+      const unsigned long long om = __ballot(c >= 0 && (c & 4)) & look_mask;
+      const unsigned long long stop = __ballot(in && c < 0) & look_mask; // not resident
+      const int first_open = ctz64(om), first_stop = ctz64(stop);
+      if (first_open < first_stop && first_open < kLook) {
+        emit_n(ALN_OP_D, first_open + 1);
+        j -= first_open + 1;
+        state = 0;
+      } else {
+        const int n = min(first_stop, min(kLook, j));
+        if (n <= 0 || (first_stop >= kLook && j < kLook)) { bad = true; break; } // must open by column 1
+        emit_n(ALN_OP_D, n);
+        j -= n;
+      }
     } else {
-      const int c = code(j);
-      cw.emit(ALN_OP_I, lane);
-      if (c & 8) state = 0;
-      up();
+      // I moves: F(i-m, j) opened from H(i-m-1, j) per the code of (i-m, j)
+      make_resident(rs, (j - 1 + rl) >> LTB);
+      const int ii = i - lane;
+      const bool in = lane < kLook && ii >= 1;
+      int c = -1;
+      if (in) {
+        int s2, l2, r2;
+        rowpos(lane, s2, l2, r2);
+        c = code_at(s2, l2, r2, j);
+      }
+      const unsigned long long om = __ballot(c >= 0 && (c & 8)) & look_mask;
+      const unsigned long long stop = __ballot(in && c < 0) & look_mask;
+      const int first_open = ctz64(om), first_stop = ctz64(stop);
+      if (first_open < first_stop && first_open < kLook) {
+        emit_n(ALN_OP_I, first_open + 1);
+        up_by(first_open + 1);
+        state = 0;
+      } else {
+        const int n = min(first_stop, min(kLook, i));
+        if (n <= 0 || (first_stop >= kLook && i < kLook)) { bad = true; break; } // must open by row 1
+        emit_n(ALN_OP_I, n);
+        up_by(n);
+      }
     }
   }
   cw.flush(lane);
@@ -249,9 +324,6 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
 //   state F  cells (i-1-m, j): likewise for the vertical gap.
 // All those cells lie within 63 antidiagonals of the current one, so within
 // the two resident blocks.
-constexpr int kLook = 32;
-
-__device__ __forceinline__ int ctz64(unsigned long long v) { return v ? __ffsll((long long)v) - 1 : 64; }
 
 __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
   __shared__ __align__(16) uint4 codes4[2][kBlockBytes / 16];
