@@ -5,7 +5,7 @@ the CPU-baseline leg of the benchmark.  The GPU library never imports, links or
 calls anything here, and this package imports nothing from the GPU library.
 """
 from .alnref import (  # noqa: F401
-    GLOBAL, LOCAL, EXTEND, FULL, BAND, XDROP,
+    GLOBAL, LOCAL, EXTEND, FULL, BAND, XDROP, ZDROP,
     OK, UNREACHABLE, CIGAR_CAP, BAD_SYMBOL,
     OP_I, OP_D, OP_EQ, OP_X,
     align, align_batch, build, load,

@@ -33,6 +33,11 @@
  *          below the best score of the antidiagonals before it is set to
  *          NEG, and the next antidiagonal is evaluated only between the first
  *          and last surviving cells (plus one step right).
+ *   ZDROP  the same antidiagonal procedure with the Z-drop condition of
+ *          Sec. 9.3 (named in Sec. 7.2): a cell is set to NEG when the best
+ *          score of the antidiagonals before it exceeds its H by more than
+ *          Z + |diag(i,j) - diag_best|, diag = j - i, diag_best the diagonal
+ *          of that best cell.
  */
 #include "alnref.h"
 
@@ -296,8 +301,9 @@ static int64_t ad_get(const adiag *a, const int64_t *A, int64_t j) {
   return A[j];
 }
 
+/* zdrop = 0: X-drop with threshold X; zdrop = 1: Z-drop with Z = X. */
 static int align_xdrop(const int32_t *mat, int32_t Al, int64_t o, int64_t e,
-                       int64_t X, const uint8_t *q, int32_t M,
+                       int64_t X, int zdrop, const uint8_t *q, int32_t M,
                        const uint8_t *r, int32_t N, alnref_out *out) {
   adiag buf[3];
   for (int t = 0; t < 3; t++) {
@@ -345,8 +351,14 @@ static int align_xdrop(const int32_t *mat, int32_t Al, int64_t o, int64_t e,
       if (IS_NEG(h)) h = NEG;
       if (IS_NEG(ev)) ev = NEG;
       if (IS_NEG(fv)) fv = NEG;
-      /* conditional definition: pruned when more than X below best_{k-1} */
-      if (IS_NEG(h) || best - h > X) {
+      /* conditional definition: pruned when more than X below best_{k-1}
+       * (Z-drop: more than Z + |diag(i,j) - diag_best_{k-1}| below it) */
+      int64_t limit = X;
+      if (zdrop) {
+        const int64_t dd = (j - i) - (bj - bi);
+        limit += dd < 0 ? -dd : dd;
+      }
+      if (IS_NEG(h) || best - h > limit) {
         h = NEG; ev = NEG; fv = NEG;
       } else {
         if (nlo < 0) nlo = j;
@@ -381,8 +393,9 @@ int alnref_align(const int32_t *matrix, int32_t alphabet, int32_t gap_open,
   if (!matrix || alphabet < 1 || alphabet > 256 || M < 0 || N < 0 ||
       (M > 0 && !q) || (N > 0 && !r) || gap_open > 0 || gap_extend > 0 ||
       mode < ALNREF_GLOBAL || mode > ALNREF_EXTEND || prune < ALNREF_FULL ||
-      prune > ALNREF_XDROP || (prune == ALNREF_BAND && band_w < 0) ||
-      (prune == ALNREF_XDROP && (xdrop < 0 || mode != ALNREF_EXTEND || cigar)) ||
+      prune > ALNREF_ZDROP || (prune == ALNREF_BAND && band_w < 0) ||
+      ((prune == ALNREF_XDROP || prune == ALNREF_ZDROP) &&
+       (xdrop < 0 || mode != ALNREF_EXTEND || cigar)) ||
       (cigar && cigar_cap < 0)) {
     out->status = ALNREF_INVAL;
     return ALNREF_INVAL;
@@ -392,8 +405,9 @@ int alnref_align(const int32_t *matrix, int32_t alphabet, int32_t gap_open,
   for (int32_t j = 0; j < N; j++)
     if (r[j] >= alphabet) { out->status = ALNREF_BAD_SYMBOL; return ALNREF_BAD_SYMBOL; }
   int rc;
-  if (prune == ALNREF_XDROP)
-    rc = align_xdrop(matrix, alphabet, gap_open, gap_extend, xdrop, q, M, r, N, out);
+  if (prune == ALNREF_XDROP || prune == ALNREF_ZDROP)
+    rc = align_xdrop(matrix, alphabet, gap_open, gap_extend, xdrop, prune == ALNREF_ZDROP,
+                     q, M, r, N, out);
   else
     rc = align_rows(matrix, alphabet, gap_open, gap_extend, mode,
                     prune == ALNREF_BAND, band_w, q, M, r, N, cigar, cigar_cap, out);

@@ -27,7 +27,7 @@ extern "C" {
 #endif
 
 enum { ALNREF_GLOBAL = 0, ALNREF_LOCAL = 1, ALNREF_EXTEND = 2 };
-enum { ALNREF_FULL = 0, ALNREF_BAND = 1, ALNREF_XDROP = 2 };
+enum { ALNREF_FULL = 0, ALNREF_BAND = 1, ALNREF_XDROP = 2, ALNREF_ZDROP = 3 };
 
 /* per-pair status */
 enum {
@@ -59,8 +59,9 @@ typedef struct {
  *              with a a query code and b a reference code
  *   gap_open, gap_extend   <= 0; a gap of length L scores gap_open + L*gap_extend
  *   mode       ALNREF_GLOBAL / LOCAL / EXTEND
- *   prune      ALNREF_FULL / BAND (band_w >= 0) / XDROP (xdrop >= 0, EXTEND only)
- *   cigar      NULL for score only; else room for cigar_cap words (not for XDROP)
+ *   prune      ALNREF_FULL / BAND (band_w >= 0) / XDROP or ZDROP (threshold X or Z in
+ *              xdrop >= 0, EXTEND only)
+ *   cigar      NULL for score only; else room for cigar_cap words (not for XDROP/ZDROP)
  * Returns the status (also stored in out->status).
  */
 int alnref_align(const int32_t *matrix, int32_t alphabet, int32_t gap_open,

@@ -11,7 +11,7 @@ import subprocess
 import numpy as np
 
 GLOBAL, LOCAL, EXTEND = 0, 1, 2
-FULL, BAND, XDROP = 0, 1, 2
+FULL, BAND, XDROP, ZDROP = 0, 1, 2, 3
 OK, UNREACHABLE, CIGAR_CAP, BAD_SYMBOL = 0, 1, 2, 3
 OP_I, OP_D, OP_EQ, OP_X = 1, 2, 7, 8
 

@@ -327,12 +327,13 @@ def test_band_cell_count_closed_form_square():
 
 
 # ---------------------------------------------------------------- x-drop
-def xdrop_dict(q, r, S, o, e, X):
+def xdrop_dict(q, r, S, o, e, X, zdrop=False):
     """Second, independent implementation of the X-drop rule: cells kept in a
     dict keyed by (i, j); a missing key is minus infinity.  Antidiagonal k's
     candidates are j in [lo, hi+1] of the previous antidiagonal's survivors,
     clipped to the matrix; a candidate is pruned when best - H > X with best
-    the running maximum over earlier antidiagonals."""
+    the running maximum over earlier antidiagonals.  With zdrop the limit is
+    X + |(j - i) - (j_best - i_best)| (the Z-drop condition, Sec. 9.3)."""
     M, N = len(q), len(r)
     Hd, Ed, Fd = {(0, 0): 0}, {}, {}
     best, end = 0, (0, 0)
@@ -364,7 +365,8 @@ def xdrop_dict(q, r, S, o, e, X):
                 if (i - 1, j - 1) in Hd:
                     cand_h.append(Hd[(i - 1, j - 1)] + S[q[i - 1]][r[j - 1]])
                 h = max(cand_h) if cand_h else None
-            if h is None or best - h > X:
+            limit = X + (abs((j - i) - (end[1] - end[0])) if zdrop else 0)
+            if h is None or best - h > limit:
                 continue
             Hd[(i, j)] = h
             if ev is not None:
@@ -431,6 +433,77 @@ def test_xdrop_identical_sequences():
     for X in (0, 5):
         got = oracle.align(S, -4, -2, x, x, mode=oracle.EXTEND, prune=oracle.XDROP, xdrop=X)
         assert (got["score"], got["q_end"], got["r_end"], got["cells"]) == (0, 0, 0, 0)
+
+
+# ---------------------------------------------------------------- z-drop
+def test_zdrop_vs_dict_implementation():
+    rng = np.random.default_rng(25)
+    for trial in range(150):
+        S = dna_matrix(2, -4) if trial % 3 else rand_matrix(rng, 4)
+        o, e = -4, -2
+        Z = int(rng.integers(0, 30))
+        M, N = int(rng.integers(0, 40)), int(rng.integers(0, 40))
+        base = rand_seq(rng, max(M, N), 4)
+        q = base[:M] if trial % 2 else rand_seq(rng, M, 4)
+        r = [c if rng.random() > 0.15 else int(rng.integers(0, 4)) for c in base[:N]]
+        if trial % 5 == 0 and N > 12:  # a long insertion: where the distance term matters
+            r = r[:N // 3] + rand_seq(rng, 10, 4) + r[N // 3:]
+        got = oracle.align(S, o, e, q, r, mode=oracle.EXTEND, prune=oracle.ZDROP, xdrop=Z)
+        best, end, cells = xdrop_dict(q, r, S.tolist(), o, e, Z, zdrop=True)
+        assert (got["score"], (got["q_end"], got["r_end"]), got["cells"]) == (best, end, cells)
+
+
+def test_zdrop_infinite_z_is_full_extend():
+    rng = np.random.default_rng(26)
+    S = dna_matrix(2, -4)
+    for _ in range(30):
+        M, N = int(rng.integers(0, 70)), int(rng.integers(0, 70))
+        q, r = rand_seq(rng, M, 4), rand_seq(rng, N, 4)
+        full = oracle.align(S, -4, -2, q, r, mode=oracle.EXTEND)
+        zd = oracle.align(S, -4, -2, q, r, mode=oracle.EXTEND, prune=oracle.ZDROP,
+                          xdrop=1 << 30)
+        assert (zd["score"], zd["q_end"], zd["r_end"], zd["cells"]) == (
+            full["score"], full["q_end"], full["r_end"], M * N)
+
+
+def test_zdrop_identical_sequences():
+    """On identical sequences the best cell stays on the main diagonal and the
+    odd antidiagonals hold cells one diagonal off it scoring best + o + e, so
+    Z-drop keeps them for Z + 1 >= -(o+e), one less than X-drop needs: with
+    o + e = -6, Z = 5 reaches the corner where X = 5 stops at (0,0)."""
+    S = dna_matrix(2, -4)
+    rng = np.random.default_rng(27)
+    x = rand_seq(rng, 300, 4)
+    for Z in (5, 10, 100):
+        got = oracle.align(S, -4, -2, x, x, mode=oracle.EXTEND, prune=oracle.ZDROP, xdrop=Z)
+        assert (got["score"], got["q_end"], got["r_end"]) == (600, 300, 300)
+    for Z in (0, 4):
+        got = oracle.align(S, -4, -2, x, x, mode=oracle.EXTEND, prune=oracle.ZDROP, xdrop=Z)
+        assert (got["score"], got["q_end"], got["r_end"], got["cells"]) == (0, 0, 0, 0)
+    xd = oracle.align(S, -4, -2, x, x, mode=oracle.EXTEND, prune=oracle.XDROP, xdrop=5)
+    assert (xd["score"], xd["cells"]) == (0, 0)
+
+
+def test_zdrop_survives_a_long_gap_that_xdrop_cuts():
+    """A 40-base insertion in the reference after 60 matching bases, then 60
+    more (a and b over letters 0-1, the insertion all letter 3, so nothing
+    matches by chance): crossing it costs o + 40e = -84 below the best so far.
+    X-drop with X = 60 stops at (60, 60) with 120 (a gap cell L deep falls
+    4 + 2L below it, pruned from L = 29); Z-drop with Z = 60 crosses it (the
+    limit on diagonal d is 60 + d, and 4 + 2d exceeds it only beyond d = 56)
+    and ends at the far corner with 120 matches minus the gap."""
+    S = dna_matrix(2, -4)
+    rng = np.random.default_rng(28)
+    a = [int(c) for c in rng.integers(0, 2, 60)]
+    b = [int(c) for c in rng.integers(0, 2, 60)]
+    ins = [3] * 40
+    q, r = a + b, a + ins + b
+    xd = oracle.align(S, -4, -2, q, r, mode=oracle.EXTEND, prune=oracle.XDROP, xdrop=60)
+    zd = oracle.align(S, -4, -2, q, r, mode=oracle.EXTEND, prune=oracle.ZDROP, xdrop=60)
+    full = oracle.align(S, -4, -2, q, r, mode=oracle.EXTEND)
+    assert xd["score"] == 120 and (xd["q_end"], xd["r_end"]) == (60, 60)
+    assert (zd["score"], zd["q_end"], zd["r_end"]) == (full["score"], full["q_end"], full["r_end"])
+    assert full["score"] == 240 - 4 - 2 * 40 and (full["q_end"], full["r_end"]) == (120, 160)
 
 
 # ---------------------------------------------------------------- schedule invariance
