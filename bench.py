@@ -42,13 +42,15 @@ METRIC = "GCUPS (bit-exact) at 1 GPU, batched vs per-pair; % int-VALU roofline; 
 #   local adds max(., 0) and the running maximum                  -> 10
 #   extension adds the running maximum                            -> 9
 #   X-drop adds the test against best - X                         -> 10
+#   Z-drop adds to that |d - d_best| (absolute difference) and its
+#   add to H                                                      -> 12
 OPS_PER_CELL = {("GLOBAL", 0): 8, ("GLOBAL", 1): 8, ("LOCAL", 0): 10, ("LOCAL", 1): 10,
-                ("EXTEND", 0): 9, ("EXTEND", 1): 9, ("EXTEND", 2): 10}
+                ("EXTEND", 0): 9, ("EXTEND", 1): 9, ("EXTEND", 2): 10, ("EXTEND", 3): 12}
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz; packed 16-bit ops do two per lane.
 PEAK_I32_TOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_I16_TOPS = 2 * PEAK_I32_TOPS
 KERNEL_WIDTH = {"sw16": "i16"}
-FILL_KERNELS = ("sw16", "strip_i32", "diag_band", "xdrop")
+FILL_KERNELS = ("sw16", "strip_i32", "diag_band", "xdrop", "zdrop")
 
 WORKLOAD_DESC = {
     "sw_protein": ("Smith-Waterman local, protein (20 letters, seeded symmetric matrix), "
@@ -61,9 +63,11 @@ WORKLOAD_DESC = {
     "xdrop_ext": ("X-drop extension, DNA +2/-4 open -4 extend -2, X = 100, 200,000 seeds x "
                   "2 sides of 150-5,000 bp at 5-25% divergence plus 10% random flank; "
                   "score + end cell"),
+    "zdrop_ext": ("Z-drop extension (Sec. 9.3 condition), the xdrop_ext pairs with Z = 100; "
+                  "score + end cell"),
 }
 MODE_NAME = {0: "GLOBAL", 1: "LOCAL", 2: "EXTEND"}
-PRUNE_NAME = {0: "full", 1: "band", 2: "xdrop"}
+PRUNE_NAME = {0: "full", 1: "band", 2: "xdrop", 3: "zdrop"}
 
 
 def log(msg):
@@ -251,7 +255,7 @@ def run_workload(name, batch, args, cpu_seconds, pp_cap):
         plan_ms=round(plan_ms, 2), autotune=tuning,
         statuses={int(s): int(c) for s, c in zip(*np.unique(res["status"], return_counts=True))},
     )
-    if batch.prune == 2:
+    if batch.prune in (2, 3):
         out["widened_pairs"] = int(((res["flags"] & aln.F_WIDENED) != 0).sum())
     if batch.mode == 1 and batch.prune == 0:
         out["int32_reruns"] = int(((res["flags"] & aln.F_I16_RERUN) != 0).sum())
@@ -333,7 +337,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="sw_protein", choices=sorted(WORKLOAD_DESC),
                     help="headline workload (the JSON line's value)")
-    ap.add_argument("--configs", default="nw_dna_1k,band_long,xdrop_ext",
+    ap.add_argument("--configs", default="nw_dna_1k,band_long,xdrop_ext,zdrop_ext",
                     help="comma list of further workloads to measure, or 'none'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",

@@ -68,7 +68,11 @@ enum {
 };
 
 enum { ALN_GLOBAL = 0, ALN_LOCAL = 1, ALN_EXTEND = 2 };
-enum { ALN_FULL = 0, ALN_BAND = 1, ALN_XDROP = 2 };
+/* ALN_ZDROP (EXTEND only) is XDROP with the Z-drop condition of Sec. 9.3: a
+ * cell (i,j) is removed when the best score of the earlier antidiagonals
+ * exceeds its H by more than Z + |(j - i) - (j* - i*)|, (i*,j*) the cell of
+ * that best score; Z is passed in aln_params.xdrop. */
+enum { ALN_FULL = 0, ALN_BAND = 1, ALN_XDROP = 2, ALN_ZDROP = 3 };
 /* score width: AUTO lets the library choose (packed int16 where it applies,
  * with an automatic int32 re-run of any pair that could have overflowed) */
 enum { ALN_W_AUTO = 0, ALN_W_I16 = 1, ALN_W_I32 = 2 };
@@ -79,15 +83,15 @@ enum {
   ALN_R_UNREACHABLE = 1, /* GLOBAL + BAND: (M,N) not connected to (0,0)      */
   ALN_R_CIGAR_CAP = 2,   /* the pair's CIGAR did not fit its slot           */
   ALN_R_BAD_SYMBOL = 3,  /* a code >= alphabet; other fields undefined       */
-  ALN_R_TOO_WIDE = 4     /* XDROP: the surviving region spanned more than the
-                            widest kernel window (2042 diagonals)            */
+  ALN_R_TOO_WIDE = 4     /* XDROP / ZDROP: the surviving region spanned more
+                            than the widest kernel window (2042 diagonals)   */
 };
 /* per-pair result flags */
 enum {
   ALN_F_I16_RERUN = 1,  /* the int16 pass could have saturated; the pair was
                            recomputed in int32 (the result is the int32 one) */
-  ALN_F_WIDENED = 2     /* X-drop region outgrew the first window; the pair
-                           was recomputed with a wider one                    */
+  ALN_F_WIDENED = 2     /* X-drop / Z-drop region outgrew the first window;
+                           the pair was recomputed with a wider one          */
 };
 
 enum { ALN_OP_I = 1, ALN_OP_D = 2, ALN_OP_EQ = 7, ALN_OP_X = 8 };
@@ -107,9 +111,10 @@ typedef struct {
 
 typedef struct {
   int32_t mode;       /* ALN_GLOBAL / ALN_LOCAL / ALN_EXTEND                  */
-  int32_t prune;      /* ALN_FULL / ALN_BAND / ALN_XDROP (EXTEND only)        */
+  int32_t prune;      /* ALN_FULL / ALN_BAND / ALN_XDROP or ALN_ZDROP (EXTEND
+                         only)                                                */
   int32_t band_w;     /* BAND half-width w >= 0                               */
-  int32_t xdrop;      /* XDROP threshold X >= 0                               */
+  int32_t xdrop;      /* XDROP threshold X >= 0, or ZDROP threshold Z >= 0    */
   int32_t width;      /* ALN_W_*                                              */
   int32_t want_cigar; /* 1: produce a CIGAR (FULL and BAND only)              */
 } aln_params;

@@ -226,12 +226,13 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     return fail(ctx, ALN_E_INVAL, "unknown scoring id %d", scoring_id);
   const aln_params &p = *params;
   if (p.mode < ALN_GLOBAL || p.mode > ALN_EXTEND) return fail(ctx, ALN_E_INVAL, "bad mode");
-  if (p.prune < ALN_FULL || p.prune > ALN_XDROP) return fail(ctx, ALN_E_INVAL, "bad prune");
+  if (p.prune < ALN_FULL || p.prune > ALN_ZDROP) return fail(ctx, ALN_E_INVAL, "bad prune");
   if (p.prune == ALN_BAND && p.band_w < 0) return fail(ctx, ALN_E_INVAL, "band_w < 0");
-  if (p.prune == ALN_XDROP && (p.xdrop < 0 || p.mode != ALN_EXTEND))
-    return fail(ctx, ALN_E_INVAL, "XDROP needs mode EXTEND and xdrop >= 0");
-  if (p.prune == ALN_XDROP && p.want_cigar)
-    return fail(ctx, ALN_E_UNSUPPORTED, "CIGAR is not produced under XDROP");
+  const bool dyn_prune = p.prune == ALN_XDROP || p.prune == ALN_ZDROP;
+  if (dyn_prune && (p.xdrop < 0 || p.mode != ALN_EXTEND))
+    return fail(ctx, ALN_E_INVAL, "XDROP / ZDROP need mode EXTEND and a threshold >= 0");
+  if (dyn_prune && p.want_cigar)
+    return fail(ctx, ALN_E_UNSUPPORTED, "CIGAR is not produced under XDROP / ZDROP");
   if (p.width < ALN_W_AUTO || p.width > ALN_W_I32) return fail(ctx, ALN_E_INVAL, "bad width");
   const DevScoring &hs = ctx->hsc[scoring_id];
   const int64_t per_step = (int64_t)std::abs(hs.gap_open) + std::abs(hs.gap_extend) + 128;
@@ -499,7 +500,7 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     L.kind = items[k].kind;
     L.rows = items[k].rows;
     L.mode = p.mode;
-    if (L.kind == K_DIAG && p.prune == ALN_XDROP) {
+    if (L.kind == K_DIAG && dyn_prune) {
       L.sides = ctx->tuning.valid ? ctx->tuning.xdrop_sides : 1;
       if (ctx->force_xdrop_sides) L.sides = ctx->force_xdrop_sides;
       if (L.sides != 1 && L.rows != 8) L.sides = 1;
@@ -556,7 +557,7 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
       }
     }
   }
-  pl->xdrop = p.prune == ALN_XDROP;
+  pl->xdrop = dyn_prune; // X-drop or Z-drop: widening queues
   pl->tasks_bytes = align_up(sizeof(PairTask) * std::max<size_t>(pl->tasks.size(), 1));
   pl->upload_bytes = sizeof(PairTask) * pl->tasks.size();
   if (pl->xdrop) {
@@ -728,12 +729,13 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
     if (L.kind == K_DIAG) {
       const int widen_rows = plan->xdrop ? 16 : 0;
       auto go = [&](const alnk::DiagArgs &da) {
-        return L.sides == 4 ? alnk::launch_xdrop_group(da, st)
+        return L.sides == 4 ? alnk::launch_xdrop_group(plan->p.prune, da, st)
                             : alnk::launch_diag(L.rows, L.mode, plan->p.prune, L.tb, da, st);
       };
       if (!per_pair) {
         alnk::DiagArgs da = diag_args(dtasks + L.first, L.count, nullptr, widen_rows, widen_cnt, wq0);
-        HIP_TRY(ctx, timed_launch(ctx, plan->xdrop ? "xdrop" : "diag_band", st, [&] { return go(da); }));
+        const char *fam = plan->p.prune == ALN_ZDROP ? "zdrop" : (plan->xdrop ? "xdrop" : "diag_band");
+        HIP_TRY(ctx, timed_launch(ctx, fam, st, [&] { return go(da); }));
       } else {
         for (int32_t k = 0; k < L.count; ++k) {
           alnk::DiagArgs da = diag_args(dtasks + L.first + k, 1, nullptr, widen_rows, widen_cnt, wq0);
@@ -767,13 +769,15 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
   }
   if (plan->xdrop) {
     // pairs whose surviving region outgrew 256 diagonals, then 1024
+    const int pr = plan->p.prune;
+    const char *fam = pr == ALN_ZDROP ? "zdrop_wide" : "xdrop_wide";
     alnk::DiagArgs d1 = diag_args(wq0, plan->n, widen_cnt, 32, widen_cnt + 1, wq1);
-    HIP_TRY(ctx, timed_launch(ctx, "xdrop_wide", st, [&] {
-              return alnk::launch_diag(16, ALN_EXTEND, ALN_XDROP, false, d1, st);
+    HIP_TRY(ctx, timed_launch(ctx, fam, st, [&] {
+              return alnk::launch_diag(16, ALN_EXTEND, pr, false, d1, st);
             }));
     alnk::DiagArgs d2 = diag_args(wq1, plan->n, widen_cnt + 1, 0, nullptr, nullptr);
-    HIP_TRY(ctx, timed_launch(ctx, "xdrop_wide", st, [&] {
-              return alnk::launch_diag(32, ALN_EXTEND, ALN_XDROP, false, d2, st);
+    HIP_TRY(ctx, timed_launch(ctx, fam, st, [&] {
+              return alnk::launch_diag(32, ALN_EXTEND, pr, false, d2, st);
             }));
   }
   if (plan->p.want_cigar) {

@@ -115,7 +115,8 @@ aln_status aln_autotune(aln_ctx *ctx, int32_t scoring_id, const aln_params *para
   };
   const bool local_full = p.mode == ALN_LOCAL && p.prune == ALN_FULL && !p.want_cigar &&
                           p.width != ALN_W_I32;
-  if (p.prune == ALN_XDROP) {
+  if (p.prune == ALN_XDROP || p.prune == ALN_ZDROP) {
+    // X-drop and Z-drop share the kernel family and its tile choice;
     // candidates rows x sides: 4x1, 2x1, 8x1, 8x4 (encoded rows + 100*(sides-1))
     static const int c[4] = {4, 2, 8, 308};
     const int best = pick(c, 4, t.xdrop_ms, 4, [&](int code) {

@@ -118,14 +118,14 @@ struct Sw16Args {
   int32_t rerun_threshold; // best >= this: may have saturated
 };
 
-// Antidiagonal kernel (BAND and XDROP).
+// Antidiagonal kernel (BAND, XDROP and ZDROP).
 struct DiagArgs {
   BatchPtrs b;
   const PairTask *tasks;      // rows = window elements per lane (RD)
   int32_t ntasks;
   const int32_t *dyn_ntasks;  // device-side count (widening queues), or null
   int32_t band_w;
-  int32_t xdrop;
+  int32_t xdrop;              // X (XDROP) or Z (ZDROP)
   const DevScoring *sc;
   uint8_t *tb;                // traceback codes + per-antidiagonal window base
   aln_result *res;
@@ -142,8 +142,9 @@ hipError_t launch_strip(int rows, int mode, bool tb, bool small_alphabet,
 hipError_t launch_walk(int layout, const WalkArgs &a, hipStream_t s);
 hipError_t launch_sw16(int rows, const Sw16Args &a, hipStream_t s);
 hipError_t launch_diag(int rows, int mode, int prune, bool tb, const DiagArgs &a, hipStream_t s);
-// X-drop (EXTEND), four sides per wavefront, 8 diagonals per lane
-hipError_t launch_xdrop_group(const DiagArgs &a, hipStream_t s);
+// X-drop or Z-drop (EXTEND, prune ALN_XDROP or ALN_ZDROP), four sides per
+// wavefront, 8 diagonals per lane
+hipError_t launch_xdrop_group(int prune, const DiagArgs &a, hipStream_t s);
 hipError_t launch_walk_diag(const WalkArgs &a, hipStream_t s);
 
 } // namespace alnk

@@ -21,7 +21,10 @@
 //   XDROP the candidates [lo - 1, hi + 1] around the previous antidiagonal's
 //         first and last surviving cells; a candidate is pruned (H = E = F =
 //         minus infinity) when it scores more than X below the best score of
-//         the earlier antidiagonals.
+//         the earlier antidiagonals;
+//   ZDROP the same, with the limit widened by the candidate's distance from
+//         the best cell's diagonal (Sec. 9.3): pruned when it scores more
+//         than Z + |d - d_best| below that best score.
 // Cells outside the domain read as minus infinity.
 //
 // Traceback (BAND): per cell a 4-bit code -- bits 0-1 the term that gave H
@@ -68,6 +71,14 @@ __device__ __forceinline__ bool better_end(int s, int i, int j, int bs, int bi, 
   return j < bj;
 }
 
+// h + |a - b| for a, b in [0, 2^31): one v_sad_u32.  Z-drop compares
+// H + |d - d_best| with best - Z; diagonals are biased by kDiagBias so that
+// both operands are non-negative.
+constexpr int kDiagBias = 1 << 24;
+__device__ __forceinline__ int add_absdiff(uint32_t a, uint32_t b, int h) {
+  return (int)((max(a, b) - min(a, b)) + (uint32_t)h);
+}
+
 // Incremental tracker of the band's j-interval on antidiagonal k: the cells
 // (k - j, j) inside the matrix with c(i) - w <= j <= c(i) + w, c(i) =
 // floor(i*N/M).  As j grows, i = k - j shrinks and c(i) cannot grow, so both
@@ -107,6 +118,8 @@ template <int RD, int MODE, int PRUNE, bool TB, bool MM>
 __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8_t *smem,
                           const int8_t *smat) {
   static_assert(RD % 2 == 0, "a lane must hold whole diagonal pairs");
+  constexpr bool DYN = PRUNE == ALN_XDROP || PRUNE == ALN_ZDROP; // dynamic pruning
+  constexpr bool ZD = PRUNE == ALN_ZDROP;
   constexpr int W = 64 * RD;
   constexpr int HALF = RD / 2;
   const PairTask tk = a.tasks[task];
@@ -291,9 +304,13 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
     else right_x = dpp_wshl1(NEG32, FN[0]);
     // ---- SIMD update of this parity's diagonals
     const int elo = dlo - dbase, ehi = dhi - dbase; // domain in element index
-    const int thr = (PRUNE == ALN_XDROP) ? max(best - a.xdrop, NEG32 / 2 + 1) : NEG32;
+    const int thr = DYN ? max(best - a.xdrop, NEG32 / 2 + 1) : NEG32;
     int kkey = -1;                                  // (H << 11) | e of the best survivor
     const int d0 = dbase + e0 + par;
+    // Z-drop: cell m of this lane lies on diagonal d0 + 2m, so its distance
+    // to d_best is |(d0 + bias) - (d_best + bias - 2m)|
+    const uint32_t zd_lane = (uint32_t)(d0 + kDiagBias);
+    const int zd_best = best_j - best_i + kDiagBias;
     const int i0 = (k - d0) >> 1, j0 = (k + d0) >> 1;
     uint32_t cw = 0;
     uint32_t qw[NWB], rw[NWB];
@@ -314,6 +331,7 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
       if (MODE == ALN_LOCAL) h = max(h, 0);
       bool keep = (unsigned)(e - elo) <= (unsigned)(ehi - elo) && elo <= ehi;
       if (PRUNE == ALN_XDROP) keep = keep && h >= thr;
+      if (ZD) keep = keep && add_absdiff(zd_lane, (uint32_t)(zd_best - 2 * m), h) >= thr;
       // Outside a band only H needs the mask, with the open term formed
       // from the masked H: an E carries a real value only to the right of
       // the band and an F only to its left, and the band's edges move by
@@ -345,7 +363,8 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
         const int d = side ? -k : k;
         if (d < dlo || d > dhi) continue;
         const int hb = (MODE == ALN_LOCAL) ? 0 : go + k * ge;
-        const bool kb = !(PRUNE == ALN_XDROP && hb < thr);
+        bool kb = !(PRUNE == ALN_XDROP && hb < thr);
+        if (ZD) kb = add_absdiff((uint32_t)(d + kDiagBias), (uint32_t)zd_best, hb) >= thr;
         set_elem(d, kb ? hb : NEG32, kb ? hb + goe : NEG32, kb ? hb + goe : NEG32);
         if (TB) {
           const int e = d - dbase, ln = e / RD, x = e - ln * RD;
@@ -382,7 +401,7 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
         if (better_end(sc, bi, bj, best, best_i, best_j)) { best = sc; best_i = bi; best_j = bj; }
       }
     }
-    if (PRUNE == ALN_XDROP) {
+    if (DYN) {
       // first and last surviving diagonals
       int slo = 1 << 30, shi = -(1 << 30);
 #pragma unroll
@@ -485,7 +504,7 @@ __device__ __forceinline__ int row_max_all(int v) {
   return v;
 }
 
-template <int RD, bool MM>
+template <int RD, bool MM, bool ZD>
 __device__ void xdrop_group(const DiagArgs &a, int task4, int ntasks, int lane, uint8_t *smem,
                             const int8_t *smat) {
   static_assert(RD % 2 == 0, "a lane must hold whole diagonal pairs");
@@ -612,6 +631,8 @@ __device__ void xdrop_group(const DiagArgs &a, int task4, int ntasks, int lane, 
     int kkey = -1;
     const int d0 = dbase + e0 + par;
     const int i0 = (k - d0) >> 1, j0 = (k + d0) >> 1;
+    const uint32_t zd_lane = (uint32_t)(d0 + kDiagBias); // Z-drop: as in diag_task
+    const int zd_best = best_j - best_i + kDiagBias;
 #pragma unroll
     for (int m = 0; m < HALF; ++m) {
       const int x = 2 * m + par;
@@ -627,7 +648,8 @@ __device__ void xdrop_group(const DiagArgs &a, int task4, int ntasks, int lane, 
       const int t = h + goe;
       const int en = max(left + ge, t);
       const int fn = max(right + ge, t);
-      const bool keep = alive && (unsigned)(e - elo) <= (unsigned)(ehi - elo) && h >= thr;
+      const int hz = ZD ? add_absdiff(zd_lane, (uint32_t)(zd_best - 2 * m), h) : h;
+      const bool keep = alive && (unsigned)(e - elo) <= (unsigned)(ehi - elo) && hz >= thr;
       H[x] = keep ? h : NEG32;
       EN[x] = keep ? en : NEG32;
       FN[x] = keep ? fn : NEG32;
@@ -640,7 +662,8 @@ __device__ void xdrop_group(const DiagArgs &a, int task4, int ntasks, int lane, 
       const int d = side ? -k : k;
       const bool inb = alive && d >= dlo && d <= dhi;
       const int hb = go + k * ge;
-      const bool kb = hb >= thr;
+      const bool kb =
+          (ZD ? add_absdiff((uint32_t)(d + kDiagBias), (uint32_t)zd_best, hb) : hb) >= thr;
       set_elem(inb, d, kb ? hb : NEG32, kb ? hb + goe : NEG32, kb ? hb + goe : NEG32);
       if (inb && kb && gl == 0) kkey = max(kkey, (max(hb, -1) << 11) | (d - dbase));
     }
@@ -704,7 +727,7 @@ __device__ void xdrop_group(const DiagArgs &a, int task4, int ntasks, int lane, 
   }
 }
 
-template <int RD, bool MM>
+template <int RD, bool MM, bool ZD>
 __global__ __launch_bounds__(256) void xdrop_group_kernel(DiagArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -718,17 +741,24 @@ __global__ __launch_bounds__(256) void xdrop_group_kernel(DiagArgs a) {
   __syncthreads();
   const int ntasks = a.ntasks;
   for (int t4 = (blockIdx.x * 4 + wave) * 4; t4 < ntasks; t4 += gridDim.x * 16)
-    xdrop_group<RD, MM>(a, t4, ntasks, lane, smem + (size_t)wave * 4 * 2 * kGroupSeq, smat);
+    xdrop_group<RD, MM, ZD>(a, t4, ntasks, lane, smem + (size_t)wave * 4 * 2 * kGroupSeq, smat);
 }
 
-hipError_t launch_xdrop_group(const DiagArgs &a, hipStream_t s) {
-  if (a.ntasks <= 0) return hipSuccess;
+template <bool ZD>
+static void launch_xdrop_group_t(const DiagArgs &a, hipStream_t s) {
   const size_t lds = (size_t)4 * 4 * 2 * kGroupSeq + kMaxAlphabet * kMaxAlphabet;
   const int blocks = (a.ntasks + 15) / 16;
   if (a.match_mismatch)
-    hipLaunchKernelGGL((xdrop_group_kernel<8, true>), dim3(blocks), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((xdrop_group_kernel<8, true, ZD>), dim3(blocks), dim3(256), lds, s, a);
   else
-    hipLaunchKernelGGL((xdrop_group_kernel<8, false>), dim3(blocks), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((xdrop_group_kernel<8, false, ZD>), dim3(blocks), dim3(256), lds, s, a);
+}
+
+hipError_t launch_xdrop_group(int prune, const DiagArgs &a, hipStream_t s) {
+  if (a.ntasks <= 0) return hipSuccess;
+  if (prune == ALN_ZDROP) launch_xdrop_group_t<true>(a, s);
+  else if (prune == ALN_XDROP) launch_xdrop_group_t<false>(a, s);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -746,6 +776,7 @@ static hipError_t launch_diag_t(const DiagArgs &a, hipStream_t s) {
 template <int RD>
 static hipError_t launch_diag_r(int mode, int prune, bool tb, const DiagArgs &a, hipStream_t s) {
   if (prune == ALN_XDROP) return launch_diag_t<RD, ALN_EXTEND, ALN_XDROP, false>(a, s);
+  if (prune == ALN_ZDROP) return launch_diag_t<RD, ALN_EXTEND, ALN_ZDROP, false>(a, s);
   switch (mode) {
   case ALN_GLOBAL:
     return tb ? launch_diag_t<RD, ALN_GLOBAL, ALN_BAND, true>(a, s)

@@ -28,13 +28,15 @@ Workloads (codes: DNA A,C,G,T = 0..3; protein = 0..19):
                  an unrelated random flank of ceil(0.1 L) bases; EXTEND + X-drop
                  X = 100, +2/-4, open -4, extend -2.  Both sides are stored as
                  sequences read away from the seed (the left side reversed).
+  zdrop_ext      the xdrop_ext pairs (same seed, same bytes) under Z-drop with
+                 Z = 100, so the two pruning rules are compared on one input.
 """
 from dataclasses import dataclass, field
 
 import numpy as np
 
 GLOBAL, LOCAL, EXTEND = 0, 1, 2
-FULL, BAND, XDROP = 0, 1, 2
+FULL, BAND, XDROP, ZDROP = 0, 1, 2, 3
 
 _GAMMA = np.uint64(0x9E3779B97F4A7C15)
 _M1 = np.uint64(0xBF58476D1CE4E5B9)
@@ -385,11 +387,21 @@ def xdrop_ext(n=200000, seed=404, min_len=150, max_len=5000, xdrop=100, seed_len
     return b
 
 
+def zdrop_ext(n=200000, seed=404, min_len=150, max_len=5000, zdrop=100, seed_len=31):
+    """The xdrop_ext extension problems under Z-drop with threshold Z."""
+    b = xdrop_ext(n=n, seed=seed, min_len=min_len, max_len=max_len, xdrop=zdrop,
+                  seed_len=seed_len)
+    b.name = "zdrop_ext"
+    b.prune = ZDROP
+    return b
+
+
 WORKLOADS = {
     "nw_dna_1k": nw_dna_1k,
     "sw_protein": sw_protein,
     "band_long": band_long,
     "xdrop_ext": xdrop_ext,
+    "zdrop_ext": zdrop_ext,
 }
 
 
