@@ -83,8 +83,10 @@ enum {
   ALN_R_UNREACHABLE = 1, /* GLOBAL + BAND: (M,N) not connected to (0,0)      */
   ALN_R_CIGAR_CAP = 2,   /* the pair's CIGAR did not fit its slot           */
   ALN_R_BAD_SYMBOL = 3,  /* a code >= alphabet; other fields undefined       */
-  ALN_R_TOO_WIDE = 4     /* XDROP / ZDROP: the surviving region spanned more
+  ALN_R_TOO_WIDE = 4,    /* XDROP / ZDROP: the surviving region spanned more
                             than the widest kernel window (2042 diagonals)   */
+  ALN_R_INTERNAL = 5     /* a kernel's bounded internal wait expired (a defect
+                            of the library); other fields undefined          */
 };
 /* per-pair result flags */
 enum {

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libaln_hip.so")
 GLOBAL, LOCAL, EXTEND = 0, 1, 2
 FULL, BAND, XDROP, ZDROP = 0, 1, 2, 3
 W_AUTO, W_I16, W_I32 = 0, 1, 2
-R_OK, R_UNREACHABLE, R_CIGAR_CAP, R_BAD_SYMBOL, R_TOO_WIDE = 0, 1, 2, 3, 4
+R_OK, R_UNREACHABLE, R_CIGAR_CAP, R_BAD_SYMBOL, R_TOO_WIDE, R_INTERNAL = 0, 1, 2, 3, 4, 5
 E_INVAL, E_NOMEM, E_DEVICE, E_CAPACITY, E_UNSUPPORTED = -1, -2, -3, -4, -5
 F_I16_RERUN, F_WIDENED = 1, 2
 OP_I, OP_D, OP_EQ, OP_X = 1, 2, 7, 8

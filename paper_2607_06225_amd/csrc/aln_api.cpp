@@ -432,10 +432,13 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     int kind;
     int rows;
     double cost;
+    int waves = 1; // full matrix: wavefronts per pair (strip pipeline)
   };
   std::vector<Item> items;
   items.reserve(n);
   static const int kDiagRows[] = {2, 4, 8, 10, 16, 32};
+  int srows = ctx->tuning.valid ? ctx->tuning.strip_rows : 0;
+  if (ctx->force_strip_rows >= 0) srows = ctx->force_strip_rows;
   for (int32_t i = 0; i < n; ++i) {
     const int32_t M = pl->qlen[i], N = pl->rlen[i];
     if (M < 0 || N < 0) {
@@ -449,8 +452,6 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     Item it{i, K_STRIP, 0, 0.0};
     const bool band_is_full = p.prune == ALN_BAND && (M == 0 || p.band_w >= std::max(M, N));
     if (p.prune == ALN_FULL || band_is_full) {
-      int srows = ctx->tuning.valid ? ctx->tuning.strip_rows : 0;
-      if (ctx->force_strip_rows >= 0) srows = ctx->force_strip_rows;
       it.rows = srows ? srows : choose_strip_rows(M, N);
       it.cost = (double)M * N;
       pl->cells += (int64_t)M * N;
@@ -481,8 +482,30 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     }
     items.push_back(it);
   }
+  // Strip pipeline: when the full-matrix pairs are too few to give every
+  // SIMD a wavefront of its own, a pair of at least two 256-row strips runs
+  // on kStripPipeWaves wavefronts of one workgroup (4 rows per lane), its
+  // strips handed down through LDS -- unless a fixed strip height is tuned
+  // or forced.  Its boundary buffers hold whole rows, which bounds N.
+  if (srows == 0) {
+    const int G = alnk::kStripPipeWaves;
+    int64_t n_full = 0;
+    for (const Item &it : items) n_full += it.kind == K_STRIP;
+    const int64_t simds = 4LL * ctx->cus;
+    for (Item &it : items) {
+      if (it.kind != K_STRIP || n_full * 4 > simds * 3) continue;
+      const int32_t M = pl->qlen[it.pair], N = pl->rlen[it.pair];
+      const uint64_t bnd = align_up((uint64_t)(N + 1) * 8, 16);
+      const uint64_t prof = small ? 0 : align_up((uint64_t)hs.alphabet * 64 * 4, 16);
+      if (M > 64 * 4 && alnk::strip_lds_bytes(G, (int)bnd, (int)prof, N) <= 160 * 1024) {
+        it.rows = 4;
+        it.waves = G;
+      }
+    }
+  }
   std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
     if (a.kind != b.kind) return a.kind < b.kind;
+    if (a.waves != b.waves) return a.waves < b.waves;
     if (a.rows != b.rows) return a.rows < b.rows;
     return a.cost > b.cost;
   });
@@ -491,7 +514,8 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     size_t e = k;
     int32_t grpN = 0;
     bool multi = false;
-    while (e < items.size() && items[e].kind == items[k].kind && items[e].rows == items[k].rows) {
+    while (e < items.size() && items[e].kind == items[k].kind && items[e].rows == items[k].rows &&
+           items[e].waves == items[k].waves) {
       grpN = std::max(grpN, pl->rlen[items[e].pair]);
       if (items[e].kind == K_STRIP && pl->qlen[items[e].pair] > 64 * items[e].rows) multi = true;
       ++e;
@@ -509,10 +533,12 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     L.small = small;
     L.first = (int32_t)pl->tasks.size();
     L.count = (int32_t)(e - k);
+    L.waves = items[k].waves;
     if (L.kind == K_STRIP) {
       L.lds_bnd = multi ? (int32_t)align_up((uint64_t)(grpN + 1) * 8, 16) : 0;
       L.lds_prof = small ? 0 : (int32_t)align_up((uint64_t)hs.alphabet * 64 * L.rows, 16);
-      if (4LL * (L.lds_bnd + L.lds_prof) > 160 * 1024) {
+      L.max_n = grpN;
+      if (alnk::strip_lds_bytes(L.waves, L.lds_bnd, L.lds_prof, L.max_n) > 160 * 1024) {
         delete pl;
         return fail(ctx, ALN_E_UNSUPPORTED,
                     "full-matrix pairs with N = %d and M > %d need more LDS than a CU has", grpN,
@@ -699,6 +725,8 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
     sa.res = d_res;
     sa.lds_bnd = L.lds_bnd;
     sa.lds_prof = L.lds_prof;
+    sa.waves = 1;
+    sa.max_n = 0;
     HIP_TRY(ctx, timed_launch(ctx, "strip_i32_rerun", st, [&] {
               return alnk::launch_strip(L.rows, L.mode, false, L.small, sa, st);
             }));
@@ -753,6 +781,8 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
     sa.res = d_res;
     sa.lds_bnd = L.lds_bnd;
     sa.lds_prof = L.lds_prof;
+    sa.waves = L.waves;
+    sa.max_n = L.max_n;
     if (!per_pair) {
       sa.tasks = dtasks + L.first;
       sa.ntasks = L.count;

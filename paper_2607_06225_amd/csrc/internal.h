@@ -58,7 +58,15 @@ struct StripArgs {
   aln_result *res;
   int32_t lds_bnd;    // bytes of LDS per wave for the inter-strip row (0: none)
   int32_t lds_prof;   // bytes of LDS per wave for the query profile (0: none)
+  int32_t waves;      // wavefronts per pair: 1, or kStripPipeWaves (a pipeline
+                      // of strips handed over through LDS; 4 rows per lane)
+  int32_t max_n;      // pipeline: largest N of the launch (reference codes in LDS)
 };
+
+// Wavefronts per pair of the full-matrix strip pipeline.
+constexpr int kStripPipeWaves = 4;
+// LDS bytes of one strip-kernel workgroup.
+size_t strip_lds_bytes(int waves, int lds_bnd, int lds_prof, int max_n);
 
 struct WalkArgs {
   BatchPtrs b;

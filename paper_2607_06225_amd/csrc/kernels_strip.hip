@@ -33,22 +33,70 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
-template <int R, int MODE, bool TB, bool SMALLA>
-__device__ void strip_task(const StripArgs &a, int task, int wave, int lane, uint8_t *smem);
+// Strip pipeline (G > 1 wavefronts per pair).  Wave w of the workgroup runs
+// strips w, w + G, w + 2G, ...; strip s reads strip s-1's bottom row (H, F per
+// column) from LDS buffer (s-1) mod G as soon as it is written, so G strips
+// advance together, each about 128 columns behind the one above.  Two LDS
+// counters per buffer carry stamps s*(N+1) + column: `prog` (columns of
+// strip s written, published every 64 steps) and `cons` (columns of strip s
+// loaded by strip s+1).  A strip waits only for the strip above it (prog)
+// and, before reusing a buffer, for the previous generation to have been
+// read in full (cons); both point to earlier strips, so every wait ends.
+// The spin bound only turns a broken invariant into ALN_R_INTERNAL instead
+// of a hung workgroup.
+constexpr int kSpinLimit = 1 << 22;
+constexpr int kStripCtrWords = 7; // per pipeline wave: prog, cons, 5 result words
 
-// One wavefront per task; waves stride over the task list so that a grid
-// smaller than the list (device-side counts) still covers it.
-template <int R, int MODE, bool TB, bool SMALLA>
-__global__ __launch_bounds__(256) void strip_kernel(StripArgs a) {
-  extern __shared__ __align__(16) uint8_t smem[];
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int ntasks = a.dyn_ntasks ? min(*a.dyn_ntasks, a.ntasks) : a.ntasks;
-  for (int task = blockIdx.x * 4 + wave; task < ntasks; task += gridDim.x * 4)
-    strip_task<R, MODE, TB, SMALLA>(a, task, wave, lane, smem);
+__device__ __forceinline__ bool lds_wait_geq(int *ctr, int need) {
+  for (int k = 0; k < kSpinLimit; ++k) {
+    const int v = __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+    if (v >= need) return true;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return false;
+}
+__device__ __forceinline__ void lds_publish(int *ctr, int v) {
+  __hip_atomic_store(ctr, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-template <int R, int MODE, bool TB, bool SMALLA>
+// A chunk's feeds are loaded once and read over 64 steps.  Read directly,
+// the loaded register makes every step wait for all memory operations in
+// flight (the traceback stores included); one ALU copy at the chunk start
+// (xor with a run-time zero the compiler cannot fold) takes that wait once.
+__device__ __forceinline__ int settle(int v, int zero) { return v ^ zero; }
+
+// end order: higher score, then smaller i, then smaller j
+__device__ __forceinline__ bool strip_better(int s, int i, int j, int bs, int bi, int bj) {
+  if (s != bs) return s > bs;
+  if (i != bi) return i < bi;
+  return j < bj;
+}
+
+template <int R, int MODE, bool TB, bool SMALLA, int G>
+__device__ void strip_task(const StripArgs &a, int task, int wave, int lane, uint8_t *smem);
+
+// G == 1: one wavefront per task, four tasks per workgroup; waves stride over
+// the task list so that a grid smaller than the list (device-side counts)
+// still covers it.  G > 1: one workgroup of G wavefronts per task.
+template <int R, int MODE, bool TB, bool SMALLA, int G>
+__global__ __launch_bounds__(256) void strip_kernel(StripArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int ntasks = a.dyn_ntasks ? min(*a.dyn_ntasks, a.ntasks) : a.ntasks;
+  if (G == 1) {
+    for (int task = blockIdx.x * 4 + wave; task < ntasks; task += gridDim.x * 4)
+      strip_task<R, MODE, TB, SMALLA, 1>(a, task, wave, lane, smem);
+  } else {
+    for (int task = blockIdx.x; task < ntasks; task += gridDim.x) {
+      strip_task<R, MODE, TB, SMALLA, G>(a, task, wave, lane, smem);
+      __syncthreads(); // the next task re-initialises the counters
+    }
+  }
+}
+
+template <int R, int MODE, bool TB, bool SMALLA, int G>
 __device__ void strip_task(const StripArgs &a, int task, int wave, int lane, uint8_t *smem) {
   const PairTask tk = a.tasks[task];
   const int p = tk.pair;
@@ -62,7 +110,7 @@ __device__ void strip_task(const StripArgs &a, int task, int wave, int lane, uin
   aln_result *res = a.res + p;
 
   if (M == 0 || N == 0) {
-    if (lane == 0) {
+    if (lane == 0 && wave == (G == 1 ? wave : 0)) {
       if (MODE == ALN_GLOBAL) {
         res->score = (M + N == 0) ? 0 : go + (M + N) * ge;
         res->q_end = M;
@@ -77,9 +125,25 @@ __device__ void strip_task(const StripArgs &a, int task, int wave, int lane, uin
     return;
   }
 
-  uint8_t *wbase = smem + (size_t)wave * (a.lds_bnd + a.lds_prof);
-  int2 *bnd = reinterpret_cast<int2 *>(wbase);
-  int8_t *prof = reinterpret_cast<int8_t *>(wbase + a.lds_bnd);
+  // LDS.  G == 1: per wave [boundary row | profile].  G > 1: [G boundary
+  // buffers | G profiles | prog[G], cons[G], per-wave results[5G] |
+  // reference codes].  With the reference in LDS the step loop issues no
+  // global load, so no step waits on the traceback stores in flight.
+  uint8_t *wbase = (G == 1) ? smem + (size_t)wave * (a.lds_bnd + a.lds_prof) : smem;
+  int8_t *prof = reinterpret_cast<int8_t *>(
+      (G == 1) ? wbase + a.lds_bnd : smem + (size_t)G * a.lds_bnd + (size_t)wave * a.lds_prof);
+  int *ctr = reinterpret_cast<int *>(smem + (size_t)G * (a.lds_bnd + a.lds_prof));
+  int *prog = ctr, *cons = ctr + G, *red = ctr + 2 * G;
+  uint8_t *rseq = reinterpret_cast<uint8_t *>(ctr + kStripCtrWords * G);
+  auto ring = [&](int s) { return reinterpret_cast<int2 *>(wbase + (size_t)(G == 1 ? 0 : s % G) * a.lds_bnd); };
+  auto stamp = [&](int s, int col) { return s * (N + 1) + col; };
+  if (G > 1) {
+    if (threadIdx.x < 2 * G) ctr[threadIdx.x] = -1;
+    for (int k = threadIdx.x; k < N + 128; k += 64 * G) rseq[k] = k < N ? Rs[k] : 0;
+    __syncthreads();
+  }
+  bool ok = true;
+  const int zero = a.waves - G; // 0: the launcher matches G to a.waves
 
   constexpr int HS = 64 * R;      // strip height
   constexpr int NW = (R + 7) / 8; // code dwords per lane per step
@@ -90,7 +154,7 @@ __device__ void strip_task(const StripArgs &a, int task, int wave, int lane, uin
   int best = 0, best_i = 0, best_j = 0; // LOCAL / EXTEND (wave-uniform)
   int gh = 0;                           // GLOBAL: H(M,N)
 
-  for (int s = 0; s < nstrips; ++s) {
+  for (int s = (G == 1 ? 0 : wave); s < nstrips; s += G) {
     const int itop = s * HS + lane * R + 1;
 
     // substitution scores of this lane's rows (padding rows: -128)
@@ -135,35 +199,33 @@ __device__ void strip_task(const StripArgs &a, int task, int wave, int lane, uin
     int hd_top = (itop - 1 == 0) ? 0 : ((MODE == ALN_LOCAL) ? 0 : go + (itop - 1) * ge);
     int out_t = 0, out_f = NEG32, out_c = 0;
 
-    // 64-column chunks of lane-0 feeds: reference codes and (strip > 0) the
-    // previous strip's bottom row; double-buffered
-    int chr_cur = 0, chr_nxt = 0, bh_cur = 0, bh_nxt = 0, bf_cur = 0, bf_nxt = 0;
-    {
-      const int j0 = lane, j1 = 64 + lane;
-      chr_cur = (j0 < N) ? Rs[j0] : 0;
-      chr_nxt = (j1 < N) ? Rs[j1] : 0;
-      if (s > 0) {
-        int2 v0 = bnd[min(j0 + 1, N)];
-        int2 v1 = bnd[min(j1 + 1, N)];
-        bh_cur = v0.x; bf_cur = v0.y;
-        bh_nxt = v1.x; bf_nxt = v1.y;
-      }
-    }
-    const bool write_bnd = multi && (s + 1 < nstrips) && lane == 63;
+    // lane-0 feeds, 64 columns at a time, read when the chunk starts: the
+    // reference codes and, for s > 0, the strip above's bottom row (LDS).  A
+    // global load carried across steps would make every step wait for the
+    // traceback stores in flight; loaded at the chunk start, the wait comes
+    // once per 64 steps.
+    const int2 *bnd_in = ring(s + G - 1);
+    int2 *bnd_out = ring(s);
+    const bool has_reader = multi && (s + 1 < nstrips);
+    const bool write_bnd = has_reader && lane == 63;
+    if (G > 1 && has_reader && s >= G) // buffer free: the previous generation was read in full
+      ok = ok && lds_wait_geq(&cons[s % G], stamp(s - G, N));
+    int chr_cur = 0;
+    int bh_cur = 0, bf_cur = 0;
     uint8_t *tbp = TB ? (a.tb + tk.tb_off + (size_t)s * T * 64 * (R / 2)) : nullptr;
 
     for (int t = 0; t < T; ++t) {
       const int tl = t & 63;
-      if (tl == 0 && t > 0) {
-        chr_cur = chr_nxt;
-        bh_cur = bh_nxt;
-        bf_cur = bf_nxt;
-        const int jn = t + 64 + lane;
-        chr_nxt = (jn < N) ? Rs[jn] : 0;
+      if (tl == 0) {
+        if (G > 1) chr_cur = settle(rseq[t + lane], zero); // t + lane < N + 127
+        else chr_cur = settle((t + lane < N) ? Rs[t + lane] : 0, zero);
         if (s > 0) {
-          int2 v = bnd[min(jn + 1, N)];
-          bh_nxt = v.x;
-          bf_nxt = v.y;
+          const int upto = min(t + 64, N); // columns t+1 .. t+64
+          if (G > 1) ok = ok && lds_wait_geq(&prog[(s - 1) % G], stamp(s - 1, upto));
+          const int2 v = bnd_in[min(t + lane + 1, N)];
+          bh_cur = settle(v.x, zero);
+          bf_cur = settle(v.y, zero);
+          if (G > 1) lds_publish(&cons[(s - 1) % G], stamp(s - 1, upto));
         }
       }
       const int feed_c = __builtin_amdgcn_readlane(chr_cur, tl);
@@ -226,14 +288,21 @@ __device__ void strip_task(const StripArgs &a, int task, int wave, int lane, uin
         out_t = tu;
         out_f = fu;
         out_c = in_c;
-        if (write_bnd) bnd[j] = make_int2(Hl[R - 1], fu);
+        if (write_bnd) bnd_out[j] = make_int2(Hl[R - 1], fu);
         if (TB) {
-          uint32_t *dst = reinterpret_cast<uint32_t *>(tbp + ((size_t)t * 64 + lane) * (R / 2));
+          if constexpr (R / 2 < 4) {
+            *reinterpret_cast<uint16_t *>(tbp + ((size_t)t * 64 + lane) * (R / 2)) = (uint16_t)cw[0];
+          } else {
+            uint32_t *dst = reinterpret_cast<uint32_t *>(tbp + ((size_t)t * 64 + lane) * (R / 2));
 #pragma unroll
-          for (int k = 0; k < NW; ++k) dst[k] = cw[k];
+            for (int k = 0; k < NW; ++k) dst[k] = cw[k];
+          }
         }
       }
+      // columns <= t - 63 of this strip's bottom row are written
+      if (G > 1 && has_reader && tl == 63) lds_publish(&prog[s % G], stamp(s, min(max(t - 63, 0), N)));
     }
+    if (G > 1 && has_reader) lds_publish(&prog[s % G], stamp(s, N));
 
     if (MODE == ALN_GLOBAL) {
       if (s == nstrips - 1) {
@@ -269,18 +338,45 @@ __device__ void strip_task(const StripArgs &a, int task, int wave, int lane, uin
     }
   }
 
-  if (lane == 0) {
-    if (MODE == ALN_GLOBAL) {
-      res->score = gh;
-      res->q_end = M;
-      res->r_end = N;
-    } else {
-      res->score = best;
-      res->q_end = best_i;
-      res->r_end = best_j;
+  if (G > 1) {
+    // combine the waves' results: within a wave strips run in i order; across
+    // waves the end order (score, then i, then j) decides
+    if (lane == 0) {
+      red[5 * wave + 0] = best;
+      red[5 * wave + 1] = best_i;
+      red[5 * wave + 2] = best_j;
+      red[5 * wave + 3] = gh;
+      red[5 * wave + 4] = ok ? 1 : 0;
     }
-    res->cells = (int64_t)M * N;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    bool all_ok = true;
+    best = red[0];
+    best_i = red[1];
+    best_j = red[2];
+    for (int w = 0; w < G; ++w) {
+      all_ok = all_ok && red[5 * w + 4] != 0;
+      if (w > 0 && strip_better(red[5 * w], red[5 * w + 1], red[5 * w + 2], best, best_i, best_j)) {
+        best = red[5 * w];
+        best_i = red[5 * w + 1];
+        best_j = red[5 * w + 2];
+      }
+    }
+    gh = red[5 * ((nstrips - 1) % G) + 3];
+    if (!all_ok) res->status = ALN_R_INTERNAL;
+  } else if (lane != 0) {
+    return;
   }
+  if (MODE == ALN_GLOBAL) {
+    res->score = gh;
+    res->q_end = M;
+    res->r_end = N;
+  } else {
+    res->score = best;
+    res->q_end = best_i;
+    res->r_end = best_j;
+  }
+  res->cells = (int64_t)M * N;
 }
 
 // ---------------------------------------------------------------- validate
@@ -322,47 +418,64 @@ hipError_t launch_validate(const ValidateArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int R, int MODE, bool TB, bool SMALLA>
+// LDS of a G-wavefront pipeline workgroup beyond its buffers and profiles:
+// prog[G], cons[G] and five result words per wave, then the reference codes
+// (N + 128 bytes, the last 128 zero)
+inline size_t strip_extra_bytes(int G, int n) {
+  return G > 1 ? (size_t)kStripCtrWords * G * 4 + (((size_t)n + 128 + 15) & ~(size_t)15) : 0;
+}
+
+template <int R, int MODE, bool TB, bool SMALLA, int G>
 static hipError_t launch_strip_t(const StripArgs &a, hipStream_t s) {
-  const size_t lds = (size_t)4 * (a.lds_bnd + a.lds_prof);
-  auto kern = strip_kernel<R, MODE, TB, SMALLA>;
+  const size_t per = (size_t)(a.lds_bnd + a.lds_prof);
+  const size_t lds = (G == 1 ? 4 * per : G * per) + strip_extra_bytes(G, a.max_n);
+  auto kern = strip_kernel<R, MODE, TB, SMALLA, G>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  int blocks = (a.ntasks + 3) / 4;
+  int blocks = G == 1 ? (a.ntasks + 3) / 4 : a.ntasks;
   if (a.dyn_ntasks) blocks = min(blocks, 1024);
-  hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, s, a);
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * (G == 1 ? 4 : G)), lds, s, a);
   return hipGetLastError();
 }
 
-template <int R, int MODE>
+template <int R, int MODE, int G>
 static hipError_t launch_strip_m(bool tb, bool small, const StripArgs &a, hipStream_t s) {
-  if (tb) return small ? launch_strip_t<R, MODE, true, true>(a, s) : launch_strip_t<R, MODE, true, false>(a, s);
-  return small ? launch_strip_t<R, MODE, false, true>(a, s) : launch_strip_t<R, MODE, false, false>(a, s);
+  if (tb) return small ? launch_strip_t<R, MODE, true, true, G>(a, s) : launch_strip_t<R, MODE, true, false, G>(a, s);
+  return small ? launch_strip_t<R, MODE, false, true, G>(a, s) : launch_strip_t<R, MODE, false, false, G>(a, s);
 }
 
-template <int R>
+template <int R, int G>
 static hipError_t launch_strip_r(int mode, bool tb, bool small, const StripArgs &a, hipStream_t s) {
   switch (mode) {
-  case ALN_GLOBAL: return launch_strip_m<R, ALN_GLOBAL>(tb, small, a, s);
-  case ALN_LOCAL: return launch_strip_m<R, ALN_LOCAL>(tb, small, a, s);
-  default: return launch_strip_m<R, ALN_EXTEND>(tb, small, a, s);
+  case ALN_GLOBAL: return launch_strip_m<R, ALN_GLOBAL, G>(tb, small, a, s);
+  case ALN_LOCAL: return launch_strip_m<R, ALN_LOCAL, G>(tb, small, a, s);
+  default: return launch_strip_m<R, ALN_EXTEND, G>(tb, small, a, s);
   }
+}
+
+size_t strip_lds_bytes(int waves, int lds_bnd, int lds_prof, int max_n) {
+  const size_t per = (size_t)(lds_bnd + lds_prof);
+  return waves == 1 ? 4 * per : (size_t)waves * per + strip_extra_bytes(waves, max_n);
 }
 
 hipError_t launch_strip(int rows, int mode, bool tb, bool small_alphabet, const StripArgs &a,
                         hipStream_t s) {
   if (a.ntasks <= 0) return hipSuccess;
+  if (a.waves == kStripPipeWaves) {
+    if (rows == 4) return launch_strip_r<4, kStripPipeWaves>(mode, tb, small_alphabet, a, s);
+    return hipErrorInvalidValue;
+  }
+  if (a.waves != 1) return hipErrorInvalidValue;
   switch (rows) {
-  case 8: return launch_strip_r<8>(mode, tb, small_alphabet, a, s);
-  case 16: return launch_strip_r<16>(mode, tb, small_alphabet, a, s);
-  case 24: return launch_strip_r<24>(mode, tb, small_alphabet, a, s);
-  case 32: return launch_strip_r<32>(mode, tb, small_alphabet, a, s);
+  case 8: return launch_strip_r<8, 1>(mode, tb, small_alphabet, a, s);
+  case 16: return launch_strip_r<16, 1>(mode, tb, small_alphabet, a, s);
+  case 24: return launch_strip_r<24, 1>(mode, tb, small_alphabet, a, s);
+  case 32: return launch_strip_r<32, 1>(mode, tb, small_alphabet, a, s);
   default: return hipErrorInvalidValue;
   }
 }
-
 
 } // namespace alnk

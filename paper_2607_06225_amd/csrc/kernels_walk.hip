@@ -87,7 +87,7 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
   const uint8_t *tb = a.tb + tk.tb_off;
   const int R = uni(tk.rows), HB = R / 2, T = N + 63;
   const int invR = (65536 + R - 1) / R; // v / R = (v * invR) >> 16 for 0 <= v < 64
-  const int LTB = R <= 16 ? 5 : 4;      // log2 of the block's steps
+  const int LTB = R <= 4 ? 7 : (R <= 8 ? 6 : (R <= 16 ? 5 : 4)); // log2 of the block's steps
   const int TBK = 1 << LTB;
   const int NTB = (T + TBK - 1) >> LTB;
   const bool local = a.mode == ALN_LOCAL;

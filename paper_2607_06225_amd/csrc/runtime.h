@@ -50,6 +50,8 @@ struct LaunchDesc {
   int32_t lds_bnd;
   int32_t lds_prof;
   int sides = 1; // X-drop: extension sides per wavefront
+  int waves = 1; // full matrix: wavefronts per pair (strip pipeline)
+  int max_n = 0; // largest reference length of the launch
 };
 
 constexpr uint64_t kAlign = 256;

@@ -122,3 +122,31 @@ def test_sw_protein_sample_int32(ctx):
     res, cig = run(ctx, b, width=aln.W_I32)
     ores = oracle_batch(b)
     assert compare(b, res, cig, ores) == []
+
+
+@pytest.mark.parametrize("cigar", [False, True])
+def test_local_end_ties_across_pipeline_strips(ctx, cigar):
+    """Equal best local scores in different 256-row strips, which different
+    wavefronts of the strip pipeline evaluate: the end cell is the one with
+    the smallest i, then the smallest j."""
+    rng = np.random.default_rng(41)
+    mat = W.dna_matrix(2, -4)
+    qs, rs = [], []
+    for gap in (200, 600, 1100):
+        x = rng.integers(0, 4, size=100).astype(np.uint8)
+        junk = rng.integers(0, 4, size=gap).astype(np.uint8)
+        qs.append(np.concatenate([x, junk, x, junk, x]))
+        rs.append(np.concatenate([x, rng.integers(0, 4, size=50).astype(np.uint8), x]))
+    b = W.pack_pairs(qs, rs, mat, -4, -2, W.LOCAL, W.FULL, want_cigar=cigar, name="ties")
+    res, cig = run(ctx, b)
+    assert compare(b, res, cig, oracle_batch(b)) == []
+
+
+def test_many_pairs_run_one_wavefront_each(ctx):
+    """More full-matrix pairs than three quarters of the SIMDs: the planner
+    keeps one wavefront per pair (multi-strip pairs included)."""
+    rng = np.random.default_rng(43)
+    lengths = [(int(rng.integers(200, 1400)), int(rng.integers(50, 400))) for _ in range(800)]
+    b = edge_batch(W.dna_matrix(2, -4), -4, -2, W.GLOBAL, True, 4343, lengths, 4)
+    res, cig = run(ctx, b)
+    assert compare(b, res, cig, oracle_batch(b)) == []
