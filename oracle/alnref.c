@@ -158,6 +158,76 @@ static int32_t ob_emit(const opbuf *b, uint32_t *cigar, int32_t cap) {
 }
 
 /* ------------------------------------------------------------------ */
+/* Traceback (Sec. 2: the optimal path through the matrix), shared by the  */
+/* row-major fill and the antidiagonal X-drop / Z-drop fill.  get(ctx, w,  */
+/* i, j) returns H (w = 0), E (w = 1) or F (w = 2) of a stored cell and    */
+/* NEG for any cell that was not evaluated or was pruned.  In each state   */
+/* the first option whose equality holds is taken:                         */
+/*   H: (LOCAL and H == 0 -> stop), diagonal, then E, then F;              */
+/*   E/F: open (from H) before extend;                                     */
+/* on row 0 the path runs left (D) and on column 0 up (I) to (0,0).        */
+/* ------------------------------------------------------------------ */
+typedef int64_t (*cell_get)(const void *ctx, int which, int64_t i, int64_t j);
+
+static int traceback(cell_get get, const void *ctx, const int32_t *mat, int32_t A, int64_t o,
+                     int64_t e, int local, const uint8_t *q, const uint8_t *r, int64_t ei,
+                     int64_t ej, uint32_t *cigar, int32_t cigar_cap, alnref_out *out) {
+  opbuf ob = {0, 0, 0};
+  int64_t i = ei, j = ej;
+  int state = 0; /* 0 = H, 1 = E, 2 = F */
+  int rc = 0;
+  for (;;) {
+    if (state == 0) {
+      if (i == 0 && j == 0) break;
+      int64_t hv = get(ctx, 0, i, j);
+      if (local && hv == 0) break;
+      if (i == 0) { rc |= ob_push(&ob, ALNREF_OP_D); j--; continue; }
+      if (j == 0) { rc |= ob_push(&ob, ALNREF_OP_I); i--; continue; }
+      int64_t sub = mat[(int64_t)q[i - 1] * A + r[j - 1]];
+      int64_t hd = get(ctx, 0, i - 1, j - 1);
+      if (!IS_NEG(hd) && hv == hd + sub) {
+        rc |= ob_push(&ob, q[i - 1] == r[j - 1] ? ALNREF_OP_EQ : ALNREF_OP_X);
+        i--; j--;
+      } else if (hv == get(ctx, 1, i, j)) {
+        state = 1;
+      } else {
+        state = 2;
+      }
+    } else if (state == 1) {
+      rc |= ob_push(&ob, ALNREF_OP_D);
+      int64_t ev = get(ctx, 1, i, j);
+      int64_t hl = get(ctx, 0, i, j - 1);
+      if (!IS_NEG(hl) && ev == hl + o + e) state = 0;
+      j--;
+    } else {
+      rc |= ob_push(&ob, ALNREF_OP_I);
+      int64_t fv = get(ctx, 2, i, j);
+      int64_t hu = get(ctx, 0, i - 1, j);
+      if (!IS_NEG(hu) && fv == hu + o + e) state = 0;
+      i--;
+    }
+    if (rc) break;
+  }
+  if (rc) { free(ob.ops); return ALNREF_NOMEM; }
+  out->q_begin = (int32_t)i;
+  out->r_begin = (int32_t)j;
+  int32_t nw = ob_emit(&ob, cigar, cigar_cap);
+  free(ob.ops);
+  if (nw < 0) {
+    out->cigar_len = 0;
+    out->status = ALNREF_CIGAR_CAP;
+    return ALNREF_CIGAR_CAP;
+  }
+  out->cigar_len = nw;
+  return ALNREF_OK;
+}
+
+static int64_t rows_get(const void *ctx, int which, int64_t i, int64_t j) {
+  const rowstore *s = (const rowstore *)ctx;
+  return rs_get(s, which == 0 ? s->H : (which == 1 ? s->E : s->F), i, j);
+}
+
+/* ------------------------------------------------------------------ */
 /* FULL and BAND: row-major fill of the whole (or banded) matrix.        */
 /* ------------------------------------------------------------------ */
 static int align_rows(const int32_t *mat, int32_t A, int64_t o, int64_t e,
@@ -228,58 +298,11 @@ static int align_rows(const int32_t *mat, int32_t A, int64_t o, int64_t e,
   out->r_begin = 0;
 
   if (cigar) {
-    /* Traceback (Sec. 2: the optimal path through the matrix).  In each
-     * state the first option whose equality holds is taken:
-     *   H: (LOCAL and H == 0 -> stop), diagonal, then E, then F;
-     *   E/F: open (from H) before extend.                               */
-    opbuf ob = {0, 0, 0};
-    int64_t i = ei, j = ej;
-    int state = 0; /* 0 = H, 1 = E, 2 = F */
-    int rc = 0;
-    for (;;) {
-      if (state == 0) {
-        if (i == 0 && j == 0) break;
-        int64_t hv = rs_get(&s, s.H, i, j);
-        if (local && hv == 0) break;
-        if (i == 0) { rc |= ob_push(&ob, ALNREF_OP_D); j--; continue; }
-        if (j == 0) { rc |= ob_push(&ob, ALNREF_OP_I); i--; continue; }
-        int64_t sub = mat[(int64_t)q[i - 1] * A + r[j - 1]];
-        int64_t hd = rs_get(&s, s.H, i - 1, j - 1);
-        if (!IS_NEG(hd) && hv == hd + sub) {
-          rc |= ob_push(&ob, q[i - 1] == r[j - 1] ? ALNREF_OP_EQ : ALNREF_OP_X);
-          i--; j--;
-        } else if (hv == rs_get(&s, s.E, i, j)) {
-          state = 1;
-        } else {
-          state = 2;
-        }
-      } else if (state == 1) {
-        rc |= ob_push(&ob, ALNREF_OP_D);
-        int64_t ev = rs_get(&s, s.E, i, j);
-        int64_t hl = rs_get(&s, s.H, i, j - 1);
-        if (!IS_NEG(hl) && ev == hl + o + e) state = 0;
-        j--;
-      } else {
-        rc |= ob_push(&ob, ALNREF_OP_I);
-        int64_t fv = rs_get(&s, s.F, i, j);
-        int64_t hu = rs_get(&s, s.H, i - 1, j);
-        if (!IS_NEG(hu) && fv == hu + o + e) state = 0;
-        i--;
-      }
-      if (rc) break;
-    }
-    if (rc) { free(ob.ops); rs_free(&s); return ALNREF_NOMEM; }
-    out->q_begin = (int32_t)i;
-    out->r_begin = (int32_t)j;
-    int32_t nw = ob_emit(&ob, cigar, cigar_cap);
-    free(ob.ops);
-    if (nw < 0) {
-      out->cigar_len = 0;
-      out->status = ALNREF_CIGAR_CAP;
+    int rc = traceback(rows_get, &s, mat, A, o, e, local, q, r, ei, ej, cigar, cigar_cap, out);
+    if (rc != ALNREF_OK) {
       rs_free(&s);
-      return ALNREF_CIGAR_CAP;
+      return rc;
     }
-    out->cigar_len = nw;
   }
   rs_free(&s);
   out->status = ALNREF_OK;
@@ -301,10 +324,66 @@ static int64_t ad_get(const adiag *a, const int64_t *A, int64_t j) {
   return A[j];
 }
 
+/* Every antidiagonal kept for the traceback: antidiagonal k holds the
+ * candidates lo[k]..hi[k] (in j) at off[k] in the value arrays; cells outside
+ * them, pruned cells and antidiagonals after the last one read NEG. */
+typedef struct {
+  int64_t nk;              /* antidiagonals stored: 0 .. nk-1 */
+  int64_t *lo, *hi, *off;  /* per antidiagonal, room for M+N+1 */
+  int64_t *H, *E, *F;
+  int64_t used, cap;
+} adstore;
+
+static void as_free(adstore *s) {
+  free(s->lo); free(s->hi); free(s->off); free(s->H); free(s->E); free(s->F);
+}
+
+static int as_push(adstore *s, const adiag *a, int64_t k) {
+  int64_t n = a->hi >= a->lo ? a->hi - a->lo + 1 : 0;
+  if (s->used + n > s->cap) {
+    int64_t nc = s->cap ? s->cap : 1024;
+    while (nc < s->used + n) nc *= 2;
+    int64_t *h = (int64_t *)realloc(s->H, sizeof(int64_t) * (size_t)nc);
+    if (h) s->H = h;
+    int64_t *e2 = (int64_t *)realloc(s->E, sizeof(int64_t) * (size_t)nc);
+    if (e2) s->E = e2;
+    int64_t *f = (int64_t *)realloc(s->F, sizeof(int64_t) * (size_t)nc);
+    if (f) s->F = f;
+    if (!h || !e2 || !f) return -1;
+    s->cap = nc;
+  }
+  s->lo[k] = a->lo; s->hi[k] = a->hi; s->off[k] = s->used;
+  for (int64_t j = a->lo; j <= a->hi; j++) {
+    s->H[s->used + j - a->lo] = a->H[j];
+    s->E[s->used + j - a->lo] = a->E[j];
+    s->F[s->used + j - a->lo] = a->F[j];
+  }
+  s->used += n;
+  s->nk = k + 1;
+  return 0;
+}
+
+static int64_t xs_get(const void *ctx, int which, int64_t i, int64_t j) {
+  const adstore *s = (const adstore *)ctx;
+  int64_t k = i + j;
+  if (i < 0 || j < 0 || k >= s->nk || j < s->lo[k] || j > s->hi[k]) return NEG;
+  const int64_t *A = which == 0 ? s->H : (which == 1 ? s->E : s->F);
+  return A[s->off[k] + j - s->lo[k]];
+}
+
 /* zdrop = 0: X-drop with threshold X; zdrop = 1: Z-drop with Z = X. */
 static int align_xdrop(const int32_t *mat, int32_t Al, int64_t o, int64_t e,
                        int64_t X, int zdrop, const uint8_t *q, int32_t M,
-                       const uint8_t *r, int32_t N, alnref_out *out) {
+                       const uint8_t *r, int32_t N, uint32_t *cigar,
+                       int32_t cigar_cap, alnref_out *out) {
+  adstore st;
+  memset(&st, 0, sizeof(st));
+  if (cigar) {
+    st.lo = (int64_t *)malloc(sizeof(int64_t) * (size_t)(M + N + 1));
+    st.hi = (int64_t *)malloc(sizeof(int64_t) * (size_t)(M + N + 1));
+    st.off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(M + N + 1));
+    if (!st.lo || !st.hi || !st.off) { as_free(&st); return ALNREF_NOMEM; }
+  }
   adiag buf[3];
   for (int t = 0; t < 3; t++) {
     buf[t].H = (int64_t *)malloc(sizeof(int64_t) * (size_t)(N + 1));
@@ -313,6 +392,7 @@ static int align_xdrop(const int32_t *mat, int32_t Al, int64_t o, int64_t e,
     buf[t].lo = 1; buf[t].hi = 0;
     if (!buf[t].H || !buf[t].E || !buf[t].F) {
       for (int u = 0; u <= t; u++) { free(buf[u].H); free(buf[u].E); free(buf[u].F); }
+      as_free(&st);
       return ALNREF_NOMEM;
     }
   }
@@ -320,9 +400,14 @@ static int align_xdrop(const int32_t *mat, int32_t Al, int64_t o, int64_t e,
   adiag *cur = &buf[0], *p1 = &buf[1], *p2 = &buf[2];
   cur->lo = 0; cur->hi = 0;
   cur->H[0] = 0; cur->E[0] = NEG; cur->F[0] = NEG;
+  int rc = 0;
+  if (cigar) rc |= as_push(&st, cur, 0);
   int64_t best = 0, bi = 0, bj = 0; /* best_{k-1}: running max through k-1 */
   int64_t lo = 0, hi = 0;           /* surviving range of the last antidiagonal */
   int64_t cells = 0;
+  /* widest candidate range so far, in diagonals (d = 2j - k spans 2(hi-lo)),
+   * and its value when the best cell was last found */
+  int64_t span = 0, best_span = 0;
 
   for (int64_t k = 1; k <= (int64_t)M + N; k++) {
     adiag *t = p2; p2 = p1; p1 = cur; cur = t; /* rotate: cur <- k */
@@ -332,6 +417,7 @@ static int align_xdrop(const int32_t *mat, int32_t Al, int64_t o, int64_t e,
     if (chi > N) chi = N;
     if (clo > chi) break;
     cur->lo = clo; cur->hi = chi;
+    if (2 * (chi - clo) > span) span = 2 * (chi - clo);
     int64_t nlo = -1, nhi = -1;
     int64_t kbest = NEG, kbi = 0, kbj = 0;
     for (int64_t j = clo; j <= chi; j++) {
@@ -367,8 +453,12 @@ static int align_xdrop(const int32_t *mat, int32_t Al, int64_t o, int64_t e,
       }
       cur->H[j] = h; cur->E[j] = ev; cur->F[j] = fv;
     }
+    if (cigar && !rc) rc |= as_push(&st, cur, k);
     if (nlo < 0) break; /* every candidate pruned: the extension stops */
-    if (better(kbest, kbi, kbj, best, bi, bj)) { best = kbest; bi = kbi; bj = kbj; }
+    if (better(kbest, kbi, kbj, best, bi, bj)) {
+      best = kbest; bi = kbi; bj = kbj;
+      best_span = span;
+    }
     lo = nlo; hi = nhi;
   }
   for (int t = 0; t < 3; t++) { free(buf[t].H); free(buf[t].E); free(buf[t].F); }
@@ -379,6 +469,14 @@ static int align_xdrop(const int32_t *mat, int32_t Al, int64_t o, int64_t e,
   out->r_begin = 0;
   out->cells = cells;
   out->cigar_len = 0;
+  out->span = (int32_t)best_span;
+  if (rc) { as_free(&st); return ALNREF_NOMEM; }
+  if (cigar) {
+    /* the path from the end cell back to (0,0), through stored cells only */
+    int trc = traceback(xs_get, &st, mat, Al, o, e, 0, q, r, bi, bj, cigar, cigar_cap, out);
+    as_free(&st);
+    if (trc != ALNREF_OK) return trc;
+  }
   out->status = ALNREF_OK;
   return ALNREF_OK;
 }
@@ -395,7 +493,7 @@ int alnref_align(const int32_t *matrix, int32_t alphabet, int32_t gap_open,
       mode < ALNREF_GLOBAL || mode > ALNREF_EXTEND || prune < ALNREF_FULL ||
       prune > ALNREF_ZDROP || (prune == ALNREF_BAND && band_w < 0) ||
       ((prune == ALNREF_XDROP || prune == ALNREF_ZDROP) &&
-       (xdrop < 0 || mode != ALNREF_EXTEND || cigar)) ||
+       (xdrop < 0 || mode != ALNREF_EXTEND)) ||
       (cigar && cigar_cap < 0)) {
     out->status = ALNREF_INVAL;
     return ALNREF_INVAL;
@@ -407,7 +505,7 @@ int alnref_align(const int32_t *matrix, int32_t alphabet, int32_t gap_open,
   int rc;
   if (prune == ALNREF_XDROP || prune == ALNREF_ZDROP)
     rc = align_xdrop(matrix, alphabet, gap_open, gap_extend, xdrop, prune == ALNREF_ZDROP,
-                     q, M, r, N, out);
+                     q, M, r, N, cigar, cigar_cap, out);
   else
     rc = align_rows(matrix, alphabet, gap_open, gap_extend, mode,
                     prune == ALNREF_BAND, band_w, q, M, r, N, cigar, cigar_cap, out);

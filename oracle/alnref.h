@@ -51,6 +51,10 @@ typedef struct {
   int64_t cells;    /* interior cells (i>=1, j>=1) evaluated                  */
   int32_t status;
   int32_t cigar_len;/* number of CIGAR words written                         */
+  int32_t span;     /* XDROP / ZDROP: widest candidate range, in diagonals
+                       (2 * (last j - first j)), of antidiagonals 1 .. the end
+                       cell's (q_end + r_end); 0 otherwise                   */
+  int32_t reserved;
 } alnref_out;
 
 /*
@@ -61,7 +65,9 @@ typedef struct {
  *   mode       ALNREF_GLOBAL / LOCAL / EXTEND
  *   prune      ALNREF_FULL / BAND (band_w >= 0) / XDROP or ZDROP (threshold X or Z in
  *              xdrop >= 0, EXTEND only)
- *   cigar      NULL for score only; else room for cigar_cap words (not for XDROP/ZDROP)
+ *   cigar      NULL for score only; else room for cigar_cap words (XDROP / ZDROP:
+ *              the path from the end cell back to (0,0) through evaluated,
+ *              unpruned cells, chosen by the same preference order)
  * Returns the status (also stored in out->status).
  */
 int alnref_align(const int32_t *matrix, int32_t alphabet, int32_t gap_open,

@@ -31,6 +31,8 @@ class AlnrefOut(ctypes.Structure):
         ("cells", ctypes.c_int64),
         ("status", ctypes.c_int32),
         ("cigar_len", ctypes.c_int32),
+        ("span", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -106,7 +108,7 @@ def align(matrix, gap_open, gap_extend, q, r, mode=GLOBAL, prune=FULL,
                      _ptr(cig), cap, ctypes.byref(out))
     res = dict(score=int(out.score), q_end=int(out.q_end), r_end=int(out.r_end),
                q_begin=int(out.q_begin), r_begin=int(out.r_begin),
-               cells=int(out.cells), status=int(out.status))
+               cells=int(out.cells), status=int(out.status), span=int(out.span))
     if want_cigar:
         res["cigar"] = cig[: out.cigar_len].copy()
     return res
@@ -149,7 +151,8 @@ def align_batch(matrix, gap_open, gap_extend, q, q_off, q_len, r, r_off, r_len,
     arr = np.frombuffer(out, dtype=np.dtype([
         ("score", np.int64), ("q_end", np.int32), ("r_end", np.int32),
         ("q_begin", np.int32), ("r_begin", np.int32), ("cells", np.int64),
-        ("status", np.int32), ("cigar_len", np.int32)]), count=n)
+        ("status", np.int32), ("cigar_len", np.int32), ("span", np.int32),
+        ("reserved", np.int32)]), count=n)
     res = {k: np.array(arr[k]) for k in arr.dtype.names}
     if want_cigar:
         res["cigar"] = cig

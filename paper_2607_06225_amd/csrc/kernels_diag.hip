@@ -152,14 +152,19 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
   uint8_t *qbuf = smem + (size_t)wave * 2 * kSeqStride;
   uint8_t *rbuf = qbuf + kSeqStride;
   int qtop = 0, rtop = 0; // codes [0, top) staged (modulo kSeqBuf)
+  // Codes past the end read as the padding letter A.  The four loads are
+  // unconditional (clamped index, len >= 1) so that they issue together and
+  // the wave waits once per pass.
   auto stage = [&](const uint8_t *src, int len, uint8_t *buf, int &top, int need) {
     while (top < len && top <= need) {
       const int base = top + lane * 4;
+      int raw[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) raw[b] = src[min(base + b, len - 1)];
       uint32_t w4 = 0;
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        const int idx = base + b;
-        const uint32_t c = (idx < len) ? (uint32_t)min((int)src[idx], A) : (uint32_t)A;
+        const uint32_t c = (base + b < len) ? (uint32_t)min(raw[b], A) : (uint32_t)A;
         w4 |= c << (8 * b);
       }
       const int at = base & (kSeqBuf - 1);
@@ -539,11 +544,13 @@ __device__ void xdrop_group(const DiagArgs &a, int task4, int ntasks, int lane, 
   auto stage = [&](const uint8_t *src, int len, uint8_t *buf, int &top, int need) {
     while (alive && top < len && top <= need) {
       const int base = top + gl * 4;
+      int raw[4]; // unconditional loads (clamped index), one wait per pass
+#pragma unroll
+      for (int b = 0; b < 4; ++b) raw[b] = src[min(base + b, len - 1)];
       uint32_t w4 = 0;
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        const int idx = base + b;
-        const uint32_t c = (idx < len) ? (uint32_t)min((int)src[idx], A) : (uint32_t)A;
+        const uint32_t c = (base + b < len) ? (uint32_t)min(raw[b], A) : (uint32_t)A;
         w4 |= c << (8 * b);
       }
       *reinterpret_cast<uint32_t *>(buf + (base & (kGroupSeq - 1))) = w4;
@@ -656,9 +663,12 @@ __device__ void xdrop_group(const DiagArgs &a, int task4, int ntasks, int lane, 
       const int key = keep ? ((max(h, -1) << 11) | e) : -1;
       kkey = max(kkey, key);
     }
-    // ---- boundary cells (i = 0 at d = k, j = 0 at d = -k)
+    // ---- boundary cells (i = 0 at d = k, j = 0 at d = -k); past the first
+    // antidiagonals no row's domain reaches them and the wave skips this
+    const bool any_b = alive && ((k >= dlo && k <= dhi) || (-k >= dlo && -k <= dhi));
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
+      if (!__ballot(any_b)) break;
       const int d = side ? -k : k;
       const bool inb = alive && d >= dlo && d <= dhi;
       const int hb = go + k * ge;

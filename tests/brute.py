@@ -165,10 +165,19 @@ def run_length(ops):
     return [(op, len(list(g))) for op, g in itertools.groupby(ops)]
 
 
-def preferred_path(q, r, S, o, e, end, local):
+def op_cells(ops, begin=(0, 0)):
+    """Cells visited by forward CIGAR ops ('=', 'X', 'I', 'D') from ``begin``."""
+    return path_cells(["M" if op in "=X" else op for op in ops], *begin)
+
+
+def preferred_path(q, r, S, o, e, end, local, allowed=None):
     """Among the optimal state paths ending at ``end``, the one with the
-    lexicographically smallest label sequence.  Returns (value, cigar, begin)."""
+    lexicographically smallest label sequence.  With ``allowed``, only paths
+    whose every cell satisfies allowed(i, j) take part.  Returns (value,
+    cigar, begin)."""
     paths = state_paths(q, r, S, o, e, end, local)
+    if allowed is not None:
+        paths = [p for p in paths if all(allowed(i, j) for i, j in op_cells(p[2], p[3]))]
     best = max(p[0] for p in paths)
     opt = [p for p in paths if p[0] == best]
     opt.sort(key=lambda p: p[1])

@@ -327,7 +327,7 @@ def test_band_cell_count_closed_form_square():
 
 
 # ---------------------------------------------------------------- x-drop
-def xdrop_dict(q, r, S, o, e, X, zdrop=False):
+def xdrop_dict(q, r, S, o, e, X, zdrop=False, detail=None):
     """Second, independent implementation of the X-drop rule: cells kept in a
     dict keyed by (i, j); a missing key is minus infinity.  Antidiagonal k's
     candidates are j in [lo, hi+1] of the previous antidiagonal's survivors,
@@ -339,10 +339,12 @@ def xdrop_dict(q, r, S, o, e, X, zdrop=False):
     best, end = 0, (0, 0)
     lo = hi = 0
     cells = 0
+    spans = {}
     for k in range(1, M + N + 1):
         js = [j for j in range(max(lo, k - M), min(hi + 1, k, N) + 1)]
         if not js:
             break
+        spans[k] = 2 * (js[-1] - js[0])
         alive = []
         kbest = None
         for j in js:
@@ -383,6 +385,9 @@ def xdrop_dict(q, r, S, o, e, X, zdrop=False):
         if kbest[0] > best or (kbest[0] == best and (kbest[1], kbest[2]) < end):
             best, end = kbest[0], (kbest[1], kbest[2])
         lo, hi = min(alive), max(alive)
+    if detail is not None:
+        detail["kept"] = set(Hd)
+        detail["span"] = max([spans[k] for k in spans if k <= end[0] + end[1]], default=0)
     return best, end, cells
 
 
@@ -576,3 +581,99 @@ def test_batch_driver_matches_single_calls():
             if prune != 2:
                 c = b["cigar"][b["cigar_off"][p]: b["cigar_off"][p] + b["cigar_len"][p]]
                 assert np.array_equal(c, s["cigar"])
+
+
+# ---------------------------------------------------------------- x-drop / z-drop traceback
+def rescore(cig, q, r, S, o, e):
+    """Score of a CIGAR from (0,0), written out independently of the oracle."""
+    i = j = 0
+    total = 0
+    for op, n in cig:
+        if op in "=X":
+            for _ in range(n):
+                total += S[q[i]][r[j]]
+                i += 1
+                j += 1
+        elif op == "I":
+            total += o + n * e
+            i += n
+        else:
+            total += o + n * e
+            j += n
+    return total, i, j
+
+
+@pytest.mark.parametrize("prune", ["XDROP", "ZDROP"])
+def test_dynamic_prune_cigar_infinite_threshold_is_full_extend(prune):
+    """With a threshold no cell can fall below, the stored antidiagonal region
+    is the whole matrix: the CIGAR equals the row-major full-matrix one."""
+    rng = np.random.default_rng(51)
+    S = dna_matrix(2, -4)
+    for _ in range(40):
+        M, N = int(rng.integers(0, 60)), int(rng.integers(0, 60))
+        base = rand_seq(rng, max(M, N), 4)
+        q = base[:M]
+        r = [c if rng.random() > 0.2 else int(rng.integers(0, 4)) for c in base[:N]]
+        full = oracle.align(S, -4, -2, q, r, mode=oracle.EXTEND, want_cigar=True)
+        dyn = oracle.align(S, -4, -2, q, r, mode=oracle.EXTEND,
+                           prune=getattr(oracle, prune), xdrop=1 << 30, want_cigar=True)
+        assert dyn["status"] == oracle.OK
+        assert (dyn["score"], dyn["q_end"], dyn["r_end"]) == (
+            full["score"], full["q_end"], full["r_end"])
+        assert np.array_equal(dyn["cigar"], full["cigar"])
+
+
+@pytest.mark.parametrize("zdrop", [False, True])
+def test_dynamic_prune_cigar_is_preferred_path_through_kept_cells(zdrop):
+    """Brute force on tiny pairs: among all state paths from the end cell to
+    (0,0) through cells the dictionary implementation keeps, the optimal ones
+    score the extension's score, and the CIGAR is the one with the smallest
+    backward label sequence (diag < E < F, open < extend)."""
+    rng = np.random.default_rng(52 + zdrop)
+    checked = 0
+    for trial in range(400):
+        S = dna_matrix(2, -4) if trial % 2 else rand_matrix(rng, 4)
+        o, e = -4, -2
+        X = int(rng.integers(0, 14))
+        M, N = int(rng.integers(1, 7)), int(rng.integers(1, 7))
+        base = rand_seq(rng, max(M, N), 4)
+        q = base[:M]
+        r = [c if rng.random() > 0.3 else int(rng.integers(0, 4)) for c in base[:N]]
+        det = {}
+        best, end, _ = xdrop_dict(q, r, S.tolist(), o, e, X, zdrop=zdrop, detail=det)
+        got = oracle.align(S, o, e, q, r, mode=oracle.EXTEND,
+                           prune=oracle.ZDROP if zdrop else oracle.XDROP, xdrop=X,
+                           want_cigar=True)
+        assert (got["score"], (got["q_end"], got["r_end"])) == (best, end)
+        assert got["span"] == det["span"]
+        if end == (0, 0):
+            assert len(got["cigar"]) == 0
+            continue
+        kept = det["kept"]
+        v, cig, begin = brute.preferred_path(q, r, S.tolist(), o, e, end, False,
+                                             allowed=lambda i, j: (i, j) in kept)
+        assert v == best and begin == (0, 0)
+        assert cigar_pairs(got["cigar"]) == cig, (q, r, X, zdrop)
+        checked += 1
+    assert checked > 100
+
+
+@pytest.mark.parametrize("prune", ["XDROP", "ZDROP"])
+def test_dynamic_prune_cigar_rescores_and_consumes_the_end_cell(prune):
+    rng = np.random.default_rng(54)
+    S = dna_matrix(2, -4)
+    for _ in range(60):
+        L = int(rng.integers(20, 400))
+        ref = rand_seq(rng, L, 4)
+        q = [c if rng.random() > 0.15 else int(rng.integers(0, 4)) for c in ref]
+        if rng.random() < 0.5:
+            at = int(rng.integers(0, L))
+            q = q[:at] + rand_seq(rng, int(rng.integers(5, 40)), 4) + q[at:]
+        q = q + rand_seq(rng, 30, 4)
+        r = ref + rand_seq(rng, 30, 4)
+        X = int(rng.integers(10, 120))
+        got = oracle.align(S, -4, -2, q, r, mode=oracle.EXTEND, prune=getattr(oracle, prune),
+                           xdrop=X, want_cigar=True)
+        sc, i, j = rescore(cigar_pairs(got["cigar"]), q, r, S.tolist(), -4, -2)
+        assert (sc, i, j) == (got["score"], got["q_end"], got["r_end"])
+        assert (got["q_begin"], got["r_begin"]) == (0, 0)
