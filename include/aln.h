@@ -81,7 +81,9 @@ enum { ALN_W_AUTO = 0, ALN_W_I16 = 1, ALN_W_I32 = 2 };
 enum {
   ALN_R_OK = 0,
   ALN_R_UNREACHABLE = 1, /* GLOBAL + BAND: (M,N) not connected to (0,0)      */
-  ALN_R_CIGAR_CAP = 2,   /* the pair's CIGAR did not fit its slot           */
+  ALN_R_CIGAR_CAP = 2,   /* the pair's CIGAR did not fit its slot, or (XDROP
+                            / ZDROP) its region was too wide for the
+                            traceback window; score and end cell are valid */
   ALN_R_BAD_SYMBOL = 3,  /* a code >= alphabet; other fields undefined       */
   ALN_R_TOO_WIDE = 4,    /* XDROP / ZDROP: the surviving region spanned more
                             than the widest kernel window (2042 diagonals)   */
@@ -118,7 +120,13 @@ typedef struct {
   int32_t band_w;     /* BAND half-width w >= 0                               */
   int32_t xdrop;      /* XDROP threshold X >= 0, or ZDROP threshold Z >= 0    */
   int32_t width;      /* ALN_W_*                                              */
-  int32_t want_cigar; /* 1: produce a CIGAR (FULL and BAND only)              */
+  int32_t want_cigar; /* 1: produce a CIGAR.  Under XDROP / ZDROP the path runs
+                         from the end cell back to (0,0) through evaluated,
+                         unpruned cells (same preference order); it is
+                         produced when every antidiagonal up to the end
+                         cell's spans at most 250 diagonals of candidates,
+                         else the pair reports ALN_R_CIGAR_CAP with score,
+                         end cell and cells still valid                    */
 } aln_params;
 
 typedef struct {

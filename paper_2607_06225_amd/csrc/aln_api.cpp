@@ -231,8 +231,6 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
   const bool dyn_prune = p.prune == ALN_XDROP || p.prune == ALN_ZDROP;
   if (dyn_prune && (p.xdrop < 0 || p.mode != ALN_EXTEND))
     return fail(ctx, ALN_E_INVAL, "XDROP / ZDROP need mode EXTEND and a threshold >= 0");
-  if (dyn_prune && p.want_cigar)
-    return fail(ctx, ALN_E_UNSUPPORTED, "CIGAR is not produced under XDROP / ZDROP");
   if (p.width < ALN_W_AUTO || p.width > ALN_W_I32) return fail(ctx, ALN_E_INVAL, "bad width");
   const DevScoring &hs = ctx->hsc[scoring_id];
   const int64_t per_step = (int64_t)std::abs(hs.gap_open) + std::abs(hs.gap_extend) + 128;
@@ -529,7 +527,7 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
       if (ctx->force_xdrop_sides) L.sides = ctx->force_xdrop_sides;
       if (L.sides != 1 && L.rows != 8) L.sides = 1;
     }
-    L.tb = p.want_cigar != 0;
+    L.tb = p.want_cigar != 0 && !dyn_prune; // X-drop codes come from a second pass
     L.small = small;
     L.first = (int32_t)pl->tasks.size();
     L.count = (int32_t)(e - k);
@@ -553,7 +551,7 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
       t.pair = i;
       t.rows = L.rows;
       t.tb_off = -1;
-      if (p.want_cigar) {
+      if (p.want_cigar && !dyn_prune) {
         uint64_t bytes;
         if (L.kind == K_STRIP) {
           const int64_t ns = (M + 64LL * L.rows - 1) / (64LL * L.rows);
@@ -573,8 +571,38 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     pl->launches.push_back(L);
     k = e;
   }
+  // X-drop / Z-drop with CIGAR: a second task list, one task per pair with
+  // 4 diagonals per lane, for the traceback pass and the walk.  Codes take 2
+  // bytes per lane and antidiagonal pair, plus the window base per
+  // antidiagonal; the pass stops at the end cell's antidiagonal.
+  if (dyn_prune && p.want_cigar) {
+    pl->xtb_first = (int32_t)pl->tasks.size();
+    pl->xtb_count = n;
+    std::vector<int32_t> order(n);
+    for (int32_t i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+      return (int64_t)pl->qlen[a] + pl->rlen[a] > (int64_t)pl->qlen[b] + pl->rlen[b];
+    });
+    for (int32_t i : order) {
+      const int32_t M = pl->qlen[i], N = pl->rlen[i];
+      PairTask t;
+      memset(&t, 0, sizeof t);
+      t.pair = i;
+      t.rows = 4;
+      const uint64_t nk = (uint64_t)M + N + 1;
+      const uint64_t bytes = (nk + 63) / 64 * 64 * 4 + ((uint64_t)(M + N) / 2 + 1) * 64 * 2;
+      t.tb_off = (int64_t)tb_off;
+      tb_off += align_up(bytes);
+      t.cigar_off = (int64_t)cg_off;
+      t.cigar_cap = M + N + 1;
+      cg_off += (uint64_t)(M + N + 1);
+      pl->tasks.push_back(t);
+    }
+    pl->first_diag_tb = pl->xtb_first;
+    pl->n_diag_tb = n;
+  }
   // walk ranges: strip tasks come first (kind order), then antidiagonal tasks
-  if (p.want_cigar) {
+  if (p.want_cigar && !dyn_prune) {
     for (const LaunchDesc &L : pl->launches) {
       if (L.kind == K_STRIP) pl->n_strip_tb += L.count;
       if (L.kind == K_DIAG) {
@@ -810,11 +838,25 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
               return alnk::launch_diag(32, ALN_EXTEND, pr, false, d2, st);
             }));
   }
+  if (plan->xtb_count > 0) {
+    // traceback pass of the X-drop / Z-drop pairs, then their walks below
+    auto xtb = [&](int32_t first, int32_t count) {
+      alnk::DiagArgs d = diag_args(dtasks + first, count, nullptr, 0, nullptr, nullptr);
+      return alnk::launch_diag(4, ALN_EXTEND, plan->p.prune, true, d, st);
+    };
+    const char *fam = plan->p.prune == ALN_ZDROP ? "zdrop_tb" : "xdrop_tb";
+    if (!per_pair) {
+      HIP_TRY(ctx, timed_launch(ctx, fam, st, [&] { return xtb(plan->xtb_first, plan->xtb_count); }));
+    } else {
+      for (int32_t k = 0; k < plan->xtb_count; ++k) HIP_TRY(ctx, xtb(plan->xtb_first + k, 1));
+    }
+  }
   if (plan->p.want_cigar) {
     alnk::WalkArgs wa;
     wa.b = bp;
     wa.mode = plan->p.mode;
     wa.layout = 0;
+    wa.diag_stride = plan->xtb_count > 0 ? 2 : 8;
     wa.sc = dsc;
     wa.tb = ws + plan->tb_base;
     wa.res = d_res;

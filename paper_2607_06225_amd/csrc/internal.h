@@ -73,7 +73,9 @@ struct WalkArgs {
   const PairTask *tasks;
   int32_t ntasks;
   int32_t mode;
-  int32_t layout;     // 0: strip layout, 1: diagonal-band layout
+  int32_t layout;     // 0: strip layout, 1: diagonal layout
+  int32_t diag_stride; // diagonal layout: code bytes per lane and antidiagonal
+                       // pair (8: bands; 2: X-drop / Z-drop, 4 diagonals per lane)
   const DevScoring *sc;
   const uint8_t *tb;
   aln_result *res;

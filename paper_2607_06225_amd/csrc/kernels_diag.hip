@@ -120,6 +120,13 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
   static_assert(RD % 2 == 0, "a lane must hold whole diagonal pairs");
   constexpr bool DYN = PRUNE == ALN_XDROP || PRUNE == ALN_ZDROP; // dynamic pruning
   constexpr bool ZD = PRUNE == ALN_ZDROP;
+  // Traceback pass of a dynamically pruned pair: the score pass already
+  // found the end cell; this pass recomputes antidiagonals 1 .. q_end + r_end
+  // identically and writes their codes (2 bytes per lane and antidiagonal
+  // pair), changing no result field except CIGAR_CAP when the region
+  // outgrows the window.
+  constexpr bool TBX = TB && DYN;
+  static_assert(!TBX || RD == 4, "dynamic-pruning codes are laid out for RD = 4");
   constexpr int W = 64 * RD;
   constexpr int HALF = RD / 2;
   const PairTask tk = a.tasks[task];
@@ -133,8 +140,14 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
   const int A = a.sc->alphabet;
   const int s_match = a.sc->match, s_mismatch = a.sc->mismatch; // MM: all that scores
 
+  int kstop = M + N; // last antidiagonal evaluated
+  if (TBX) {
+    if (__builtin_amdgcn_readfirstlane(res->status) != ALN_R_OK) return;
+    kstop = __builtin_amdgcn_readfirstlane(res->q_end + res->r_end);
+    if (kstop == 0) return; // empty extension: no codes needed
+  }
   if (M == 0 || N == 0) {
-    if (lane == 0) {
+    if (lane == 0 && !TBX) {
       if (MODE == ALN_GLOBAL) {
         res->score = (M + N == 0) ? 0 : go + (M + N) * ge;
         res->q_end = M;
@@ -261,7 +274,7 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
   }
   int gh = NEG32; // GLOBAL: H(M, N)
 
-  const int KMAX = M + N;
+  const int KMAX = kstop;
   // One antidiagonal.  The window base and RD are even, so element x holds a
   // cell of antidiagonal k exactly when x = k (mod 2): with the parity a
   // compile-time constant every register index below is static.
@@ -387,7 +400,10 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
       if (par == 1 || k == KMAX) {
         const uint32_t lo32 = code_lo | (HALF < 8 ? (code_hi << (4 * HALF)) : 0u);
         const uint32_t hi32 = (HALF < 8) ? (code_hi >> (32 - 4 * HALF)) : code_hi;
-        *reinterpret_cast<uint2 *>(tbw + ((size_t)(k >> 1) * 64 + lane) * 2) = make_uint2(lo32, hi32);
+        if (TBX)
+          reinterpret_cast<uint16_t *>(tbw)[(size_t)(k >> 1) * 64 + lane] = (uint16_t)lo32;
+        else
+          *reinterpret_cast<uint2 *>(tbw + ((size_t)(k >> 1) * 64 + lane) * 2) = make_uint2(lo32, hi32);
         code_lo = code_hi = 0;
       }
     }
@@ -435,6 +451,10 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
     if (k + 1 > KMAX || !step(std::integral_constant<int, 0>{}, k + 1)) break;
   }
 
+  if (TBX) {
+    if (lane == 0 && overflow) res->status = ALN_R_CIGAR_CAP;
+    return;
+  }
   if (lane == 0) {
     if (overflow) {
       res->flags |= ALN_F_WIDENED;
@@ -785,8 +805,15 @@ static hipError_t launch_diag_t(const DiagArgs &a, hipStream_t s) {
 
 template <int RD>
 static hipError_t launch_diag_r(int mode, int prune, bool tb, const DiagArgs &a, hipStream_t s) {
-  if (prune == ALN_XDROP) return launch_diag_t<RD, ALN_EXTEND, ALN_XDROP, false>(a, s);
-  if (prune == ALN_ZDROP) return launch_diag_t<RD, ALN_EXTEND, ALN_ZDROP, false>(a, s);
+  if (prune == ALN_XDROP || prune == ALN_ZDROP) {
+    if constexpr (RD == 4) {
+      if (tb) return prune == ALN_XDROP ? launch_diag_t<RD, ALN_EXTEND, ALN_XDROP, true>(a, s)
+                                        : launch_diag_t<RD, ALN_EXTEND, ALN_ZDROP, true>(a, s);
+    }
+    if (tb) return hipErrorInvalidValue;
+    return prune == ALN_XDROP ? launch_diag_t<RD, ALN_EXTEND, ALN_XDROP, false>(a, s)
+                              : launch_diag_t<RD, ALN_EXTEND, ALN_ZDROP, false>(a, s);
+  }
   switch (mode) {
   case ALN_GLOBAL:
     return tb ? launch_diag_t<RD, ALN_GLOBAL, ALN_BAND, true>(a, s)

@@ -307,10 +307,11 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
 
 // ---------------------------------------------------------- diagonal layout
 // Per antidiagonal k the window base dbase(k) (ints, rounded up to 64), then
-// per antidiagonal pair k/2 and lane 8 bytes: the RD/2 cells of the even
-// antidiagonal in the low nibbles, then those of the odd one.  Cell (i, j):
-// element e = (j - i) - dbase(k), lane e / RD, slot e mod RD.  A block is 64
-// antidiagonals: 16 KB of codes plus 64 window bases.
+// per antidiagonal pair k/2 and lane S bytes (S = diag_stride: 8 for bands,
+// 2 for X-drop / Z-drop regions): the RD/2 cells of the even antidiagonal in
+// the low nibbles, then those of the odd one.  Cell (i, j): element e = (j -
+// i) - dbase(k), lane e / RD, slot e mod RD.  A block is 64 antidiagonals:
+// 2048*S bytes of codes plus 64 window bases.
 //
 // The walk advances by whole runs.  The two most recent blocks (the one
 // holding the walk's antidiagonal and the one before) stay in two LDS slots,
@@ -347,6 +348,7 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
   const uint8_t *Qs = a.b.q + a.b.q_off[p];
   const uint8_t *Rs = a.b.r + a.b.r_off[p];
   const int RD = uni(tk.rows);
+  const int S = a.diag_stride;           // code bytes per lane and antidiagonal pair
   const int inv = (65536 + RD - 1) / RD; // e / RD = (e * inv) >> 16 for 0 <= e < 64*RD
   const int nk = M + N + 1;
   const int nks = (M + N) / 2 + 1; // antidiagonal pairs stored
@@ -360,11 +362,11 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
   int pre_aux = 0, pre_blk = -1, cur = -1;
   auto fetch = [&](int b) {
     const int pairs = min(32, nks - b * 32);
-    const uint4 *src = cod + (size_t)b * (kBlockBytes / 16);
+    const uint4 *src = cod + (size_t)b * 128 * S; // 32 pairs x 64 lanes x S bytes
 #pragma unroll
     for (int m = 0; m < kPre; ++m) {
       const int u = lane + 64 * m;
-      pre[m] = u < pairs * 32 ? src[u] : make_uint4(0u, 0u, 0u, 0u);
+      pre[m] = u < pairs * 4 * S ? src[u] : make_uint4(0u, 0u, 0u, 0u);
     }
     pre_aux = dbh[b * 64 + lane];
     pre_blk = b;
@@ -405,7 +407,7 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
     const int ln = (e * inv) >> 16;
     const int x = e - ln * RD;
     const int pos = (kk & 1) * (RD >> 1) + (x >> 1);
-    const int byte = slot * kBlockBytes + ((kk >> 1) & 31) * 512 + ln * 8 + (pos >> 1);
+    const int byte = slot * kBlockBytes + ((kk >> 1) & 31) * 64 * S + ln * S + (pos >> 1);
     return (codes0[byte] >> ((pos & 1) * 4)) & 15;
   };
   // sequence windows covering the next kLook + 1 positions below i and j
@@ -554,6 +556,7 @@ hipError_t launch_walk(int layout, const WalkArgs &a, hipStream_t s) {
 
 hipError_t launch_walk_diag(const WalkArgs &a, hipStream_t s) {
   if (a.ntasks <= 0) return hipSuccess;
+  if (a.diag_stride != 8 && a.diag_stride != 2) return hipErrorInvalidValue;
   hipLaunchKernelGGL(walk_diag_wave, dim3(a.ntasks), dim3(64), 0, s, a);
   return hipGetLastError();
 }

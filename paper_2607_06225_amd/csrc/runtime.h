@@ -83,6 +83,7 @@ struct aln_plan {
   uint64_t widen_cnt_off = 0, widen_off[2] = {0, 0};
   bool xdrop = false;
   int32_t n_strip_tb = 0, first_diag_tb = 0, n_diag_tb = 0; // walk ranges
+  int32_t xtb_first = 0, xtb_count = 0; // X-drop / Z-drop traceback-pass tasks
   uint64_t upload_bytes = 0; // task lists copied to the front of the workspace
   uint64_t tasks_bytes = 0;
   uint64_t tb_base = 0;
