@@ -65,6 +65,9 @@ WORKLOAD_DESC = {
                   "score + end cell"),
     "zdrop_ext": ("Z-drop extension (Sec. 9.3 condition), the xdrop_ext pairs with Z = 100; "
                   "score + end cell"),
+    "xdrop_cigar": ("X-drop extension with CIGAR: the xdrop_ext pairs, score + end cell + "
+                    "CIGAR through the pruned region (score pass, traceback pass to the end "
+                    "cell, walk)"),
 }
 MODE_NAME = {0: "GLOBAL", 1: "LOCAL", 2: "EXTEND"}
 PRUNE_NAME = {0: "full", 1: "band", 2: "xdrop", 3: "zdrop"}
@@ -257,6 +260,8 @@ def run_workload(name, batch, args, cpu_seconds, pp_cap):
     )
     if batch.prune in (2, 3):
         out["widened_pairs"] = int(((res["flags"] & aln.F_WIDENED) != 0).sum())
+        if batch.want_cigar:
+            out["cigar_cap_pairs"] = int((res["status"] == aln.R_CIGAR_CAP).sum())
     if batch.mode == 1 and batch.prune == 0:
         out["int32_reruns"] = int(((res["flags"] & aln.F_I16_RERUN) != 0).sum())
     plan.close()
@@ -337,7 +342,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="sw_protein", choices=sorted(WORKLOAD_DESC),
                     help="headline workload (the JSON line's value)")
-    ap.add_argument("--configs", default="nw_dna_1k,band_long,xdrop_ext,zdrop_ext",
+    ap.add_argument("--configs", default="nw_dna_1k,band_long,xdrop_ext,zdrop_ext,xdrop_cigar",
                     help="comma list of further workloads to measure, or 'none'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
@@ -435,7 +440,7 @@ def main():
         "configs": configs,
         "serving": serving_out,
     }
-    for k in ("int32_reruns", "statuses"):
+    for k in ("int32_reruns", "statuses", "widened_pairs", "cigar_cap_pairs"):
         if k in head:
             out[k] = head[k]
     print(json.dumps(out), flush=True)

@@ -326,8 +326,11 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
 // All those cells lie within 63 antidiagonals of the current one, so within
 // the two resident blocks.
 
+template <int S>
 __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
-  __shared__ __align__(16) uint4 codes4[2][kBlockBytes / 16];
+  // two block slots of 2048*S bytes each (dynamic LDS, sized by the stride,
+  // so that narrow layouts let more walks share a CU)
+  extern __shared__ __align__(16) uint4 codes_dyn[];
   __shared__ int dbl[2][64];
   __shared__ uint8_t qwin[256], rwin[256];
   const int lane = threadIdx.x;
@@ -348,7 +351,10 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
   const uint8_t *Qs = a.b.q + a.b.q_off[p];
   const uint8_t *Rs = a.b.r + a.b.r_off[p];
   const int RD = uni(tk.rows);
-  const int S = a.diag_stride;           // code bytes per lane and antidiagonal pair
+  // S: code bytes per lane and antidiagonal pair
+  constexpr int blk_bytes = 2048 * S;    // one block: 32 antidiagonal pairs x 64 lanes
+  constexpr int n4 = 2 * S;              // uint4 per lane per block
+  static_assert(n4 <= kPre, "block larger than the prefetch registers");
   const int inv = (65536 + RD - 1) / RD; // e / RD = (e * inv) >> 16 for 0 <= e < 64*RD
   const int nk = M + N + 1;
   const int nks = (M + N) / 2 + 1; // antidiagonal pairs stored
@@ -366,7 +372,7 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
 #pragma unroll
     for (int m = 0; m < kPre; ++m) {
       const int u = lane + 64 * m;
-      pre[m] = u < pairs * 4 * S ? src[u] : make_uint4(0u, 0u, 0u, 0u);
+      if (m < n4) pre[m] = u < pairs * 4 * S ? src[u] : make_uint4(0u, 0u, 0u, 0u);
     }
     pre_aux = dbh[b * 64 + lane];
     pre_blk = b;
@@ -374,7 +380,8 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
   auto install = [&](int b) { // put block b (already fetched) into its slot
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < kPre; ++m) codes4[b & 1][lane + 64 * m] = pre[m];
+    for (int m = 0; m < kPre; ++m)
+      if (m < n4) codes_dyn[(b & 1) * 128 * S + lane + 64 * m] = pre[m];
     dbl[b & 1][lane] = pre_aux;
     __syncthreads();
   };
@@ -394,7 +401,7 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
     cur = b;
     if (b >= 2) fetch(b - 2);
   };
-  const uint8_t *codes0 = reinterpret_cast<const uint8_t *>(codes4[0]);
+  const uint8_t *codes0 = reinterpret_cast<const uint8_t *>(codes_dyn);
   // code of (ii, jj), any lane; the cell must lie in a resident block
   auto code_at = [&](int ii, int jj, bool &bad_lane) -> int {
     const int kk = ii + jj;
@@ -407,7 +414,7 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
     const int ln = (e * inv) >> 16;
     const int x = e - ln * RD;
     const int pos = (kk & 1) * (RD >> 1) + (x >> 1);
-    const int byte = slot * kBlockBytes + ((kk >> 1) & 31) * 64 * S + ln * S + (pos >> 1);
+    const int byte = slot * blk_bytes + ((kk >> 1) & 31) * 64 * S + ln * S + (pos >> 1);
     return (codes0[byte] >> ((pos & 1) * 4)) & 15;
   };
   // sequence windows covering the next kLook + 1 positions below i and j
@@ -556,8 +563,12 @@ hipError_t launch_walk(int layout, const WalkArgs &a, hipStream_t s) {
 
 hipError_t launch_walk_diag(const WalkArgs &a, hipStream_t s) {
   if (a.ntasks <= 0) return hipSuccess;
-  if (a.diag_stride != 8 && a.diag_stride != 2) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(walk_diag_wave, dim3(a.ntasks), dim3(64), 0, s, a);
+  if (a.diag_stride == 8)
+    hipLaunchKernelGGL(walk_diag_wave<8>, dim3(a.ntasks), dim3(64), (size_t)2 * 2048 * 8, s, a);
+  else if (a.diag_stride == 2)
+    hipLaunchKernelGGL(walk_diag_wave<2>, dim3(a.ntasks), dim3(64), (size_t)2 * 2048 * 2, s, a);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

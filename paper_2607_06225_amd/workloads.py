@@ -30,6 +30,8 @@ Workloads (codes: DNA A,C,G,T = 0..3; protein = 0..19):
                  sequences read away from the seed (the left side reversed).
   zdrop_ext      the xdrop_ext pairs (same seed, same bytes) under Z-drop with
                  Z = 100, so the two pruning rules are compared on one input.
+  xdrop_cigar    the xdrop_ext pairs with a CIGAR per extension side (the
+                 traceback through the X-drop region).
 """
 from dataclasses import dataclass, field
 
@@ -396,12 +398,22 @@ def zdrop_ext(n=200000, seed=404, min_len=150, max_len=5000, zdrop=100, seed_len
     return b
 
 
+def xdrop_cigar(n=200000, seed=404, min_len=150, max_len=5000, xdrop=100, seed_len=31):
+    """The xdrop_ext extension problems with a CIGAR per side."""
+    b = xdrop_ext(n=n, seed=seed, min_len=min_len, max_len=max_len, xdrop=xdrop,
+                  seed_len=seed_len)
+    b.name = "xdrop_cigar"
+    b.want_cigar = True
+    return b
+
+
 WORKLOADS = {
     "nw_dna_1k": nw_dna_1k,
     "sw_protein": sw_protein,
     "band_long": band_long,
     "xdrop_ext": xdrop_ext,
     "zdrop_ext": zdrop_ext,
+    "xdrop_cigar": xdrop_cigar,
 }
 
 
