@@ -72,7 +72,14 @@ enum { ALN_GLOBAL = 0, ALN_LOCAL = 1, ALN_EXTEND = 2 };
  * cell (i,j) is removed when the best score of the earlier antidiagonals
  * exceeds its H by more than Z + |(j - i) - (j* - i*)|, (i*,j*) the cell of
  * that best score; Z is passed in aln_params.xdrop. */
-enum { ALN_FULL = 0, ALN_BAND = 1, ALN_XDROP = 2, ALN_ZDROP = 3 };
+/* ALN_SEARCH evaluates the score-major search schedule of Sec. 6.3 for unit
+ * edit costs: GLOBAL mode, a scoring with every diagonal entry 0, every
+ * off-diagonal entry -1, gap_open 0 and gap_extend -1 (so the score is minus
+ * the edit distance), no CIGAR.  For s = 0, 1, ... it keeps, per diagonal
+ * d = j - i in [max(-s, -M), min(s, N)], the furthest row reached with s
+ * edits, extended along matches, and stops when diagonal N - M reaches row
+ * M.  `cells` then counts those (score, diagonal) entries, s = 0 included. */
+enum { ALN_FULL = 0, ALN_BAND = 1, ALN_XDROP = 2, ALN_ZDROP = 3, ALN_SEARCH = 4 };
 /* score width: AUTO lets the library choose (packed int16 where it applies,
  * with an automatic int32 re-run of any pair that could have overflowed) */
 enum { ALN_W_AUTO = 0, ALN_W_I16 = 1, ALN_W_I32 = 2 };
@@ -116,7 +123,7 @@ typedef struct {
 typedef struct {
   int32_t mode;       /* ALN_GLOBAL / ALN_LOCAL / ALN_EXTEND                  */
   int32_t prune;      /* ALN_FULL / ALN_BAND / ALN_XDROP or ALN_ZDROP (EXTEND
-                         only)                                                */
+                         only) / ALN_SEARCH (GLOBAL, unit edit costs)        */
   int32_t band_w;     /* BAND half-width w >= 0                               */
   int32_t xdrop;      /* XDROP threshold X >= 0, or ZDROP threshold Z >= 0    */
   int32_t width;      /* ALN_W_*                                              */

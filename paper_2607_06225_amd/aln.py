@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libaln_hip.so")
 
 GLOBAL, LOCAL, EXTEND = 0, 1, 2
-FULL, BAND, XDROP, ZDROP = 0, 1, 2, 3
+FULL, BAND, XDROP, ZDROP, SEARCH = 0, 1, 2, 3, 4
 W_AUTO, W_I16, W_I32 = 0, 1, 2
 R_OK, R_UNREACHABLE, R_CIGAR_CAP, R_BAD_SYMBOL, R_TOO_WIDE, R_INTERNAL = 0, 1, 2, 3, 4, 5
 E_INVAL, E_NOMEM, E_DEVICE, E_CAPACITY, E_UNSUPPORTED = -1, -2, -3, -4, -5

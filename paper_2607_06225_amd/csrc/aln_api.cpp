@@ -226,7 +226,7 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     return fail(ctx, ALN_E_INVAL, "unknown scoring id %d", scoring_id);
   const aln_params &p = *params;
   if (p.mode < ALN_GLOBAL || p.mode > ALN_EXTEND) return fail(ctx, ALN_E_INVAL, "bad mode");
-  if (p.prune < ALN_FULL || p.prune > ALN_ZDROP) return fail(ctx, ALN_E_INVAL, "bad prune");
+  if (p.prune < ALN_FULL || p.prune > ALN_SEARCH) return fail(ctx, ALN_E_INVAL, "bad prune");
   if (p.prune == ALN_BAND && p.band_w < 0) return fail(ctx, ALN_E_INVAL, "band_w < 0");
   const bool dyn_prune = p.prune == ALN_XDROP || p.prune == ALN_ZDROP;
   if (dyn_prune && (p.xdrop < 0 || p.mode != ALN_EXTEND))
@@ -234,6 +234,14 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
   if (p.width < ALN_W_AUTO || p.width > ALN_W_I32) return fail(ctx, ALN_E_INVAL, "bad width");
   const DevScoring &hs = ctx->hsc[scoring_id];
   const int64_t per_step = (int64_t)std::abs(hs.gap_open) + std::abs(hs.gap_extend) + 128;
+  if (p.prune == ALN_SEARCH) {
+    if (p.mode != ALN_GLOBAL || p.want_cigar)
+      return fail(ctx, ALN_E_UNSUPPORTED, "SEARCH is GLOBAL edit distance without CIGAR");
+    if (!hs.match_mismatch || hs.match != 0 || hs.mismatch != -1 || hs.gap_open != 0 ||
+        hs.gap_extend != -1)
+      return fail(ctx, ALN_E_UNSUPPORTED,
+                  "SEARCH needs unit edit costs (match 0, mismatch -1, open 0, extend -1)");
+  }
 
   aln_plan *pl = new (std::nothrow) aln_plan;
   if (!pl) return fail(ctx, ALN_E_NOMEM, "plan allocation");
@@ -250,6 +258,44 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     maxM = std::max(maxM, pl->qlen[i]);
     maxN = std::max(maxN, pl->rlen[i]);
   }
+  // score-major search (edit distance): one wavefront per pair, longest
+  // first; both sequences and the furthest-row array in LDS
+  if (p.prune == ALN_SEARCH) {
+    std::vector<int32_t> order(n);
+    for (int32_t i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+      return (int64_t)pl->qlen[a] + pl->rlen[a] > (int64_t)pl->qlen[b] + pl->rlen[b];
+    });
+    LaunchDesc L{};
+    L.kind = K_SEARCH;
+    L.mode = ALN_GLOBAL;
+    L.first = 0;
+    L.count = n;
+    L.lds_bnd = (int32_t)align_up((uint64_t)maxM + 8, 16);  // query codes
+    L.lds_prof = (int32_t)align_up((uint64_t)maxN + 8, 16); // reference codes
+    L.lds_f = (int32_t)align_up(((uint64_t)maxM + maxN + 1) * 4, 16);
+    if ((int64_t)L.lds_bnd + L.lds_prof + L.lds_f > 160 * 1024) {
+      delete pl;
+      return fail(ctx, ALN_E_UNSUPPORTED, "SEARCH pairs need M + N <= about 32000");
+    }
+    for (int32_t i : order) {
+      PairTask t;
+      memset(&t, 0, sizeof t);
+      t.pair = i;
+      t.tb_off = -1;
+      pl->tasks.push_back(t);
+    }
+    pl->launches.push_back(L);
+    pl->tasks_bytes = align_up(sizeof(PairTask) * std::max<size_t>(pl->tasks.size(), 1));
+    pl->upload_bytes = sizeof(PairTask) * pl->tasks.size();
+    pl->tb_base = pl->tasks_bytes;
+    pl->tb_bytes = 0;
+    pl->ws_bytes = pl->tasks_bytes;
+    pl->cigar_words = 0;
+    *plan = pl;
+    return ALN_OK;
+  }
+
   // packed int16 Smith-Waterman: LOCAL, full matrix, score + end cell
   const int rerun_rows = 16;
   const int32_t rerun_bnd = (int32_t)align_up((uint64_t)(maxN + 1) * 8, 16);
@@ -710,6 +756,21 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
   alnk::ValidateArgs va{bp, plan->n, hsc.alphabet, d_res, sw16 ? rerun_cnt : widen_cnt,
                         sw16 ? 1 : (plan->xdrop ? 2 : 0)};
   HIP_TRY(ctx, timed_launch(ctx, "validate", st, [&] { return alnk::launch_validate(va, st); }));
+
+  if (!plan->launches.empty() && plan->launches[0].kind == K_SEARCH) {
+    const LaunchDesc &L = plan->launches[0];
+    alnk::SearchArgs sa{bp, dtasks, L.count, d_res, L.lds_bnd, L.lds_prof, L.lds_f};
+    if (!per_pair) {
+      HIP_TRY(ctx, timed_launch(ctx, "search", st, [&] { return alnk::launch_search(sa, st); }));
+    } else {
+      for (int32_t k = 0; k < L.count; ++k) {
+        sa.tasks = dtasks + k;
+        sa.ntasks = 1;
+        HIP_TRY(ctx, alnk::launch_search(sa, st));
+      }
+    }
+    return ALN_OK;
+  }
 
   if (sw16) {
     alnk::Sw16Args a16;

@@ -145,6 +145,15 @@ struct DiagArgs {
   int32_t match_mismatch;     // 1: the scoring is one match and one mismatch score
 };
 
+// Score-major search for unit-cost edit distance (one wavefront per task).
+struct SearchArgs {
+  BatchPtrs b;
+  const PairTask *tasks;
+  int32_t ntasks;
+  aln_result *res;
+  int32_t lds_q, lds_r, lds_f; // LDS bytes: query codes, reference codes, F row
+};
+
 // Launchers (defined in the kernel translation units).
 hipError_t launch_validate(const ValidateArgs &a, hipStream_t s);
 hipError_t launch_strip(int rows, int mode, bool tb, bool small_alphabet,
@@ -156,5 +165,6 @@ hipError_t launch_diag(int rows, int mode, int prune, bool tb, const DiagArgs &a
 // wavefront, 8 diagonals per lane
 hipError_t launch_xdrop_group(int prune, const DiagArgs &a, hipStream_t s);
 hipError_t launch_walk_diag(const WalkArgs &a, hipStream_t s);
+hipError_t launch_search(const SearchArgs &a, hipStream_t s);
 
 } // namespace alnk

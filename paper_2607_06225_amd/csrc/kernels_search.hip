@@ -1,0 +1,131 @@
+// kernels_search.hip -- unit-cost edit distance by the score-major search
+// schedule (Sec. 6.3) on gfx950.
+//
+// The search transformation re-indexes the edit-distance recurrence by score:
+// F(s, d) is the furthest row i reached on diagonal d = j - i with exactly s
+// edits.  From F(s-1, .) three costly moves lead to diagonal d --
+//   a mismatch   from (i, j) on d:     row F(s-1, d) + 1,
+//   an insertion from (i, j) on d + 1: row F(s-1, d+1) + 1  (steps down),
+//   a deletion   from (i, j) on d - 1: row F(s-1, d-1)      (steps right) --
+// each kept only if it stays inside the matrix (row <= min(M, N - d)); the
+// furthest survivor then advances for free along matching characters
+// (extend).  The active diagonals widen by one on each side per score,
+// clipped to the matrix: [max(-s, -M), min(s, N)].  The search stops at the
+// first score s whose diagonal N - M reaches row M: s is the edit distance.
+//
+// One wavefront per pair.  Both sequences and one row of F (int32 per
+// diagonal, updated in place) live in LDS.  Lanes take 64 consecutive
+// diagonals at a time; the neighbours' old values come by DPP, the chunk's
+// left neighbour from a register saved before the previous chunk overwrote
+// it, and its right neighbour from LDS (not yet updated).  Extension compares
+// four characters per step: two aligned dword reads per sequence and a byte
+// align, then the first differing byte.
+#include "internal.h"
+
+namespace alnk {
+
+constexpr int kNegF = -(1 << 30);
+
+__device__ __forceinline__ int sdpp_shr1(int old, int v) { // lane l <- lane l-1
+  return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int sdpp_shl1(int old, int v) { // lane l <- lane l+1
+  return __builtin_amdgcn_update_dpp(old, v, 0x130, 0xf, 0xf, false);
+}
+
+// four codes starting at byte `off` of an LDS sequence buffer (readable up to
+// off + 7)
+__device__ __forceinline__ uint32_t load4(const uint8_t *buf, int off) {
+  const uint32_t *w = reinterpret_cast<const uint32_t *>(buf + (off & ~3));
+  return __builtin_amdgcn_alignbyte(w[1], w[0], (uint32_t)(off & 3));
+}
+
+// advance row f of diagonal d while the next characters match, up to lim
+__device__ __forceinline__ int extend(const uint8_t *qs, const uint8_t *rs, int f, int d, int lim) {
+  while (f < lim) {
+    const uint32_t x = load4(qs, f) ^ load4(rs, f + d);
+    const int n = x ? (__builtin_ctz(x) >> 3) : 4;
+    f = min(f + n, lim);
+    if (n < 4) break;
+  }
+  return f;
+}
+
+__global__ __launch_bounds__(64) void search_edit_kernel(SearchArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int lane = threadIdx.x;
+  const int task = blockIdx.x;
+  if (task >= a.ntasks) return;
+  const int p = __builtin_amdgcn_readfirstlane(a.tasks[task].pair);
+  aln_result *res = a.res + p;
+  if (__builtin_amdgcn_readfirstlane(res->status) != ALN_R_OK) return; // bad symbol
+  const int M = __builtin_amdgcn_readfirstlane(a.b.q_len[p]);
+  const int N = __builtin_amdgcn_readfirstlane(a.b.r_len[p]);
+  const uint8_t *Q = a.b.q + a.b.q_off[p];
+  const uint8_t *Rs = a.b.r + a.b.r_off[p];
+
+  // LDS: query codes (M + 8 bytes, padding 0xFE), reference codes (N + 8,
+  // padding 0xFF; the paddings never match each other or a code), F[d + M]
+  uint8_t *qs = smem;
+  uint8_t *rs = smem + a.lds_q;
+  int *F = reinterpret_cast<int *>(smem + a.lds_q + a.lds_r);
+  for (int k = lane; k < M + 8; k += 64) qs[k] = k < M ? Q[k] : 0xFE;
+  for (int k = lane; k < N + 8; k += 64) rs[k] = k < N ? Rs[k] : 0xFF;
+  for (int k = lane; k <= M + N; k += 64) F[k] = kNegF;
+  __syncthreads();
+
+  const int dt = N - M; // the end cell's diagonal
+  int s = 0, dmin = 0, dmax = 0;
+  long long cells = 1;
+  {
+    const int f0 = extend(qs, rs, 0, 0, min(M, N));
+    if (lane == 0) F[M] = f0;
+  }
+  __syncthreads();
+  bool done = dt == 0 && __builtin_amdgcn_readfirstlane(F[M]) >= M;
+  while (!done && s < M + N) {
+    ++s;
+    dmin = max(dmin - 1, -M);
+    dmax = min(dmax + 1, N);
+    cells += dmax - dmin + 1;
+    int carry = kNegF; // F(s-1, d0 - 1), saved before its chunk was overwritten
+    for (int d0 = dmin; d0 <= dmax; d0 += 64) {
+      const int d = d0 + lane;
+      const bool act = d <= dmax;
+      const int old = act ? F[d + M] : kNegF;
+      int right = sdpp_shl1(kNegF, old);
+      int left = sdpp_shr1(kNegF, old);
+      if (lane == 63) right = (d + 1 <= N) ? F[d + 1 + M] : kNegF;
+      if (lane == 0) left = carry;
+      carry = __builtin_amdgcn_readlane(old, 63);
+      const int lim = min(M, N - d);
+      int f = kNegF;
+      if (old + 1 <= lim) f = max(f, old + 1);     // mismatch
+      if (right + 1 <= lim) f = max(f, right + 1); // insertion
+      if (left <= lim) f = max(f, left);           // deletion
+      if (act && f >= 0) f = extend(qs, rs, f, d, lim);
+      if (act) F[d + M] = f >= 0 ? f : kNegF;
+    }
+    done = dt >= dmin && dt <= dmax && __builtin_amdgcn_readfirstlane(F[dt + M]) >= M;
+  }
+  if (lane == 0) {
+    res->score = -s;
+    res->q_end = M;
+    res->r_end = N;
+    res->cells = cells;
+  }
+}
+
+hipError_t launch_search(const SearchArgs &a, hipStream_t s) {
+  if (a.ntasks <= 0) return hipSuccess;
+  const size_t lds = (size_t)a.lds_q + a.lds_r + a.lds_f;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void *)search_edit_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(search_edit_kernel, dim3(a.ntasks), dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+
+} // namespace alnk

@@ -37,7 +37,7 @@ struct aln_ctx {
 
 namespace alnrt {
 
-enum Kind { K_STRIP = 0, K_SW16 = 1, K_RERUN = 2, K_DIAG = 3 };
+enum Kind { K_STRIP = 0, K_SW16 = 1, K_RERUN = 2, K_DIAG = 3, K_SEARCH = 4 };
 
 struct LaunchDesc {
   int kind;
@@ -52,6 +52,7 @@ struct LaunchDesc {
   int sides = 1; // X-drop: extension sides per wavefront
   int waves = 1; // full matrix: wavefronts per pair (strip pipeline)
   int max_n = 0; // largest reference length of the launch
+  int32_t lds_f = 0; // search: LDS bytes of the furthest-row array
 };
 
 constexpr uint64_t kAlign = 256;

@@ -38,7 +38,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 GLOBAL, LOCAL, EXTEND = 0, 1, 2
-FULL, BAND, XDROP, ZDROP = 0, 1, 2, 3
+FULL, BAND, XDROP, ZDROP, SEARCH = 0, 1, 2, 3, 4
 
 _GAMMA = np.uint64(0x9E3779B97F4A7C15)
 _M1 = np.uint64(0xBF58476D1CE4E5B9)

@@ -12,12 +12,25 @@ INT32_MIN = -(1 << 31)
 DYN_CIGAR_SPAN = 250
 
 
+SEARCH = 4  # the library's score-major search schedule (unit-cost edit distance)
+
+
+def search_cells(S, M, N):
+    """(score, diagonal) entries of the search domain for edit distance S:
+    diagonals max(-s, -M) .. min(s, N) for s = 0 .. S."""
+    return sum(min(s, N) + min(s, M) + 1 for s in range(S + 1))
+
+
 def oracle_batch(batch, want_cigar=None, nthreads=None):
+    """The oracle's results for a batch.  A search batch is checked against
+    the definition it computes: the full-matrix global alignment under the
+    same (unit-cost) scoring."""
     wc = batch.want_cigar if want_cigar is None else want_cigar
+    prune = oracle.FULL if batch.prune == SEARCH else batch.prune
     return oracle.align_batch(batch.matrix, batch.gap_open, batch.gap_extend,
                               batch.q, batch.q_off, batch.q_len,
                               batch.r, batch.r_off, batch.r_len,
-                              mode=batch.mode, prune=batch.prune, band_w=batch.band_w,
+                              mode=batch.mode, prune=prune, band_w=batch.band_w,
                               xdrop=batch.xdrop, want_cigar=wc,
                               nthreads=nthreads or min(16, os.cpu_count() or 1))
 
@@ -41,8 +54,11 @@ def compare(batch, gres, gcig, ores, check_cigar=None, idx=None, max_report=8):
             continue
         if so == oracle.BAD_SYMBOL:
             continue
-        exp = (int(ores["score"][p]), int(ores["q_end"][p]), int(ores["r_end"][p]),
-               int(ores["cells"][p]))
+        exp_cells = int(ores["cells"][p])
+        if batch.prune == SEARCH:
+            exp_cells = search_cells(-int(ores["score"][p]), int(batch.q_len[p]),
+                                     int(batch.r_len[p]))
+        exp = (int(ores["score"][p]), int(ores["q_end"][p]), int(ores["r_end"][p]), exp_cells)
         got = (int(g["score"]), int(g["q_end"]), int(g["r_end"]), int(g["cells"]))
         if exp != got:
             bad.append(f"pair {p} (M={batch.q_len[p]}, N={batch.r_len[p]}): "

@@ -1,0 +1,117 @@
+"""GPU parity of the score-major search schedule (unit-cost edit distance,
+Sec. 6.3) against the CPU oracle: the score equals minus the edit distance
+from the oracle's full-matrix unit-cost global alignment (itself pinned to
+an independent Levenshtein), the end cell is (M, N), and `cells` equals the
+number of (score, diagonal) entries of the widening domain,
+sum over s = 0..S of (min(s, N) + min(s, M) + 1)."""
+import numpy as np
+import pytest
+
+from paper_2607_06225_amd import workloads as W
+from tests.parity import compare, oracle_batch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2607_06225_amd import aln
+    assert torch.cuda.is_available()
+    c = aln.Context(0)
+    yield c
+    c.close()
+
+
+def run(ctx, batch, **kw):
+    from paper_2607_06225_amd import aln
+    print(f"[gpu] {batch.name} n={batch.n} search {kw}", flush=True)
+    return aln.align(ctx, batch, **kw)
+
+
+def check(batch, res):
+    return compare(batch, res, None, oracle_batch(batch))
+
+
+def pairs(rng, lengths, div):
+    st = W.Stream(int(rng.integers(1, 1 << 30)), 15)
+    qs, rs = [], []
+    for M, N in lengths:
+        ref = rng.integers(0, 4, size=N).astype(np.uint8)
+        q = W.mutate(ref, div, 2, 1, 1, 4, st)[:M] if div < 1 else \
+            rng.integers(0, 4, size=M).astype(np.uint8)
+        if len(q) < M:
+            q = np.concatenate([q, rng.integers(0, 4, size=M - len(q)).astype(np.uint8)])
+        qs.append(q)
+        rs.append(ref)
+    return qs, rs
+
+
+def sbatch(qs, rs, name):
+    return W.pack_pairs(qs, rs, W.dna_matrix(0, -1), 0, -1, W.GLOBAL, W.SEARCH, name=name)
+
+
+@pytest.mark.parametrize("div", [0.0, 0.01, 0.05, 0.3, 1.0])
+def test_search_edit_distance(ctx, div):
+    rng = np.random.default_rng(900 + int(100 * div))
+    lengths = [(0, 0), (0, 5), (5, 0), (1, 1), (1, 70), (70, 1), (63, 64), (64, 63),
+               (65, 129)] + [(int(rng.integers(1, 2500)), int(rng.integers(1, 2500)))
+                             for _ in range(40)]
+    if div < 0.5:  # similar lengths, as for related sequences
+        lengths = lengths[:9] + [(L, L + int(rng.integers(-20, 21))) for L, _ in lengths[9:]]
+        lengths = [(max(M, 0), max(N, 0)) for M, N in lengths]
+    qs, rs = pairs(rng, lengths, div)
+    b = sbatch(qs, rs, f"search_{div}")
+    res, _ = run(ctx, b)
+    assert check(b, res) == []
+
+
+def test_search_long_pairs_and_indels(ctx):
+    """Pairs of 4 kbp (the paper's largest table size) at 1% and 5%
+    divergence, some with a 60-base insertion."""
+    rng = np.random.default_rng(911)
+    qs, rs = [], []
+    for k in range(24):
+        q, r = pairs(rng, [(4000, 4000)], 0.01 if k % 2 else 0.05)
+        q, r = q[0], r[0]
+        if k % 3 == 0:
+            q = np.concatenate([q[:2000], rng.integers(0, 4, 60).astype(np.uint8), q[2000:]])
+        qs.append(q)
+        rs.append(r)
+    b = sbatch(qs, rs, "search_4k")
+    res, _ = run(ctx, b)
+    assert check(b, res) == []
+
+
+def test_search_matches_full_matrix_on_gpu(ctx):
+    """The same pairs through the full-matrix strip path (unit-cost global
+    alignment): identical scores."""
+    rng = np.random.default_rng(913)
+    qs, rs = pairs(rng, [(int(L), int(L) + 7) for L in rng.integers(100, 1500, 30)], 0.05)
+    bs = sbatch(qs, rs, "search_vs_full")
+    bf = W.pack_pairs(qs, rs, W.dna_matrix(0, -1), 0, -1, W.GLOBAL, W.FULL, name="full_unit")
+    rs_, _ = run(ctx, bs)
+    rf, _ = run(ctx, bf)
+    assert np.array_equal(rs_["score"], rf["score"])
+
+
+def test_search_per_pair_and_graph_match(ctx):
+    rng = np.random.default_rng(917)
+    qs, rs = pairs(rng, [(300, 310), (50, 60), (1200, 1190), (0, 9)], 0.1)
+    b = sbatch(qs, rs, "search_pp")
+    r1, _ = run(ctx, b)
+    r2, _ = run(ctx, b, per_pair=True)
+    r3, _ = run(ctx, b, graph=True)
+    assert np.array_equal(r1, r2) and np.array_equal(r1, r3)
+    assert check(b, r1) == []
+
+
+def test_search_rejects_what_it_does_not_compute(ctx):
+    from paper_2607_06225_amd import aln
+    ql = np.array([10], np.int32)
+    sid_unit = ctx.set_scoring(W.dna_matrix(0, -1), 0, -1)
+    sid_affine = ctx.set_scoring(W.dna_matrix(2, -4), -4, -2)
+    for sid, mode, cig in ((sid_affine, W.GLOBAL, False), (sid_unit, W.LOCAL, False),
+                           (sid_unit, W.GLOBAL, True)):
+        with pytest.raises(aln.AlnError):
+            ctx.plan(sid, ql, ql, mode, W.SEARCH, want_cigar=cig)
