@@ -44,13 +44,17 @@ METRIC = "GCUPS (bit-exact) at 1 GPU, batched vs per-pair; % int-VALU roofline; 
 #   X-drop adds the test against best - X                         -> 10
 #   Z-drop adds to that |d - d_best| (absolute difference) and its
 #   add to H                                                      -> 12
+# A search entry (score s, diagonal d) of unit-cost edit distance: two adds
+# (mismatch, insertion), three bound tests, two max; the character compares of
+# its extension depend on the data and are not counted                -> 7
 OPS_PER_CELL = {("GLOBAL", 0): 8, ("GLOBAL", 1): 8, ("LOCAL", 0): 10, ("LOCAL", 1): 10,
-                ("EXTEND", 0): 9, ("EXTEND", 1): 9, ("EXTEND", 2): 10, ("EXTEND", 3): 12}
+                ("EXTEND", 0): 9, ("EXTEND", 1): 9, ("EXTEND", 2): 10, ("EXTEND", 3): 12,
+                ("GLOBAL", 4): 7}
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz; packed 16-bit ops do two per lane.
 PEAK_I32_TOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_I16_TOPS = 2 * PEAK_I32_TOPS
 KERNEL_WIDTH = {"sw16": "i16"}
-FILL_KERNELS = ("sw16", "strip_i32", "diag_band", "xdrop", "zdrop")
+FILL_KERNELS = ("sw16", "strip_i32", "diag_band", "xdrop", "zdrop", "search")
 
 WORKLOAD_DESC = {
     "sw_protein": ("Smith-Waterman local, protein (20 letters, seeded symmetric matrix), "
@@ -68,9 +72,20 @@ WORKLOAD_DESC = {
     "xdrop_cigar": ("X-drop extension with CIGAR: the xdrop_ext pairs, score + end cell + "
                     "CIGAR through the pruned region (score pass, traceback pass to the end "
                     "cell, walk)"),
+    "edit_search": ("unit-cost edit distance by the score-major search schedule (Sec. 6.3), "
+                    "4,096 pairs of 2,000 bp at 5% divergence; score (= -edit distance)"),
 }
 MODE_NAME = {0: "GLOBAL", 1: "LOCAL", 2: "EXTEND"}
-PRUNE_NAME = {0: "full", 1: "band", 2: "xdrop", 3: "zdrop"}
+PRUNE_NAME = {0: "full", 1: "band", 2: "xdrop", 3: "zdrop", 4: "search"}
+
+# The paper's edit-distance table (Sec. 9.1): antidiagonal (full matrix) and
+# search times on its CPU, in the table's units (the text calls them
+# milliseconds, the caption seconds), keyed by (length, divergence).
+PAPER_EDIT_TABLE = {(500, 0.01): (0.069, 0.0007), (2000, 0.01): (0.87, 0.0089),
+                    (4000, 0.01): (4.15, 0.0138), (500, 0.05): (0.050, 0.0019),
+                    (2000, 0.05): (0.71, 0.052), (4000, 0.05): (4.27, 0.19),
+                    (500, 0.30): (0.051, 0.11), (2000, 0.30): (0.72, 1.58),
+                    (4000, 0.30): (4.36, 6.02)}
 
 
 def log(msg):
@@ -108,7 +123,7 @@ def cpu_baseline(batch, work, target_s):
     cells = float(ores["cells"].sum())
     return dict(value=round(cells / dt / 1e9, 4), unit="GCUPS", cores=cores, kind="oracle",
                 sample=f"first {k} of {n} pairs in generation order ({cells:.3e} cells), "
-                       f"{dt:.1f} s on {cores} host threads"), ores, k
+                       f"{dt:.1f} s on {cores} host threads", seconds=round(dt, 3)), ores, k
 
 
 def measured_traffic(family, workload):
@@ -242,7 +257,13 @@ def run_workload(name, batch, args, cpu_seconds, pp_cap):
     cpu = verified = None
     if cpu_seconds > 0:
         log(f"[bench] {name}: CPU oracle on a bounded sample")
-        cpu, ores, k = cpu_baseline(batch, res["cells"], cpu_seconds)
+        # the oracle's work per pair: its own cells (for a search batch, the
+        # full matrix of the definition it evaluates)
+        work = (batch.q_len.astype(np.int64) * batch.r_len if batch.prune == 4
+                else res["cells"])
+        cpu, ores, k = cpu_baseline(batch, work, cpu_seconds)
+        if batch.prune == 4:
+            cpu["alignments_per_s"] = round(k / cpu["seconds"], 1)
         sub = batch.subset(np.arange(k))
         bad = compare(sub, res[:k], cig[:k] if cig is not None else None, ores)
         verified = dict(pairs=k, mismatches=len(bad), first=bad[:3])
@@ -264,12 +285,75 @@ def run_workload(name, batch, args, cpu_seconds, pp_cap):
             out["cigar_cap_pairs"] = int((res["status"] == aln.R_CIGAR_CAP).sum())
     if batch.mode == 1 and batch.prune == 0:
         out["int32_reruns"] = int(((res["flags"] & aln.F_I16_RERUN) != 0).sum())
+    if batch.prune == 4:
+        # entries are (score, diagonal) pairs; also report the full-matrix
+        # equivalent rate and alignments per second
+        out["equivalent_gcups"] = round(full_cells / (ms_per_step * 1e-3) / 1e9, 3)
+        out["alignments_per_s"] = round(batch.n / (ms_per_step * 1e-3), 1)
+        out["mean_edit_distance"] = round(float(-res["score"].mean()), 2)
     plan.close()
     ctx.close()
     log(f"[bench] {name}: " + json.dumps({k: out[k] for k in (
         "gcups", "ms_per_step", "cells", "kernel_ms_per_step", "per_pair", "cpu_baseline",
         "bit_exact_check")}))
     return out
+
+
+def run_edit_table(args):
+    """Unit-cost edit distance at the lengths and divergences of the paper's
+    table (Sec. 9.1): the same pairs through the score-major search schedule
+    and through the full-matrix path (the antidiagonal schedule), each timed
+    with HIP events (median of 3 after a warm-up).  Scores must agree with
+    each other on every pair and with the CPU oracle on a sample."""
+    import torch
+    from paper_2607_06225_amd import aln
+    from paper_2607_06225_amd import workloads as W
+    from tests.parity import compare, oracle_batch
+
+    ctx = aln.Context(0)
+    stream = torch.cuda.current_stream()
+    rows = []
+    for (length, div), (p_ad, p_search) in sorted(PAPER_EDIT_TABLE.items(),
+                                                   key=lambda x: (x[0][1], x[0][0])):
+        n = args.edit_table_pairs
+        bs = W.edit_pairs(n, length, div, seed=700 + length + int(1000 * div))
+        sid = ctx.set_scoring(bs.matrix, bs.gap_open, bs.gap_extend)
+        db = aln.DeviceBatch(bs)
+        times, res = {}, {}
+        for prune in (W.SEARCH, W.FULL):
+            plan = ctx.plan(sid, bs.q_len, bs.r_len, W.GLOBAL, prune)
+            buf = aln.Buffers(plan)
+            ctx.execute(plan, db, buf.ws, buf.res, None, stream=stream)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+            for k in range(3):
+                ev[2 * k].record(stream)
+                ctx.execute(plan, db, buf.ws, buf.res, None, stream=stream)
+                ev[2 * k + 1].record(stream)
+            torch.cuda.synchronize()
+            times[prune] = float(np.median([ev[2 * k].elapsed_time(ev[2 * k + 1])
+                                            for k in range(3)]))
+            res[prune] = buf.results(n)
+            plan.close()
+        agree = bool(np.array_equal(res[W.SEARCH]["score"], res[W.FULL]["score"]))
+        k = min(n, args.edit_table_check)
+        sub = bs.subset(np.arange(k))
+        bad = compare(sub, res[W.SEARCH][:k], None, oracle_batch(sub))
+        rows.append(dict(
+            length=length, divergence=div, pairs=n,
+            mean_edit_distance=round(float(-res[W.SEARCH]["score"].mean()), 2),
+            search_ms=round(times[W.SEARCH], 4), full_ms=round(times[W.FULL], 4),
+            search_us_per_alignment=round(1e3 * times[W.SEARCH] / n, 3),
+            full_us_per_alignment=round(1e3 * times[W.FULL] / n, 3),
+            search_over_full=round(times[W.FULL] / times[W.SEARCH], 2),
+            scores_agree=agree, oracle_checked=k, oracle_mismatches=len(bad),
+            paper_ad_time=p_ad, paper_search_time=p_search,
+            paper_search_over_ad=round(p_ad / p_search, 2)))
+        log(f"[bench] edit table {length} bp {div}: {json.dumps(rows[-1])}")
+        del db
+    ctx.close()
+    return dict(note="paper times: its CPU (Intel Core i9-285K), one alignment, in the table's "
+                     "units (ms per the text of Sec. 9.1, s per the caption); context only",
+                rows=rows)
 
 
 def run_serving(args):
@@ -342,7 +426,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="sw_protein", choices=sorted(WORKLOAD_DESC),
                     help="headline workload (the JSON line's value)")
-    ap.add_argument("--configs", default="nw_dna_1k,band_long,xdrop_ext,zdrop_ext,xdrop_cigar",
+    ap.add_argument("--edit-table-pairs", type=int, default=1024,
+                    help="pairs per cell of the edit-distance table (0: skip the table)")
+    ap.add_argument("--edit-table-check", type=int, default=16,
+                    help="pairs per cell checked against the CPU oracle")
+    ap.add_argument("--configs",
+                    default="nw_dna_1k,band_long,xdrop_ext,zdrop_ext,xdrop_cigar,edit_search",
                     help="comma list of further workloads to measure, or 'none'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
@@ -410,6 +499,7 @@ def main():
         configs[c] = run_workload(c, b, args, 0 if args.no_cpu_baseline
                                   else args.extra_cpu_seconds, pp_cap)
         del b
+    edit_table = run_edit_table(args) if args.edit_table_pairs > 0 else None
     serving_out = run_serving(args) if args.serving_requests > 0 else None
 
     out = {
@@ -438,6 +528,7 @@ def main():
         "plan_ms": head["plan_ms"],
         "autotune": head["autotune"],
         "configs": configs,
+        "edit_table": edit_table,
         "serving": serving_out,
     }
     for k in ("int32_reruns", "statuses", "widened_pairs", "cigar_cap_pairs"):

@@ -32,6 +32,11 @@ Workloads (codes: DNA A,C,G,T = 0..3; protein = 0..19):
                  Z = 100, so the two pruning rules are compared on one input.
   xdrop_cigar    the xdrop_ext pairs with a CIGAR per extension side (the
                  traceback through the X-drop region).
+  edit_search    4,096 pairs of 2,000 bp at 5% divergence (sub:ins:del = 2:1:1),
+                 unit edit costs, global; the score-major search schedule.
+                 edit_pairs() builds the same kind of batch for any length and
+                 divergence (the sizes and divergences of the paper's
+                 edit-distance table).
 """
 from dataclasses import dataclass, field
 
@@ -407,6 +412,26 @@ def xdrop_cigar(n=200000, seed=404, min_len=150, max_len=5000, xdrop=100, seed_l
     return b
 
 
+def edit_pairs(n, length, div, seed, prune=SEARCH, name=None):
+    """n pairs for unit-cost edit distance: a uniform ACGT reference of
+    `length` bases and a query that is the reference with per-base edits at
+    rate `div` (substitution:insertion:deletion = 2:1:1)."""
+    st = Stream(seed, 6)
+    qs, rs = [], []
+    for _ in range(n):
+        ref = random_codes(st, length, 4)
+        qs.append(mutate(ref, div, 2, 1, 1, 4, st))
+        rs.append(ref)
+    b = pack_pairs(qs, rs, dna_matrix(0, -1), 0, -1, GLOBAL, prune,
+                   name=name or f"edit_{length}_{div}")
+    b.meta = dict(seed=seed, length=length, div=div)
+    return b
+
+
+def edit_search(n=4096, length=2000, div=0.05, seed=606):
+    return edit_pairs(n, length, div, seed, name="edit_search")
+
+
 WORKLOADS = {
     "nw_dna_1k": nw_dna_1k,
     "sw_protein": sw_protein,
@@ -414,6 +439,7 @@ WORKLOADS = {
     "xdrop_ext": xdrop_ext,
     "zdrop_ext": zdrop_ext,
     "xdrop_cigar": xdrop_cigar,
+    "edit_search": edit_search,
 }
 
 
