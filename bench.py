@@ -531,7 +531,8 @@ def main():
         "edit_table": edit_table,
         "serving": serving_out,
     }
-    for k in ("int32_reruns", "statuses", "widened_pairs", "cigar_cap_pairs"):
+    for k in ("int32_reruns", "statuses", "widened_pairs", "cigar_cap_pairs",
+              "equivalent_gcups", "alignments_per_s", "mean_edit_distance"):
         if k in head:
             out[k] = head[k]
     print(json.dumps(out), flush=True)
