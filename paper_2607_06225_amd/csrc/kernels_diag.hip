@@ -302,8 +302,12 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
       while (dhi > dbase + W - 3) shift_right2();
       while (dlo < dbase + 2) shift_left2();
     }
-    // ---- stage sequence codes for this step's window
-    {
+    // ---- stage sequence codes for this step's window.  Under X-drop /
+    // Z-drop every 8 antidiagonals: a domain end moves by at most one
+    // diagonal per antidiagonal, so the window's largest i and j grow by at
+    // most 8 in between, well inside the 64-code slack.  (A band of an
+    // elongated rectangle can move faster and is checked every step.)
+    if (!DYN || (par == 1 && ((k >> 1) & 3) == 0)) {
       const int needq = ((k - dbase) >> 1) + 64; // largest i on the window, plus slack
       const int needr = ((k + dbase + W) >> 1) + 64;
       stage(Q, M, qbuf, qtop, min(needq, M + 64));
@@ -415,7 +419,7 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
     // ---- best cell of this antidiagonal, next domain
     if (MODE != ALN_GLOBAL) {
       const int kb = wave_max_i32(kkey);
-      if (kb >= 0) {
+      if (kb >= 0 && (kb >> 11) >= best) { // the end order starts with the score
         const int sc = kb >> 11;
         const int d = dbase + (kb & 2047);
         const int bi = (k - d) >> 1, bj = (k + d) >> 1;
@@ -423,22 +427,22 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
       }
     }
     if (DYN) {
-      // first and last surviving diagonals
-      int slo = 1 << 30, shi = -(1 << 30);
+      // first and last surviving diagonals: each lane's first and last
+      // surviving slot, then the first and last lane holding one
+      int xf = RD, xl = -1;
 #pragma unroll
       for (int m = 0; m < HALF; ++m) {
         const int x = 2 * m + par;
-        const unsigned long long bal = __ballot(H[x] > NEG32 / 2);
-        if (bal) {
-          const int lf = __ffsll((long long)bal) - 1;
-          const int ll = 63 - __clzll((long long)bal);
-          slo = min(slo, dbase + lf * RD + x);
-          shi = max(shi, dbase + ll * RD + x);
-        }
+        const bool sv = H[x] > NEG32 / 2;
+        xf = (sv && xf == RD) ? x : xf;
+        xl = sv ? x : xl;
       }
-      if (slo > shi) return false; // every candidate pruned: the extension stops
-      lo = slo;
-      hi = shi;
+      const unsigned long long bal = __ballot(xl >= 0);
+      if (!bal) return false; // every candidate pruned: the extension stops
+      const int lf = __ffsll((long long)bal) - 1;
+      const int ll = 63 - __clzll((long long)bal);
+      lo = dbase + lf * RD + __builtin_amdgcn_readlane(xf, lf);
+      hi = dbase + ll * RD + __builtin_amdgcn_readlane(xl, ll);
     } else {
       lo = dlo;
       hi = dhi;
