@@ -54,7 +54,8 @@ OPS_PER_CELL = {("GLOBAL", 0): 8, ("GLOBAL", 1): 8, ("LOCAL", 0): 10, ("LOCAL", 
 PEAK_I32_TOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_I16_TOPS = 2 * PEAK_I32_TOPS
 KERNEL_WIDTH = {"sw16": "i16"}
-FILL_KERNELS = ("sw16", "strip_i32", "diag_band", "xdrop", "zdrop", "search")
+FILL_KERNELS = ("sw16", "strip_i32", "diag_band", "xdrop", "zdrop", "xdrop_tb", "zdrop_tb",
+                "search")
 
 WORKLOAD_DESC = {
     "sw_protein": ("Smith-Waterman local, protein (20 letters, seeded symmetric matrix), "

@@ -842,8 +842,24 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
   };
   PairTask *wq0 = plan->xdrop ? reinterpret_cast<PairTask *>(ws + plan->widen_off[0]) : nullptr;
   PairTask *wq1 = plan->xdrop ? reinterpret_cast<PairTask *>(ws + plan->widen_off[1]) : nullptr;
+  if (plan->xtb_count > 0) {
+    // X-drop / Z-drop with CIGAR: one pass per pair computes the results and
+    // writes the traceback codes; regions that outgrow its window go to the
+    // widening queue below (score only) and the walk decides their CIGAR
+    auto xtb = [&](int32_t first, int32_t count) {
+      alnk::DiagArgs d = diag_args(dtasks + first, count, nullptr, 16, widen_cnt, wq0);
+      return alnk::launch_diag(4, ALN_EXTEND, plan->p.prune, true, d, st);
+    };
+    const char *fam = plan->p.prune == ALN_ZDROP ? "zdrop_tb" : "xdrop_tb";
+    if (!per_pair) {
+      HIP_TRY(ctx, timed_launch(ctx, fam, st, [&] { return xtb(plan->xtb_first, plan->xtb_count); }));
+    } else {
+      for (int32_t k = 0; k < plan->xtb_count; ++k) HIP_TRY(ctx, xtb(plan->xtb_first + k, 1));
+    }
+  }
   for (const LaunchDesc &L : plan->launches) {
     if (L.kind == K_DIAG) {
+      if (plan->xtb_count > 0) continue; // the traceback pass above replaces it
       const int widen_rows = plan->xdrop ? 16 : 0;
       auto go = [&](const alnk::DiagArgs &da) {
         return L.sides == 4 ? alnk::launch_xdrop_group(plan->p.prune, da, st)
@@ -898,19 +914,6 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
     HIP_TRY(ctx, timed_launch(ctx, fam, st, [&] {
               return alnk::launch_diag(32, ALN_EXTEND, pr, false, d2, st);
             }));
-  }
-  if (plan->xtb_count > 0) {
-    // traceback pass of the X-drop / Z-drop pairs, then their walks below
-    auto xtb = [&](int32_t first, int32_t count) {
-      alnk::DiagArgs d = diag_args(dtasks + first, count, nullptr, 0, nullptr, nullptr);
-      return alnk::launch_diag(4, ALN_EXTEND, plan->p.prune, true, d, st);
-    };
-    const char *fam = plan->p.prune == ALN_ZDROP ? "zdrop_tb" : "xdrop_tb";
-    if (!per_pair) {
-      HIP_TRY(ctx, timed_launch(ctx, fam, st, [&] { return xtb(plan->xtb_first, plan->xtb_count); }));
-    } else {
-      for (int32_t k = 0; k < plan->xtb_count; ++k) HIP_TRY(ctx, xtb(plan->xtb_first + k, 1));
-    }
   }
   if (plan->p.want_cigar) {
     alnk::WalkArgs wa;

@@ -120,11 +120,12 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
   static_assert(RD % 2 == 0, "a lane must hold whole diagonal pairs");
   constexpr bool DYN = PRUNE == ALN_XDROP || PRUNE == ALN_ZDROP; // dynamic pruning
   constexpr bool ZD = PRUNE == ALN_ZDROP;
-  // Traceback pass of a dynamically pruned pair: the score pass already
-  // found the end cell; this pass recomputes antidiagonals 1 .. q_end + r_end
-  // identically and writes their codes (2 bytes per lane and antidiagonal
-  // pair), changing no result field except CIGAR_CAP when the region
-  // outgrows the window.
+  // Dynamic pruning with traceback: a full pass (results, widening queue)
+  // that also writes every antidiagonal's codes, 2 bytes per lane and
+  // antidiagonal pair.  When the region outgrows the window at antidiagonal
+  // k, the codes of antidiagonals < k are complete; k goes to the task's aux
+  // field, and the walk gives the pair a CIGAR only if its end cell (found
+  // by the wider re-run) lies before it.
   constexpr bool TBX = TB && DYN;
   static_assert(!TBX || RD == 4, "dynamic-pruning codes are laid out for RD = 4");
   constexpr int W = 64 * RD;
@@ -140,14 +141,9 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
   const int A = a.sc->alphabet;
   const int s_match = a.sc->match, s_mismatch = a.sc->mismatch; // MM: all that scores
 
-  int kstop = M + N; // last antidiagonal evaluated
-  if (TBX) {
-    if (__builtin_amdgcn_readfirstlane(res->status) != ALN_R_OK) return;
-    kstop = __builtin_amdgcn_readfirstlane(res->q_end + res->r_end);
-    if (kstop == 0) return; // empty extension: no codes needed
-  }
+  const int kstop = M + N; // last antidiagonal evaluated
   if (M == 0 || N == 0) {
-    if (lane == 0 && !TBX) {
+    if (lane == 0) {
       if (MODE == ALN_GLOBAL) {
         res->score = (M + N == 0) ? 0 : go + (M + N) * ge;
         res->q_end = M;
@@ -261,12 +257,18 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
   const bool band_full = (PRUNE == ALN_BAND) && M == 0;
   if (PRUNE == ALN_BAND) bt.init(M, N, a.band_w);
   bool overflow = false;
+  int kovf = 0; // antidiagonal at which the region outgrew the window
 
   // traceback output
   uint32_t *tbw = nullptr;
   int *dbh = nullptr;
   uint32_t code_lo = 0, code_hi = 0;
   int dbase_acc = 0;
+  // codes of an even antidiagonal, and window bases of a block, are written
+  // with the next odd antidiagonal / at the block's end; an extension that
+  // stops early writes what is pending after the loop
+  bool code_pend = false, dbase_pend = false;
+  int kcode = 0, kdb = 0;
   if (TB) {
     const int nk = M + N + 1;
     dbh = reinterpret_cast<int *>(a.tb + tk.tb_off);
@@ -298,7 +300,7 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
     }
     // ---- keep the domain inside the window
     if (dlo <= dhi) {
-      if (dhi - dlo > W - 6) { overflow = true; return false; }
+      if (dhi - dlo > W - 6) { overflow = true; kovf = k; return false; }
       while (dhi > dbase + W - 3) shift_right2();
       while (dlo < dbase + 2) shift_left2();
     }
@@ -315,9 +317,12 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
     }
     if (TB) {
       if (lane == (k & 63)) dbase_acc = dbase;
+      dbase_pend = true;
+      kdb = k;
       if ((k & 63) == 63 || k == KMAX) {
         const int blk = k >> 6;
         if (lane <= (k & 63)) dbh[blk * 64 + lane] = dbase_acc;
+        dbase_pend = false;
       }
     }
     // ---- neighbour values across the lane boundary
@@ -399,8 +404,13 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
       }
     }
     if (TB) {
-      if (par == 0) code_lo = cw;
-      else code_hi = cw;
+      if (par == 0) {
+        code_lo = cw;
+        code_pend = true;
+        kcode = k;
+      } else {
+        code_hi = cw;
+      }
       if (par == 1 || k == KMAX) {
         const uint32_t lo32 = code_lo | (HALF < 8 ? (code_hi << (4 * HALF)) : 0u);
         const uint32_t hi32 = (HALF < 8) ? (code_hi >> (32 - 4 * HALF)) : code_hi;
@@ -409,6 +419,7 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
         else
           *reinterpret_cast<uint2 *>(tbw + ((size_t)(k >> 1) * 64 + lane) * 2) = make_uint2(lo32, hi32);
         code_lo = code_hi = 0;
+        code_pend = false;
       }
     }
     // ---- cells evaluated on this antidiagonal (i >= 1 and j >= 1)
@@ -454,13 +465,18 @@ __device__ void diag_task(const DiagArgs &a, int task, int wave, int lane, uint8
     if (!step(std::integral_constant<int, 1>{}, k)) break;
     if (k + 1 > KMAX || !step(std::integral_constant<int, 0>{}, k + 1)) break;
   }
-
-  if (TBX) {
-    if (lane == 0 && overflow) res->status = ALN_R_CIGAR_CAP;
-    return;
+  if (TB && code_pend) { // the last even antidiagonal, without its odd partner
+    if (TBX)
+      reinterpret_cast<uint16_t *>(tbw)[(size_t)(kcode >> 1) * 64 + lane] = (uint16_t)code_lo;
+    else
+      *reinterpret_cast<uint2 *>(tbw + ((size_t)(kcode >> 1) * 64 + lane) * 2) =
+          make_uint2(code_lo, 0u);
   }
+  if (TB && dbase_pend && lane <= (kdb & 63)) dbh[(kdb >> 6) * 64 + lane] = dbase_acc;
+
   if (lane == 0) {
     if (overflow) {
+      if (TBX) const_cast<PairTask *>(a.tasks)[task].aux = kovf;
       res->flags |= ALN_F_WIDENED;
       if (a.widen_rows > 0) {
         const int slot = atomicAdd(a.widen_count, 1);

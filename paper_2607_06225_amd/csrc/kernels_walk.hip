@@ -347,6 +347,12 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
     res->cigar_len = 0;
   }
   if (status != ALN_R_OK) return;
+  // X-drop / Z-drop: codes stop before the antidiagonal at which the region
+  // outgrew the traceback window (aux, 0: never)
+  if (S == 2 && tk.aux > 0 && i_end + j_end >= tk.aux) {
+    if (lane == 0) res->status = ALN_R_CIGAR_CAP;
+    return;
+  }
   const int M = uni(a.b.q_len[p]), N = uni(a.b.r_len[p]);
   const uint8_t *Qs = a.b.q + a.b.q_off[p];
   const uint8_t *Rs = a.b.r + a.b.r_off[p];
