@@ -78,7 +78,10 @@ enum { ALN_GLOBAL = 0, ALN_LOCAL = 1, ALN_EXTEND = 2 };
  * the edit distance), no CIGAR.  For s = 0, 1, ... it keeps, per diagonal
  * d = j - i in [max(-s, -M), min(s, N)], the furthest row reached with s
  * edits, extended along matches, and stops when diagonal N - M reaches row
- * M.  `cells` then counts those (score, diagonal) entries, s = 0 included. */
+ * M.  `cells` then counts those (score, diagonal) entries, s = 0 included.
+ * Pairs need M <= 32767, and the batch's longest M plus its longest N at
+ * most about 54 000 (both sequences and one int16 row sit in LDS); else
+ * ALN_E_UNSUPPORTED. */
 enum { ALN_FULL = 0, ALN_BAND = 1, ALN_XDROP = 2, ALN_ZDROP = 3, ALN_SEARCH = 4 };
 /* score width: AUTO lets the library choose (packed int16 where it applies,
  * with an automatic int32 re-run of any pair that could have overflowed) */

@@ -273,10 +273,10 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     L.count = n;
     L.lds_bnd = (int32_t)align_up((uint64_t)maxM + 8, 16);  // query codes
     L.lds_prof = (int32_t)align_up((uint64_t)maxN + 8, 16); // reference codes
-    L.lds_f = (int32_t)align_up(((uint64_t)maxM + maxN + 1) * 4, 16);
-    if ((int64_t)L.lds_bnd + L.lds_prof + L.lds_f > 160 * 1024) {
+    L.lds_f = (int32_t)align_up(((uint64_t)maxM + maxN + 1) * 2, 16); // int16 rows
+    if (maxM > 32767 || (int64_t)L.lds_bnd + L.lds_prof + L.lds_f > 160 * 1024) {
       delete pl;
-      return fail(ctx, ALN_E_UNSUPPORTED, "SEARCH pairs need M + N <= about 32000");
+      return fail(ctx, ALN_E_UNSUPPORTED, "SEARCH needs M <= 32767 and the longest M plus the longest N of the batch <= about 54000");
     }
     for (int32_t i : order) {
       PairTask t;

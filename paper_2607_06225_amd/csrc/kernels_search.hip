@@ -13,9 +13,10 @@
 // clipped to the matrix: [max(-s, -M), min(s, N)].  The search stops at the
 // first score s whose diagonal N - M reaches row M: s is the edit distance.
 //
-// One wavefront per pair.  Both sequences and one row of F (int32 per
-// diagonal, updated in place) live in LDS.  Lanes take 64 consecutive
-// diagonals at a time; the neighbours' old values come by DPP, the chunk's
+// One wavefront per pair.  Both sequences and one row of F (int16 per
+// diagonal, -32768 for "not reached", updated in place) live in LDS, so
+// rows are at most 32767.  Narrow entries let more wavefronts share a CU.
+// Lanes take 64 consecutive diagonals at a time; the neighbours' old values come by DPP, the chunk's
 // left neighbour from a register saved before the previous chunk overwrote
 // it, and its right neighbour from LDS (not yet updated).  Extension compares
 // four characters per step: two aligned dword reads per sequence and a byte
@@ -24,7 +25,13 @@
 
 namespace alnk {
 
-constexpr int kNegF = -(1 << 30);
+constexpr int kNegF = -(1 << 30);      // "not reached" in registers
+constexpr int16_t kNegF16 = -32768;     // ... and in the LDS row
+
+__device__ __forceinline__ int fload(const int16_t *F, int idx) {
+  const int v = F[idx];
+  return v < 0 ? kNegF : v;
+}
 
 __device__ __forceinline__ int sdpp_shr1(int old, int v) { // lane l <- lane l-1
   return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xf, 0xf, false);
@@ -68,10 +75,10 @@ __global__ __launch_bounds__(64) void search_edit_kernel(SearchArgs a) {
   // padding 0xFF; the paddings never match each other or a code), F[d + M]
   uint8_t *qs = smem;
   uint8_t *rs = smem + a.lds_q;
-  int *F = reinterpret_cast<int *>(smem + a.lds_q + a.lds_r);
+  int16_t *F = reinterpret_cast<int16_t *>(smem + a.lds_q + a.lds_r);
   for (int k = lane; k < M + 8; k += 64) qs[k] = k < M ? Q[k] : 0xFE;
   for (int k = lane; k < N + 8; k += 64) rs[k] = k < N ? Rs[k] : 0xFF;
-  for (int k = lane; k <= M + N; k += 64) F[k] = kNegF;
+  for (int k = lane; k <= M + N; k += 64) F[k] = kNegF16;
   __syncthreads();
 
   const int dt = N - M; // the end cell's diagonal
@@ -79,10 +86,10 @@ __global__ __launch_bounds__(64) void search_edit_kernel(SearchArgs a) {
   long long cells = 1;
   {
     const int f0 = extend(qs, rs, 0, 0, min(M, N));
-    if (lane == 0) F[M] = f0;
+    if (lane == 0) F[M] = (int16_t)f0;
   }
   __syncthreads();
-  bool done = dt == 0 && __builtin_amdgcn_readfirstlane(F[M]) >= M;
+  bool done = dt == 0 && __builtin_amdgcn_readfirstlane(fload(F, M)) >= M;
   while (!done && s < M + N) {
     ++s;
     dmin = max(dmin - 1, -M);
@@ -92,10 +99,10 @@ __global__ __launch_bounds__(64) void search_edit_kernel(SearchArgs a) {
     for (int d0 = dmin; d0 <= dmax; d0 += 64) {
       const int d = d0 + lane;
       const bool act = d <= dmax;
-      const int old = act ? F[d + M] : kNegF;
+      const int old = act ? fload(F, d + M) : kNegF;
       int right = sdpp_shl1(kNegF, old);
       int left = sdpp_shr1(kNegF, old);
-      if (lane == 63) right = (d + 1 <= N) ? F[d + 1 + M] : kNegF;
+      if (lane == 63) right = (d + 1 <= N) ? fload(F, d + 1 + M) : kNegF;
       if (lane == 0) left = carry;
       carry = __builtin_amdgcn_readlane(old, 63);
       const int lim = min(M, N - d);
@@ -104,9 +111,9 @@ __global__ __launch_bounds__(64) void search_edit_kernel(SearchArgs a) {
       if (right + 1 <= lim) f = max(f, right + 1); // insertion
       if (left <= lim) f = max(f, left);           // deletion
       if (act && f >= 0) f = extend(qs, rs, f, d, lim);
-      if (act) F[d + M] = f >= 0 ? f : kNegF;
+      if (act) F[d + M] = f >= 0 ? (int16_t)f : kNegF16;
     }
-    done = dt >= dmin && dt <= dmax && __builtin_amdgcn_readfirstlane(F[dt + M]) >= M;
+    done = dt >= dmin && dt <= dmax && __builtin_amdgcn_readfirstlane(fload(F, dt + M)) >= M;
   }
   if (lane == 0) {
     res->score = -s;

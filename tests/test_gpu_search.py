@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from paper_2607_06225_amd import workloads as W
-from tests.parity import compare, oracle_batch
+from tests.parity import compare, oracle_batch, search_cells
 
 pytestmark = pytest.mark.gpu
 
@@ -95,6 +95,29 @@ def test_search_matches_full_matrix_on_gpu(ctx):
     assert np.array_equal(rs_["score"], rf["score"])
 
 
+def test_search_maximum_rows(ctx):
+    """The largest query the int16 row store holds (32 767 rows), in a batch
+    whose longest query plus longest reference fills most of the LDS limit:
+    scores equal the oracle's where no closed form exists, and the closed
+    forms (identical sequences: 0; one side empty: the other's length)
+    elsewhere; `cells` follows the domain's count."""
+    rng = np.random.default_rng(919)
+    L, N = 32767, 20000
+    qs, rs = pairs(rng, [(L, 4000), (4000, 3991)], 0.005)
+    same = rng.integers(0, 4, size=N).astype(np.uint8)
+    qs += [same, rng.integers(0, 4, size=L).astype(np.uint8), np.zeros(0, np.uint8)]
+    rs += [same.copy(), np.zeros(0, np.uint8), rng.integers(0, 4, size=N).astype(np.uint8)]
+    b = sbatch(qs, rs, "search_max_rows")
+    res, _ = run(ctx, b)
+    assert list(res["status"]) == [0] * 5
+    assert check(sbatch(qs[:2], rs[:2], "search_max_rows_head"), res[:2]) == []
+    assert list(res["score"][2:]) == [0, -L, -N]
+    for p in range(5):
+        S = -int(res["score"][p])
+        assert int(res["cells"][p]) == search_cells(S, len(qs[p]), len(rs[p]))
+        assert (int(res["q_end"][p]), int(res["r_end"][p])) == (len(qs[p]), len(rs[p]))
+
+
 def test_search_per_pair_and_graph_match(ctx):
     rng = np.random.default_rng(917)
     qs, rs = pairs(rng, [(300, 310), (50, 60), (1200, 1190), (0, 9)], 0.1)
@@ -115,3 +138,8 @@ def test_search_rejects_what_it_does_not_compute(ctx):
                            (sid_unit, W.GLOBAL, True)):
         with pytest.raises(aln.AlnError):
             ctx.plan(sid, ql, ql, mode, W.SEARCH, want_cigar=cig)
+    with pytest.raises(aln.AlnError):  # rows beyond the int16 row store
+        ctx.plan(sid_unit, np.array([32768], np.int32), ql, W.GLOBAL, W.SEARCH)
+    with pytest.raises(aln.AlnError):  # longest query + longest reference beyond LDS
+        ctx.plan(sid_unit, np.array([30000, 10], np.int32), np.array([10, 30000], np.int32),
+                 W.GLOBAL, W.SEARCH)
