@@ -19,8 +19,8 @@
 // Lanes take 64 consecutive diagonals at a time; the neighbours' old values come by DPP, the chunk's
 // left neighbour from a register saved before the previous chunk overwrote
 // it, and its right neighbour from LDS (not yet updated).  Extension compares
-// four characters per step: two aligned dword reads per sequence and a byte
-// align, then the first differing byte.
+// eight characters per step: three aligned dword reads per sequence and two
+// byte aligns, then the first differing byte.
 #include "internal.h"
 
 namespace alnk {
@@ -40,20 +40,23 @@ __device__ __forceinline__ int sdpp_shl1(int old, int v) { // lane l <- lane l+1
   return __builtin_amdgcn_update_dpp(old, v, 0x130, 0xf, 0xf, false);
 }
 
-// four codes starting at byte `off` of an LDS sequence buffer (readable up to
-// off + 7)
-__device__ __forceinline__ uint32_t load4(const uint8_t *buf, int off) {
+// eight codes starting at byte `off` of an LDS sequence buffer (readable up
+// to off + 11)
+__device__ __forceinline__ uint64_t load8(const uint8_t *buf, int off) {
   const uint32_t *w = reinterpret_cast<const uint32_t *>(buf + (off & ~3));
-  return __builtin_amdgcn_alignbyte(w[1], w[0], (uint32_t)(off & 3));
+  const uint32_t sh = (uint32_t)(off & 3);
+  const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
+  return ((uint64_t)__builtin_amdgcn_alignbyte(w2, w1, sh) << 32) |
+         __builtin_amdgcn_alignbyte(w1, w0, sh);
 }
 
 // advance row f of diagonal d while the next characters match, up to lim
 __device__ __forceinline__ int extend(const uint8_t *qs, const uint8_t *rs, int f, int d, int lim) {
   while (f < lim) {
-    const uint32_t x = load4(qs, f) ^ load4(rs, f + d);
-    const int n = x ? (__builtin_ctz(x) >> 3) : 4;
+    const uint64_t x = load8(qs, f) ^ load8(rs, f + d);
+    const int n = x ? (__builtin_ctzll(x) >> 3) : 8;
     f = min(f + n, lim);
-    if (n < 4) break;
+    if (n < 8) break;
   }
   return f;
 }
@@ -71,13 +74,13 @@ __global__ __launch_bounds__(64) void search_edit_kernel(SearchArgs a) {
   const uint8_t *Q = a.b.q + a.b.q_off[p];
   const uint8_t *Rs = a.b.r + a.b.r_off[p];
 
-  // LDS: query codes (M + 8 bytes, padding 0xFE), reference codes (N + 8,
+  // LDS: query codes (M + 12 bytes, padding 0xFE), reference codes (N + 12,
   // padding 0xFF; the paddings never match each other or a code), F[d + M]
   uint8_t *qs = smem;
   uint8_t *rs = smem + a.lds_q;
   int16_t *F = reinterpret_cast<int16_t *>(smem + a.lds_q + a.lds_r);
-  for (int k = lane; k < M + 8; k += 64) qs[k] = k < M ? Q[k] : 0xFE;
-  for (int k = lane; k < N + 8; k += 64) rs[k] = k < N ? Rs[k] : 0xFF;
+  for (int k = lane; k < M + 12; k += 64) qs[k] = k < M ? Q[k] : 0xFE;
+  for (int k = lane; k < N + 12; k += 64) rs[k] = k < N ? Rs[k] : 0xFF;
   for (int k = lane; k <= M + N; k += 64) F[k] = kNegF16;
   __syncthreads();
 
