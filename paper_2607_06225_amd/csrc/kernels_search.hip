@@ -25,13 +25,13 @@
 
 namespace alnk {
 
-constexpr int kNegF = -(1 << 30);      // "not reached" in registers
-constexpr int16_t kNegF16 = -32768;     // ... and in the LDS row
+// "Not reached": -32768 in the LDS row and, sign-extended, in registers.  A
+// move from it stays negative (at most -32767) and every store maps a
+// negative row back to -32768, so it never drifts towards a real row.
+constexpr int16_t kNegF16 = -32768;
+constexpr int kNegF = kNegF16;
 
-__device__ __forceinline__ int fload(const int16_t *F, int idx) {
-  const int v = F[idx];
-  return v < 0 ? kNegF : v;
-}
+__device__ __forceinline__ int fload(const int16_t *F, int idx) { return F[idx]; }
 
 __device__ __forceinline__ int sdpp_shr1(int old, int v) { // lane l <- lane l-1
   return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xf, 0xf, false);
