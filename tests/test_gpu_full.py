@@ -142,6 +142,20 @@ def test_local_end_ties_across_pipeline_strips(ctx, cigar):
     assert compare(b, res, cig, oracle_batch(b)) == []
 
 
+@pytest.mark.parametrize("mode", [W.GLOBAL, W.LOCAL])
+def test_strip_pipeline_forms(ctx, mode):
+    """The strip pipeline (four wavefronts per pair, 4 rows per lane) on
+    random shapes above 256 rows, with CIGARs: a few long pairs, and 400
+    pairs (still below three quarters of a wavefront per SIMD)."""
+    rng = np.random.default_rng(47 + mode)
+    few = [(int(rng.integers(257, 2600)), int(rng.integers(1, 1100))) for _ in range(30)]
+    many = [(int(rng.integers(257, 1400)), int(rng.integers(1, 600))) for _ in range(400)]
+    for lengths in (few, many):
+        b = edge_batch(W.dna_matrix(2, -4), -4, -2, mode, True, 4747, lengths, 4)
+        res, cig = run(ctx, b)
+        assert compare(b, res, cig, oracle_batch(b)) == []
+
+
 def test_many_pairs_run_one_wavefront_each(ctx):
     """More full-matrix pairs than three quarters of the SIMDs: the planner
     keeps one wavefront per pair (multi-strip pairs included)."""
