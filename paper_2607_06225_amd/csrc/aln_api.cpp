@@ -258,8 +258,10 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     maxM = std::max(maxM, pl->qlen[i]);
     maxN = std::max(maxN, pl->rlen[i]);
   }
-  // score-major search (edit distance): one wavefront per pair, longest
-  // first; both sequences and the furthest-row array in LDS
+  // score-major search (edit distance): one workgroup per pair, longest
+  // first; both sequences and the furthest-row array in LDS.  Four
+  // wavefronts share a pair when two rows fit in LDS, else one wavefront
+  // updates a single row in place.
   if (p.prune == ALN_SEARCH) {
     std::vector<int32_t> order(n);
     for (int32_t i = 0; i < n; ++i) order[i] = i;
@@ -278,6 +280,7 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
       delete pl;
       return fail(ctx, ALN_E_UNSUPPORTED, "SEARCH needs M <= 32767 and the longest M plus the longest N of the batch <= about 54000");
     }
+    L.waves = (int64_t)L.lds_bnd + L.lds_prof + 2 * (int64_t)L.lds_f <= 160 * 1024 ? 4 : 1;
     for (int32_t i : order) {
       PairTask t;
       memset(&t, 0, sizeof t);
@@ -759,7 +762,7 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
 
   if (!plan->launches.empty() && plan->launches[0].kind == K_SEARCH) {
     const LaunchDesc &L = plan->launches[0];
-    alnk::SearchArgs sa{bp, dtasks, L.count, d_res, L.lds_bnd, L.lds_prof, L.lds_f};
+    alnk::SearchArgs sa{bp, dtasks, L.count, d_res, L.lds_bnd, L.lds_prof, L.lds_f, L.waves};
     if (!per_pair) {
       HIP_TRY(ctx, timed_launch(ctx, "search", st, [&] { return alnk::launch_search(sa, st); }));
     } else {

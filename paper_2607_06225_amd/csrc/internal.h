@@ -145,13 +145,16 @@ struct DiagArgs {
   int32_t match_mismatch;     // 1: the scoring is one match and one mismatch score
 };
 
-// Score-major search for unit-cost edit distance (one wavefront per task).
+// Score-major search for unit-cost edit distance: one workgroup per task,
+// of `waves` wavefronts (1: one F row in LDS; 4: two rows, the previous
+// score's and the current one's).
 struct SearchArgs {
   BatchPtrs b;
   const PairTask *tasks;
   int32_t ntasks;
   aln_result *res;
-  int32_t lds_q, lds_r, lds_f; // LDS bytes: query codes, reference codes, F row
+  int32_t lds_q, lds_r, lds_f; // LDS bytes: query codes, reference codes, one F row
+  int32_t waves;
 };
 
 // Launchers (defined in the kernel translation units).

@@ -13,14 +13,17 @@
 // clipped to the matrix: [max(-s, -M), min(s, N)].  The search stops at the
 // first score s whose diagonal N - M reaches row M: s is the edit distance.
 //
-// One wavefront per pair.  Both sequences and one row of F (int16 per
-// diagonal, -32768 for "not reached", updated in place) live in LDS, so
-// rows are at most 32767.  Narrow entries let more wavefronts share a CU.
-// Lanes take 64 consecutive diagonals at a time; the neighbours' old values come by DPP, the chunk's
-// left neighbour from a register saved before the previous chunk overwrote
-// it, and its right neighbour from LDS (not yet updated).  Extension compares
-// eight characters per step: three aligned dword reads per sequence and two
-// byte aligns, then the first differing byte.
+// One workgroup per pair, with both sequences and F (int16 per diagonal,
+// -32768 for "not reached", so rows are at most 32767) in LDS.  Two forms:
+// - search_group_kernel: four wavefronts and two F rows (previous score,
+//   current score), used whenever both rows fit;
+// - search_edit_kernel: one wavefront updating a single row in place, for
+//   the longest pairs.  Lanes take 64 consecutive diagonals at a time; the
+//   neighbours' old values come by DPP, the chunk's left neighbour from a
+//   register saved before the previous chunk overwrote it, and its right
+//   neighbour from LDS (not yet updated).
+// Extension compares eight characters per step: three aligned dword reads
+// per sequence and two byte aligns, then the first differing byte.
 #include "internal.h"
 
 namespace alnk {
@@ -126,16 +129,105 @@ __global__ __launch_bounds__(64) void search_edit_kernel(SearchArgs a) {
   }
 }
 
-hipError_t launch_search(const SearchArgs &a, hipStream_t s) {
-  if (a.ntasks <= 0) return hipSuccess;
-  const size_t lds = (size_t)a.lds_q + a.lds_r + a.lds_f;
+// Several wavefronts per pair.  F(s-1, .) and F(s, .) live in two LDS rows
+// that swap roles every score, so a step reads only the previous row and
+// needs no carried neighbour: the active diagonals are cut into 64-diagonal
+// chunks dealt round-robin to the wavefronts, and one barrier per score
+// separates the writes of a score from the reads of the next.  A row entry
+// outside the previous score's diagonals was never written (the active
+// diagonals only widen, and each row is written on every other score), so it
+// still reads "not reached".
+template <int NWV>
+__global__ __launch_bounds__(64 * NWV) void search_group_kernel(SearchArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int task = blockIdx.x;
+  if (task >= a.ntasks) return;
+  const int p = __builtin_amdgcn_readfirstlane(a.tasks[task].pair);
+  aln_result *res = a.res + p;
+  // the same status for every wavefront: the whole workgroup leaves
+  if (__builtin_amdgcn_readfirstlane(res->status) != ALN_R_OK) return;
+  const int M = __builtin_amdgcn_readfirstlane(a.b.q_len[p]);
+  const int N = __builtin_amdgcn_readfirstlane(a.b.r_len[p]);
+  const uint8_t *Q = a.b.q + a.b.q_off[p];
+  const uint8_t *Rs = a.b.r + a.b.r_off[p];
+
+  uint8_t *qs = smem;
+  uint8_t *rs = smem + a.lds_q;
+  int16_t *Fp = reinterpret_cast<int16_t *>(smem + a.lds_q + a.lds_r);
+  int16_t *Fn = reinterpret_cast<int16_t *>(smem + a.lds_q + a.lds_r + a.lds_f);
+  for (int k = tid; k < M + 12; k += 64 * NWV) qs[k] = k < M ? Q[k] : 0xFE;
+  for (int k = tid; k < N + 12; k += 64 * NWV) rs[k] = k < N ? Rs[k] : 0xFF;
+  for (int k = tid; k <= M + N; k += 64 * NWV) {
+    Fp[k] = kNegF16;
+    Fn[k] = kNegF16;
+  }
+  __syncthreads();
+  if (tid == 0) Fp[M] = (int16_t)extend(qs, rs, 0, 0, min(M, N));
+  __syncthreads();
+
+  const int dt = N - M;
+  int s = 0, dmin = 0, dmax = 0;
+  long long cells = 1;
+  bool done = dt == 0 && __builtin_amdgcn_readfirstlane(fload(Fp, M)) >= M;
+  while (!done && s < M + N) {
+    ++s;
+    dmin = max(dmin - 1, -M);
+    dmax = min(dmax + 1, N);
+    cells += dmax - dmin + 1;
+    for (int d0 = dmin + 64 * wave; d0 <= dmax; d0 += 64 * NWV) {
+      const int d = d0 + lane;
+      const bool act = d <= dmax;
+      int old = kNegF, left = kNegF, right = kNegF;
+      if (act) {
+        old = fload(Fp, d + M);
+        if (d > -M) left = fload(Fp, d - 1 + M);
+        if (d < N) right = fload(Fp, d + 1 + M);
+      }
+      const int lim = min(M, N - d);
+      int f = kNegF;
+      if (old + 1 <= lim) f = max(f, old + 1);     // mismatch
+      if (right + 1 <= lim) f = max(f, right + 1); // insertion
+      if (left <= lim) f = max(f, left);           // deletion
+      if (act && f >= 0) f = extend(qs, rs, f, d, lim);
+      if (act) Fn[d + M] = f >= 0 ? (int16_t)f : kNegF16;
+    }
+    __syncthreads();
+    int16_t *t = Fp;
+    Fp = Fn;
+    Fn = t;
+    done = dt >= dmin && dt <= dmax && __builtin_amdgcn_readfirstlane(fload(Fp, dt + M)) >= M;
+  }
+  if (tid == 0) {
+    res->score = -s;
+    res->q_end = M;
+    res->r_end = N;
+    res->cells = cells;
+  }
+}
+
+template <typename K>
+static hipError_t launch_search_k(K kern, int threads, size_t lds, const SearchArgs &a,
+                                  hipStream_t s) {
   if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void *)search_edit_kernel,
+    hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(search_edit_kernel, dim3(a.ntasks), dim3(64), lds, s, a);
+  hipLaunchKernelGGL(kern, dim3(a.ntasks), dim3(threads), lds, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_search(const SearchArgs &a, hipStream_t s) {
+  if (a.ntasks <= 0) return hipSuccess;
+  const size_t one = (size_t)a.lds_q + a.lds_r + a.lds_f;
+  switch (a.waves) {
+  case 1: return launch_search_k(search_edit_kernel, 64, one, a, s);
+  case 4: return launch_search_k(search_group_kernel<4>, 256, one + a.lds_f, a, s);
+  default: return hipErrorInvalidValue;
+  }
 }
 
 } // namespace alnk
