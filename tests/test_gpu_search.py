@@ -118,6 +118,17 @@ def test_search_maximum_rows(ctx):
         assert (int(res["q_end"][p]), int(res["r_end"][p])) == (len(qs[p]), len(rs[p]))
 
 
+def test_search_four_wavefronts_near_their_lds_limit(ctx):
+    """Pairs whose two F rows and sequences still fit one CU's LDS (the batch's
+    longest query plus longest reference about 31 000), so four wavefronts
+    share each pair: scores, end cells and cells equal the oracle's."""
+    rng = np.random.default_rng(923)
+    qs, rs = pairs(rng, [(16000, 15990), (20000, 11000), (300, 310)], 0.01)
+    b = sbatch(qs, rs, "search_group_limit")
+    res, _ = run(ctx, b)
+    assert check(b, res) == []
+
+
 def test_search_per_pair_and_graph_match(ctx):
     rng = np.random.default_rng(917)
     qs, rs = pairs(rng, [(300, 310), (50, 60), (1200, 1190), (0, 9)], 0.1)
