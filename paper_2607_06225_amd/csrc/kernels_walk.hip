@@ -247,6 +247,13 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
       }
       up_by(L);
       j -= L;
+      // the cell that ended the run is read already: take its move now
+      // instead of in a step of its own
+      const int cL = __builtin_amdgcn_readlane(c, L); // -1: not read (L = kLook, edge, block)
+      if (cL >= 0) {
+        if (local && (cL & 3) == 3) break;
+        state = cL & 3; // 1: E, 2: F
+      }
     } else if (state == 1) {
       // D moves: E(i, j-m) opened from H(i, j-m-1) per the code of (i, j-m)
       make_resident(rs, (j - 1 + rl) >> LTB);
@@ -495,6 +502,13 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
       }
       i -= L;
       j -= L;
+      // the cell that ended the run is read already: take its move now
+      // instead of in a step of its own
+      const int hL = __builtin_amdgcn_readlane(valid && !bl ? hs : -1, L); // -1: not read
+      if (hL >= 0) {
+        if (local && hL == 3) break;
+        state = hL; // 1: E, 2: F
+      }
     } else if (state == 1) {
       // D moves from (i, j): E(i, j-m) opened from H(i, j-1-m) per code(i, j-1-m)
       make_resident((i + j) >> 6);
