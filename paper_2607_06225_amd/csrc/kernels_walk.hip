@@ -249,10 +249,20 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
       j -= L;
       // the cell that ended the run is read already: take its move now
       // instead of in a step of its own
+      // (and a gap of one, whose opening bit is in that same code)
       const int cL = __builtin_amdgcn_readlane(c, L); // -1: not read (L = kLook, edge, block)
       if (cL >= 0) {
-        if (local && (cL & 3) == 3) break;
-        state = cL & 3; // 1: E, 2: F
+        const int hs = cL & 3;
+        if (local && hs == 3) break;
+        if (hs == 1 && (cL & 4)) { // E(i, j) opened from H(i, j-1)
+          emit_n(ALN_OP_D, 1);
+          j -= 1;
+        } else if (hs == 2 && (cL & 8)) { // F(i, j) opened from H(i-1, j)
+          emit_n(ALN_OP_I, 1);
+          up_by(1);
+        } else {
+          state = hs; // 1: E, 2: F
+        }
       }
     } else if (state == 1) {
       // D moves: E(i, j-m) opened from H(i, j-m-1) per the code of (i, j-m)
@@ -507,7 +517,22 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
       const int hL = __builtin_amdgcn_readlane(valid && !bl ? hs : -1, L); // -1: not read
       if (hL >= 0) {
         if (local && hL == 3) break;
-        state = hL; // 1: E, 2: F
+        // a gap of one cell: E(i, j) opened from H(i, j-1) is bit 2 of
+        // code(i, j-1), F(i, j) from H(i-1, j) bit 3 of code(i-1, j).  That
+        // cell's antidiagonal may lie two blocks back, which is not resident.
+        bool bl1 = ((i + j - 1) >> 6) < cur - 1;
+        const int c1 = bl1 ? 0 : (hL == 1 ? code_at(i, j - 1, bl1) : code_at(i - 1, j, bl1));
+        if (!bl1 && (c1 & (hL == 1 ? 4 : 8))) {
+          if (hL == 1) {
+            emit_n(ALN_OP_D, 1);
+            j -= 1;
+          } else {
+            emit_n(ALN_OP_I, 1);
+            i -= 1;
+          }
+        } else {
+          state = hL; // 1: E, 2: F
+        }
       }
     } else if (state == 1) {
       // D moves from (i, j): E(i, j-m) opened from H(i, j-1-m) per code(i, j-1-m)
