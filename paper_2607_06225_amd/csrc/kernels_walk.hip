@@ -221,10 +221,12 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
       const int m = lane;
       const int ii = i - m, jj = j - m;
       int c = -1;
+      bool neq = false; // the cell's letters differ (read with its code: one LDS wait)
       if (m < kLook && ii >= 1 && jj >= 1) {
         int s2, l2, r2;
         rowpos(m, s2, l2, r2);
         c = code_at(s2, l2, r2, jj);
+        neq = qwin[ii - 1 - qbase] != rwin[jj - 1 - rbase];
       }
       const bool diag = c >= 0 && (c & 3) == 0;
       const int L = min(ctz64(~__ballot(diag) & look_mask), kLook); // diagonal run length
@@ -235,8 +237,7 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
         continue;
       }
       // '=' / 'X' of the run, first step of the walk first
-      const bool mism = lane < L && qwin[ii - 1 - qbase] != rwin[jj - 1 - rbase];
-      const unsigned long long mm = __ballot(mism) & ((1ull << L) - 1);
+      const unsigned long long mm = __ballot(neq) & ((1ull << L) - 1);
       int pos = 0;
       while (pos < L) {
         const bool x = (mm >> pos) & 1ull;
@@ -487,6 +488,8 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
       const bool valid = lane < kLook && ii >= 1 && jj >= 1;
       bool bl = false;
       const int c = valid ? code_at(ii, jj, bl) : 0;
+      // the cell's letters differ (read with its code: one LDS wait)
+      const bool neq = valid && qwin[ii - 1 - qbase] != rwin[jj - 1 - rbase];
       const int hs = c & 3;
       const bool diag = valid && !bl && hs == 0;
       const unsigned long long badm = __ballot(valid && bl);
@@ -500,8 +503,7 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
       }
       if (badm & ((1ull << L) - 1)) { bad = true; break; }
       // '=' / 'X' of the run, first step of the walk first
-      const bool mism = lane < L && qwin[ii - 1 - qbase] != rwin[jj - 1 - rbase];
-      unsigned long long mm = __ballot(mism) & ((1ull << L) - 1);
+      unsigned long long mm = __ballot(neq) & ((1ull << L) - 1);
       int pos = 0;
       while (pos < L) {
         const bool x = (mm >> pos) & 1ull;
