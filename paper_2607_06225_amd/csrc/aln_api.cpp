@@ -236,11 +236,11 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
   const int64_t per_step = (int64_t)std::abs(hs.gap_open) + std::abs(hs.gap_extend) + 128;
   if (p.prune == ALN_SEARCH) {
     if (p.mode != ALN_GLOBAL || p.want_cigar)
-      return fail(ctx, ALN_E_UNSUPPORTED, "SEARCH is GLOBAL edit distance without CIGAR");
-    if (!hs.match_mismatch || hs.match != 0 || hs.mismatch != -1 || hs.gap_open != 0 ||
-        hs.gap_extend != -1)
+      return fail(ctx, ALN_E_UNSUPPORTED, "SEARCH is GLOBAL, score only, without CIGAR");
+    if (!hs.match_mismatch || hs.match != 0 || hs.mismatch >= 0 || hs.gap_open > 0 ||
+        hs.gap_extend >= 0)
       return fail(ctx, ALN_E_UNSUPPORTED,
-                  "SEARCH needs unit edit costs (match 0, mismatch -1, open 0, extend -1)");
+                  "SEARCH needs penalties: match 0, one mismatch score < 0, open <= 0, extend < 0");
   }
 
   aln_plan *pl = new (std::nothrow) aln_plan;
@@ -281,6 +281,23 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
       return fail(ctx, ALN_E_UNSUPPORTED, "SEARCH needs M <= 32767 and the longest M plus the longest N of the batch <= about 54000");
     }
     L.waves = (int64_t)L.lds_bnd + L.lds_prof + 2 * (int64_t)L.lds_f <= 160 * 1024 ? 4 : 1;
+    const bool unit = hs.mismatch == -1 && hs.gap_open == 0 && hs.gap_extend == -1;
+    if (!unit) { // gap-affine: rings of past score rows, four wavefronts
+      L.pen_x = -hs.mismatch;
+      L.pen_o = -hs.gap_open;
+      L.pen_e = -hs.gap_extend;
+      L.ring_h = std::max(L.pen_x, L.pen_o + L.pen_e) + 1;
+      L.ring_e = L.pen_e + 1;
+      L.waves = 4;
+      const int64_t lds = (int64_t)L.lds_bnd + L.lds_prof +
+                          (int64_t)(L.ring_h + 2 * L.ring_e) * L.lds_f;
+      if (lds > 160 * 1024) {
+        delete pl;
+        return fail(ctx, ALN_E_UNSUPPORTED,
+                    "gap-affine SEARCH keeps %d score rows of %d bytes in LDS: %lld bytes > 160 KB",
+                    L.ring_h + 2 * L.ring_e, L.lds_f, (long long)lds);
+      }
+    }
     for (int32_t i : order) {
       PairTask t;
       memset(&t, 0, sizeof t);
@@ -762,7 +779,8 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
 
   if (!plan->launches.empty() && plan->launches[0].kind == K_SEARCH) {
     const LaunchDesc &L = plan->launches[0];
-    alnk::SearchArgs sa{bp, dtasks, L.count, d_res, L.lds_bnd, L.lds_prof, L.lds_f, L.waves};
+    alnk::SearchArgs sa{bp,      dtasks,  L.count, d_res,    L.lds_bnd, L.lds_prof, L.lds_f,
+                        L.waves, L.pen_x, L.pen_o, L.pen_e, L.ring_h,  L.ring_e};
     if (!per_pair) {
       HIP_TRY(ctx, timed_launch(ctx, "search", st, [&] { return alnk::launch_search(sa, st); }));
     } else {

@@ -155,6 +155,10 @@ struct SearchArgs {
   aln_result *res;
   int32_t lds_q, lds_r, lds_f; // LDS bytes: query codes, reference codes, one F row
   int32_t waves;
+  // gap-affine penalties (pen_x = 0: unit edit costs) and the number of
+  // score rows each wavefront ring keeps: H rows for s - x and s - o - e,
+  // E and F rows for s - e
+  int32_t pen_x, pen_o, pen_e, ring_h, ring_e;
 };
 
 // Launchers (defined in the kernel translation units).

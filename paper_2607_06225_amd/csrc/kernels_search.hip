@@ -208,6 +208,115 @@ __global__ __launch_bounds__(64 * NWV) void search_group_kernel(SearchArgs a) {
   }
 }
 
+// Gap-affine penalties: mismatch x > 0, a gap of length L costs o + L e
+// (o >= 0, e > 0), a match 0.  The search keeps three wavefronts per score,
+// furthest rows as before:
+//   E(s, d) = max(H(s-o-e, d-1), E(s-e, d-1))       a step right, same row
+//   F(s, d) = max(H(s-o-e, d+1), F(s-e, d+1)) + 1   a step down
+//   H(s, d) = max(H(s-x, d) + 1, E(s, d), F(s, d)), then extended along
+//             matches,
+// each candidate kept only if its source was reached and it stays inside the
+// matrix (row <= min(M, N - d)).  A path of penalty s spends at least e per
+// diagonal it moves, so the active diagonals are |d| <= s / e, clipped to the
+// matrix.  The search stops at the first s with H(s, N - M) = M: s is the
+// smallest penalty, minus the Gotoh global score under (0, -x, -o, -e).
+// Rows for past scores live in LDS rings (H: ring_h rows, E and F: ring_e
+// rows each, slot s mod ring size); four wavefronts share a pair as in
+// search_group_kernel, one barrier per score.  A slot's earlier scores had
+// narrower diagonal ranges, all rewritten when it is reused, so an entry
+// outside a row's range still reads "not reached".
+template <int NWV>
+__global__ __launch_bounds__(64 * NWV) void search_affine_kernel(SearchArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int task = blockIdx.x;
+  if (task >= a.ntasks) return;
+  const int p = __builtin_amdgcn_readfirstlane(a.tasks[task].pair);
+  aln_result *res = a.res + p;
+  if (__builtin_amdgcn_readfirstlane(res->status) != ALN_R_OK) return;
+  const int M = __builtin_amdgcn_readfirstlane(a.b.q_len[p]);
+  const int N = __builtin_amdgcn_readfirstlane(a.b.r_len[p]);
+  const uint8_t *Q = a.b.q + a.b.q_off[p];
+  const uint8_t *Rs = a.b.r + a.b.r_off[p];
+  const int X = a.pen_x, O = a.pen_o, E = a.pen_e, RH = a.ring_h, RE = a.ring_e;
+
+  uint8_t *qs = smem;
+  uint8_t *rs = smem + a.lds_q;
+  uint8_t *rows = smem + a.lds_q + a.lds_r;
+  const int stride = a.lds_f; // bytes per row
+  auto hrow = [&](int s) { return reinterpret_cast<int16_t *>(rows + (size_t)(s % RH) * stride); };
+  auto erow = [&](int s) { return reinterpret_cast<int16_t *>(rows + (size_t)(RH + s % RE) * stride); };
+  auto frow = [&](int s) {
+    return reinterpret_cast<int16_t *>(rows + (size_t)(RH + RE + s % RE) * stride);
+  };
+  for (int k = tid; k < M + 12; k += 64 * NWV) qs[k] = k < M ? Q[k] : 0xFE;
+  for (int k = tid; k < N + 12; k += 64 * NWV) rs[k] = k < N ? Rs[k] : 0xFF;
+  {
+    int16_t *all = reinterpret_cast<int16_t *>(rows);
+    const int n16 = (RH + 2 * RE) * (stride / 2);
+    for (int k = tid; k < n16; k += 64 * NWV) all[k] = kNegF16;
+  }
+  __syncthreads();
+  if (tid == 0) hrow(0)[M] = (int16_t)extend(qs, rs, 0, 0, min(M, N));
+  __syncthreads();
+
+  const int dt = N - M;
+  const int smax = 2 * O + E * (M + N); // a gap of the whole query, then one of the reference
+  int s = 0;
+  long long cells = 1;
+  bool done = dt == 0 && __builtin_amdgcn_readfirstlane(fload(hrow(0), M)) >= M;
+  while (!done && s < smax) {
+    ++s;
+    const int w = s / E;
+    const int dmin = max(-M, -w), dmax = min(N, w);
+    cells += dmax - dmin + 1;
+    const bool hx = s >= X, ho = s >= O + E, ge = s >= E;
+    const int16_t *Hx = hrow(hx ? s - X : 0);
+    const int16_t *Ho = hrow(ho ? s - O - E : 0);
+    const int16_t *Ee = erow(ge ? s - E : 0);
+    const int16_t *Fe = frow(ge ? s - E : 0);
+    int16_t *Hn = hrow(s), *En = erow(s), *Fn = frow(s);
+    for (int d0 = dmin + 64 * wave; d0 <= dmax; d0 += 64 * NWV) {
+      const int d = d0 + lane;
+      if (d <= dmax) {
+        const int lim = min(M, N - d);
+        int ev = kNegF, fv = kNegF, hv = kNegF;
+        if (d > -M) { // a step right from diagonal d - 1
+          int src = kNegF;
+          if (ho) src = fload(Ho, d - 1 + M);
+          if (ge) src = max(src, fload(Ee, d - 1 + M));
+          if (src >= 0 && src <= lim) ev = src;
+        }
+        if (d < N) { // a step down from diagonal d + 1
+          int src = kNegF;
+          if (ho) src = fload(Ho, d + 1 + M);
+          if (ge) src = max(src, fload(Fe, d + 1 + M));
+          if (src >= 0 && src + 1 <= lim) fv = src + 1;
+        }
+        if (hx) { // a mismatch on diagonal d
+          const int v = fload(Hx, d + M);
+          if (v >= 0 && v + 1 <= lim) hv = v + 1;
+        }
+        int h = max(hv, max(ev, fv));
+        if (h >= 0) h = extend(qs, rs, h, d, lim);
+        En[d + M] = ev >= 0 ? (int16_t)ev : kNegF16;
+        Fn[d + M] = fv >= 0 ? (int16_t)fv : kNegF16;
+        Hn[d + M] = h >= 0 ? (int16_t)h : kNegF16;
+      }
+    }
+    __syncthreads();
+    done = dt >= dmin && dt <= dmax && __builtin_amdgcn_readfirstlane(fload(hrow(s), dt + M)) >= M;
+  }
+  if (tid == 0) {
+    res->score = -s;
+    res->q_end = M;
+    res->r_end = N;
+    res->cells = cells;
+  }
+}
+
 template <typename K>
 static hipError_t launch_search_k(K kern, int threads, size_t lds, const SearchArgs &a,
                                   hipStream_t s) {
@@ -223,6 +332,11 @@ static hipError_t launch_search_k(K kern, int threads, size_t lds, const SearchA
 hipError_t launch_search(const SearchArgs &a, hipStream_t s) {
   if (a.ntasks <= 0) return hipSuccess;
   const size_t one = (size_t)a.lds_q + a.lds_r + a.lds_f;
+  if (a.pen_x > 0) {
+    if (a.waves != 4 || a.pen_e <= 0 || a.ring_h < 1 || a.ring_e < 1) return hipErrorInvalidValue;
+    const size_t lds = (size_t)a.lds_q + a.lds_r + (size_t)(a.ring_h + 2 * a.ring_e) * a.lds_f;
+    return launch_search_k(search_affine_kernel<4>, 256, lds, a, s);
+  }
   switch (a.waves) {
   case 1: return launch_search_k(search_edit_kernel, 64, one, a, s);
   case 4: return launch_search_k(search_group_kernel<4>, 256, one + a.lds_f, a, s);

@@ -52,7 +52,8 @@ struct LaunchDesc {
   int sides = 1; // X-drop: extension sides per wavefront
   int waves = 1; // full matrix: wavefronts per pair (strip pipeline)
   int max_n = 0; // largest reference length of the launch
-  int32_t lds_f = 0; // search: LDS bytes of the furthest-row array
+  int32_t lds_f = 0;  // search: LDS bytes of one furthest-row array
+  int32_t pen_x = 0, pen_o = 0, pen_e = 0, ring_h = 0, ring_e = 0; // gap-affine SEARCH
 };
 
 constexpr uint64_t kAlign = 256;

@@ -12,19 +12,20 @@ INT32_MIN = -(1 << 31)
 DYN_CIGAR_SPAN = 250
 
 
-SEARCH = 4  # the library's score-major search schedule (unit-cost edit distance)
+SEARCH = 4  # the library's score-major search schedule (edit distance, gap-affine penalties)
 
 
-def search_cells(S, M, N):
-    """(score, diagonal) entries of the search domain for edit distance S:
-    diagonals max(-s, -M) .. min(s, N) for s = 0 .. S."""
-    return sum(min(s, N) + min(s, M) + 1 for s in range(S + 1))
+def search_cells(S, M, N, e=1):
+    """(score, diagonal) entries of the search domain for smallest penalty S
+    and gap-extension penalty e: diagonals max(-s//e, -M) .. min(s//e, N) for
+    s = 0 .. S (edit distance: e = 1)."""
+    return sum(min(s // e, N) + min(s // e, M) + 1 for s in range(S + 1))
 
 
 def oracle_batch(batch, want_cigar=None, nthreads=None):
     """The oracle's results for a batch.  A search batch is checked against
     the definition it computes: the full-matrix global alignment under the
-    same (unit-cost) scoring."""
+    same scoring (unit edit costs or gap-affine penalties)."""
     wc = batch.want_cigar if want_cigar is None else want_cigar
     prune = oracle.FULL if batch.prune == SEARCH else batch.prune
     return oracle.align_batch(batch.matrix, batch.gap_open, batch.gap_extend,
@@ -57,7 +58,7 @@ def compare(batch, gres, gcig, ores, check_cigar=None, idx=None, max_report=8):
         exp_cells = int(ores["cells"][p])
         if batch.prune == SEARCH:
             exp_cells = search_cells(-int(ores["score"][p]), int(batch.q_len[p]),
-                                     int(batch.r_len[p]))
+                                     int(batch.r_len[p]), -int(batch.gap_extend))
         exp = (int(ores["score"][p]), int(ores["q_end"][p]), int(ores["r_end"][p]), exp_cells)
         got = (int(g["score"]), int(g["q_end"]), int(g["r_end"]), int(g["cells"]))
         if exp != got:

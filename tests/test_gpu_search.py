@@ -1,9 +1,10 @@
-"""GPU parity of the score-major search schedule (unit-cost edit distance,
-Sec. 6.3) against the CPU oracle: the score equals minus the edit distance
-from the oracle's full-matrix unit-cost global alignment (itself pinned to
-an independent Levenshtein), the end cell is (M, N), and `cells` equals the
-number of (score, diagonal) entries of the widening domain,
-sum over s = 0..S of (min(s, N) + min(s, M) + 1)."""
+"""GPU parity of the score-major search schedule (Sec. 6.3) against the CPU
+oracle, for unit edit costs and for gap-affine penalties: the score equals
+the oracle's full-matrix global score under the same scoring (for unit costs
+minus the edit distance, the oracle itself pinned to an independent
+Levenshtein), the end cell is (M, N), and `cells` equals the number of
+(score, diagonal) entries of the widening domain, sum over s = 0..S of
+(min(s // e, N) + min(s // e, M) + 1) with e the gap-extension penalty."""
 import numpy as np
 import pytest
 
@@ -140,6 +141,56 @@ def test_search_per_pair_and_graph_match(ctx):
     assert check(b, r1) == []
 
 
+AFFINE = [(4, 6, 2), (2, 3, 1), (3, 0, 2), (1, 2, 1), (5, 1, 3)]  # (mismatch x, open o, extend e)
+
+
+def abatch(qs, rs, pen, name):
+    x, o, e = pen
+    return W.pack_pairs(qs, rs, W.dna_matrix(0, -x), -o, -e, W.GLOBAL, W.SEARCH, name=name)
+
+
+@pytest.mark.parametrize("pen", AFFINE)
+@pytest.mark.parametrize("div", [0.02, 0.15, 1.0])
+def test_search_gap_affine(ctx, pen, div):
+    """Gap-affine penalties (match 0, mismatch x, a gap of length L costing
+    o + L e): the score is minus the smallest penalty, equal to the oracle's
+    full-matrix Gotoh global score under (0, -x, -o, -e); `cells` counts the
+    (score, diagonal) entries with |d| <= s / e."""
+    rng = np.random.default_rng(930 + int(100 * div) + 7 * pen[0] + pen[1])
+    lengths = [(0, 0), (0, 5), (5, 0), (1, 1), (2, 9), (9, 2), (63, 64), (65, 129)] + \
+              [(int(L), int(L) + int(rng.integers(-30, 31))) for L in rng.integers(30, 1500, 30)]
+    lengths = [(max(M, 0), max(N, 0)) for M, N in lengths]
+    qs, rs = pairs(rng, lengths, div)
+    b = abatch(qs, rs, pen, f"search_affine_{pen}_{div}")
+    res, _ = run(ctx, b)
+    assert check(b, res) == []
+
+
+def test_search_gap_affine_indels_and_graph(ctx):
+    """Long indels (a single gap of 40-200 bases) under gap-affine penalties,
+    per-pair and graph launches identical to the batch."""
+    rng = np.random.default_rng(941)
+    qs, rs = [], []
+    for k in range(16):
+        q, r = pairs(rng, [(int(rng.integers(400, 2000)),) * 2], 0.02)
+        q, r = q[0], r[0]
+        g = int(rng.integers(40, 200))
+        at = int(rng.integers(10, len(q) - 10))
+        ins = rng.integers(0, 4, g).astype(np.uint8)
+        if k % 2:
+            q = np.concatenate([q[:at], ins, q[at:]])
+        else:
+            r = np.concatenate([r[:at], ins, r[at:]])
+        qs.append(q)
+        rs.append(r)
+    b = abatch(qs, rs, (4, 6, 2), "search_affine_indel")
+    r1, _ = run(ctx, b)
+    r2, _ = run(ctx, b, per_pair=True)
+    r3, _ = run(ctx, b, graph=True)
+    assert np.array_equal(r1, r2) and np.array_equal(r1, r3)
+    assert check(b, r1) == []
+
+
 def test_search_rejects_what_it_does_not_compute(ctx):
     from paper_2607_06225_amd import aln
     ql = np.array([10], np.int32)
@@ -151,6 +202,10 @@ def test_search_rejects_what_it_does_not_compute(ctx):
             ctx.plan(sid, ql, ql, mode, W.SEARCH, want_cigar=cig)
     with pytest.raises(aln.AlnError):  # rows beyond the int16 row store
         ctx.plan(sid_unit, np.array([32768], np.int32), ql, W.GLOBAL, W.SEARCH)
+    sid_wide = ctx.set_scoring(W.dna_matrix(0, -4), -300, -2)
+    with pytest.raises(aln.AlnError):  # gap-affine score rows beyond LDS
+        ctx.plan(sid_wide, np.array([2000], np.int32), np.array([2000], np.int32), W.GLOBAL,
+                 W.SEARCH)
     with pytest.raises(aln.AlnError):  # longest query + longest reference beyond LDS
         ctx.plan(sid_unit, np.array([30000, 10], np.int32), np.array([10, 30000], np.int32),
                  W.GLOBAL, W.SEARCH)
