@@ -47,15 +47,18 @@ METRIC = "GCUPS (bit-exact) at 1 GPU, batched vs per-pair; % int-VALU roofline; 
 # A search entry (score s, diagonal d) of unit-cost edit distance: two adds
 # (mismatch, insertion), three bound tests, two max; the character compares of
 # its extension depend on the data and are not counted                -> 7
+# A gap-affine search entry: E (max of two sources, two bound tests), F (the
+# same plus an add), H (an add, two bound tests, two max)             -> 12
 OPS_PER_CELL = {("GLOBAL", 0): 8, ("GLOBAL", 1): 8, ("LOCAL", 0): 10, ("LOCAL", 1): 10,
                 ("EXTEND", 0): 9, ("EXTEND", 1): 9, ("EXTEND", 2): 10, ("EXTEND", 3): 12,
                 ("GLOBAL", 4): 7}
+OPS_PER_CELL_KERNEL = {"search_affine": 12}  # kernels whose count differs from their (mode, prune)
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz; packed 16-bit ops do two per lane.
 PEAK_I32_TOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_I16_TOPS = 2 * PEAK_I32_TOPS
 KERNEL_WIDTH = {"sw16": "i16"}
 FILL_KERNELS = ("sw16", "strip_i32", "diag_band", "xdrop", "zdrop", "xdrop_tb", "zdrop_tb",
-                "search")
+                "search", "search_affine")
 
 WORKLOAD_DESC = {
     "sw_protein": ("Smith-Waterman local, protein (20 letters, seeded symmetric matrix), "
@@ -75,6 +78,9 @@ WORKLOAD_DESC = {
                     "cell, walk)"),
     "edit_search": ("unit-cost edit distance by the score-major search schedule (Sec. 6.3), "
                     "4,096 pairs of 2,000 bp at 5% divergence; score (= -edit distance)"),
+    "affine_search": ("gap-affine penalties (mismatch 4, open 6, extend 2) by the score-major "
+                      "search schedule, the edit_search pair shape (4,096 pairs of 2,000 bp at "
+                      "5% divergence, other seed); score (= -smallest penalty)"),
 }
 MODE_NAME = {0: "GLOBAL", 1: "LOCAL", 2: "EXTEND"}
 PRUNE_NAME = {0: "full", 1: "band", 2: "xdrop", 3: "zdrop", 4: "search"}
@@ -210,7 +216,7 @@ def run_workload(name, batch, args, cpu_seconds, pp_cap):
     dom_launch_ms = ktimes[dom][0] / ktimes[dom][1]
     width = KERNEL_WIDTH.get(dom, "i32")
     peak = PEAK_I16_TOPS if width == "i16" else PEAK_I32_TOPS
-    ops = OPS_PER_CELL[(mode_name, batch.prune)]
+    ops = OPS_PER_CELL_KERNEL.get(dom, OPS_PER_CELL[(mode_name, batch.prune)])
     # every evaluated cell passes through the dominant fill kernel once
     cells_per_launch = cells / dom_launches
     achieved = cells_per_launch * ops / (dom_launch_ms * 1e-3) / 1e12
@@ -291,7 +297,8 @@ def run_workload(name, batch, args, cpu_seconds, pp_cap):
         # equivalent rate and alignments per second
         out["equivalent_gcups"] = round(full_cells / (ms_per_step * 1e-3) / 1e9, 3)
         out["alignments_per_s"] = round(batch.n / (ms_per_step * 1e-3), 1)
-        out["mean_edit_distance"] = round(float(-res["score"].mean()), 2)
+        out["mean_edit_distance" if batch.gap_open == 0 and batch.gap_extend == -1
+            else "mean_penalty"] = round(float(-res["score"].mean()), 2)
     plan.close()
     ctx.close()
     log(f"[bench] {name}: " + json.dumps({k: out[k] for k in (
@@ -432,7 +439,8 @@ def main():
     ap.add_argument("--edit-table-check", type=int, default=16,
                     help="pairs per cell checked against the CPU oracle")
     ap.add_argument("--configs",
-                    default="nw_dna_1k,band_long,xdrop_ext,zdrop_ext,xdrop_cigar,edit_search",
+                    default="nw_dna_1k,band_long,xdrop_ext,zdrop_ext,xdrop_cigar,edit_search,"
+                            "affine_search",
                     help="comma list of further workloads to measure, or 'none'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
@@ -533,7 +541,7 @@ def main():
         "serving": serving_out,
     }
     for k in ("int32_reruns", "statuses", "widened_pairs", "cigar_cap_pairs",
-              "equivalent_gcups", "alignments_per_s", "mean_edit_distance"):
+              "equivalent_gcups", "alignments_per_s", "mean_edit_distance", "mean_penalty"):
         if k in head:
             out[k] = head[k]
     print(json.dumps(out), flush=True)

@@ -782,7 +782,8 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
     alnk::SearchArgs sa{bp,      dtasks,  L.count, d_res,    L.lds_bnd, L.lds_prof, L.lds_f,
                         L.waves, L.pen_x, L.pen_o, L.pen_e, L.ring_h,  L.ring_e};
     if (!per_pair) {
-      HIP_TRY(ctx, timed_launch(ctx, "search", st, [&] { return alnk::launch_search(sa, st); }));
+      HIP_TRY(ctx, timed_launch(ctx, L.pen_x > 0 ? "search_affine" : "search", st,
+                                [&] { return alnk::launch_search(sa, st); }));
     } else {
       for (int32_t k = 0; k < L.count; ++k) {
         sa.tasks = dtasks + k;

@@ -412,24 +412,33 @@ def xdrop_cigar(n=200000, seed=404, min_len=150, max_len=5000, xdrop=100, seed_l
     return b
 
 
-def edit_pairs(n, length, div, seed, prune=SEARCH, name=None):
-    """n pairs for unit-cost edit distance: a uniform ACGT reference of
-    `length` bases and a query that is the reference with per-base edits at
-    rate `div` (substitution:insertion:deletion = 2:1:1)."""
+def edit_pairs(n, length, div, seed, prune=SEARCH, name=None, pen=(1, 0, 1)):
+    """n pairs for edit distance: a uniform ACGT reference of `length`
+    bases and a query that is the reference with per-base edits at rate
+    `div` (substitution:insertion:deletion = 2:1:1).  `pen` = (mismatch x,
+    gap open o, gap extend e) penalties, scored as (0, -x, -o, -e); the
+    default is unit edit costs."""
     st = Stream(seed, 6)
     qs, rs = [], []
     for _ in range(n):
         ref = random_codes(st, length, 4)
         qs.append(mutate(ref, div, 2, 1, 1, 4, st))
         rs.append(ref)
-    b = pack_pairs(qs, rs, dna_matrix(0, -1), 0, -1, GLOBAL, prune,
+    x, o, e = pen
+    b = pack_pairs(qs, rs, dna_matrix(0, -x), -o, -e, GLOBAL, prune,
                    name=name or f"edit_{length}_{div}")
-    b.meta = dict(seed=seed, length=length, div=div)
+    b.meta = dict(seed=seed, length=length, div=div, pen=pen)
     return b
 
 
 def edit_search(n=4096, length=2000, div=0.05, seed=606):
     return edit_pairs(n, length, div, seed, name="edit_search")
+
+
+def affine_search(n=4096, length=2000, div=0.05, seed=707, pen=(4, 6, 2)):
+    """The edit_search shape under gap-affine penalties (mismatch 4, open 6,
+    extend 2)."""
+    return edit_pairs(n, length, div, seed, name="affine_search", pen=pen)
 
 
 WORKLOADS = {
@@ -440,6 +449,7 @@ WORKLOADS = {
     "zdrop_ext": zdrop_ext,
     "xdrop_cigar": xdrop_cigar,
     "edit_search": edit_search,
+    "affine_search": affine_search,
 }
 
 
