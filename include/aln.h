@@ -72,15 +72,20 @@ enum { ALN_GLOBAL = 0, ALN_LOCAL = 1, ALN_EXTEND = 2 };
  * cell (i,j) is removed when the best score of the earlier antidiagonals
  * exceeds its H by more than Z + |(j - i) - (j* - i*)|, (i*,j*) the cell of
  * that best score; Z is passed in aln_params.xdrop. */
-/* ALN_SEARCH evaluates the score-major search schedule of Sec. 6.3 for unit
- * edit costs: GLOBAL mode, a scoring with every diagonal entry 0, every
- * off-diagonal entry -1, gap_open 0 and gap_extend -1 (so the score is minus
- * the edit distance), no CIGAR.  For s = 0, 1, ... it keeps, per diagonal
- * d = j - i in [max(-s, -M), min(s, N)], the furthest row reached with s
- * edits, extended along matches, and stops when diagonal N - M reaches row
- * M.  `cells` then counts those (score, diagonal) entries, s = 0 included.
- * Pairs need M <= 32767, and the batch's longest M plus its longest N at
- * most about 54 000 (both sequences and one int16 row sit in LDS); else
+/* ALN_SEARCH evaluates the score-major search schedule of Sec. 6.3: GLOBAL
+ * mode, no CIGAR, a scoring of penalties -- every diagonal entry 0, every
+ * off-diagonal entry -x < 0, gap_open -o <= 0, gap_extend -e < 0 (a gap of
+ * length L costs o + L e) -- so the score is minus the smallest penalty.
+ * For s = 0, 1, ... it keeps, per diagonal d = j - i with |d| <= s / e
+ * (clipped to the matrix), the furthest row reached with penalty s, extended
+ * along matches, and stops when diagonal N - M reaches row M.  `cells` then
+ * counts those (score, diagonal) entries, s = 0 included.
+ * Unit edit costs (x = 1, o = 0, e = 1: the score is minus the edit
+ * distance) keep one row per score: pairs need M <= 32767 and the batch's
+ * longest M plus its longest N at most about 54 000.  Other penalties keep
+ * three wavefronts (H, E, F) of past scores in LDS: max(x, o + e) + 1 + 2 (e
+ * + 1) rows of 2 (maxM + maxN + 1) bytes plus both sequences must fit 160 KB
+ * (about 2 500 + 2 500 bases at x = 4, o = 6, e = 2).  Else
  * ALN_E_UNSUPPORTED. */
 enum { ALN_FULL = 0, ALN_BAND = 1, ALN_XDROP = 2, ALN_ZDROP = 3, ALN_SEARCH = 4 };
 /* score width: AUTO lets the library choose (packed int16 where it applies,
@@ -126,7 +131,7 @@ typedef struct {
 typedef struct {
   int32_t mode;       /* ALN_GLOBAL / ALN_LOCAL / ALN_EXTEND                  */
   int32_t prune;      /* ALN_FULL / ALN_BAND / ALN_XDROP or ALN_ZDROP (EXTEND
-                         only) / ALN_SEARCH (GLOBAL, unit edit costs)        */
+                         only) / ALN_SEARCH (GLOBAL, penalty scoring)        */
   int32_t band_w;     /* BAND half-width w >= 0                               */
   int32_t xdrop;      /* XDROP threshold X >= 0, or ZDROP threshold Z >= 0    */
   int32_t width;      /* ALN_W_*                                              */
