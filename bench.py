@@ -52,13 +52,13 @@ METRIC = "GCUPS (bit-exact) at 1 GPU, batched vs per-pair; % int-VALU roofline; 
 OPS_PER_CELL = {("GLOBAL", 0): 8, ("GLOBAL", 1): 8, ("LOCAL", 0): 10, ("LOCAL", 1): 10,
                 ("EXTEND", 0): 9, ("EXTEND", 1): 9, ("EXTEND", 2): 10, ("EXTEND", 3): 12,
                 ("GLOBAL", 4): 7}
-OPS_PER_CELL_KERNEL = {"search_affine": 12}  # kernels whose count differs from their (mode, prune)
+OPS_PER_CELL_KERNEL = {"search_affine": 12, "search_affine_wide": 12}  # kernels whose count differs from their (mode, prune)
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz; packed 16-bit ops do two per lane.
 PEAK_I32_TOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_I16_TOPS = 2 * PEAK_I32_TOPS
 KERNEL_WIDTH = {"sw16": "i16"}
 FILL_KERNELS = ("sw16", "strip_i32", "diag_band", "xdrop", "zdrop", "xdrop_tb", "zdrop_tb",
-                "search", "search_affine")
+                "search", "search_affine", "search_affine_wide")
 
 WORKLOAD_DESC = {
     "sw_protein": ("Smith-Waterman local, protein (20 letters, seeded symmetric matrix), "

@@ -297,6 +297,20 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
                     "gap-affine SEARCH keeps %d score rows of %d bytes in LDS: %lld bytes > 160 KB",
                     L.ring_h + 2 * L.ring_e, L.lds_f, (long long)lds);
       }
+      // First pass: rows of diagonals -dcap..dcap, dcap as large as lets four
+      // workgroups share a CU; pairs whose range outgrows it run again with
+      // full rows.  Skipped when capped rows would not be shorter.
+      const int64_t nrows = L.ring_h + 2 * L.ring_e;
+      const int64_t per_row = (40 * 1024 - (int64_t)L.lds_bnd - L.lds_prof) / nrows;
+      const int64_t cap = (per_row / 2 - 1) / 2;
+      if (cap >= 16 && 2 * cap + 1 < (int64_t)maxM + maxN + 1) {
+        L.dcap = (int32_t)cap;
+        L.lds_fc = (int32_t)align_up((uint64_t)(2 * cap + 1) * 2, 16);
+        if ((int64_t)L.lds_bnd + L.lds_prof + nrows * L.lds_fc > 40 * 1024) { // rounding
+          L.dcap -= 8;
+          L.lds_fc = (int32_t)align_up((uint64_t)(2 * L.dcap + 1) * 2, 16);
+        }
+      }
     }
     for (int32_t i : order) {
       PairTask t;
@@ -780,15 +794,30 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
   if (!plan->launches.empty() && plan->launches[0].kind == K_SEARCH) {
     const LaunchDesc &L = plan->launches[0];
     alnk::SearchArgs sa{bp,      dtasks,  L.count, d_res,    L.lds_bnd, L.lds_prof, L.lds_f,
-                        L.waves, L.pen_x, L.pen_o, L.pen_e, L.ring_h,  L.ring_e};
-    if (!per_pair) {
-      HIP_TRY(ctx, timed_launch(ctx, L.pen_x > 0 ? "search_affine" : "search", st,
-                                [&] { return alnk::launch_search(sa, st); }));
+                        L.waves, L.pen_x, L.pen_o, L.pen_e, L.ring_h,  L.ring_e,  0, 0};
+    // gap-affine with a diagonal cap: a capped pass, then full rows for the
+    // pairs it flagged
+    std::vector<std::pair<const char *, alnk::SearchArgs>> passes;
+    if (L.pen_x > 0 && L.dcap > 0) {
+      alnk::SearchArgs c = sa;
+      c.lds_f = L.lds_fc;
+      c.dcap = L.dcap;
+      passes.push_back({"search_affine", c});
+      sa.pass = 1;
+      passes.push_back({"search_affine_wide", sa});
     } else {
-      for (int32_t k = 0; k < L.count; ++k) {
-        sa.tasks = dtasks + k;
-        sa.ntasks = 1;
-        HIP_TRY(ctx, alnk::launch_search(sa, st));
+      passes.push_back({L.pen_x > 0 ? "search_affine" : "search", sa});
+    }
+    for (auto &ps : passes) {
+      alnk::SearchArgs &x = ps.second;
+      if (!per_pair) {
+        HIP_TRY(ctx, timed_launch(ctx, ps.first, st, [&] { return alnk::launch_search(x, st); }));
+      } else {
+        for (int32_t k = 0; k < L.count; ++k) {
+          x.tasks = dtasks + k;
+          x.ntasks = 1;
+          HIP_TRY(ctx, alnk::launch_search(x, st));
+        }
       }
     }
     return ALN_OK;

@@ -159,6 +159,11 @@ struct SearchArgs {
   // score rows each wavefront ring keeps: H rows for s - x and s - o - e,
   // E and F rows for s - e
   int32_t pen_x, pen_o, pen_e, ring_h, ring_e;
+  // gap-affine: dcap > 0 stores diagonals -dcap..dcap only (rows of lds_f
+  // bytes); a pair whose range outgrows them is flagged ALN_F_WIDENED and
+  // left to a second launch with dcap = 0 (rows of every diagonal), which
+  // skips unflagged pairs (pass = 1)
+  int32_t dcap, pass;
 };
 
 // Launchers (defined in the kernel translation units).

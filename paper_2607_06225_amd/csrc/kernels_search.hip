@@ -225,6 +225,11 @@ __global__ __launch_bounds__(64 * NWV) void search_group_kernel(SearchArgs a) {
 // search_group_kernel, one barrier per score.  A slot's earlier scores had
 // narrower diagonal ranges, all rewritten when it is reused, so an entry
 // outside a row's range still reads "not reached".
+// Rows first hold diagonals -dcap..dcap only, so that several pairs share a
+// CU; a pair whose range would leave them is flagged and recomputed by a
+// second launch with rows of every diagonal.  A source diagonal outside the
+// stored ones was never active (the range at an earlier score was inside
+// them), so it reads "not reached".
 template <int NWV>
 __global__ __launch_bounds__(64 * NWV) void search_affine_kernel(SearchArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
@@ -240,7 +245,12 @@ __global__ __launch_bounds__(64 * NWV) void search_affine_kernel(SearchArgs a) {
   const int N = __builtin_amdgcn_readfirstlane(a.b.r_len[p]);
   const uint8_t *Q = a.b.q + a.b.q_off[p];
   const uint8_t *Rs = a.b.r + a.b.r_off[p];
+  if (a.pass == 1 && !(__builtin_amdgcn_readfirstlane(res->flags) & ALN_F_WIDENED)) return;
   const int X = a.pen_x, O = a.pen_o, E = a.pen_e, RH = a.ring_h, RE = a.ring_e;
+  const bool capped = a.dcap > 0;
+  const int off = capped ? a.dcap : M;             // row index of diagonal 0
+  const int lo_st = capped ? max(-M, -a.dcap) : -M; // stored diagonals lo_st..hi_st
+  const int hi_st = capped ? min(N, a.dcap) : N;
 
   uint8_t *qs = smem;
   uint8_t *rs = smem + a.lds_q;
@@ -259,18 +269,23 @@ __global__ __launch_bounds__(64 * NWV) void search_affine_kernel(SearchArgs a) {
     for (int k = tid; k < n16; k += 64 * NWV) all[k] = kNegF16;
   }
   __syncthreads();
-  if (tid == 0) hrow(0)[M] = (int16_t)extend(qs, rs, 0, 0, min(M, N));
+  if (tid == 0) hrow(0)[off] = (int16_t)extend(qs, rs, 0, 0, min(M, N));
   __syncthreads();
 
   const int dt = N - M;
   const int smax = 2 * O + E * (M + N); // a gap of the whole query, then one of the reference
   int s = 0;
   long long cells = 1;
-  bool done = dt == 0 && __builtin_amdgcn_readfirstlane(fload(hrow(0), M)) >= M;
+  bool done = dt == 0 && __builtin_amdgcn_readfirstlane(fload(hrow(0), off)) >= M;
+  bool outgrown = false;
   while (!done && s < smax) {
     ++s;
     const int w = s / E;
     const int dmin = max(-M, -w), dmax = min(N, w);
+    if (dmin < lo_st || dmax > hi_st) { // only with capped rows (uniform)
+      outgrown = true;
+      break;
+    }
     cells += dmax - dmin + 1;
     const bool hx = s >= X, ho = s >= O + E, ge = s >= E;
     const int16_t *Hx = hrow(hx ? s - X : 0);
@@ -283,37 +298,41 @@ __global__ __launch_bounds__(64 * NWV) void search_affine_kernel(SearchArgs a) {
       if (d <= dmax) {
         const int lim = min(M, N - d);
         int ev = kNegF, fv = kNegF, hv = kNegF;
-        if (d > -M) { // a step right from diagonal d - 1
+        if (d > lo_st) { // a step right from diagonal d - 1
           int src = kNegF;
-          if (ho) src = fload(Ho, d - 1 + M);
-          if (ge) src = max(src, fload(Ee, d - 1 + M));
+          if (ho) src = fload(Ho, d - 1 + off);
+          if (ge) src = max(src, fload(Ee, d - 1 + off));
           if (src >= 0 && src <= lim) ev = src;
         }
-        if (d < N) { // a step down from diagonal d + 1
+        if (d < hi_st) { // a step down from diagonal d + 1
           int src = kNegF;
-          if (ho) src = fload(Ho, d + 1 + M);
-          if (ge) src = max(src, fload(Fe, d + 1 + M));
+          if (ho) src = fload(Ho, d + 1 + off);
+          if (ge) src = max(src, fload(Fe, d + 1 + off));
           if (src >= 0 && src + 1 <= lim) fv = src + 1;
         }
         if (hx) { // a mismatch on diagonal d
-          const int v = fload(Hx, d + M);
+          const int v = fload(Hx, d + off);
           if (v >= 0 && v + 1 <= lim) hv = v + 1;
         }
         int h = max(hv, max(ev, fv));
         if (h >= 0) h = extend(qs, rs, h, d, lim);
-        En[d + M] = ev >= 0 ? (int16_t)ev : kNegF16;
-        Fn[d + M] = fv >= 0 ? (int16_t)fv : kNegF16;
-        Hn[d + M] = h >= 0 ? (int16_t)h : kNegF16;
+        En[d + off] = ev >= 0 ? (int16_t)ev : kNegF16;
+        Fn[d + off] = fv >= 0 ? (int16_t)fv : kNegF16;
+        Hn[d + off] = h >= 0 ? (int16_t)h : kNegF16;
       }
     }
     __syncthreads();
-    done = dt >= dmin && dt <= dmax && __builtin_amdgcn_readfirstlane(fload(hrow(s), dt + M)) >= M;
+    done = dt >= dmin && dt <= dmax && __builtin_amdgcn_readfirstlane(fload(hrow(s), dt + off)) >= M;
   }
   if (tid == 0) {
-    res->score = -s;
-    res->q_end = M;
-    res->r_end = N;
-    res->cells = cells;
+    if (outgrown) {
+      res->flags |= ALN_F_WIDENED;
+    } else {
+      res->score = -s;
+      res->q_end = M;
+      res->r_end = N;
+      res->cells = cells;
+    }
   }
 }
 

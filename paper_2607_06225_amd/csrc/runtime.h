@@ -54,6 +54,7 @@ struct LaunchDesc {
   int max_n = 0; // largest reference length of the launch
   int32_t lds_f = 0;  // search: LDS bytes of one furthest-row array
   int32_t pen_x = 0, pen_o = 0, pen_e = 0, ring_h = 0, ring_e = 0; // gap-affine SEARCH
+  int32_t dcap = 0, lds_fc = 0; // gap-affine: first-pass diagonal cap and its row bytes
 };
 
 constexpr uint64_t kAlign = 256;

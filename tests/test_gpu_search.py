@@ -164,6 +164,12 @@ def test_search_gap_affine(ctx, pen, div):
     b = abatch(qs, rs, pen, f"search_affine_{pen}_{div}")
     res, _ = run(ctx, b)
     assert check(b, res) == []
+    if pen == (4, 6, 2):
+        # a first pass keeps a capped diagonal range (a few hundred diagonals
+        # here); unrelated pairs outgrow it and are recomputed with full rows
+        from paper_2607_06225_amd import aln
+        widened = (res["flags"] & aln.F_WIDENED) != 0
+        assert widened.any() if div == 1.0 else not widened.any()
 
 
 def test_search_gap_affine_indels_and_graph(ctx):
