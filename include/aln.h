@@ -86,7 +86,8 @@ enum { ALN_GLOBAL = 0, ALN_LOCAL = 1, ALN_EXTEND = 2 };
  * three wavefronts (H, E, F) of past scores in LDS: max(x, o + e) + 1 + 2 (e
  * + 1) rows of 2 (maxM + maxN + 1) bytes plus both sequences must fit 160 KB
  * (about 2 500 + 2 500 bases at x = 4, o = 6, e = 2).  Else
- * ALN_E_UNSUPPORTED. */
+ * ALN_E_UNSUPPORTED.  A first pass keeps fewer diagonals per row; a pair
+ * whose range outgrows them is recomputed and flagged ALN_F_WIDENED. */
 enum { ALN_FULL = 0, ALN_BAND = 1, ALN_XDROP = 2, ALN_ZDROP = 3, ALN_SEARCH = 4 };
 /* score width: AUTO lets the library choose (packed int16 where it applies,
  * with an automatic int32 re-run of any pair that could have overflowed) */
@@ -109,8 +110,9 @@ enum {
 enum {
   ALN_F_I16_RERUN = 1,  /* the int16 pass could have saturated; the pair was
                            recomputed in int32 (the result is the int32 one) */
-  ALN_F_WIDENED = 2     /* X-drop / Z-drop region outgrew the first window;
-                           the pair was recomputed with a wider one          */
+  ALN_F_WIDENED = 2     /* X-drop / Z-drop region, or a gap-affine SEARCH's
+                           diagonal range, outgrew the first window; the
+                           pair was recomputed with a wider one              */
 };
 
 enum { ALN_OP_I = 1, ALN_OP_D = 2, ALN_OP_EQ = 7, ALN_OP_X = 8 };
