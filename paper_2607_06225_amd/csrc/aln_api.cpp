@@ -258,10 +258,11 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     maxM = std::max(maxM, pl->qlen[i]);
     maxN = std::max(maxN, pl->rlen[i]);
   }
-  // score-major search (edit distance): one workgroup per pair, longest
-  // first; both sequences and the furthest-row array in LDS.  Four
+  // score-major search: one workgroup per pair, longest first, both
+  // sequences and the furthest-row arrays in LDS.  Unit edit costs: four
   // wavefronts share a pair when two rows fit in LDS, else one wavefront
-  // updates a single row in place.
+  // updates a single row in place.  Gap-affine penalties: four wavefronts
+  // over rings of past H, E and F rows.
   if (p.prune == ALN_SEARCH) {
     std::vector<int32_t> order(n);
     for (int32_t i = 0; i < n; ++i) order[i] = i;

@@ -1,5 +1,5 @@
-// kernels_search.hip -- unit-cost edit distance by the score-major search
-// schedule (Sec. 6.3) on gfx950.
+// kernels_search.hip -- the score-major search schedule (Sec. 6.3) on
+// gfx950: unit-cost edit distance, and gap-affine penalties (further below).
 //
 // The search transformation re-indexes the edit-distance recurrence by score:
 // F(s, d) is the furthest row i reached on diagonal d = j - i with exactly s

@@ -36,7 +36,9 @@ Workloads (codes: DNA A,C,G,T = 0..3; protein = 0..19):
                  unit edit costs, global; the score-major search schedule.
                  edit_pairs() builds the same kind of batch for any length and
                  divergence (the sizes and divergences of the paper's
-                 edit-distance table).
+                 edit-distance table) and penalties.
+  affine_search  the edit_search shape (seed 707) under gap-affine penalties:
+                 mismatch 4, gap open 6, extend 2.
 """
 from dataclasses import dataclass, field
 
