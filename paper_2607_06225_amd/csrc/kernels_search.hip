@@ -256,11 +256,11 @@ __global__ __launch_bounds__(64 * NWV) void search_affine_kernel(SearchArgs a) {
   uint8_t *rs = smem + a.lds_q;
   uint8_t *rows = smem + a.lds_q + a.lds_r;
   const int stride = a.lds_f; // bytes per row
-  auto hrow = [&](int s) { return reinterpret_cast<int16_t *>(rows + (size_t)(s % RH) * stride); };
-  auto erow = [&](int s) { return reinterpret_cast<int16_t *>(rows + (size_t)(RH + s % RE) * stride); };
-  auto frow = [&](int s) {
-    return reinterpret_cast<int16_t *>(rows + (size_t)(RH + RE + s % RE) * stride);
-  };
+  // ring slots by index (the slot of score s is s mod ring size, kept
+  // incrementally below: no division in the score loop)
+  auto hrow = [&](int k) { return reinterpret_cast<int16_t *>(rows + (size_t)k * stride); };
+  auto erow = [&](int k) { return reinterpret_cast<int16_t *>(rows + (size_t)(RH + k) * stride); };
+  auto frow = [&](int k) { return reinterpret_cast<int16_t *>(rows + (size_t)(RH + RE + k) * stride); };
   for (int k = tid; k < M + 12; k += 64 * NWV) qs[k] = k < M ? Q[k] : 0xFE;
   for (int k = tid; k < N + 12; k += 64 * NWV) rs[k] = k < N ? Rs[k] : 0xFF;
   {
@@ -275,12 +275,19 @@ __global__ __launch_bounds__(64 * NWV) void search_affine_kernel(SearchArgs a) {
   const int dt = N - M;
   const int smax = 2 * O + E * (M + N); // a gap of the whole query, then one of the reference
   int s = 0;
+  int sh = 0, se = 0;  // s mod RH, s mod RE
+  int w = 0, wr = 0;   // s / E, s mod E
   long long cells = 1;
   bool done = dt == 0 && __builtin_amdgcn_readfirstlane(fload(hrow(0), off)) >= M;
   bool outgrown = false;
   while (!done && s < smax) {
     ++s;
-    const int w = s / E;
+    sh = sh + 1 == RH ? 0 : sh + 1;
+    se = se + 1 == RE ? 0 : se + 1;
+    if (++wr == E) {
+      wr = 0;
+      ++w;
+    }
     const int dmin = max(-M, -w), dmax = min(N, w);
     if (dmin < lo_st || dmax > hi_st) { // only with capped rows (uniform)
       outgrown = true;
@@ -288,11 +295,15 @@ __global__ __launch_bounds__(64 * NWV) void search_affine_kernel(SearchArgs a) {
     }
     cells += dmax - dmin + 1;
     const bool hx = s >= X, ho = s >= O + E, ge = s >= E;
-    const int16_t *Hx = hrow(hx ? s - X : 0);
-    const int16_t *Ho = hrow(ho ? s - O - E : 0);
-    const int16_t *Ee = erow(ge ? s - E : 0);
-    const int16_t *Fe = frow(ge ? s - E : 0);
-    int16_t *Hn = hrow(s), *En = erow(s), *Fn = frow(s);
+    // slots of s - X and s - O - E (both < RH back) and s - E (< RE back)
+    const int shx = sh - X < 0 ? sh - X + RH : sh - X;
+    const int sho = sh - O - E < 0 ? sh - O - E + RH : sh - O - E;
+    const int see = se - E < 0 ? se - E + RE : se - E;
+    const int16_t *Hx = hrow(shx);
+    const int16_t *Ho = hrow(sho);
+    const int16_t *Ee = erow(see);
+    const int16_t *Fe = frow(see);
+    int16_t *Hn = hrow(sh), *En = erow(se), *Fn = frow(se);
     for (int d0 = dmin + 64 * wave; d0 <= dmax; d0 += 64 * NWV) {
       const int d = d0 + lane;
       if (d <= dmax) {
@@ -322,7 +333,7 @@ __global__ __launch_bounds__(64 * NWV) void search_affine_kernel(SearchArgs a) {
       }
     }
     __syncthreads();
-    done = dt >= dmin && dt <= dmax && __builtin_amdgcn_readfirstlane(fload(hrow(s), dt + off)) >= M;
+    done = dt >= dmin && dt <= dmax && __builtin_amdgcn_readfirstlane(fload(hrow(sh), dt + off)) >= M;
   }
   if (tid == 0) {
     if (outgrown) {
