@@ -274,8 +274,8 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     L.mode = ALN_GLOBAL;
     L.first = 0;
     L.count = n;
-    L.lds_bnd = (int32_t)align_up((uint64_t)maxM + 12, 16);  // query codes + padding
-    L.lds_prof = (int32_t)align_up((uint64_t)maxN + 12, 16); // reference codes + padding
+    L.lds_bnd = (int32_t)align_up((uint64_t)maxM + 20, 16);  // query codes + padding
+    L.lds_prof = (int32_t)align_up((uint64_t)maxN + 20, 16); // reference codes + padding
     L.lds_f = (int32_t)align_up(((uint64_t)maxM + maxN + 1) * 2, 16); // int16 rows
     if (maxM > 32767 || (int64_t)L.lds_bnd + L.lds_prof + L.lds_f > 160 * 1024) {
       delete pl;

@@ -22,8 +22,8 @@
 //   neighbours' old values come by DPP, the chunk's left neighbour from a
 //   register saved before the previous chunk overwrote it, and its right
 //   neighbour from LDS (not yet updated).
-// Extension compares eight characters per step: three aligned dword reads
-// per sequence and two byte aligns, then the first differing byte.
+// Extension compares sixteen characters per step: five aligned dword reads
+// per sequence and four byte aligns, then the first differing byte.
 #include "internal.h"
 
 namespace alnk {
@@ -43,23 +43,27 @@ __device__ __forceinline__ int sdpp_shl1(int old, int v) { // lane l <- lane l+1
   return __builtin_amdgcn_update_dpp(old, v, 0x130, 0xf, 0xf, false);
 }
 
-// eight codes starting at byte `off` of an LDS sequence buffer (readable up
-// to off + 11)
-__device__ __forceinline__ uint64_t load8(const uint8_t *buf, int off) {
+// sixteen codes starting at byte `off` of an LDS sequence buffer (readable
+// up to off + 19): five aligned dword reads and four byte aligns
+__device__ __forceinline__ void load16(const uint8_t *buf, int off, uint64_t &lo, uint64_t &hi) {
   const uint32_t *w = reinterpret_cast<const uint32_t *>(buf + (off & ~3));
   const uint32_t sh = (uint32_t)(off & 3);
-  const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
-  return ((uint64_t)__builtin_amdgcn_alignbyte(w2, w1, sh) << 32) |
-         __builtin_amdgcn_alignbyte(w1, w0, sh);
+  const uint32_t w0 = w[0], w1 = w[1], w2 = w[2], w3 = w[3], w4 = w[4];
+  lo = ((uint64_t)__builtin_amdgcn_alignbyte(w2, w1, sh) << 32) | __builtin_amdgcn_alignbyte(w1, w0, sh);
+  hi = ((uint64_t)__builtin_amdgcn_alignbyte(w4, w3, sh) << 32) | __builtin_amdgcn_alignbyte(w3, w2, sh);
 }
 
 // advance row f of diagonal d while the next characters match, up to lim
+// (sixteen characters per step: one LDS round trip and one loop test)
 __device__ __forceinline__ int extend(const uint8_t *qs, const uint8_t *rs, int f, int d, int lim) {
   while (f < lim) {
-    const uint64_t x = load8(qs, f) ^ load8(rs, f + d);
-    const int n = x ? (__builtin_ctzll(x) >> 3) : 8;
+    uint64_t qa, qb, ra, rb;
+    load16(qs, f, qa, qb);
+    load16(rs, f + d, ra, rb);
+    const uint64_t x0 = qa ^ ra, x1 = qb ^ rb;
+    const int n = x0 ? (__builtin_ctzll(x0) >> 3) : (x1 ? 8 + (__builtin_ctzll(x1) >> 3) : 16);
     f = min(f + n, lim);
-    if (n < 8) break;
+    if (n < 16) break;
   }
   return f;
 }
@@ -77,13 +81,13 @@ __global__ __launch_bounds__(64) void search_edit_kernel(SearchArgs a) {
   const uint8_t *Q = a.b.q + a.b.q_off[p];
   const uint8_t *Rs = a.b.r + a.b.r_off[p];
 
-  // LDS: query codes (M + 12 bytes, padding 0xFE), reference codes (N + 12,
+  // LDS: query codes (M + 20 bytes, padding 0xFE), reference codes (N + 20,
   // padding 0xFF; the paddings never match each other or a code), F[d + M]
   uint8_t *qs = smem;
   uint8_t *rs = smem + a.lds_q;
   int16_t *F = reinterpret_cast<int16_t *>(smem + a.lds_q + a.lds_r);
-  for (int k = lane; k < M + 12; k += 64) qs[k] = k < M ? Q[k] : 0xFE;
-  for (int k = lane; k < N + 12; k += 64) rs[k] = k < N ? Rs[k] : 0xFF;
+  for (int k = lane; k < M + 20; k += 64) qs[k] = k < M ? Q[k] : 0xFE;
+  for (int k = lane; k < N + 20; k += 64) rs[k] = k < N ? Rs[k] : 0xFF;
   for (int k = lane; k <= M + N; k += 64) F[k] = kNegF16;
   __syncthreads();
 
@@ -158,8 +162,8 @@ __global__ __launch_bounds__(64 * NWV) void search_group_kernel(SearchArgs a) {
   uint8_t *rs = smem + a.lds_q;
   int16_t *Fp = reinterpret_cast<int16_t *>(smem + a.lds_q + a.lds_r);
   int16_t *Fn = reinterpret_cast<int16_t *>(smem + a.lds_q + a.lds_r + a.lds_f);
-  for (int k = tid; k < M + 12; k += 64 * NWV) qs[k] = k < M ? Q[k] : 0xFE;
-  for (int k = tid; k < N + 12; k += 64 * NWV) rs[k] = k < N ? Rs[k] : 0xFF;
+  for (int k = tid; k < M + 20; k += 64 * NWV) qs[k] = k < M ? Q[k] : 0xFE;
+  for (int k = tid; k < N + 20; k += 64 * NWV) rs[k] = k < N ? Rs[k] : 0xFF;
   for (int k = tid; k <= M + N; k += 64 * NWV) {
     Fp[k] = kNegF16;
     Fn[k] = kNegF16;
@@ -261,8 +265,8 @@ __global__ __launch_bounds__(64 * NWV) void search_affine_kernel(SearchArgs a) {
   auto hrow = [&](int k) { return reinterpret_cast<int16_t *>(rows + (size_t)k * stride); };
   auto erow = [&](int k) { return reinterpret_cast<int16_t *>(rows + (size_t)(RH + k) * stride); };
   auto frow = [&](int k) { return reinterpret_cast<int16_t *>(rows + (size_t)(RH + RE + k) * stride); };
-  for (int k = tid; k < M + 12; k += 64 * NWV) qs[k] = k < M ? Q[k] : 0xFE;
-  for (int k = tid; k < N + 12; k += 64 * NWV) rs[k] = k < N ? Rs[k] : 0xFF;
+  for (int k = tid; k < M + 20; k += 64 * NWV) qs[k] = k < M ? Q[k] : 0xFE;
+  for (int k = tid; k < N + 20; k += 64 * NWV) rs[k] = k < N ? Rs[k] : 0xFF;
   {
     int16_t *all = reinterpret_cast<int16_t *>(rows);
     const int n16 = (RH + 2 * RE) * (stride / 2);
