@@ -215,12 +215,15 @@ __device__ void strip_task(const StripArgs &a, int task, int wave, int lane, uin
     uint8_t *tbp = TB ? (a.tb + tk.tb_off + (size_t)s * T * 64 * (R / 2)) : nullptr;
 
     for (int t = 0; t < T; ++t) {
-      const int tl = t & 63;
+      // feeds are read CH columns at a time; the pipeline uses shorter
+      // chunks so that a strip can start sooner behind the one above
+      constexpr int CH = G > 1 ? 16 : 64;
+      const int tl = t & (CH - 1);
       if (tl == 0) {
         if (G > 1) chr_cur = settle(rseq[t + lane], zero); // t + lane < N + 127
         else chr_cur = settle((t + lane < N) ? Rs[t + lane] : 0, zero);
         if (s > 0) {
-          const int upto = min(t + 64, N); // columns t+1 .. t+64
+          const int upto = min(t + CH, N); // columns t+1 .. t+CH
           if (G > 1) ok = ok && lds_wait_geq(&prog[(s - 1) % G], stamp(s - 1, upto));
           const int2 v = bnd_in[min(t + lane + 1, N)];
           bh_cur = settle(v.x, zero);
@@ -300,7 +303,8 @@ __device__ void strip_task(const StripArgs &a, int task, int wave, int lane, uin
         }
       }
       // columns <= t - 63 of this strip's bottom row are written
-      if (G > 1 && has_reader && tl == 63) lds_publish(&prog[s % G], stamp(s, min(max(t - 63, 0), N)));
+      if (G > 1 && has_reader && tl == CH - 1)
+        lds_publish(&prog[s % G], stamp(s, min(max(t - 63, 0), N)));
     }
     if (G > 1 && has_reader) lds_publish(&prog[s % G], stamp(s, N));
 
