@@ -467,8 +467,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(json.dumps({"error": "this build measures one GPU only; pairs shard across GPUs "
-                                   "with no exchange (see DESIGN.md), run with --gpus 1"}))
+        print(json.dumps({"error": "one GPU only: pairs are independent, so a multi-GPU run "
+                                   "would shard them by cells with no exchange between GPUs; "
+                                   "run with --gpus 1"}))
         return 2
 
     import torch
