@@ -46,6 +46,38 @@ struct WaveCigar {
       overflow = true;
     }
   }
+  // The '=' / 'X' ops of a diagonal run of L <= kLook cells, first step of
+  // the walk first (bit p of mm: cell p mismatches), all at once: the same
+  // words and final state as emitting its sub-runs one by one.  Lane p that
+  // starts a sub-run other than the last writes that sub-run's word; the
+  // last sub-run stays pending (the next ops may extend it).
+  __device__ void emit_diag_run(uint32_t mm, int L, int lane) {
+    const uint32_t lmask = L >= 32 ? 0xffffffffu : ((1u << L) - 1u);
+    const uint32_t starts = ((mm ^ (mm << 1)) | 1u) & lmask;
+    const int K = __builtin_popcount(starts);
+    const int last = 31 - __builtin_clz(starts);
+    const int op0 = (mm & 1u) ? ALN_OP_X : ALN_OP_EQ;
+    const bool merge = cur == op0;
+    if (!merge) flush(lane); // the pending word ends here (nothing if none)
+    if (lane < L && lane != last && ((starts >> lane) & 1u)) {
+      const int r = __builtin_popcount(starts & ((1u << lane) - 1u)); // sub-runs before
+      const uint64_t after = (uint64_t)starts >> (lane + 1);          // non-zero: not last
+      int len = __builtin_ctzll(after) + 1;
+      if (r == 0 && merge) len += run;
+      const int idx = w - 1 - r;
+      const int op = ((mm >> lane) & 1u) ? ALN_OP_X : ALN_OP_EQ;
+      if (idx >= 0) out[idx] = ((uint32_t)len << 4) | (uint32_t)op;
+    }
+    if (w - (K - 1) < 0) {
+      overflow = true;
+      w = 0;
+    } else {
+      w -= K - 1;
+    }
+    const int len_last = L - last + ((K == 1 && merge) ? run : 0);
+    cur = ((mm >> last) & 1u) ? ALN_OP_X : ALN_OP_EQ;
+    run = len_last;
+  }
 };
 
 } // namespace
@@ -237,15 +269,7 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
         continue;
       }
       // '=' / 'X' of the run, first step of the walk first
-      const unsigned long long mm = __ballot(neq) & ((1ull << L) - 1);
-      int pos = 0;
-      while (pos < L) {
-        const bool x = (mm >> pos) & 1ull;
-        const unsigned long long rest = (x ? ~mm : mm) >> pos;
-        const int run = min(ctz64(rest), L - pos);
-        emit_n(x ? ALN_OP_X : ALN_OP_EQ, run);
-        pos += run;
-      }
+      cw.emit_diag_run((uint32_t)(__ballot(neq) & ((1ull << L) - 1)), L, lane);
       up_by(L);
       j -= L;
       // the cell that ended the run is read already: take its move now
@@ -503,15 +527,7 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
       }
       if (badm & ((1ull << L) - 1)) { bad = true; break; }
       // '=' / 'X' of the run, first step of the walk first
-      unsigned long long mm = __ballot(neq) & ((1ull << L) - 1);
-      int pos = 0;
-      while (pos < L) {
-        const bool x = (mm >> pos) & 1ull;
-        const unsigned long long rest = (x ? ~mm : mm) >> pos;
-        const int run = min(ctz64(rest), L - pos);
-        emit_n(x ? ALN_OP_X : ALN_OP_EQ, run);
-        pos += run;
-      }
+      cw.emit_diag_run((uint32_t)(__ballot(neq) & ((1ull << L) - 1)), L, lane);
       i -= L;
       j -= L;
       // the cell that ended the run is read already: take its move now
