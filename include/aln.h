@@ -238,6 +238,26 @@ aln_status aln_execute(aln_ctx *ctx, aln_plan *plan, const aln_batch *batch,
                        void *d_ws, uint64_t ws_bytes, aln_result *d_res,
                        uint32_t *d_cigar, uint64_t cigar_words, void *stream);
 
+/* Size of the fixed workspace aln_execute_noalloc uses on each GPU. */
+#define ALN_NOALLOC_WORKSPACE_BYTES (64ull << 20)
+
+/* aln_execute without a workspace argument, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  The workspace is a fixed device array of
+ * ALN_NOALLOC_WORKSPACE_BYTES per GPU, held from the first aln_create on that
+ * GPU until the process ends.  The call allocates nothing (device, pinned or
+ * host memory) and creates no HIP object; the plan must come from an earlier
+ * aln_plan_create.  Errors: ALN_E_CAPACITY when the plan's
+ * fp.workspace_bytes exceed the array (or d_cigar is too small), ALN_E_INVAL
+ * while kernel timing (aln_set_profiling) is on, else as aln_execute.
+ * Results equal aln_execute's.  Every call on one GPU shares that GPU's array
+ * and leaves its contents behind (the kernels clear what they need cleared):
+ * calls that overlap on one GPU -- other streams, other contexts, other
+ * threads -- race and give undefined results, so serialise them. */
+aln_status aln_execute_noalloc(aln_ctx *ctx, aln_plan *plan, const aln_batch *batch,
+                               aln_result *d_res, uint32_t *d_cigar, uint64_t cigar_words,
+                               void *stream);
+
 /* The same kernels, one launch per pair (the per-pair baseline the batched
  * form is compared with).  Same arguments and results as aln_execute. */
 aln_status aln_execute_per_pair(aln_ctx *ctx, aln_plan *plan,

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libaln_hip.so")
 GLOBAL, LOCAL, EXTEND = 0, 1, 2
 FULL, BAND, XDROP, ZDROP, SEARCH = 0, 1, 2, 3, 4
 W_AUTO, W_I16, W_I32 = 0, 1, 2
+NOALLOC_WORKSPACE_BYTES = 64 << 20  # ALN_NOALLOC_WORKSPACE_BYTES
 R_OK, R_UNREACHABLE, R_CIGAR_CAP, R_BAD_SYMBOL, R_TOO_WIDE, R_INTERNAL = 0, 1, 2, 3, 4, 5
 E_INVAL, E_NOMEM, E_DEVICE, E_CAPACITY, E_UNSUPPORTED = -1, -2, -3, -4, -5
 F_I16_RERUN, F_WIDENED = 1, 2
@@ -99,7 +100,7 @@ _lib = None
 EXPORTS = [
     "aln_abi_version", "aln_create", "aln_destroy", "aln_last_error",
     "aln_set_scoring", "aln_plan_create", "aln_plan_destroy", "aln_execute",
-    "aln_execute_per_pair", "aln_graph_capture", "aln_graph_launch",
+    "aln_execute_noalloc", "aln_execute_per_pair", "aln_graph_capture", "aln_graph_launch",
     "aln_set_profiling", "aln_kernel_times", "aln_autotune", "aln_get_tuning", "aln_set_tuning",
     "aln_server_create", "aln_server_destroy", "aln_server_submit", "aln_server_poll",
     "aln_server_drain", "aln_server_clock", "aln_server_get_stats", "aln_server_last_error",
@@ -124,6 +125,7 @@ def load_library(path=LIB_PATH):
         "aln_plan_create": ([P, I32, P, I32, P, P, P, P], I32),
         "aln_plan_destroy": ([P], None),
         "aln_execute": ([P, P, P, P, U64, P, P, U64, P], I32),
+        "aln_execute_noalloc": ([P, P, P, P, P, U64, P], I32),
         "aln_execute_per_pair": ([P, P, P, P, U64, P, P, U64, P], I32),
         "aln_graph_capture": ([P, P, P, P, U64, P, P, U64, P], I32),
         "aln_graph_launch": ([P, P, P], I32),
@@ -256,6 +258,12 @@ class Context:
 
     def execute(self, plan, dbatch, ws, res, cigar=None, stream=None):
         self._exec(self.lib.aln_execute, plan, dbatch, ws, res, cigar, stream)
+
+    def execute_noalloc(self, plan, dbatch, res, cigar=None, stream=None):
+        """aln_execute on the library's fixed per-GPU workspace (no allocation)."""
+        self._check(self.lib.aln_execute_noalloc(
+            self.handle, plan.handle, ctypes.byref(dbatch.c), _ptr(res), _ptr(cigar),
+            int(cigar.numel()) if cigar is not None else 0, _stream_handle(stream)))
 
     def execute_per_pair(self, plan, dbatch, ws, res, cigar=None, stream=None):
         self._exec(self.lib.aln_execute_per_pair, plan, dbatch, ws, res, cigar, stream)

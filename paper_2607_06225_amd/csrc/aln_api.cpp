@@ -112,6 +112,10 @@ aln_status aln_create(aln_ctx **ctx, int32_t device) {
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) ==
           hipSuccess && v > 0)
     c->lds_per_cu = v;
+  if (alnrt::scratch_init(c) != ALN_OK) {
+    delete c;
+    return ALN_E_DEVICE;
+  }
   *ctx = c;
   return ALN_OK;
 }
@@ -755,7 +759,9 @@ void aln_plan_destroy(aln_plan *plan) {
   delete plan;
 }
 
-static aln_status check_exec(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, void *d_ws,
+} // extern "C"
+
+aln_status alnrt::exec_check(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, void *d_ws,
                              uint64_t ws_bytes, aln_result *d_res, uint32_t *d_cigar,
                              uint64_t cigar_words) {
   if (!ctx || !plan || !b || plan->ctx != ctx) return fail(ctx, ALN_E_INVAL, "bad context or plan");
@@ -771,6 +777,8 @@ static aln_status check_exec(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, v
                 (unsigned long long)cigar_words, (unsigned long long)plan->cigar_words);
   return ALN_OK;
 }
+
+extern "C" {
 
 static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, void *d_ws,
                            aln_result *d_res, uint32_t *d_cigar, hipStream_t st, bool per_pair) {
@@ -798,21 +806,22 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
                         L.waves, L.pen_x, L.pen_o, L.pen_e, L.ring_h,  L.ring_e,  0, 0};
     // gap-affine with a diagonal cap: a capped pass, then full rows for the
     // pairs it flagged
-    std::vector<std::pair<const char *, alnk::SearchArgs>> passes;
+    std::pair<const char *, alnk::SearchArgs> passes[2];
+    int npass = 0;
     if (L.pen_x > 0 && L.dcap > 0) {
       alnk::SearchArgs c = sa;
       c.lds_f = L.lds_fc;
       c.dcap = L.dcap;
-      passes.push_back({"search_affine", c});
+      passes[npass++] = {"search_affine", c};
       sa.pass = 1;
-      passes.push_back({"search_affine_wide", sa});
+      passes[npass++] = {"search_affine_wide", sa};
     } else {
-      passes.push_back({L.pen_x > 0 ? "search_affine" : "search", sa});
+      passes[npass++] = {L.pen_x > 0 ? "search_affine" : "search", sa};
     }
-    for (auto &ps : passes) {
-      alnk::SearchArgs &x = ps.second;
+    for (int ip = 0; ip < npass; ++ip) {
+      alnk::SearchArgs &x = passes[ip].second;
       if (!per_pair) {
-        HIP_TRY(ctx, timed_launch(ctx, ps.first, st, [&] { return alnk::launch_search(x, st); }));
+        HIP_TRY(ctx, timed_launch(ctx, passes[ip].first, st, [&] { return alnk::launch_search(x, st); }));
       } else {
         for (int32_t k = 0; k < L.count; ++k) {
           x.tasks = dtasks + k;
@@ -1000,7 +1009,7 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
 aln_status aln_execute(aln_ctx *ctx, aln_plan *plan, const aln_batch *batch, void *d_ws,
                        uint64_t ws_bytes, aln_result *d_res, uint32_t *d_cigar,
                        uint64_t cigar_words, void *stream) {
-  aln_status st = check_exec(ctx, plan, batch, d_ws, ws_bytes, d_res, d_cigar, cigar_words);
+  aln_status st = exec_check(ctx, plan, batch, d_ws, ws_bytes, d_res, d_cigar, cigar_words);
   if (st != ALN_OK) return st;
   return run_plan(ctx, plan, batch, d_ws, d_res, d_cigar, (hipStream_t)stream, false);
 }
@@ -1008,7 +1017,7 @@ aln_status aln_execute(aln_ctx *ctx, aln_plan *plan, const aln_batch *batch, voi
 aln_status aln_execute_per_pair(aln_ctx *ctx, aln_plan *plan, const aln_batch *batch, void *d_ws,
                                 uint64_t ws_bytes, aln_result *d_res, uint32_t *d_cigar,
                                 uint64_t cigar_words, void *stream) {
-  aln_status st = check_exec(ctx, plan, batch, d_ws, ws_bytes, d_res, d_cigar, cigar_words);
+  aln_status st = exec_check(ctx, plan, batch, d_ws, ws_bytes, d_res, d_cigar, cigar_words);
   if (st != ALN_OK) return st;
   return run_plan(ctx, plan, batch, d_ws, d_res, d_cigar, (hipStream_t)stream, true);
 }
@@ -1016,7 +1025,7 @@ aln_status aln_execute_per_pair(aln_ctx *ctx, aln_plan *plan, const aln_batch *b
 aln_status aln_graph_capture(aln_ctx *ctx, aln_plan *plan, const aln_batch *batch, void *d_ws,
                              uint64_t ws_bytes, aln_result *d_res, uint32_t *d_cigar,
                              uint64_t cigar_words, void *stream) {
-  aln_status st = check_exec(ctx, plan, batch, d_ws, ws_bytes, d_res, d_cigar, cigar_words);
+  aln_status st = exec_check(ctx, plan, batch, d_ws, ws_bytes, d_res, d_cigar, cigar_words);
   if (st != ALN_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   if (s == nullptr) return fail(ctx, ALN_E_INVAL, "graph capture needs a non-default stream");

@@ -33,6 +33,8 @@ struct aln_ctx {
   int force_xdrop_rows = 0;
   int force_xdrop_sides = 0;
   int force_sw16_wide_pct = 0;
+  // device address of the fixed workspace of aln_execute_noalloc (this device)
+  void *scratch = nullptr;
 };
 
 namespace alnrt {
@@ -108,6 +110,13 @@ aln_status plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params *params
                       const int32_t *q_len_host, const int32_t *r_len_host, aln_plan **out);
 // Write the plan's upload image (plan->upload_bytes bytes) to dst.
 void plan_stage(const aln_plan *pl, void *dst);
+// Look up the device address of the fixed no-allocation workspace on
+// ctx->device (current) and keep it in ctx->scratch.
+aln_status scratch_init(aln_ctx *ctx);
+// Argument checks shared by the execute entry points.
+aln_status exec_check(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, void *d_ws,
+                      uint64_t ws_bytes, aln_result *d_res, uint32_t *d_cigar,
+                      uint64_t cigar_words);
 // Enqueue the plan on `st` (upload from pl->pinned, then the kernels).
 aln_status plan_run(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, void *d_ws,
                     aln_result *d_res, uint32_t *d_cigar, hipStream_t st, bool per_pair);
