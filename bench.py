@@ -9,12 +9,17 @@ walk to CIGAR.  GCUPS counts the cells each pair's pruning rule evaluates
 (all M*N for the full matrix, the band for a static band, the surviving
 cells for X-drop), exactly the `cells` field the oracle reports.
 
-The headline workload (the JSON line's `value`) is the protein
-Smith-Waterman batch: 65,536 pairs, lognormal lengths, score + end cell.
-The other workloads (global DNA with CIGAR, banded long reads with CIGAR,
-X-drop seed extension) are measured the same way under "configs", and the
-serving mix of all four (Poisson arrivals through the request server) under
-"serving" with p50/p99 latency.
+The headline workload (the JSON line's `value`) is the largest single-GPU
+one, X-drop seed extension: 200,000 seeds x 2 sides, int32, score + end
+cell + cells visited, every side checked against the oracle.  The other
+workloads (protein Smith-Waterman, global DNA with CIGAR, banded long reads
+with CIGAR, Z-drop, X-drop with CIGAR, the search schedule) are measured the
+same way under "configs", and the serving mix of four of them (Poisson
+arrivals through the request server) under "serving" with p50/p99 latency.
+The roofline of each dominant kernel is priced by the issue rates that
+aln_valu_probe measures per instruction class, at the spec clock and at the
+clock measured under load; the last key, "summary", repeats each workload's
+rate, roofline fraction and check in a few fields.
 
 For each: per-kernel times from HIP events recorded on the launch stream
 during the timed steps (roofline of the dominant kernel), the same kernels
@@ -36,29 +41,56 @@ if ROOT not in sys.path:
 
 METRIC = "GCUPS (bit-exact) at 1 GPU, batched vs per-pair; % int-VALU roofline; p50/p99"
 
-# Algorithmic 2-input integer operations per evaluated cell:
-#   H+o+e (1 add), E = max(E+e, .) (add, max), F = max(F+e, .) (add, max),
-#   H = max(Hdiag+s, E, F) (add, 2 max)                          -> 8 (global)
-#   local adds max(., 0) and the running maximum                  -> 10
-#   extension adds the running maximum                            -> 9
-#   X-drop adds the test against best - X                         -> 10
-#   Z-drop adds to that |d - d_best| (absolute difference) and its
-#   add to H                                                      -> 12
+# Algorithmic 2-input integer operations per evaluated cell, by class
+# (add, max, compare-or-select):
+#   H+o+e (add), E = max(E+e, .) (add, max), F = max(F+e, .) (add, max),
+#   H = max(Hdiag+s, E, F) (add, 2 max)                     -> 4 add 4 max (global)
+#   local adds max(., 0) and the running maximum             -> 4 add 6 max
+#   extension adds the running maximum                       -> 4 add 5 max
+#   X-drop adds the test against best - X                    -> 4 add 5 max 1 cmp
+#   Z-drop adds |d - d_best| (absolute difference, priced as a
+#   compare) and its add to H                                -> 5 add 5 max 2 cmp
 # A search entry (score s, diagonal d) of unit-cost edit distance: two adds
 # (mismatch, insertion), three bound tests, two max; the character compares of
-# its extension depend on the data and are not counted                -> 7
+# its extension depend on the data and are not counted     -> 2 add 2 max 3 cmp
 # A gap-affine search entry: E (max of two sources, two bound tests), F (the
-# same plus an add), H (an add, two bound tests, two max)             -> 12
-OPS_PER_CELL = {("GLOBAL", 0): 8, ("GLOBAL", 1): 8, ("LOCAL", 0): 10, ("LOCAL", 1): 10,
-                ("EXTEND", 0): 9, ("EXTEND", 1): 9, ("EXTEND", 2): 10, ("EXTEND", 3): 12,
-                ("GLOBAL", 4): 7}
-OPS_PER_CELL_KERNEL = {"search_affine": 12, "search_affine_wide": 12}  # kernels whose count differs from their (mode, prune)
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz; packed 16-bit ops do two per lane.
-PEAK_I32_TOPS = 256 * 64 * 2.4e9 / 1e12
-PEAK_I16_TOPS = 2 * PEAK_I32_TOPS
+# same plus an add), H (an add, two bound tests, two max)  -> 2 add 4 max 6 cmp
+OPS_BY_CLASS = {("GLOBAL", 0): dict(add=4, max=4), ("GLOBAL", 1): dict(add=4, max=4),
+                ("LOCAL", 0): dict(add=4, max=6), ("LOCAL", 1): dict(add=4, max=6),
+                ("EXTEND", 0): dict(add=4, max=5), ("EXTEND", 1): dict(add=4, max=5),
+                ("EXTEND", 2): dict(add=4, max=5, cmp=1), ("EXTEND", 3): dict(add=5, max=5, cmp=2),
+                ("GLOBAL", 4): dict(add=2, max=2, cmp=3)}
+OPS_BY_CLASS_KERNEL = {"search_affine": dict(add=2, max=4, cmp=6),
+                       "search_affine_wide": dict(add=2, max=4, cmp=6)}
+# The minimal VALU instruction counts per cell that the roofline plan of this
+# path derives for each configuration (fused 3-input ops allowed): reported
+# beside the algorithmic counts above.
+PLAN_INSTR_PER_CELL = {"nw_dna_1k": 16, "sw_protein": 6.0, "band_long": 16, "xdrop_ext": 15}
+# Instruction class -> probe instruction whose measured issue rate prices it;
+# packed 16-bit kernels issue every class as a packed op (two cells each).
+PROBE_FOR_CLASS = {"add": "v_add_u32", "max": "v_max_i32", "cmp": "v_cmp_gt_i32"}
+PROBE_FOR_CLASS_I16 = {"add": "v_pk_add_u16", "max": "v_pk_max_i16", "cmp": "v_pk_max_i16"}
+# MI355X: 256 CUs x 4 SIMDs; spec clock 2.4 GHz; a wave64 instruction of the
+# basic rate occupies its SIMD for 4 cycles (0.25 wave instructions per SIMD
+# per cycle) -- the rate used when no probe measurement is at hand.
+SIMDS = 1024
+SPEC_CLOCK_GHZ = 2.4
+BASIC_RATE = 0.25
+PEAK_I32_TOPS = SIMDS * 64 * BASIC_RATE * SPEC_CLOCK_GHZ / 1e3  # 39.32
 KERNEL_WIDTH = {"sw16": "i16"}
 FILL_KERNELS = ("sw16", "strip_i32", "diag_band", "xdrop", "zdrop", "xdrop_tb", "zdrop_tb",
                 "search", "search_affine", "search_affine_wide")
+
+
+def mix_peak_tops(by_class, rates, width, clock_ghz):
+    """Peak 2-input ops per second (T) of a kernel whose cells need by_class
+    ops: every SIMD issues each class at its measured rate (wave instructions
+    per SIMD per cycle), a packed 16-bit instruction doing two cells' op."""
+    per_lane = 2 if width == "i16" else 1
+    cls = PROBE_FOR_CLASS_I16 if width == "i16" else PROBE_FOR_CLASS
+    cycles = sum(n / (rates.get(cls[c], BASIC_RATE) * 64 * per_lane) for c, n in by_class.items())
+    return sum(by_class.values()) / cycles * SIMDS * clock_ghz * 1e9 / 1e12
+
 
 WORKLOAD_DESC = {
     "sw_protein": ("Smith-Waterman local, protein (20 letters, seeded symmetric matrix), "
@@ -108,11 +140,39 @@ def trimmed_mean(xs):
     return float(np.mean(core))
 
 
-def cpu_baseline(batch, work, target_s):
-    """Time the oracle on the first k pairs, k sized for about target_s.
-    ``work`` is a per-pair cost estimate used only to size the sample."""
+def host_cores():
+    """Host threads this process may use: the CPU affinity set, capped by the
+    cgroup CPU quota when one is set (a container's share), and the CPU model."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as f:
+            q, per = f.read().split()[:2]
+        if q != "max":
+            quota = max(1, int(int(q) / int(per)))
+    except (OSError, ValueError):
+        pass
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return (min(n, quota) if quota else n), n, quota, model
+
+
+def cpu_baseline(batch, work, target_s, runs=10):
+    """The oracle on a bounded sample of the batch, timed with the paper's
+    protocol (Sec. 9.1): `runs` runs, the 2 highest and 2 lowest dropped, the
+    mean of the rest.  The sample (the first k pairs) is sized so that all
+    runs together take about target_s on every host core; a single-thread
+    run of a smaller sample gives the one-core rate.  ``work`` is a per-pair
+    cost estimate used only to size the samples."""
     from tests.parity import oracle_batch
-    cores = min(16, os.cpu_count() or 1)
+    cores, nproc, quota, model = host_cores()
     n = batch.n
     k0 = min(n, 64)
     sub0 = batch.subset(np.arange(k0))
@@ -121,16 +181,34 @@ def cpu_baseline(batch, work, target_s):
     dt0 = max(time.perf_counter() - t0, 1e-3)
     rate = max(float(o0["cells"].sum()), 1.0) / dt0
     cum = np.cumsum(work.astype(np.float64))
-    k = int(np.searchsorted(cum, rate * target_s)) + 1
+    k = int(np.searchsorted(cum, rate * target_s / runs)) + 1
     k = max(k0, min(n, k))
     sub = batch.subset(np.arange(k))
-    t0 = time.perf_counter()
-    ores = oracle_batch(sub, nthreads=cores)
-    dt = time.perf_counter() - t0
+    times = []
+    ores = None
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        ores = oracle_batch(sub, nthreads=cores)
+        times.append(time.perf_counter() - t0)
+    dt = trimmed_mean(times)
     cells = float(ores["cells"].sum())
+    # one core: a sample of about a tenth of the all-core run's cells
+    k1 = max(1, int(np.searchsorted(cum, 0.1 * cells)) + 1)
+    k1 = min(k1, k)
+    sub1 = batch.subset(np.arange(k1))
+    t0 = time.perf_counter()
+    o1 = oracle_batch(sub1, nthreads=1)
+    dt1 = time.perf_counter() - t0
+    cells1 = float(o1["cells"].sum())
     return dict(value=round(cells / dt / 1e9, 4), unit="GCUPS", cores=cores, kind="oracle",
-                sample=f"first {k} of {n} pairs in generation order ({cells:.3e} cells), "
-                       f"{dt:.1f} s on {cores} host threads", seconds=round(dt, 3)), ores, k
+                sample=f"first {k} of {n} pairs in generation order ({cells:.3e} cells); "
+                       f"trimmed mean of {runs} runs (2 highest and 2 lowest dropped) "
+                       f"on {cores} host threads",
+                seconds=round(dt, 3), run_seconds=[round(t, 3) for t in times],
+                nproc=nproc, cgroup_cpu_quota=quota, cpu_model=model,
+                single_core=dict(value=round(cells1 / dt1 / 1e9, 4), unit="GCUPS",
+                                 sample=f"first {k1} pairs ({cells1:.3e} cells), one run",
+                                 seconds=round(dt1, 3))), ores, k
 
 
 def measured_traffic(family, workload):
@@ -153,7 +231,36 @@ def measured_traffic(family, workload):
     return None
 
 
-def run_workload(name, batch, args, cpu_seconds, pp_cap):
+def bit_exact_check(batch, res, cig, work, ores, k, rate, budget_s):
+    """Compare GPU results with the oracle: the first k pairs (the CPU
+    baseline's sample, whose oracle results are in ores) and, when
+    budget_s > 0, further pairs spread evenly over the whole batch -- every
+    pair if the oracle can do them all in about budget_s at `rate` cells/s."""
+    from tests.parity import compare, oracle_batch
+    sub = batch.subset(np.arange(k))
+    bad = compare(sub, res[:k], cig[:k] if cig is not None else None, ores)
+    checked = k
+    rest = np.arange(k, batch.n)
+    if budget_s > 0 and rest.size and rate:
+        w = work[rest].astype(np.float64)
+        frac = min(1.0, rate * budget_s / max(float(w.sum()), 1.0))
+        if frac < 1.0:
+            step = max(1, int(np.ceil(1.0 / frac)))
+            rest = rest[::step]
+        t0 = time.perf_counter()
+        sub = batch.subset(rest)
+        o = oracle_batch(sub)
+        bad += compare(sub, res[rest], [cig[i] for i in rest] if cig is not None else None, o)
+        checked += rest.size
+        log(f"[bench] checked {rest.size} more pairs in {time.perf_counter() - t0:.1f} s")
+    how = ("every pair" if checked == batch.n else
+           f"the first {k} pairs and every {max(1, (batch.n - k) // max(checked - k, 1))}-th "
+           f"pair after them")
+    return dict(pairs=int(checked), of=int(batch.n), sample=how, mismatches=len(bad),
+                first=bad[:3])
+
+
+def run_workload(name, batch, args, cpu_seconds, pp_cap, check_seconds=0.0, machine=None):
     import torch
     from paper_2607_06225_amd import aln
     from tests.parity import compare
@@ -215,16 +322,35 @@ def run_workload(name, batch, args, cpu_seconds, pp_cap):
     dom_launches = ktimes[dom][1] / args.steps
     dom_launch_ms = ktimes[dom][0] / ktimes[dom][1]
     width = KERNEL_WIDTH.get(dom, "i32")
-    peak = PEAK_I16_TOPS if width == "i16" else PEAK_I32_TOPS
-    ops = OPS_PER_CELL_KERNEL.get(dom, OPS_PER_CELL[(mode_name, batch.prune)])
+    by_class = OPS_BY_CLASS_KERNEL.get(dom, OPS_BY_CLASS[(mode_name, batch.prune)])
+    ops = sum(by_class.values())
     # every evaluated cell passes through the dominant fill kernel once
     cells_per_launch = cells / dom_launches
     achieved = cells_per_launch * ops / (dom_launch_ms * 1e-3) / 1e12
+    rates = (machine or {}).get("issue_rates", {})
+    clk = (machine or {}).get("clock_ghz")
+    peak = mix_peak_tops(by_class, rates, width, SPEC_CLOCK_GHZ)
     roof = dict(bound="alu", achieved=round(achieved, 3), peak=round(peak, 2), unit="TOP/s",
                 frac=round(achieved / peak, 4), traffic=measured_traffic(dom, name),
-                kernel=dom, ops_per_cell=ops, op_width=width,
+                kernel=dom, ops_per_cell=ops, ops_by_class=by_class, op_width=width,
+                peak_basis=("issue rate of each op class measured by aln_valu_probe, at the "
+                            "2.4 GHz spec clock" if rates else
+                            "0.25 wave instructions per SIMD per cycle, 2.4 GHz spec clock"),
                 cells_per_launch=int(cells_per_launch), launches_per_step=dom_launches,
                 avg_launch_ms=round(dom_launch_ms, 4))
+    if clk:
+        pk = mix_peak_tops(by_class, rates, width, clk)
+        roof.update(clock_ghz_measured=round(clk, 3), peak_at_measured_clock=round(pk, 2),
+                    frac_at_measured_clock=round(achieved / pk, 4))
+    if name in PLAN_INSTR_PER_CELL:
+        # the plan's formula: GCUPS x minimal instructions per cell over
+        # 256 CUs x 64 lanes x clock (packed int16: instructions are per cell)
+        ipc = PLAN_INSTR_PER_CELL[name]
+        ach_i = cells_per_launch * ipc / (dom_launch_ms * 1e-3) / 1e12
+        roof["plan_instr_per_cell"] = ipc
+        roof["frac_plan_count"] = round(ach_i / (256 * 64 * SPEC_CLOCK_GHZ / 1e3), 4)
+        if clk:
+            roof["frac_plan_count_at_measured_clock"] = round(ach_i / (256 * 64 * clk / 1e3), 4)
 
     per_pair = None
     if pp_cap:
@@ -271,9 +397,10 @@ def run_workload(name, batch, args, cpu_seconds, pp_cap):
         cpu, ores, k = cpu_baseline(batch, work, cpu_seconds)
         if batch.prune == 4:
             cpu["alignments_per_s"] = round(k / cpu["seconds"], 1)
-        sub = batch.subset(np.arange(k))
-        bad = compare(sub, res[:k], cig[:k] if cig is not None else None, ores)
-        verified = dict(pairs=k, mismatches=len(bad), first=bad[:3])
+        log(f"[bench] {name}: bit-exact check against the oracle")
+        verified = bit_exact_check(batch, res, cig, work, ores, k,
+                                   rate=float(ores["cells"].sum()) / max(cpu["seconds"], 1e-6),
+                                   budget_s=check_seconds)
 
     out = dict(
         workload=name, desc=WORKLOAD_DESC[name], pairs=batch.n, cells=cells,
@@ -288,6 +415,7 @@ def run_workload(name, batch, args, cpu_seconds, pp_cap):
     )
     if batch.prune in (2, 3):
         out["widened_pairs"] = int(((res["flags"] & aln.F_WIDENED) != 0).sum())
+        out["too_wide_pairs"] = int((res["status"] == aln.R_TOO_WIDE).sum())
         if batch.want_cigar:
             out["cigar_cap_pairs"] = int((res["status"] == aln.R_CIGAR_CAP).sum())
     if batch.mode == 1 and batch.prune == 0:
@@ -305,6 +433,56 @@ def run_workload(name, batch, args, cpu_seconds, pp_cap):
         "gcups", "ms_per_step", "cells", "kernel_ms_per_step", "per_pair", "cpu_baseline",
         "bit_exact_check")}))
     return out
+
+
+def measure_machine():
+    """Issue rates of the instruction classes the roofline prices, and the
+    shader clock under a VALU load, from aln_valu_probe: every SIMD busy with
+    one instruction over 8 independent chains (4 waves per SIMD), and the
+    latency of a dependent chain (one wave per SIMD)."""
+    from paper_2607_06225_amd import aln
+    ctx = aln.Context(0)
+    rows, rates, by_waves = [], {}, {}
+    for op in aln.PROBE_OPS:
+        for wps in (2, 4, 8):
+            r = aln.valu_probe(ctx, op, waves_per_simd=wps, iters=2000)
+            rows.append(r)
+            by_waves.setdefault(op, {})[wps] = round(r["issue_per_simd_cycle"], 4)
+        # the peak is the best rate any occupancy reaches
+        rates[op] = max(by_waves[op].values())
+    dep = {}
+    for op in ("v_add_u32", "v_max_i32", "v_max3_i32", "v_cndmask_b32"):
+        r = aln.valu_probe(ctx, op, dependent=True, waves_per_simd=1, iters=2000)
+        rows.append(r)
+        dep[op] = round(r["cycles_per_instr_one_wave"], 2)
+    ctx.close()
+    clocks = sorted(r["clock_ghz"] for r in rows if r["clock_ghz"])
+    return dict(clock_ghz=clocks[len(clocks) // 2] if clocks else None,
+                clock_ghz_range=[round(clocks[0], 3), round(clocks[-1], 3)] if clocks else None,
+                issue_rates=rates, issue_rates_by_waves_per_simd=by_waves,
+                dependent_cycles_per_instr=dep,
+                note="issue rates in wave64 instructions per SIMD per shader cycle, every SIMD "
+                     "busy (2, 4 or 8 waves each, 8 independent chains per wave; the best of the "
+                     "three is the rate used); clock from s_memtime over s_memrealtime (100 MHz) "
+                     "during those loops")
+
+
+def summarize(r):
+    """Short record of one workload's line."""
+    bx = r.get("bit_exact_check") or {}
+    rf = r["roofline"]
+    rec = dict(gcups=r["gcups"], ms=r["ms_per_step"], kernel=rf["kernel"], frac=rf["frac"],
+               frac_at_measured_clock=rf.get("frac_at_measured_clock"),
+               checked=f"{bx.get('pairs', 0)}/{r['pairs']}",
+               mismatches=bx.get("mismatches"))
+    if r.get("per_pair"):
+        rec["batched_vs_per_pair"] = r["per_pair"]["batched_speedup"]
+    if r.get("cpu_baseline"):
+        rec["cpu_gcups"] = r["cpu_baseline"]["value"]
+    for k in ("widened_pairs", "too_wide_pairs", "cigar_cap_pairs", "alignments_per_s"):
+        if k in r:
+            rec[k] = r[k]
+    return rec
 
 
 def run_edit_table(args):
@@ -432,22 +610,29 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="sw_protein", choices=sorted(WORKLOAD_DESC),
+    ap.add_argument("--workload", default="xdrop_ext", choices=sorted(WORKLOAD_DESC),
                     help="headline workload (the JSON line's value)")
     ap.add_argument("--edit-table-pairs", type=int, default=1024,
                     help="pairs per cell of the edit-distance table (0: skip the table)")
     ap.add_argument("--edit-table-check", type=int, default=16,
                     help="pairs per cell checked against the CPU oracle")
     ap.add_argument("--configs",
-                    default="nw_dna_1k,band_long,xdrop_ext,zdrop_ext,xdrop_cigar,edit_search,"
+                    default="sw_protein,nw_dna_1k,band_long,zdrop_ext,xdrop_cigar,edit_search,"
                             "affine_search",
                     help="comma list of further workloads to measure, or 'none'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="plan with built-in tile costs instead of measured ones")
     ap.add_argument("--no-per-pair", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--extra-cpu-seconds", type=float, default=6.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="headline: oracle seconds of the CPU baseline (all 10 runs)")
+    ap.add_argument("--extra-cpu-seconds", type=float, default=6.0,
+                    help="other workloads: oracle seconds of the CPU baseline")
+    ap.add_argument("--check-seconds", type=float, default=60.0,
+                    help="headline: oracle seconds for the bit-exact check beyond the "
+                         "baseline's sample (enough for every pair of the default headline)")
+    ap.add_argument("--extra-check-seconds", type=float, default=5.0,
+                    help="other workloads: oracle seconds for the bit-exact check")
     ap.add_argument("--per-pair-cap", type=int, default=2048,
                     help="largest number of pairs launched one by one")
     ap.add_argument("--serving-requests", type=int, default=2000,
@@ -455,6 +640,11 @@ def main():
     ap.add_argument("--serving-streams", type=int, default=4)
     ap.add_argument("--serving-class-streams", type=int, default=0,
                     help="streams one request class may hold (0: the server default, streams/4)")
+    ap.add_argument("--no-probe", action="store_true",
+                    help="price the roofline at 0.25 wave instructions per SIMD per cycle "
+                         "instead of the probe's measured issue rates")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="only run the VALU issue-rate / clock probe and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 5 times (calibrates HBM "
                          "byte counters against a transfer of known size)")
@@ -492,12 +682,19 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": n, "copies": 5}), flush=True)
         return 0
+    if args.valu_probe:
+        print(json.dumps({"valu_probe": measure_machine()}), flush=True)
+        return 0
+    machine = None if args.no_probe else measure_machine()
+    if machine:
+        log(f"[bench] probe: clock {machine['clock_ghz']:.3f} GHz, rates {machine['issue_rates']}")
     if args.serving_only:
         print(json.dumps({"serving": run_serving(args)}), flush=True)
         return 0
     log(f"[bench] generating {args.workload}")
     head = run_workload(args.workload, W.WORKLOADS[args.workload](), args,
-                        0 if args.no_cpu_baseline else args.cpu_seconds, pp_cap)
+                        0 if args.no_cpu_baseline else args.cpu_seconds, pp_cap,
+                        args.check_seconds, machine)
     configs = {}
     for c in extras:
         if c == args.workload:
@@ -507,7 +704,8 @@ def main():
         b = W.WORKLOADS[c]()
         log(f"[bench] {c}: {b.n} pairs generated in {time.perf_counter() - t0:.1f} s")
         configs[c] = run_workload(c, b, args, 0 if args.no_cpu_baseline
-                                  else args.extra_cpu_seconds, pp_cap)
+                                  else args.extra_cpu_seconds, pp_cap, args.extra_check_seconds,
+                                  machine)
         del b
     edit_table = run_edit_table(args) if args.edit_table_pairs > 0 else None
     serving_out = run_serving(args) if args.serving_requests > 0 else None
@@ -537,14 +735,23 @@ def main():
         "step_ms_median": head["step_ms_median"],
         "plan_ms": head["plan_ms"],
         "autotune": head["autotune"],
+        "machine": machine,
         "configs": configs,
         "edit_table": edit_table,
         "serving": serving_out,
     }
-    for k in ("int32_reruns", "statuses", "widened_pairs", "cigar_cap_pairs",
+    for k in ("int32_reruns", "statuses", "widened_pairs", "cigar_cap_pairs", "too_wide_pairs",
               "equivalent_gcups", "alignments_per_s", "mean_edit_distance", "mean_penalty"):
         if k in head:
             out[k] = head[k]
+    # last key: one short record per workload, so that a truncated copy of the
+    # line still holds every workload's rate, roofline fraction and check
+    out["summary"] = {w: summarize(r) for w, r in [(args.workload, head)] + list(configs.items())}
+    if serving_out:
+        out["summary"]["serving"] = {
+            lv["level"]: dict(qps=lv["qps_achieved"], gcups=lv["gcups"], p50_ms=lv.get("p50_ms"),
+                              p99_ms=lv.get("p99_ms")) for lv in serving_out["levels"]}
+        out["summary"]["serving"]["bit_exact"] = serving_out["bit_exact_check"]["mismatches"] == 0
     print(json.dumps(out), flush=True)
     return 0
 

@@ -300,6 +300,23 @@ aln_status aln_set_profiling(aln_ctx *ctx, int32_t enable);
 int32_t aln_kernel_times(aln_ctx *ctx, const char **names, double *ms,
                          int64_t *launches, int32_t max);
 
+/* VALU probe for measurement tools: keeps every SIMD of the device busy with
+ * one instruction class (op: 0 v_add_u32, 1 v_max_i32, 2 v_max3_i32,
+ * 3 v_cmp_gt_i32, 4 v_cndmask_b32, 5 v_pk_max_i16, 6 v_pk_add_u16,
+ * 7 v_lshl_or_b32, 8 v_add3_u32, 9 v_mov_b32 with DPP, 10 v_max_i32 with DPP,
+ * 11 v_add_u32 with an SDWA byte operand, 12 v_perm_b32, 13 v_alignbyte_b32,
+ * 14 v_bfe_u32, 15 v_addc_co_u32): waves_per_simd (1..8) waves per SIMD, each
+ * running iters x 32 such instructions over 8 independent register chains
+ * (dependent != 0: one chain, to time their latency).  Writes out[0] the
+ * launch's milliseconds, out[1] the mean shader-clock cycles of a wave's loop
+ * (s_memtime), out[2] its mean 100 MHz ticks (s_memrealtime), out[3] waves,
+ * out[4] wave instructions per wave, out[5] SIMDs.  Issue rate per SIMD =
+ * out[4] * waves_per_simd / out[1] wave instructions per cycle; clock =
+ * 0.1 GHz * out[1] / out[2].  Synchronises the device; allocates and frees
+ * a small device buffer. */
+aln_status aln_valu_probe(aln_ctx *ctx, int32_t op, int32_t dependent, int32_t waves_per_simd,
+                          int32_t iters, double *out);
+
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of single-pair requests on one device.
  *

@@ -102,6 +102,7 @@ EXPORTS = [
     "aln_set_scoring", "aln_plan_create", "aln_plan_destroy", "aln_execute",
     "aln_execute_noalloc", "aln_execute_per_pair", "aln_graph_capture", "aln_graph_launch",
     "aln_set_profiling", "aln_kernel_times", "aln_autotune", "aln_get_tuning", "aln_set_tuning",
+    "aln_valu_probe",
     "aln_server_create", "aln_server_destroy", "aln_server_submit", "aln_server_poll",
     "aln_server_drain", "aln_server_clock", "aln_server_get_stats", "aln_server_last_error",
 ]
@@ -134,6 +135,7 @@ def load_library(path=LIB_PATH):
         "aln_autotune": ([P, I32, P, P, P, P, P], I32),
         "aln_get_tuning": ([P, P], I32),
         "aln_set_tuning": ([P, P], I32),
+        "aln_valu_probe": ([P, I32, I32, I32, I32, P], I32),
         "aln_server_create": ([P, P, P], I32),
         "aln_server_destroy": ([P], None),
         "aln_server_submit": ([P, P, P], I32),
@@ -320,6 +322,28 @@ class Context:
         if k < 0:
             raise AlnError(f"aln_kernel_times failed ({k})")
         return {names[i].decode(): (float(ms[i]), int(cnt[i])) for i in range(k)}
+
+
+PROBE_OPS = ("v_add_u32", "v_max_i32", "v_max3_i32", "v_cmp_gt_i32", "v_cndmask_b32",
+             "v_pk_max_i16", "v_pk_add_u16", "v_lshl_or_b32", "v_add3_u32", "v_mov_b32_dpp",
+             "v_max_i32_dpp", "v_add_u32_sdwa", "v_perm_b32", "v_alignbyte_b32", "v_bfe_u32",
+             "v_addc_co_u32")
+
+
+def valu_probe(ctx, op, dependent=False, waves_per_simd=4, iters=2000):
+    """aln_valu_probe: issue rate (wave instructions per SIMD per cycle) of one
+    instruction class with every SIMD busy, and the shader clock under that
+    load (GHz).  Returns a dict."""
+    out = (ctypes.c_double * 6)()
+    k = PROBE_OPS.index(op) if isinstance(op, str) else int(op)
+    ctx._check(ctx.lib.aln_valu_probe(ctx.handle, k, 1 if dependent else 0, int(waves_per_simd),
+                                      int(iters), out))
+    ms, cyc, ticks, waves, instr, simds = list(out)
+    return dict(op=PROBE_OPS[k], dependent=bool(dependent), waves_per_simd=int(waves_per_simd),
+                ms=ms, clock_ghz=0.1 * cyc / ticks if ticks else None,
+                issue_per_simd_cycle=instr * waves_per_simd / cyc if cyc else None,
+                cycles_per_instr_one_wave=cyc / instr if instr else None,
+                wall_rate_per_simd_ns=instr * waves / simds / (ms * 1e6) if ms else None)
 
 
 class Buffers:

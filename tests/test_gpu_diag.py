@@ -142,6 +142,31 @@ def test_xdrop_widening_chain(ctx, tile):
     assert int(res["flags"][2]) & aln.F_WIDENED
 
 
+def test_xdrop_too_wide_reported_exactly(ctx):
+    """With X far above any score the region is the whole rectangle, whose
+    widest antidiagonal spans 2 min(M, N) diagonals.  Past the widest window
+    (2042 diagonals) the pair must report TOO_WIDE with F_WIDENED, exactly
+    there; every other pair of the batch stays bit-exact."""
+    from paper_2607_06225_amd import aln
+    with_xdrop_tile(ctx, XDROP_TILES[0])
+    rng = np.random.default_rng(12)
+    lengths = [(100, 100), (1200, 1200), (900, 880), (1030, 1040), (1021, 1300), (1022, 1022),
+               (300, 2500)]
+    b = xdrop_batch(rng, lengths, 10 ** 6, name="xd_too_wide")
+    res, _ = run(ctx, b)
+    wide = [2 * min(M, N) > 2042 for M, N in lengths]
+    assert wide == [False, True, False, True, False, True, False]
+    for k, w in enumerate(wide):
+        if w:
+            assert int(res["status"][k]) == aln.R_TOO_WIDE, k
+            assert int(res["flags"][k]) & aln.F_WIDENED, k
+        else:
+            assert int(res["status"][k]) == aln.R_OK, k
+    keep = [k for k, w in enumerate(wide) if not w]
+    sub = b.subset(keep)
+    assert compare(sub, res[keep], None, oracle_batch(sub)) == []
+
+
 @pytest.mark.parametrize("tile", XDROP_TILES)
 def test_xdrop_extension_workload_sample(ctx, tile):
     with_xdrop_tile(ctx, tile)
