@@ -1,4 +1,4 @@
-"""CPU oracle for affine-gap (Gotoh H/E/F) alignment.
+"""CPU oracle for affine-gap (Gotoh H/E/F) alignment and Nussinov folding.
 
 TEST INFRASTRUCTURE ONLY: imported by the test suite, by the smoke check and by
 the CPU-baseline leg of the benchmark.  The GPU library never imports, links or
@@ -10,3 +10,4 @@ from .alnref import (  # noqa: F401
     OP_I, OP_D, OP_EQ, OP_X,
     align, align_batch, build, load,
 )
+from .foldref import fold, fold_batch, FOLD_DTYPE, NO_XDROP  # noqa: F401,E402

@@ -17,6 +17,7 @@ OP_I, OP_D, OP_EQ, OP_X = 1, 2, 7, 8
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "alnref.c")
+_SRC_FOLD = os.path.join(_HERE, "foldref.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -37,13 +38,14 @@ class AlnrefOut(ctypes.Structure):
 
 
 def build(force=True):
-    """Compile liboracle.so with gcc (plain -O2, no intrinsics)."""
+    """Compile liboracle.so (alignment and folding oracles) with gcc (plain
+    -O2, no intrinsics)."""
     if not force and os.path.exists(_LIB):
         return _LIB
     tmp = _LIB + ".tmp"
     subprocess.run(
         ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared",
-         "-o", tmp, _SRC, "-lpthread"],
+         "-o", tmp, _SRC, _SRC_FOLD, "-lpthread"],
         check=True,
     )
     os.replace(tmp, _LIB)
@@ -66,6 +68,10 @@ def load():
     lib.alnref_align_batch.argtypes = [P, i32, i32, i32, i32, i32, i32, i32, i32,
                                        P, P, P, P, P, P, P, P, P, P, i32]
     lib.alnref_align_batch.restype = ctypes.c_int
+    lib.foldref_fold.argtypes = [P, i32, i32, i32, P, i32, P]
+    lib.foldref_fold.restype = ctypes.c_int
+    lib.foldref_fold_batch.argtypes = [P, i32, i32, i32, i32, P, P, P, P, i32]
+    lib.foldref_fold_batch.restype = ctypes.c_int
     _lib = lib
     return lib
 
