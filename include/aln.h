@@ -318,6 +318,62 @@ aln_status aln_valu_probe(aln_ctx *ctx, int32_t op, int32_t dependent, int32_t w
                           int32_t iters, double *out);
 
 /* ------------------------------------------------------------------------
+ * RNA folding: the RNA-folding recurrence of Sec. 3's example table
+ * (Nussinov base-pair maximisation) over sequences x_0 .. x_{n-1} of codes
+ * A, C, G, U = 0..3, for 0 <= i < j < n:
+ *   F(i,j) = max( F(i+1,j), F(i,j-1), F(i+1,j-1) + in1(i,j),
+ *                 max over i <= k < j of F(i,k) + F(k+1,j) ),
+ * F(i,i) = 0, the empty interval = 0, in1(i,j) = pair[x_i*4 + x_j] when
+ * j - i > min_loop, else 0.  The triangle is evaluated span t = j - i by
+ * span.  With xdrop >= 0 the X-drop rule (Sec. 7.2) is transferred to it
+ * (Sec. 9.5): past the warm-up (t > warmup) a cell scoring more than X below
+ * the best score of the earlier spans is removed, and the next span is
+ * evaluated only from one position before the first survivor (by i) to the
+ * last; removed and unevaluated cells read as minus infinity.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t pair[16]; /* pairing scores, each 0..127                          */
+  int32_t min_loop; /* >= 0                                                 */
+  int32_t xdrop;    /* < 0: unpruned; else X                                */
+  int32_t warmup;   /* spans t <= warmup are never pruned (>= 0)            */
+  int32_t reserved; /* 0                                                    */
+} aln_fold_params;  /* 80 bytes */
+
+typedef struct {
+  int32_t n;          /* sequences                                          */
+  const uint8_t *x;   /* device: codes, concatenated                        */
+  const int64_t *off; /* device: start of each sequence                     */
+  const int32_t *len; /* device: length of each sequence                    */
+} aln_fold_batch;
+
+typedef struct {
+  int32_t score;    /* best surviving F (unpruned: F(0, n-1))                */
+  int32_t i, j;     /* its interval: highest F, then the largest span, then
+                       the smallest i                                       */
+  int32_t full;     /* 1 when (0, n-1) was evaluated and kept               */
+  int64_t cells;    /* cells evaluated with span >= 1                       */
+  int32_t status;   /* ALN_R_OK, or ALN_R_BAD_SYMBOL (a code > 3)          */
+  int32_t reserved;
+} aln_fold_result;  /* 32 bytes */
+
+/* Plan a folding batch from its host-side lengths: one workgroup per
+ * sequence with the whole triangle in LDS (one byte per cell when every
+ * score fits 0..253, else two), sequences grouped by LDS size and run
+ * longest first.  Reports the workspace (the uploaded task list) in
+ * fp->workspace_bytes and the unpruned cell count in fp->cells.
+ * ALN_E_UNSUPPORTED when a sequence's triangle cannot fit 160 KB of LDS
+ * (about 570 nt with one-byte scores, 400 nt with two-byte ones) or its
+ * scores could exceed 32767.  Destroy with aln_plan_destroy. */
+aln_status aln_fold_plan_create(aln_ctx *ctx, const aln_fold_params *params, int32_t n,
+                                const int32_t *len_host, aln_plan **plan, aln_footprint *fp);
+/* Run a folding plan on a batch with the lengths it was planned with.
+ * d_ws: >= fp.workspace_bytes; d_res: n results.  Enqueues on `stream`;
+ * allocates nothing. */
+aln_status aln_fold_execute(aln_ctx *ctx, aln_plan *plan, const aln_fold_batch *batch,
+                            void *d_ws, uint64_t ws_bytes, aln_fold_result *d_res,
+                            void *stream);
+
+/* ------------------------------------------------------------------------
  * Serving: continuous batching of single-pair requests on one device.
  *
  * A server owns a worker thread, `streams` HIP streams (default priority)

@@ -50,6 +50,22 @@ class _Batch(ctypes.Structure):
                 ("r_off", ctypes.c_void_p), ("r_len", ctypes.c_void_p)]
 
 
+class _FoldParams(ctypes.Structure):
+    _fields_ = [("pair", ctypes.c_int32 * 16), ("min_loop", ctypes.c_int32),
+                ("xdrop", ctypes.c_int32), ("warmup", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class _FoldBatch(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("x", ctypes.c_void_p), ("off", ctypes.c_void_p),
+                ("len", ctypes.c_void_p)]
+
+
+FOLD_RESULT_DTYPE = np.dtype([("score", "<i4"), ("i", "<i4"), ("j", "<i4"), ("full", "<i4"),
+                              ("cells", "<i8"), ("status", "<i4"), ("reserved", "<i4")])
+assert FOLD_RESULT_DTYPE.itemsize == 32
+
+
 class _Footprint(ctypes.Structure):
     _fields_ = [("workspace_bytes", ctypes.c_uint64), ("traceback_bytes", ctypes.c_uint64),
                 ("cigar_words", ctypes.c_uint64), ("cells", ctypes.c_int64)]
@@ -102,7 +118,7 @@ EXPORTS = [
     "aln_set_scoring", "aln_plan_create", "aln_plan_destroy", "aln_execute",
     "aln_execute_noalloc", "aln_execute_per_pair", "aln_graph_capture", "aln_graph_launch",
     "aln_set_profiling", "aln_kernel_times", "aln_autotune", "aln_get_tuning", "aln_set_tuning",
-    "aln_valu_probe",
+    "aln_valu_probe", "aln_fold_plan_create", "aln_fold_execute",
     "aln_server_create", "aln_server_destroy", "aln_server_submit", "aln_server_poll",
     "aln_server_drain", "aln_server_clock", "aln_server_get_stats", "aln_server_last_error",
 ]
@@ -136,6 +152,8 @@ def load_library(path=LIB_PATH):
         "aln_get_tuning": ([P, P], I32),
         "aln_set_tuning": ([P, P], I32),
         "aln_valu_probe": ([P, I32, I32, I32, I32, P], I32),
+        "aln_fold_plan_create": ([P, P, I32, P, P, P], I32),
+        "aln_fold_execute": ([P, P, P, P, U64, P, P], I32),
         "aln_server_create": ([P, P, P], I32),
         "aln_server_destroy": ([P], None),
         "aln_server_submit": ([P, P, P], I32),
@@ -344,6 +362,59 @@ def valu_probe(ctx, op, dependent=False, waves_per_simd=4, iters=2000):
                 issue_per_simd_cycle=instr * waves_per_simd / cyc if cyc else None,
                 cycles_per_instr_one_wave=cyc / instr if instr else None,
                 wall_rate_per_simd_ns=instr * waves / simds / (ms * 1e6) if ms else None)
+
+
+class FoldDeviceBatch:
+    """A workloads.FoldBatch copied to device tensors (aln_fold_batch)."""
+
+    def __init__(self, fb, device="cuda"):
+        import torch
+        self.src = fb
+        self.n = fb.n
+        self.x = torch.from_numpy(np.ascontiguousarray(fb.x)).to(device)
+        self.off = torch.from_numpy(np.ascontiguousarray(fb.off)).to(device)
+        self.len = torch.from_numpy(np.ascontiguousarray(fb.length)).to(device)
+        self.len_host = np.ascontiguousarray(fb.length, dtype=np.int32)
+        self.c = _FoldBatch(self.n, self.x.data_ptr(), self.off.data_ptr(), self.len.data_ptr())
+
+
+def fold_params(pair, min_loop=0, xdrop=-1, warmup=15):
+    p = _FoldParams()
+    flat = np.asarray(pair, dtype=np.int32).reshape(16)
+    for k in range(16):
+        p.pair[k] = int(flat[k])
+    p.min_loop, p.xdrop, p.warmup, p.reserved = int(min_loop), int(xdrop), int(warmup), 0
+    return p
+
+
+def fold_plan(ctx, fb, len_host=None):
+    """aln_fold_plan_create for a workloads.FoldBatch (its parameters and lengths)."""
+    lens = np.ascontiguousarray(fb.length if len_host is None else len_host, dtype=np.int32)
+    params = fold_params(fb.pair, fb.min_loop, fb.xdrop, fb.warmup)
+    h = ctypes.c_void_p()
+    fp = _Footprint()
+    ctx._check(ctx.lib.aln_fold_plan_create(ctx.handle, ctypes.byref(params), int(lens.size),
+                                            lens.ctypes.data, ctypes.byref(h), ctypes.byref(fp)))
+    return Plan(ctx, h, fp, int(lens.size), params)
+
+
+def fold_execute(ctx, plan, fdb, ws, res, stream=None):
+    ctx._check(ctx.lib.aln_fold_execute(ctx.handle, plan.handle, ctypes.byref(fdb.c), _ptr(ws),
+                                        int(ws.numel()), _ptr(res), _stream_handle(stream)))
+
+
+def fold(ctx, fb, stream=None):
+    """Plan and run one workloads.FoldBatch; returns the results ndarray."""
+    import torch
+    plan = fold_plan(ctx, fb)
+    fdb = FoldDeviceBatch(fb)
+    ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device="cuda")
+    res = torch.zeros(max(fb.n, 1) * FOLD_RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    fold_execute(ctx, plan, fdb, ws, res, stream=stream)
+    torch.cuda.synchronize()
+    out = np.frombuffer(res.cpu().numpy().tobytes(), dtype=FOLD_RESULT_DTYPE, count=fb.n).copy()
+    plan.close()
+    return out
 
 
 class Buffers:

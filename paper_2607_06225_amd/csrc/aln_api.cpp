@@ -715,6 +715,10 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
 
 void alnrt::plan_stage(const aln_plan *pl, void *dst) {
   uint8_t *d = static_cast<uint8_t *>(dst);
+  if (pl->fold) {
+    memcpy(d, pl->fold_tasks.data(), sizeof(alnk::FoldTask) * pl->fold_tasks.size());
+    return;
+  }
   if (!pl->sw16_tasks.empty()) {
     memcpy(d + pl->sw16_off, pl->sw16_tasks.data(), sizeof(alnk::Sw16Task) * pl->sw16_tasks.size());
     memcpy(d + pl->sw16_items_off, pl->sw16_items.data(),
@@ -765,6 +769,7 @@ aln_status alnrt::exec_check(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, v
                              uint64_t ws_bytes, aln_result *d_res, uint32_t *d_cigar,
                              uint64_t cigar_words) {
   if (!ctx || !plan || !b || plan->ctx != ctx) return fail(ctx, ALN_E_INVAL, "bad context or plan");
+  if (plan->fold) return fail(ctx, ALN_E_INVAL, "a folding plan runs with aln_fold_execute");
   if (b->n != plan->n) return fail(ctx, ALN_E_INVAL, "batch has %d pairs, plan %d", b->n, plan->n);
   if (plan->n == 0) return ALN_OK;
   if (!d_res || !b->q_off || !b->q_len || !b->r_off || !b->r_len)
@@ -1066,3 +1071,139 @@ aln_status alnrt::plan_run(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
                            aln_result *d_res, uint32_t *d_cigar, hipStream_t st, bool per_pair) {
   return run_plan(ctx, plan, b, d_ws, d_res, d_cigar, st, per_pair);
 }
+
+// ------------------------------------------------------------------ folding
+
+extern "C" {
+
+aln_status aln_fold_plan_create(aln_ctx *ctx, const aln_fold_params *params, int32_t n,
+                                const int32_t *len_host, aln_plan **plan, aln_footprint *fp) {
+  if (!ctx || !params || !plan || n < 0 || (n > 0 && !len_host))
+    return fail(ctx, ALN_E_INVAL, "null argument or negative n");
+  *plan = nullptr;
+  const aln_fold_params &p = *params;
+  int maxpair = 0;
+  for (int k = 0; k < 16; ++k) {
+    if (p.pair[k] < 0 || p.pair[k] > 127) return fail(ctx, ALN_E_INVAL, "pair scores must be 0..127");
+    maxpair = std::max(maxpair, p.pair[k]);
+  }
+  if (p.min_loop < 0 || p.warmup < 0) return fail(ctx, ALN_E_INVAL, "min_loop and warmup >= 0");
+  // LDS of one CU, less the kernel's few static words
+  const int64_t lds_max = std::min<int64_t>(ctx->lds_per_cu, 160 * 1024) - 256;
+  // element width per sequence: one byte when every score fits 0..253 (255
+  // marks minus infinity), else two.  Under X-drop a one-byte term costs one
+  // more instruction, so two bytes are kept while they leave room for two
+  // workgroups per CU.
+  struct Cls {
+    int elt, lds_class;
+  };
+  std::vector<Cls> cls(n);
+  for (int32_t s = 0; s < n; ++s) {
+    const int32_t L = len_host[s];
+    if (L < 0) return fail(ctx, ALN_E_INVAL, "negative length");
+    const int64_t maxF = (int64_t)maxpair * (L / 2);
+    const bool u8 = maxF <= 253 && (int64_t)alnk::fold_lds_bytes(1, L) <= lds_max;
+    const bool i16 = maxF <= 32767 && (int64_t)alnk::fold_lds_bytes(2, L) <= lds_max;
+    int elt;
+    if (p.xdrop >= 0)
+      elt = (i16 && (int64_t)alnk::fold_lds_bytes(2, L) <= lds_max / 2) || !u8 ? 2 : 1;
+    else
+      elt = u8 ? 1 : 2;
+    if ((elt == 1 && !u8) || (elt == 2 && !i16))
+      return fail(ctx, ALN_E_UNSUPPORTED,
+                  "sequence %d (%d nt): its triangle does not fit LDS, or its scores exceed 32767",
+                  s, L);
+    // LDS classes: workgroups per CU 8, 4, 2, 1
+    const int64_t lds = (int64_t)alnk::fold_lds_bytes(elt, L);
+    int c = 0;
+    while (c < 3 && lds > lds_max >> (3 - c)) ++c;
+    cls[s] = Cls{elt, c};
+  }
+  aln_plan *pl = new (std::nothrow) aln_plan;
+  if (!pl) return fail(ctx, ALN_E_NOMEM, "plan allocation");
+  pl->ctx = ctx;
+  pl->n = n;
+  pl->fold = true;
+  pl->fold_p = p;
+  pl->qlen.assign(len_host, len_host + n);
+  // launches: largest LDS class first; within a launch the longest sequence
+  // first (LPT)
+  int64_t cells = 0;
+  for (int c = 3; c >= 0; --c) {
+    for (int elt = 2; elt >= 1; --elt) {
+      std::vector<int32_t> idx;
+      int32_t max_n = 0;
+      for (int32_t s = 0; s < n; ++s)
+        if (cls[s].lds_class == c && cls[s].elt == elt) {
+          idx.push_back(s);
+          max_n = std::max(max_n, len_host[s]);
+        }
+      if (idx.empty()) continue;
+      std::stable_sort(idx.begin(), idx.end(),
+                       [&](int32_t x, int32_t y) { return len_host[x] > len_host[y]; });
+      aln_plan::FoldLaunch L;
+      L.elt = elt;
+      L.block = c == 3 ? 1024 : (c == 2 ? 512 : 256);
+      L.first = (int32_t)pl->fold_tasks.size();
+      L.count = (int32_t)idx.size();
+      L.max_n = max_n;
+      for (int32_t s : idx) {
+        pl->fold_tasks.push_back(alnk::FoldTask{s, len_host[s]});
+        cells += (int64_t)len_host[s] * (len_host[s] - 1) / 2;
+      }
+      pl->fold_launches.push_back(L);
+    }
+  }
+  pl->upload_bytes = sizeof(alnk::FoldTask) * pl->fold_tasks.size();
+  pl->tasks_bytes = align_up(std::max<uint64_t>(pl->upload_bytes, 1));
+  pl->ws_bytes = pl->tasks_bytes;
+  pl->cells = cells;
+  if (hipHostMalloc(&pl->pinned, std::max<uint64_t>(pl->upload_bytes, 1), hipHostMallocDefault) !=
+      hipSuccess) {
+    delete pl;
+    return fail(ctx, ALN_E_NOMEM, "pinned staging");
+  }
+  plan_stage(pl, pl->pinned);
+  if (fp) {
+    fp->workspace_bytes = pl->ws_bytes;
+    fp->traceback_bytes = 0;
+    fp->cigar_words = 0;
+    fp->cells = cells;
+  }
+  *plan = pl;
+  return ALN_OK;
+}
+
+aln_status aln_fold_execute(aln_ctx *ctx, aln_plan *plan, const aln_fold_batch *b, void *d_ws,
+                            uint64_t ws_bytes, aln_fold_result *d_res, void *stream) {
+  if (!ctx || !plan || !b || plan->ctx != ctx || !plan->fold)
+    return fail(ctx, ALN_E_INVAL, "bad context or folding plan");
+  if (b->n != plan->n) return fail(ctx, ALN_E_INVAL, "batch has %d sequences, plan %d", b->n, plan->n);
+  if (plan->n == 0) return ALN_OK;
+  if (!d_res || !b->x || !b->off || !b->len) return fail(ctx, ALN_E_INVAL, "null device pointer");
+  if (!d_ws || ws_bytes < plan->ws_bytes)
+    return fail(ctx, ALN_E_CAPACITY, "workspace %llu < %llu bytes", (unsigned long long)ws_bytes,
+                (unsigned long long)plan->ws_bytes);
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  HIP_TRY(ctx, hipMemcpyAsync(d_ws, plan->pinned, plan->upload_bytes, hipMemcpyHostToDevice, st));
+  alnk::FoldArgs a;
+  a.x = b->x;
+  a.off = b->off;
+  a.len = b->len;
+  for (int k = 0; k < 16; ++k) a.pair[k] = plan->fold_p.pair[k];
+  a.min_loop = plan->fold_p.min_loop;
+  a.xdrop = plan->fold_p.xdrop;
+  a.warmup = plan->fold_p.warmup;
+  a.res = d_res;
+  const alnk::FoldTask *tasks = static_cast<const alnk::FoldTask *>(d_ws);
+  for (const aln_plan::FoldLaunch &L : plan->fold_launches) {
+    a.tasks = tasks + L.first;
+    a.ntasks = L.count;
+    a.max_n = L.max_n;
+    HIP_TRY(ctx, timed_launch(ctx, "fold", st, [&] { return alnk::launch_fold(L.elt, L.block, a, st); }));
+  }
+  return ALN_OK;
+}
+
+} // extern "C"

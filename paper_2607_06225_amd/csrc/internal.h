@@ -166,6 +166,27 @@ struct SearchArgs {
   int32_t dcap, pass;
 };
 
+// Nussinov folding: one workgroup per sequence (tasks in LPT order).
+struct FoldTask {
+  int32_t seq; // index into the batch
+  int32_t n;   // its length
+};
+struct FoldArgs {
+  const uint8_t *x;
+  const int64_t *off;
+  const int32_t *len;
+  const FoldTask *tasks;
+  int32_t ntasks;
+  int32_t pair[16];  // in1 of (x_i, x_j) = pair[x_i*4 + x_j]
+  int32_t min_loop;  // pairs score only when j - i > min_loop
+  int32_t xdrop;     // < 0: unpruned
+  int32_t warmup;    // spans t <= warmup are never pruned
+  int32_t max_n;     // longest sequence of the launch (LDS size)
+  aln_fold_result *res;
+};
+// LDS bytes of one folding workgroup for sequences up to max_n long.
+size_t fold_lds_bytes(int elt_bytes, int max_n);
+
 // Launchers (defined in the kernel translation units).
 hipError_t launch_validate(const ValidateArgs &a, hipStream_t s);
 hipError_t launch_strip(int rows, int mode, bool tb, bool small_alphabet,
@@ -178,5 +199,7 @@ hipError_t launch_diag(int rows, int mode, int prune, bool tb, const DiagArgs &a
 hipError_t launch_xdrop_group(int prune, const DiagArgs &a, hipStream_t s);
 hipError_t launch_walk_diag(const WalkArgs &a, hipStream_t s);
 hipError_t launch_search(const SearchArgs &a, hipStream_t s);
+// elt_bytes 1 (uint8 triangle) or 2 (int16); block 256, 512 or 1024 threads
+hipError_t launch_fold(int elt_bytes, int block, const FoldArgs &a, hipStream_t s);
 
 } // namespace alnk

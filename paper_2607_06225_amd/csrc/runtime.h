@@ -100,6 +100,17 @@ struct aln_plan {
   bool own_pinned = true;   // false: staging belongs to the server slot
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  // RNA folding plans (aln_fold_plan_create): parameters, tasks in launch
+  // order and one launch per LDS size class
+  bool fold = false;
+  aln_fold_params fold_p{};
+  std::vector<alnk::FoldTask> fold_tasks;
+  struct FoldLaunch {
+    int elt;   // bytes per triangle element
+    int block; // threads per workgroup
+    int32_t first, count, max_n;
+  };
+  std::vector<FoldLaunch> fold_launches;
 };
 
 namespace alnrt {

@@ -443,6 +443,78 @@ def affine_search(n=4096, length=2000, div=0.05, seed=707, pen=(4, 6, 2)):
     return edit_pairs(n, length, div, seed, name="affine_search", pen=pen)
 
 
+@dataclass
+class FoldBatch:
+    """A batch of RNA sequences for the folding recurrence (codes A, C, G, U =
+    0..3), with its pairing table and pruning parameters."""
+    name: str
+    x: np.ndarray        # uint8 codes, concatenated
+    off: np.ndarray      # int64
+    length: np.ndarray   # int32
+    pair: np.ndarray     # int32 [4, 4] pairing scores
+    min_loop: int = 0
+    xdrop: int = -1      # < 0: unpruned
+    warmup: int = 15
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self):
+        return int(self.length.size)
+
+    def seq(self, p):
+        o = int(self.off[p])
+        return self.x[o: o + int(self.length[p])]
+
+    def subset(self, idx, name=None):
+        xs = [self.seq(int(p)) for p in np.asarray(idx, dtype=np.int64)]
+        return pack_fold(xs, self.pair, self.min_loop, self.xdrop, self.warmup,
+                         name or self.name + "_subset")
+
+    def with_params(self, **kw):
+        b = FoldBatch(self.name, self.x, self.off, self.length, self.pair, self.min_loop,
+                      self.xdrop, self.warmup, dict(self.meta))
+        for k, v in kw.items():
+            setattr(b, k, v)
+        return b
+
+
+def pack_fold(xs, pair, min_loop=0, xdrop=-1, warmup=15, name="fold"):
+    length = np.array([len(x) for x in xs], dtype=np.int32)
+    off = np.zeros(len(xs), dtype=np.int64)
+    if len(xs) > 1:
+        off[1:] = np.cumsum(length[:-1], dtype=np.int64)
+    x = (np.concatenate([np.asarray(v, dtype=np.uint8) for v in xs]) if xs
+         else np.zeros(0, dtype=np.uint8))
+    return FoldBatch(name, x, off, length, np.asarray(pair, dtype=np.int32).reshape(4, 4),
+                     int(min_loop), int(xdrop), int(warmup))
+
+
+def rna_pair_table():
+    """Pairing scores: one point per Watson-Crick pair (A-U, C-G) and per G-U
+    wobble pair, symmetric; every other pair 0."""
+    P = np.zeros((4, 4), dtype=np.int32)
+    for a, b in ((0, 3), (1, 2), (2, 3)):
+        P[a, b] = P[b, a] = 1
+    return P
+
+
+def rna_fold(n=4096, seed=808, min_len=76, max_len=500, xdrop=2, warmup=15, min_loop=3):
+    """Seeded synthetic RNA: n sequences of i.i.d. uniform A, C, G, U with
+    lengths uniform in [min_len, max_len] (the span of RNA lengths the folding
+    experiment uses), pairing table rna_pair_table(), minimum hairpin loop
+    min_loop, X-drop threshold xdrop (< 0: unpruned) after `warmup` spans."""
+    st = Stream(seed, 1)
+    lens = st.integers(min_len, max_len, n).astype(np.int32)
+    codes = (st.u64(int(lens.sum())) & np.uint64(3)).astype(np.uint8)
+    off = np.zeros(n, dtype=np.int64)
+    if n > 1:
+        off[1:] = np.cumsum(lens[:-1], dtype=np.int64)
+    b = FoldBatch(f"rna_fold_x{xdrop}", codes, off, lens, rna_pair_table(), int(min_loop),
+                  int(xdrop), int(warmup))
+    b.meta = dict(seed=seed, min_len=min_len, max_len=max_len)
+    return b
+
+
 WORKLOADS = {
     "nw_dna_1k": nw_dna_1k,
     "sw_protein": sw_protein,
