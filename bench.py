@@ -110,6 +110,10 @@ WORKLOAD_DESC = {
                     "cell, walk)"),
     "edit_search": ("unit-cost edit distance by the score-major search schedule (Sec. 6.3), "
                     "4,096 pairs of 2,000 bp at 5% divergence; score (= -edit distance)"),
+    "rna_fold": ("Nussinov RNA folding (the folding recurrence of Sec. 3) with X-drop "
+                 "transferred to it (Sec. 9.5): 4,096 synthetic RNAs of 76-500 nt, one point "
+                 "per A-U / C-G / G-U pair, minimum loop 3, X = 2 after a warm-up of 15 spans; "
+                 "the same sequences unpruned beside it"),
     "affine_search": ("gap-affine penalties (mismatch 4, open 6, extend 2) by the score-major "
                       "search schedule, the edit_search pair shape (4,096 pairs of 2,000 bp at "
                       "5% divergence, other seed); score (= -smallest penalty)"),
@@ -485,6 +489,126 @@ def summarize(r):
     return rec
 
 
+def run_fold(args, cpu_seconds, check_seconds, machine):
+    """Nussinov folding with X-drop (and the same sequences unpruned): cells
+    and bifurcation terms per second, the kernel's roofline (one add and one
+    max per term), the oracle beside it, and every sequence checked."""
+    import torch
+    import oracle
+    from paper_2607_06225_amd import aln
+    from paper_2607_06225_amd import workloads as W
+
+    ctx = aln.Context(0)
+    stream = torch.cuda.current_stream()
+    fbx = W.rna_fold()
+    out = dict(workload="rna_fold", desc=WORKLOAD_DESC["rna_fold"], sequences=fbx.n,
+               lengths=[int(fbx.length.min()), int(fbx.length.max())])
+    runs = {}
+    for tag, fb in (("xdrop", fbx), ("unpruned", fbx.with_params(xdrop=-1))):
+        plan = aln.fold_plan(ctx, fb)
+        fdb = aln.FoldDeviceBatch(fb)
+        ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device="cuda")
+        res = torch.zeros(fb.n * aln.FOLD_RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        for _ in range(args.warmup):
+            aln.fold_execute(ctx, plan, fdb, ws, res, stream=stream)
+        torch.cuda.synchronize()
+        ctx.kernel_times()
+        ctx.set_profiling(True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        ev[0].record(stream)
+        for k in range(args.steps):
+            aln.fold_execute(ctx, plan, fdb, ws, res, stream=stream)
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        ctx.set_profiling(False)
+        kt = ctx.kernel_times()
+        per_step = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+        ms = ev[0].elapsed_time(ev[-1]) / args.steps
+        r = np.frombuffer(res.cpu().numpy().tobytes(), dtype=aln.FOLD_RESULT_DTYPE, count=fb.n).copy()
+        cells, terms = int(r["cells"].sum()), int(r["terms"].sum())
+        kms, launches = kt["fold"][0] / args.steps, kt["fold"][1] / args.steps
+        by_class = dict(add=1, max=1)
+        rates = (machine or {}).get("issue_rates", {})
+        clk = (machine or {}).get("clock_ghz")
+        achieved = terms * 2 / (kms * 1e-3) / 1e12
+        peak = mix_peak_tops(by_class, rates, "i32", SPEC_CLOCK_GHZ)
+        roof = dict(bound="alu", achieved=round(achieved, 3), peak=round(peak, 2), unit="TOP/s",
+                    frac=round(achieved / peak, 4), traffic=None, kernel="fold",
+                    ops_per_term=2, ops_by_class=by_class, launches_per_step=launches,
+                    avg_launch_ms=round(kms / max(launches, 1), 4),
+                    note="achieved = bifurcation terms x 2 (add, max) / fold kernel time; the "
+                         "kernel also spends two address adds and two LDS reads per term")
+        if clk:
+            pk = mix_peak_tops(by_class, rates, "i32", clk)
+            roof.update(clock_ghz_measured=round(clk, 3), frac_at_measured_clock=round(achieved / pk, 4))
+        runs[tag] = dict(ms_per_step=round(ms, 4), step_ms_trimmed_mean=round(trimmed_mean(per_step), 4),
+                         kernel_ms_per_step=round(kms, 4), cells=cells, terms=terms,
+                         gcups=round(cells / (ms * 1e-3) / 1e9, 3),
+                         gterms_per_s=round(terms / (ms * 1e-3) / 1e9, 2),
+                         sequences_per_s=round(fb.n / (ms * 1e-3), 1), roofline=roof,
+                         results=r, batch=fb)
+        plan.close()
+        log(f"[bench] rna_fold {tag}: {ms:.3f} ms, {runs[tag]['gterms_per_s']} Gterms/s")
+    rx, ru = runs["xdrop"]["results"], runs["unpruned"]["results"]
+    out["xdrop_equals_unpruned"] = round(float(np.mean(rx["score"] == ru["score"])), 4)
+    out["xdrop_cells_fraction"] = round(runs["xdrop"]["cells"] / max(runs["unpruned"]["cells"], 1), 4)
+    out["xdrop_speedup"] = round(runs["unpruned"]["ms_per_step"] / runs["xdrop"]["ms_per_step"], 3)
+    # the oracle: CPU baseline on a sample (paper's protocol), then every
+    # sequence of both runs checked
+    if cpu_seconds > 0:
+        cores, nproc, quota, model = host_cores()
+        fb = runs["xdrop"]["batch"]
+
+        def ofold(b, nthreads):
+            return oracle.fold_batch(b.pair, b.x, b.off, b.length, min_loop=b.min_loop,
+                                     xdrop=b.xdrop, warmup=b.warmup, nthreads=nthreads)
+        t0 = time.perf_counter()
+        o0 = ofold(fb.subset(np.arange(64)), cores)
+        rate = float(o0["terms"].sum()) / max(time.perf_counter() - t0, 1e-3)
+        cum = np.cumsum(rx["terms"].astype(np.float64))
+        k = max(64, min(fb.n, int(np.searchsorted(cum, rate * cpu_seconds / 10)) + 1))
+        sub = fb.subset(np.arange(k))
+        times = []
+        for _ in range(10):
+            t0 = time.perf_counter()
+            o = ofold(sub, cores)
+            times.append(time.perf_counter() - t0)
+        dt = trimmed_mean(times)
+        k1 = max(1, k // 10)
+        t0 = time.perf_counter()
+        o1 = ofold(fb.subset(np.arange(k1)), 1)
+        dt1 = time.perf_counter() - t0
+        out["cpu_baseline"] = dict(
+            value=round(float(o["cells"].sum()) / dt / 1e9, 4), unit="GCUPS", cores=cores,
+            kind="oracle", gterms_per_s=round(float(o["terms"].sum()) / dt / 1e9, 3),
+            sample=f"first {k} of {fb.n} sequences (X-drop), trimmed mean of 10 runs on "
+                   f"{cores} host threads", seconds=round(dt, 3), nproc=nproc,
+            cgroup_cpu_quota=quota, cpu_model=model,
+            single_core=dict(value=round(float(o1["cells"].sum()) / dt1 / 1e9, 4),
+                             gterms_per_s=round(float(o1["terms"].sum()) / dt1 / 1e9, 3),
+                             sample=f"first {k1} sequences, one run"))
+    if check_seconds > 0:
+        for tag in ("xdrop", "unpruned"):
+            b, r = runs[tag]["batch"], runs[tag]["results"]
+            o = oracle.fold_batch(b.pair, b.x, b.off, b.length, min_loop=b.min_loop,
+                                  xdrop=b.xdrop, warmup=b.warmup, nthreads=host_cores()[0])
+            mism = [p for p in range(b.n)
+                    if any(int(r[f][p]) != int(o[f][p]) for f in ("score", "i", "j", "cells",
+                                                                    "terms", "full"))]
+            runs[tag]["bit_exact_check"] = dict(pairs=b.n, of=b.n, sample="every sequence",
+                                                mismatches=len(mism), first=mism[:3])
+    for tag in runs:
+        runs[tag].pop("results")
+        runs[tag].pop("batch")
+    out.update(runs)
+    # the line-level fields the summary reads: the X-drop run
+    x = runs["xdrop"]
+    out.update(gcups=x["gcups"], ms_per_step=x["ms_per_step"], roofline=x["roofline"],
+               pairs=fbx.n, bit_exact_check=x.get("bit_exact_check"), per_pair=None)
+    ctx.close()
+    return out
+
+
 def run_edit_table(args):
     """Unit-cost edit distance at the lengths and divergences of the paper's
     table (Sec. 9.1): the same pairs through the score-major search schedule
@@ -610,7 +734,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="xdrop_ext", choices=sorted(WORKLOAD_DESC),
+    ap.add_argument("--workload", default="xdrop_ext",
+                    choices=sorted(k for k in WORKLOAD_DESC if k != "rna_fold"),
                     help="headline workload (the JSON line's value)")
     ap.add_argument("--edit-table-pairs", type=int, default=1024,
                     help="pairs per cell of the edit-distance table (0: skip the table)")
@@ -618,7 +743,7 @@ def main():
                     help="pairs per cell checked against the CPU oracle")
     ap.add_argument("--configs",
                     default="sw_protein,nw_dna_1k,band_long,zdrop_ext,xdrop_cigar,edit_search,"
-                            "affine_search",
+                            "affine_search,rna_fold",
                     help="comma list of further workloads to measure, or 'none'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
@@ -698,6 +823,10 @@ def main():
     configs = {}
     for c in extras:
         if c == args.workload:
+            continue
+        if c == "rna_fold":
+            configs[c] = run_fold(args, 0 if args.no_cpu_baseline else args.extra_cpu_seconds,
+                                  args.extra_check_seconds, machine)
             continue
         log(f"[bench] generating {c}")
         t0 = time.perf_counter()

@@ -336,7 +336,9 @@ typedef struct {
   int32_t min_loop; /* >= 0                                                 */
   int32_t xdrop;    /* < 0: unpruned; else X                                */
   int32_t warmup;   /* spans t <= warmup are never pruned (>= 0)            */
-  int32_t reserved; /* 0                                                    */
+  int32_t block;    /* threads per workgroup: 256, 512 or 1024; 0: about 16
+                       wavefronts per CU (a tuning choice: results do not
+                       depend on it)                                        */
 } aln_fold_params;  /* 80 bytes */
 
 typedef struct {
@@ -352,18 +354,20 @@ typedef struct {
                        the smallest i                                       */
   int32_t full;     /* 1 when (0, n-1) was evaluated and kept               */
   int64_t cells;    /* cells evaluated with span >= 1                       */
+  int64_t terms;    /* their bifurcation terms (a cell of span t has t)     */
   int32_t status;   /* ALN_R_OK, or ALN_R_BAD_SYMBOL (a code > 3)          */
   int32_t reserved;
-} aln_fold_result;  /* 32 bytes */
+} aln_fold_result;  /* 40 bytes */
 
 /* Plan a folding batch from its host-side lengths: one workgroup per
  * sequence with the whole triangle in LDS (one byte per cell when every
  * score fits 0..253, else two), sequences grouped by LDS size and run
  * longest first.  Reports the workspace (the uploaded task list) in
  * fp->workspace_bytes and the unpruned cell count in fp->cells.
- * ALN_E_UNSUPPORTED when a sequence's triangle cannot fit 160 KB of LDS
- * (about 570 nt with one-byte scores, 400 nt with two-byte ones) or its
- * scores could exceed 32767.  Destroy with aln_plan_destroy. */
+ * ALN_E_UNSUPPORTED when a sequence is longer than 511 nt, or longer than
+ * 383 nt with scores that need two bytes (its triangle would not fit 160 KB
+ * of LDS), or its scores could exceed 32767.  Destroy with
+ * aln_plan_destroy. */
 aln_status aln_fold_plan_create(aln_ctx *ctx, const aln_fold_params *params, int32_t n,
                                 const int32_t *len_host, aln_plan **plan, aln_footprint *fp);
 /* Run a folding plan on a batch with the lengths it was planned with.

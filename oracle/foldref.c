@@ -77,7 +77,7 @@ int foldref_fold(const int32_t *pair, int32_t min_loop, int32_t xdrop, int32_t w
   int64_t best = 0;
   int32_t bi = 0, bj = 0; /* best cell so far: F = 0 at the largest span 0, smallest i */
   int32_t lo = 0, hi = n - 1;
-  int64_t cells = 0;
+  int64_t cells = 0, terms = 0;
   for (int32_t t = 1; t < n; t++) {
     int32_t a = lo - 1, b = hi;
     if (a < 0) a = 0;
@@ -102,6 +102,7 @@ int foldref_fold(const int32_t *pair, int32_t min_loop, int32_t xdrop, int32_t w
         if (l > NEG && r > NEG) v = max2(v, l + r);
       }
       cells++;
+      terms += t;
       int keep = v > NEG;
       if (keep && prune && best - v > (int64_t)xdrop) keep = 0;
       F[(size_t)i * n + j] = v;
@@ -130,6 +131,7 @@ int foldref_fold(const int32_t *pair, int32_t min_loop, int32_t xdrop, int32_t w
   out->i = bi;
   out->j = bj;
   out->cells = cells;
+  out->terms = terms;
   out->full = (n == 1) || alive[(size_t)0 * n + (n - 1)];
   free(F);
   free(alive);

@@ -34,6 +34,7 @@ typedef struct {
   int64_t score;  /* best surviving F                                      */
   int32_t i, j;   /* its interval (largest span, then smallest i, on ties) */
   int64_t cells;  /* cells evaluated with span t >= 1                       */
+  int64_t terms;  /* bifurcation terms of those cells (span t: t terms each) */
   int32_t full;   /* 1 when the whole sequence (0, n-1) was evaluated and kept */
   int32_t status; /* 0, or -1 (bad arguments) / -2 (allocation failed)      */
 } foldref_out;

@@ -17,11 +17,13 @@ NO_XDROP = -1
 
 class FoldrefOut(ctypes.Structure):
     _fields_ = [("score", ctypes.c_int64), ("i", ctypes.c_int32), ("j", ctypes.c_int32),
-                ("cells", ctypes.c_int64), ("full", ctypes.c_int32), ("status", ctypes.c_int32)]
+                ("cells", ctypes.c_int64), ("terms", ctypes.c_int64), ("full", ctypes.c_int32),
+                ("status", ctypes.c_int32)]
 
 
 FOLD_DTYPE = np.dtype([("score", np.int64), ("i", np.int32), ("j", np.int32),
-                       ("cells", np.int64), ("full", np.int32), ("status", np.int32)])
+                       ("cells", np.int64), ("terms", np.int64), ("full", np.int32),
+                       ("status", np.int32)])
 assert FOLD_DTYPE.itemsize == ctypes.sizeof(FoldrefOut)
 
 
@@ -31,7 +33,7 @@ def _pair(pair):
 
 
 def fold(pair, x, min_loop=0, xdrop=NO_XDROP, warmup=15):
-    """Fold one sequence; returns a dict (score, i, j, cells, full, status)."""
+    """Fold one sequence; returns a dict (score, i, j, cells, terms, full, status)."""
     lib = load()
     p = _pair(pair)
     xa = _u8(x)
@@ -39,7 +41,7 @@ def fold(pair, x, min_loop=0, xdrop=NO_XDROP, warmup=15):
     lib.foldref_fold(_ptr(p), int(min_loop), int(xdrop), int(warmup),
                      _ptr(xa) if xa.size else None, int(xa.size), ctypes.byref(out))
     return dict(score=int(out.score), i=int(out.i), j=int(out.j), cells=int(out.cells),
-                full=int(out.full), status=int(out.status))
+                terms=int(out.terms), full=int(out.full), status=int(out.status))
 
 
 def fold_batch(pair, x, off, length, min_loop=0, xdrop=NO_XDROP, warmup=15, nthreads=None):

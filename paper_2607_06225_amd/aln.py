@@ -53,7 +53,7 @@ class _Batch(ctypes.Structure):
 class _FoldParams(ctypes.Structure):
     _fields_ = [("pair", ctypes.c_int32 * 16), ("min_loop", ctypes.c_int32),
                 ("xdrop", ctypes.c_int32), ("warmup", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("block", ctypes.c_int32)]
 
 
 class _FoldBatch(ctypes.Structure):
@@ -62,8 +62,9 @@ class _FoldBatch(ctypes.Structure):
 
 
 FOLD_RESULT_DTYPE = np.dtype([("score", "<i4"), ("i", "<i4"), ("j", "<i4"), ("full", "<i4"),
-                              ("cells", "<i8"), ("status", "<i4"), ("reserved", "<i4")])
-assert FOLD_RESULT_DTYPE.itemsize == 32
+                              ("cells", "<i8"), ("terms", "<i8"), ("status", "<i4"),
+                              ("reserved", "<i4")])
+assert FOLD_RESULT_DTYPE.itemsize == 40
 
 
 class _Footprint(ctypes.Structure):
@@ -378,19 +379,19 @@ class FoldDeviceBatch:
         self.c = _FoldBatch(self.n, self.x.data_ptr(), self.off.data_ptr(), self.len.data_ptr())
 
 
-def fold_params(pair, min_loop=0, xdrop=-1, warmup=15):
+def fold_params(pair, min_loop=0, xdrop=-1, warmup=15, block=0):
     p = _FoldParams()
     flat = np.asarray(pair, dtype=np.int32).reshape(16)
     for k in range(16):
         p.pair[k] = int(flat[k])
-    p.min_loop, p.xdrop, p.warmup, p.reserved = int(min_loop), int(xdrop), int(warmup), 0
+    p.min_loop, p.xdrop, p.warmup, p.block = int(min_loop), int(xdrop), int(warmup), int(block)
     return p
 
 
-def fold_plan(ctx, fb, len_host=None):
+def fold_plan(ctx, fb, len_host=None, block=0):
     """aln_fold_plan_create for a workloads.FoldBatch (its parameters and lengths)."""
     lens = np.ascontiguousarray(fb.length if len_host is None else len_host, dtype=np.int32)
-    params = fold_params(fb.pair, fb.min_loop, fb.xdrop, fb.warmup)
+    params = fold_params(fb.pair, fb.min_loop, fb.xdrop, fb.warmup, block)
     h = ctypes.c_void_p()
     fp = _Footprint()
     ctx._check(ctx.lib.aln_fold_plan_create(ctx.handle, ctypes.byref(params), int(lens.size),
@@ -403,10 +404,10 @@ def fold_execute(ctx, plan, fdb, ws, res, stream=None):
                                         int(ws.numel()), _ptr(res), _stream_handle(stream)))
 
 
-def fold(ctx, fb, stream=None):
+def fold(ctx, fb, stream=None, block=0):
     """Plan and run one workloads.FoldBatch; returns the results ndarray."""
     import torch
-    plan = fold_plan(ctx, fb)
+    plan = fold_plan(ctx, fb, block=block)
     fdb = FoldDeviceBatch(fb)
     ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device="cuda")
     res = torch.zeros(max(fb.n, 1) * FOLD_RESULT_DTYPE.itemsize, dtype=torch.uint8, device="cuda")

@@ -1088,36 +1088,35 @@ aln_status aln_fold_plan_create(aln_ctx *ctx, const aln_fold_params *params, int
     maxpair = std::max(maxpair, p.pair[k]);
   }
   if (p.min_loop < 0 || p.warmup < 0) return fail(ctx, ALN_E_INVAL, "min_loop and warmup >= 0");
+  if (p.block != 0 && p.block != 256 && p.block != 512 && p.block != 1024)
+    return fail(ctx, ALN_E_INVAL, "block must be 0, 256, 512 or 1024");
   // LDS of one CU, less the kernel's few static words
   const int64_t lds_max = std::min<int64_t>(ctx->lds_per_cu, 160 * 1024) - 256;
-  // element width per sequence: one byte when every score fits 0..253 (255
-  // marks minus infinity), else two.  Under X-drop a one-byte term costs one
-  // more instruction, so two bytes are kept while they leave room for two
-  // workgroups per CU.
+  // Per sequence: the row stride of its folded triangle (the smallest of
+  // kFoldStrides above its length) and the element width (one byte when
+  // every score fits 0..253 -- 255 marks minus infinity -- else two).
   struct Cls {
-    int elt, lds_class;
+    int elt, stride;
   };
   std::vector<Cls> cls(n);
   for (int32_t s = 0; s < n; ++s) {
     const int32_t L = len_host[s];
     if (L < 0) return fail(ctx, ALN_E_INVAL, "negative length");
+    int stride = 0;
+    for (int sc : alnk::kFoldStrides)
+      if (L + 1 <= sc) {
+        stride = sc;
+        break;
+      }
     const int64_t maxF = (int64_t)maxpair * (L / 2);
-    const bool u8 = maxF <= 253 && (int64_t)alnk::fold_lds_bytes(1, L) <= lds_max;
-    const bool i16 = maxF <= 32767 && (int64_t)alnk::fold_lds_bytes(2, L) <= lds_max;
-    int elt;
-    if (p.xdrop >= 0)
-      elt = (i16 && (int64_t)alnk::fold_lds_bytes(2, L) <= lds_max / 2) || !u8 ? 2 : 1;
-    else
-      elt = u8 ? 1 : 2;
-    if ((elt == 1 && !u8) || (elt == 2 && !i16))
+    const bool u8 = stride && maxF <= 253 && (int64_t)alnk::fold_lds_bytes(1, stride, L) <= lds_max;
+    const bool i16 =
+        stride && maxF <= 32767 && (int64_t)alnk::fold_lds_bytes(2, stride, L) <= lds_max;
+    if (!u8 && !i16)
       return fail(ctx, ALN_E_UNSUPPORTED,
-                  "sequence %d (%d nt): its triangle does not fit LDS, or its scores exceed 32767",
-                  s, L);
-    // LDS classes: workgroups per CU 8, 4, 2, 1
-    const int64_t lds = (int64_t)alnk::fold_lds_bytes(elt, L);
-    int c = 0;
-    while (c < 3 && lds > lds_max >> (3 - c)) ++c;
-    cls[s] = Cls{elt, c};
+                  "sequence %d (%d nt): longer than 511, or its triangle does not fit LDS, or "
+                  "its scores could exceed 32767", s, L);
+    cls[s] = Cls{u8 ? 1 : 2, stride};
   }
   aln_plan *pl = new (std::nothrow) aln_plan;
   if (!pl) return fail(ctx, ALN_E_NOMEM, "plan allocation");
@@ -1126,24 +1125,29 @@ aln_status aln_fold_plan_create(aln_ctx *ctx, const aln_fold_params *params, int
   pl->fold = true;
   pl->fold_p = p;
   pl->qlen.assign(len_host, len_host + n);
-  // launches: largest LDS class first; within a launch the longest sequence
-  // first (LPT)
+  // one launch per (stride, width), the widest rows first; within a launch
+  // the longest sequence first (LPT).  Threads per workgroup so that the
+  // workgroups LDS lets share a CU hold about 16 wavefronts.
   int64_t cells = 0;
-  for (int c = 3; c >= 0; --c) {
+  for (int si = 3; si >= 0; --si) {
     for (int elt = 2; elt >= 1; --elt) {
+      const int stride = alnk::kFoldStrides[si];
       std::vector<int32_t> idx;
       int32_t max_n = 0;
       for (int32_t s = 0; s < n; ++s)
-        if (cls[s].lds_class == c && cls[s].elt == elt) {
+        if (cls[s].stride == stride && cls[s].elt == elt) {
           idx.push_back(s);
           max_n = std::max(max_n, len_host[s]);
         }
       if (idx.empty()) continue;
       std::stable_sort(idx.begin(), idx.end(),
                        [&](int32_t x, int32_t y) { return len_host[x] > len_host[y]; });
+      const int64_t lds = (int64_t)alnk::fold_lds_bytes(elt, stride, max_n);
+      const int64_t per_cu = std::max<int64_t>(1, lds_max / std::max<int64_t>(lds, 1));
       aln_plan::FoldLaunch L;
       L.elt = elt;
-      L.block = c == 3 ? 1024 : (c == 2 ? 512 : 256);
+      L.stride = stride;
+      L.block = p.block ? p.block : (per_cu >= 4 ? 256 : (per_cu >= 2 ? 512 : 1024));
       L.first = (int32_t)pl->fold_tasks.size();
       L.count = (int32_t)idx.size();
       L.max_n = max_n;
@@ -1201,7 +1205,9 @@ aln_status aln_fold_execute(aln_ctx *ctx, aln_plan *plan, const aln_fold_batch *
     a.tasks = tasks + L.first;
     a.ntasks = L.count;
     a.max_n = L.max_n;
-    HIP_TRY(ctx, timed_launch(ctx, "fold", st, [&] { return alnk::launch_fold(L.elt, L.block, a, st); }));
+    HIP_TRY(ctx, timed_launch(ctx, "fold", st, [&] {
+              return alnk::launch_fold(L.elt, L.block, L.stride, a, st);
+            }));
   }
   return ALN_OK;
 }

@@ -184,8 +184,10 @@ struct FoldArgs {
   int32_t max_n;     // longest sequence of the launch (LDS size)
   aln_fold_result *res;
 };
-// LDS bytes of one folding workgroup for sequences up to max_n long.
-size_t fold_lds_bytes(int elt_bytes, int max_n);
+// Row strides (elements) of the folded triangle, and the LDS bytes of one
+// folding workgroup for sequences up to max_n long (stride >= max_n + 1).
+constexpr int kFoldStrides[4] = {128, 256, 384, 512};
+size_t fold_lds_bytes(int elt_bytes, int stride, int max_n);
 
 // Launchers (defined in the kernel translation units).
 hipError_t launch_validate(const ValidateArgs &a, hipStream_t s);
@@ -199,7 +201,8 @@ hipError_t launch_diag(int rows, int mode, int prune, bool tb, const DiagArgs &a
 hipError_t launch_xdrop_group(int prune, const DiagArgs &a, hipStream_t s);
 hipError_t launch_walk_diag(const WalkArgs &a, hipStream_t s);
 hipError_t launch_search(const SearchArgs &a, hipStream_t s);
-// elt_bytes 1 (uint8 triangle) or 2 (int16); block 256, 512 or 1024 threads
-hipError_t launch_fold(int elt_bytes, int block, const FoldArgs &a, hipStream_t s);
+// elt_bytes 1 (uint8 triangle) or 2 (int16); block 256, 512 or 1024 threads;
+// stride one of kFoldStrides
+hipError_t launch_fold(int elt_bytes, int block, int stride, const FoldArgs &a, hipStream_t s);
 
 } // namespace alnk

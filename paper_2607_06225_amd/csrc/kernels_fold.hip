@@ -14,22 +14,25 @@
 // triangle's wavefronts; with rows flipped they are its antidiagonals, which
 // the pruning rule of Sec. 9.5 counts) with a barrier between them.
 //
-// Storage: the whole triangle lives in LDS in sheared, span-major order,
-// G[t][p] = F(p, p+t) at element rowoff(t) + p, rowoff(t) = t*n - t(t-1)/2.
-// For cell (i, i+t) the term of split k = i+u reads G[u][i] and
-// G[t-1-u][i+u+1]: as lanes take consecutive cells i, both reads are
-// consecutive elements across the wave (no bank conflicts), and with the
-// loop over u the same for every lane the row offsets stay in scalar
-// registers.  Elements are int16 (minus infinity = -32768) or, when every
-// score fits, uint8 (254 at most; 255 is minus infinity), which halves LDS
-// so that 500-nt sequences fit and more short sequences share a CU.
+// Storage: the whole triangle lives in LDS, folded into ceil(n/2) rows of a
+// compile-time stride SC >= n + 1: row v holds span v (positions 0 .. n-1-v)
+// followed by span n-1-v (positions 0 .. v), so F(p, p+t) sits at
+//   t <  ceil(n/2):  t*SC + p
+//   t >= ceil(n/2):  (n-1-t)*SC + t + 1 + p.
+// For cell (i, i+t) the term of split k = i+u reads F(i, i+u) (span u,
+// position i) and F(i+u+1, i+t) (span t-1-u, position i+u+1).  As u steps by
+// one, each of the two addresses moves by SC (its span in the upper half of
+// the rows, resp. the lower) or by 1 - SC: between the two break points u =
+// ceil(n/2) and u = t - ceil(n/2) both steps are compile-time constants, so
+// a block of eight splits reads with immediate offsets from two address
+// registers and costs an add and a max per term.  Lanes take consecutive
+// cells i, so the reads of a wave are consecutive bytes.  Elements are int16
+// (minus infinity = -32768) or, when every score fits, uint8 (at most 253;
+// 255 is minus infinity), which halves LDS so that 500-nt sequences fit a CU.
 //
-// Work split per wavefront: each wave takes 64*CPL consecutive cells (CPL =
-// 1, 2 or 4 cells per lane, the cells of a lane adjacent so their reads share
-// one address register); when there are fewer cell chunks than waves, the
-// u-range of each chunk is split among waves and their partial maxima meet in
-// LDS (one more barrier).  CPL and the split are chosen per span for the
-// fewest instructions on the busiest wave.
+// Work split per wavefront: each wave takes 64 consecutive cells; when there
+// are fewer such chunks than waves, the u-range of each chunk is split among
+// waves and their partial maxima meet in LDS (one more barrier).
 //
 // X-drop (Sec. 7.2 rule, Sec. 9.5 transfer): candidates of span t are the
 // positions from one before the first survivor of span t-1 to its last
@@ -81,54 +84,102 @@ template <> struct FoldElt<uint8_t, true> {
   static constexpr int kAccInit = -1;
 };
 
-__device__ __forceinline__ int rowoff(int t, int n) { return t * n - ((t * (t - 1)) >> 1); }
+// Maximum / minimum over the wave by DPP (prefix within each 16-lane row,
+// then across rows); lane 63 ends with the result.  Lanes without a source
+// read the identity.
+__device__ __forceinline__ int fold_wave_max(int v) {
+  constexpr int id = INT32_MIN;
+  v = max(v, __builtin_amdgcn_update_dpp(id, v, 0x111, 0xf, 0xf, false)); // row_shr:1
+  v = max(v, __builtin_amdgcn_update_dpp(id, v, 0x112, 0xf, 0xf, false)); // row_shr:2
+  v = max(v, __builtin_amdgcn_update_dpp(id, v, 0x114, 0xf, 0xf, false)); // row_shr:4
+  v = max(v, __builtin_amdgcn_update_dpp(id, v, 0x118, 0xf, 0xf, false)); // row_shr:8
+  v = max(v, __builtin_amdgcn_update_dpp(id, v, 0x142, 0xa, 0xf, false)); // row_bcast:15
+  v = max(v, __builtin_amdgcn_update_dpp(id, v, 0x143, 0xc, 0xf, false)); // row_bcast:31
+  return v;
+}
+__device__ __forceinline__ int fold_wave_min(int v) {
+  constexpr int id = INT32_MAX;
+  v = min(v, __builtin_amdgcn_update_dpp(id, v, 0x111, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(id, v, 0x112, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(id, v, 0x114, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(id, v, 0x118, 0xf, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(id, v, 0x142, 0xa, 0xf, false));
+  v = min(v, __builtin_amdgcn_update_dpp(id, v, 0x143, 0xc, 0xf, false));
+  return v;
+}
 
 } // namespace
 
-// Partial maxima of CPL adjacent cells i0 .. i0+CPL-1 (span t) over splits u
-// in [u0, u1): acc[m] = max over u of term(G[u][i0+m], G[t-1-u][i0+m+u+1]).
-template <typename T, bool XD, int CPL>
-__device__ __forceinline__ void fold_partial(const T *G, int n, int t, int i0, int u0, int u1,
-                                             int (&acc)[CPL]) {
-  using E = FoldElt<T, XD>;
-  int accb[CPL];
-#pragma unroll
-  for (int m = 0; m < CPL; ++m) {
-    acc[m] = E::kAccInit;
-    accb[m] = E::kAccInit;
-  }
-  // scalar row offsets of the two operands, stepped with u
-  int r1 = rowoff(u0, n);          // G[u]
-  int r2 = rowoff(t - 1 - u0, n);  // G[t-1-u]
-  int u = u0;
-  // two splits per iteration into separate accumulators (shorter max chains)
-  for (; u + 1 < u1; u += 2) {
-    const T *a1 = G + r1 + i0;
-    const T *b1 = G + r2 + i0 + u + 1;
-    const int r1n = r1 + (n - u);
-    const int w = t - 1 - u;
-    const int r2n = r2 - (n - w + 1);
-    const T *a2 = G + r1n + i0;
-    const T *b2 = G + r2n + i0 + u + 2;
-#pragma unroll
-    for (int m = 0; m < CPL; ++m) {
-      acc[m] = max(acc[m], E::term((int)a1[m], (int)b1[m]));
-      accb[m] = max(accb[m], E::term((int)a2[m], (int)b2[m]));
-    }
-    r1 = r1n + (n - u - 1);
-    r2 = r2n - (n - w + 2);
-  }
-  if (u < u1) {
-    const T *a1 = G + r1 + i0;
-    const T *b1 = G + r2 + i0 + u + 1;
-#pragma unroll
-    for (int m = 0; m < CPL; ++m) acc[m] = max(acc[m], E::term((int)a1[m], (int)b1[m]));
-  }
-#pragma unroll
-  for (int m = 0; m < CPL; ++m) acc[m] = max(acc[m], accb[m]);
+// Element index of F(p, p+u) in the folded triangle (H = ceil(n/2)).
+template <int SC>
+__device__ __forceinline__ int fold_at(int u, int p, int n, int H) {
+  return u < H ? u * SC + p : (n - 1 - u) * SC + u + 1 + p;
 }
 
-template <typename T, bool XD, int B>
+// cnt splits with compile-time address steps D1 / D2, eight per block from
+// the block's lowest address (immediate offsets), into two accumulators.
+template <typename T, bool XD, int D1, int D2>
+__device__ __forceinline__ void fold_run(const T *G, int &a1, int &a2, int cnt, int &acc0,
+                                         int &acc1) {
+  using E = FoldElt<T, XD>;
+  constexpr int U = 8;
+  for (; cnt >= U; cnt -= U) {
+    // the block's lowest addresses; the empty asm keeps the compiler from
+    // folding them back into one add per read (DS offsets are unsigned)
+    int b1 = D1 > 0 ? a1 : a1 + (U - 1) * D1;
+    int b2 = D2 > 0 ? a2 : a2 + (U - 1) * D2;
+    asm volatile("" : "+v"(b1), "+v"(b2));
+    const T *p1 = G + b1;
+    const T *p2 = G + b2;
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int o1 = D1 > 0 ? k * D1 : (U - 1 - k) * -D1;
+      const int o2 = D2 > 0 ? k * D2 : (U - 1 - k) * -D2;
+      const int tv = E::term((int)p1[o1], (int)p2[o2]);
+      if (k & 1) acc1 = max(acc1, tv);
+      else acc0 = max(acc0, tv);
+    }
+    a1 += U * D1;
+    a2 += U * D2;
+  }
+  for (; cnt > 0; --cnt) {
+    acc0 = max(acc0, E::term((int)G[a1], (int)G[a2]));
+    a1 += D1;
+    a2 += D2;
+  }
+}
+
+// Maximum over splits u in [u0, u1) of the bifurcation terms of cell (i, i+t).
+template <typename T, bool XD, int SC>
+__device__ __forceinline__ int fold_partial(const T *G, int n, int H, int t, int i, int u0,
+                                            int u1) {
+  using E = FoldElt<T, XD>;
+  int acc0 = E::kAccInit, acc1 = E::kAccInit;
+  int u = u0;
+  int a1 = fold_at<SC>(u, i, n, H), a2 = fold_at<SC>(t - 1 - u, i + u + 1, n, H);
+  while (u < u1) {
+    // the segment up to the next break point: span u leaves the upper rows
+    // at u = H, span t-1-u enters them at u = t - H
+    int e = u1;
+    if (u < H) e = min(e, H);
+    if (u < t - H) e = min(e, t - H);
+    const int cnt = e - u;
+    const bool top1 = u < H, top2 = t - 1 - u < H;
+    if (top1 && top2) fold_run<T, XD, SC, 1 - SC>(G, a1, a2, cnt, acc0, acc1);
+    else if (top1) fold_run<T, XD, SC, SC>(G, a1, a2, cnt, acc0, acc1);
+    else if (top2) fold_run<T, XD, 1 - SC, 1 - SC>(G, a1, a2, cnt, acc0, acc1);
+    else fold_run<T, XD, 1 - SC, SC>(G, a1, a2, cnt, acc0, acc1);
+    u = e;
+    // crossing a break point moves an address by other than its step
+    if (u < u1) {
+      a1 = fold_at<SC>(u, i, n, H);
+      a2 = fold_at<SC>(t - 1 - u, i + u + 1, n, H);
+    }
+  }
+  return max(acc0, acc1);
+}
+
+template <typename T, bool XD, int B, int SC>
 __global__ __launch_bounds__(B) void fold_kernel(FoldArgs a) {
   using E = FoldElt<T, XD>;
   constexpr int W = B / 64;
@@ -141,9 +192,10 @@ __global__ __launch_bounds__(B) void fold_kernel(FoldArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
 
-  // LDS: G (triangle) | codes | partial maxima (one int per cell of a span) |
-  // control
-  const int gbytes = (int)(((size_t)n * (n + 1) / 2 * sizeof(T) + 15) & ~(size_t)15);
+  // LDS: G (folded triangle) | codes | partial maxima (one int per cell of
+  // a span) | control
+  const int H = (n + 1) >> 1;
+  const int gbytes = (int)(((size_t)((a.max_n + 1) >> 1) * SC * sizeof(T) + 15) & ~(size_t)15);
   T *G = reinterpret_cast<T *>(smem);
   uint8_t *xs = smem + gbytes;
   int *red = reinterpret_cast<int *>(smem + gbytes + ((n + 15) & ~15));
@@ -166,9 +218,10 @@ __global__ __launch_bounds__(B) void fold_kernel(FoldArgs a) {
   if (mine) atomicOr(&bad, 1);
   // span 0: F(i,i) = 0; every longer span starts as minus infinity when
   // cells can be left unevaluated (X-drop)
-  for (int p = tid; p < n; p += B) G[p] = (T)0;
   if (XD)
-    for (int e = n + tid; e < n * (n + 1) / 2; e += B) G[e] = (T)E::kDead;
+    for (int e = tid; e < H * SC; e += B) G[e] = (T)E::kDead;
+  __syncthreads();
+  for (int p = tid; p < n; p += B) G[p] = (T)0; // span 0 (row 0, upper part)
   __syncthreads();
   if (bad || n <= 1) {
     if (tid == 0) {
@@ -177,6 +230,7 @@ __global__ __launch_bounds__(B) void fold_kernel(FoldArgs a) {
       res->j = 0;
       res->full = (!bad && n == 1) ? 1 : 0;
       res->cells = 0;
+      res->terms = 0;
       res->status = bad ? ALN_R_BAD_SYMBOL : ALN_R_OK;
       res->reserved = 0;
     }
@@ -185,7 +239,7 @@ __global__ __launch_bounds__(B) void fold_kernel(FoldArgs a) {
 
   int best = 0, bi = 0, bj = 0; // best cell through the last span (span 0: F = 0 at (0,0))
   int lo = 0, hi = n - 1;       // survivors of the last span
-  long long cells = 0;
+  long long cells = 0, terms = 0;
   int full = 0;
   const int X = a.xdrop;
   for (int t = 1; t < n; ++t) {
@@ -194,6 +248,7 @@ __global__ __launch_bounds__(B) void fold_kernel(FoldArgs a) {
     if (ca > cb) break;
     const int c = cb - ca + 1;
     cells += c;
+    terms += (long long)c * t;
     const int slot = t % kFoldCtlSlots;
     int *cs = ctl + 4 * slot;
     const bool prune = XD && t > a.warmup;
@@ -204,69 +259,44 @@ __global__ __launch_bounds__(B) void fold_kernel(FoldArgs a) {
       nx[1] = -1;
       nx[2] = -1;
     }
+    // this thread's survivors and best cell of the span, combined per wave
+    // (DPP) and then per workgroup (one LDS atomic per wave)
+    int my_lo = INT32_MAX, my_hi = -1, my_key = -1;
     // finish cell i of span t from its bifurcation maximum
     auto finish = [&](int i, int acc) {
       const int j = i + t;
-      const int in = (t == 1) ? 0 : (int)G[rowoff(t - 2, n) + i + 1];
+      const int in = (t == 1) ? 0 : (int)G[fold_at<SC>(t - 2, i + 1, n, H)];
       const int s = (j - i > a.min_loop) ? pair[xs[i] * 4 + xs[j]] : 0;
       int v = max(acc, E::inner(in, s));
       bool keep = E::live(v);
       const int f = keep ? E::value(v) : 0;
       if (keep && prune && best - f > X) keep = false;
-      G[rowoff(t, n) + i] = keep ? (T)f : (T)E::kDead;
+      G[fold_at<SC>(t, i, n, H)] = keep ? (T)f : (T)E::kDead;
       if (keep) {
-        if (XD) {
-          atomicMin(&cs[0], i);
-          atomicMax(&cs[1], i);
-        }
-        atomicMax(&cs[2], (f << 16) | (0xffff - i)); // highest F, then smallest i
+        my_lo = min(my_lo, i);
+        my_hi = max(my_hi, i);
+        my_key = max(my_key, (f << 16) | (0xffff - i)); // highest F, then smallest i
       }
     };
-    // cells per lane (CPL) and the split of each chunk's u-range among
-    // waves (S): the choice with the fewest instructions on the busiest
-    // wave, about (t / S) * (2 + 2 CPL) per item (two address adds per split
-    // plus an add and a max per cell)
-    int cpl = 1, chunks = 1, S = 1;
-    {
-      long long best_cost = -1;
-      for (int cand = 1; cand <= 4; cand *= 2) {
-        const int ch = (c + 64 * cand - 1) / (64 * cand);
-        int sp = 1;
-        long long cost;
-        if (ch >= W) {
-          cost = (long long)((ch + W - 1) / W) * t * (2 + 2 * cand);
-        } else {
-          sp = min(W / ch, t);
-          cost = (long long)((t + sp - 1) / sp) * (2 + 2 * cand);
-        }
-        if (best_cost < 0 || cost < best_cost) {
-          best_cost = cost;
-          cpl = cand;
-          chunks = ch;
-          S = sp;
-        }
-      }
-    }
-    const int chunk_cells = 64 * cpl;
+    // 64 cells per wave; when fewer chunks than waves, each chunk's
+    // u-range is cut into S = 2^ls pieces of len splits (shifts only: the
+    // scalar unit, shared by the CU's waves, has no divide)
+    const int chunks = (c + 63) >> 6;
+    const int cl = chunks > 1 ? 32 - __builtin_clz(chunks - 1) : 0; // ceil(log2(chunks))
+    const int ls = chunks >= W ? 0 : (31 - __builtin_clz(W)) - cl;
+    const int S = 1 << ls;
+    const int len = (t + S - 1) >> ls;
     int *rb = red;
     for (int item = wave; item < chunks * S; item += W) {
-      const int ch = item / S, seg = item - ch * S;
-      const int u0 = (int)((long long)seg * t / S), u1 = (int)((long long)(seg + 1) * t / S);
-      const int q0 = ch * chunk_cells + lane * cpl; // first cell of this lane
-      // lanes past the last cell read inside the triangle (clamped) and drop
-      // their result
-      const int qc = min(q0, c - cpl > 0 ? c - cpl : 0);
-      const int i0 = ca + qc;
-      int acc[4];
-      if (cpl == 4) fold_partial<T, XD, 4>(G, n, t, i0, u0, u1, reinterpret_cast<int(&)[4]>(acc));
-      else if (cpl == 2) fold_partial<T, XD, 2>(G, n, t, i0, u0, u1, reinterpret_cast<int(&)[2]>(acc));
-      else fold_partial<T, XD, 1>(G, n, t, i0, u0, u1, reinterpret_cast<int(&)[1]>(acc));
-      // acc[m] belongs to cell qc + m; a clamped lane owns cells q0 .. c-1
-      for (int m = 0; m < cpl; ++m) {
-        const int q = qc + m;
-        if (q < q0 || q >= c) continue;
-        if (S == 1) finish(ca + q, acc[m]);
-        else atomicMax(&rb[q], acc[m]);
+      const int ch = item >> ls, seg = item & (S - 1);
+      const int u0 = min(seg * len, t), u1 = min(u0 + len, t);
+      const int q = ch * 64 + lane;
+      // lanes past the last cell read inside the triangle and drop the result
+      const int i = ca + min(q, c - 1);
+      const int acc = fold_partial<T, XD, SC>(G, n, H, t, i, u0, u1);
+      if (q < c) {
+        if (S == 1) finish(ca + q, acc);
+        else atomicMax(&rb[q], acc);
       }
     }
     if (S > 1) {
@@ -274,6 +304,18 @@ __global__ __launch_bounds__(B) void fold_kernel(FoldArgs a) {
       for (int q = tid; q < c; q += B) {
         finish(ca + q, rb[q]);
         rb[q] = E::kAccInit; // ready for the next span (its atomics follow the barrier below)
+      }
+    }
+    {
+      const int wk = fold_wave_max(my_key);
+      const int wl = XD ? fold_wave_min(my_lo) : 0;
+      const int wh = XD ? fold_wave_max(my_hi) : 0;
+      if (lane == 63 && wk >= 0) {
+        if (XD) {
+          atomicMin(&cs[0], wl);
+          atomicMax(&cs[1], wh);
+        }
+        atomicMax(&cs[2], wk);
       }
     }
     __syncthreads();
@@ -301,20 +343,21 @@ __global__ __launch_bounds__(B) void fold_kernel(FoldArgs a) {
     res->j = bj;
     res->full = full;
     res->cells = cells;
+    res->terms = terms;
     res->status = ALN_R_OK;
     res->reserved = 0;
   }
 }
 
-size_t fold_lds_bytes(int elt_bytes, int max_n) {
-  return (((size_t)max_n * (max_n + 1) / 2 * elt_bytes + 15) & ~(size_t)15) +
+size_t fold_lds_bytes(int elt_bytes, int stride, int max_n) {
+  return (((size_t)((max_n + 1) / 2) * stride * elt_bytes + 15) & ~(size_t)15) +
          (((size_t)max_n + 15) & ~(size_t)15) + ((size_t)max_n + 4 * kFoldCtlSlots) * sizeof(int);
 }
 
-template <typename T, bool XD, int B>
+template <typename T, bool XD, int B, int SC>
 static hipError_t launch_fold_t(const FoldArgs &a, hipStream_t s) {
-  const size_t lds = fold_lds_bytes(sizeof(T), a.max_n);
-  auto kern = fold_kernel<T, XD, B>;
+  const size_t lds = fold_lds_bytes(sizeof(T), SC, a.max_n);
+  auto kern = fold_kernel<T, XD, B, SC>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -324,23 +367,37 @@ static hipError_t launch_fold_t(const FoldArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename T, bool XD>
-static hipError_t launch_fold_b(int block, const FoldArgs &a, hipStream_t s) {
-  switch (block) {
-  case 256: return launch_fold_t<T, XD, 256>(a, s);
-  case 512: return launch_fold_t<T, XD, 512>(a, s);
-  case 1024: return launch_fold_t<T, XD, 1024>(a, s);
+template <typename T, bool XD, int B>
+static hipError_t launch_fold_s(int stride, const FoldArgs &a, hipStream_t s) {
+  switch (stride) {
+  case 128: return launch_fold_t<T, XD, B, 128>(a, s);
+  case 256: return launch_fold_t<T, XD, B, 256>(a, s);
+  case 384: return launch_fold_t<T, XD, B, 384>(a, s);
+  case 512: return launch_fold_t<T, XD, B, 512>(a, s);
   default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_fold(int elt_bytes, int block, const FoldArgs &a, hipStream_t s) {
+template <typename T, bool XD>
+static hipError_t launch_fold_b(int block, int stride, const FoldArgs &a, hipStream_t s) {
+  switch (block) {
+  case 256: return launch_fold_s<T, XD, 256>(stride, a, s);
+  case 512: return launch_fold_s<T, XD, 512>(stride, a, s);
+  case 1024: return launch_fold_s<T, XD, 1024>(stride, a, s);
+  default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fold(int elt_bytes, int block, int stride, const FoldArgs &a, hipStream_t s) {
   if (a.ntasks <= 0) return hipSuccess;
+  if (a.max_n + 1 > stride) return hipErrorInvalidValue;
   const bool xd = a.xdrop >= 0;
   if (elt_bytes == 2)
-    return xd ? launch_fold_b<int16_t, true>(block, a, s) : launch_fold_b<int16_t, false>(block, a, s);
+    return xd ? launch_fold_b<int16_t, true>(block, stride, a, s)
+              : launch_fold_b<int16_t, false>(block, stride, a, s);
   if (elt_bytes == 1)
-    return xd ? launch_fold_b<uint8_t, true>(block, a, s) : launch_fold_b<uint8_t, false>(block, a, s);
+    return xd ? launch_fold_b<uint8_t, true>(block, stride, a, s)
+              : launch_fold_b<uint8_t, false>(block, stride, a, s);
   return hipErrorInvalidValue;
 }
 

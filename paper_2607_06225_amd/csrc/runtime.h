@@ -106,8 +106,9 @@ struct aln_plan {
   aln_fold_params fold_p{};
   std::vector<alnk::FoldTask> fold_tasks;
   struct FoldLaunch {
-    int elt;   // bytes per triangle element
-    int block; // threads per workgroup
+    int elt;    // bytes per triangle element
+    int stride; // row stride of the folded triangle (elements)
+    int block;  // threads per workgroup
     int32_t first, count, max_n;
   };
   std::vector<FoldLaunch> fold_launches;

@@ -48,9 +48,11 @@ STRUCTS = {
     "aln_scoring": aln._Scoring, "aln_params": aln._Params, "aln_batch": aln._Batch,
     "aln_footprint": aln._Footprint, "aln_server_cfg": aln._ServerCfg,
     "aln_request": aln._Request, "aln_server_stats": aln._ServerStats,
-    "aln_tuning": aln._Tuning,
+    "aln_tuning": aln._Tuning, "aln_fold_params": aln._FoldParams,
+    "aln_fold_batch": aln._FoldBatch,
 }
-NUMPY_STRUCTS = {"aln_result": aln.RESULT_DTYPE, "aln_completion": aln.COMPLETION_DTYPE}
+NUMPY_STRUCTS = {"aln_result": aln.RESULT_DTYPE, "aln_completion": aln.COMPLETION_DTYPE,
+                 "aln_fold_result": aln.FOLD_RESULT_DTYPE}
 
 
 def test_header_layouts_match_the_binding(tmp_path):

@@ -1,7 +1,7 @@
 """GPU parity of the RNA-folding kernel (the folding recurrence, unpruned or
 with X-drop transferred to it) against the CPU oracle, through the C ABI.
-Bit-exact: score, best interval, cells evaluated and whether the whole
-sequence was reached."""
+Bit-exact: score, best interval, cells and bifurcation terms evaluated and
+whether the whole sequence was reached."""
 import numpy as np
 import pytest
 
@@ -34,8 +34,8 @@ def check(ctx, fb):
     exp = oracle_fold(fb)
     bad = []
     for p in range(fb.n):
-        g = tuple(int(got[k][p]) for k in ("score", "i", "j", "cells", "full"))
-        e = tuple(int(exp[k][p]) for k in ("score", "i", "j", "cells", "full"))
+        g = tuple(int(got[k][p]) for k in ("score", "i", "j", "cells", "terms", "full"))
+        e = tuple(int(exp[k][p]) for k in ("score", "i", "j", "cells", "terms", "full"))
         if g != e or int(got["status"][p]) != 0:
             bad.append(f"seq {p} (n={int(fb.length[p])}): gpu {g} status {int(got['status'][p])}"
                        f" oracle {e}")
@@ -64,12 +64,12 @@ def test_fold_edge_lengths(ctx, xdrop, warmup, min_loop):
 @pytest.mark.parametrize("xdrop", [-1, 1, 3, 40])
 def test_fold_weighted_pairs_two_byte_scores(ctx, xdrop):
     """Weights up to 3 per pair push scores of long sequences past one byte:
-    the two-byte triangle (and its LDS limit, about 400 nt)."""
+    the two-byte triangle (and its LDS limit, 383 nt)."""
     P = np.zeros((4, 4), dtype=np.int32)
     for (a, b), w in (((0, 3), 2), ((1, 2), 3), ((2, 3), 1)):
         P[a, b] = P[b, a] = w
     st = W.Stream(77, 4)
-    lengths = [5, 60, 170, 171, 250, 333, 390, 399]
+    lengths = [5, 60, 170, 171, 250, 255, 256, 333, 382, 383]
     xs = [(st.u64(L) & np.uint64(3)).astype(np.uint8) for L in lengths]
     fb = W.pack_fold(xs, P, min_loop=3, xdrop=xdrop, warmup=15, name="weighted")
     check(ctx, fb)
@@ -114,3 +114,15 @@ def test_fold_bad_symbol(ctx):
     assert list(got["status"]) == [aln.R_OK, aln.R_BAD_SYMBOL, aln.R_OK]
     exp = oracle_fold(fb.subset([0, 2]))
     assert [int(v) for v in got["score"][[0, 2]]] == [int(v) for v in exp["score"]]
+
+
+def test_fold_limits_refused(ctx):
+    """Past 511 nt, or past 383 nt when scores need two bytes, the plan is
+    refused with ALN_E_UNSUPPORTED (the triangle would not fit LDS)."""
+    from paper_2607_06225_amd import aln
+    P = np.zeros((4, 4), dtype=np.int32)
+    P[1, 2] = P[2, 1] = 3
+    for pair, L in ((W.rna_pair_table(), 512), (P, 384)):
+        fb = W.pack_fold([np.zeros(L, dtype=np.uint8)], pair, name="too_long")
+        with pytest.raises(aln.AlnError, match=r"\(-5\)"):
+            aln.fold_plan(ctx, fb)

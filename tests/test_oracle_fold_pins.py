@@ -75,6 +75,7 @@ def test_unpruned_equals_brute_force(table, min_loop):
         assert got["score"] == brute_force(x, P, min_loop), (x, got)
         assert (got["i"], got["j"]) == (0, n - 1)
         assert got["cells"] == n * (n - 1) // 2
+        assert got["terms"] == n * (n * n - 1) // 6  # sum over spans t of (n - t) t
         assert got["full"] == 1
 
 
@@ -110,7 +111,7 @@ def dict_fold(x, P, min_loop, X, warmup):
     surviving cells in a dictionary keyed by interval, wavefronts by span."""
     n = len(x)
     if n == 0:
-        return 0, 0, 0, 0
+        return 0, 0, 0, 0, 0
     kept = {(i, i): 0 for i in range(n)}
 
     def get(a, b):
@@ -120,7 +121,7 @@ def dict_fold(x, P, min_loop, X, warmup):
 
     best, bcell = 0, (0, 0)
     first, last = 0, n - 1
-    cells = 0
+    cells = terms = 0
     for t in range(1, n):
         cand = range(max(first - 1, 0), min(last, n - 1 - t) + 1)
         if len(cand) == 0:
@@ -140,6 +141,7 @@ def dict_fold(x, P, min_loop, X, warmup):
                 if a is not None and b is not None:
                     opts.append(a + b)
             cells += 1
+            terms += j - i
             if not opts:
                 continue
             v = max(opts)
@@ -155,7 +157,7 @@ def dict_fold(x, P, min_loop, X, warmup):
             bcell = min(c for c, v in new.items() if v == top)
         first = min(i for i, _ in new)
         last = max(i for i, _ in new)
-    return best, bcell[0], bcell[1], cells
+    return best, bcell[0], bcell[1], cells, terms
 
 
 @pytest.mark.parametrize("X", [0, 1, 2, 5])
@@ -169,7 +171,8 @@ def test_xdrop_matches_independent_implementation(X, warmup):
         P = TABLES["weighted" if trial % 3 == 0 else "unit"]
         got = oracle.fold(P, x, min_loop=ml, xdrop=X, warmup=warmup)
         exp = dict_fold(x, P, ml, X, warmup)
-        assert (got["score"], got["i"], got["j"], got["cells"]) == exp, (n, X, warmup, ml)
+        assert (got["score"], got["i"], got["j"], got["cells"], got["terms"]) == exp, \
+            (n, X, warmup, ml)
 
 
 def test_xdrop_limits():
