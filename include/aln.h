@@ -185,9 +185,9 @@ typedef struct {
  * Smith-Waterman kernel, rows per lane of the int32 full-matrix strips (0:
  * the planner's per-pair choice) and the X-drop kernel's starting window
  * (diagonals per lane, and extension sides per wavefront: 1 side over all
- * 64 lanes, or 4 sides of 16 lanes each).  Each ms[] entry is the measured
- * time of one candidate on the tuning batch (0: not measured, negative: not
- * runnable).  While `valid`, aln_plan_create uses the chosen tiles.
+ * 64 lanes, 4 sides of 16 lanes each, or 16 sides of 4 lanes each).  Each
+ * ms[] entry is the measured time of one candidate on the tuning batch (0:
+ * not measured, negative: not runnable).  While `valid`, aln_plan_create uses the chosen tiles.
  * sw16_wide_pct sets when the packed kernel gives a pair-of-pairs a whole
  * 64-lane wavefront (64*R-row strips) instead of a 16-lane group: when the
  * task's serial column steps exceed that percent of the launch's balanced
@@ -198,12 +198,15 @@ typedef struct {
   int32_t sw16_rows;      /* 4, 8, 12 or 16                                   */
   int32_t strip_rows;     /* 0 (per pair), 8, 16, 24 or 32                    */
   int32_t xdrop_rows;     /* 2, 4 or 8                                        */
-  int32_t xdrop_sides;    /* 1, or 4 (with xdrop_rows 8)                      */
+  int32_t xdrop_sides;    /* 1, 4 (with xdrop_rows 8) or 16 (with xdrop_rows
+                             4: 16 sides of 4 lanes, 64 cells per side and
+                             antidiagonal; X-drop without CIGAR under
+                             match / mismatch scoring, else as 4x1)       */
   int32_t sw16_wide_pct;  /* 0 (default 80), -1 (never) or 1..10000          */
   double sw16_ms[4];      /* candidates 16, 12, 8, 4 (each: best of the wide
                              thresholds 25, 40, 60, 80 it was timed with)    */
   double strip_ms[5];     /* candidates 0, 8, 16, 24, 32                      */
-  double xdrop_ms[4];     /* candidates 4x1, 2x1, 8x1, 8x4 (rows x sides)     */
+  double xdrop_ms[4];     /* candidates 4x1, 4x16, 8x1, 8x4 (rows x sides)    */
 } aln_tuning;             /* 128 bytes */
 
 /* ABI version of the loaded library (ALN_ABI_VERSION). */

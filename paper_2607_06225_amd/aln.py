@@ -108,7 +108,7 @@ class _Tuning(ctypes.Structure):
 
 
 SW16_TILES, STRIP_TILES = (16, 12, 8, 4), (0, 8, 16, 24, 32)
-XDROP_TILES = ("4x1", "2x1", "8x1", "8x4")  # diagonals per lane x sides per wavefront
+XDROP_TILES = ("4x1", "4x16", "8x1", "8x4")  # window cells per lane x sides per wavefront
 
 
 _lib = None

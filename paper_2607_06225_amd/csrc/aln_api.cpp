@@ -586,6 +586,16 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
       }
     }
   }
+  // X-drop without traceback under match / mismatch scoring on a small
+  // alphabet runs on the sixteen-sides-per-wavefront kernel when its
+  // arithmetic fits: offset-frame scores in one byte, the out-of-range
+  // penalty (-128) below every threshold (X < 128 + 2|e|), end cells in 16
+  // bits and keys (score << 6) in 31.
+  const bool lanes_ok =
+      p.prune == ALN_XDROP && !p.want_cigar && hs.match_mismatch && hs.alphabet <= 4 &&
+      (int64_t)p.xdrop <= 127 - 2LL * hs.gap_extend && hs.match - 2 * hs.gap_extend <= 127 &&
+      hs.mismatch - 2 * hs.gap_extend >= -128 && maxM <= 65535 && maxN <= 65535 &&
+      ((int64_t)maxM + maxN) * (1 - hs.gap_extend + std::max(hs.match, 0)) < (1LL << 23);
   std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
     if (a.kind != b.kind) return a.kind < b.kind;
     if (a.waves != b.waves) return a.waves < b.waves;
@@ -608,9 +618,15 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     L.rows = items[k].rows;
     L.mode = p.mode;
     if (L.kind == K_DIAG && dyn_prune) {
-      L.sides = ctx->tuning.valid ? ctx->tuning.xdrop_sides : 1;
+      L.sides = ctx->tuning.valid ? ctx->tuning.xdrop_sides : (lanes_ok ? 16 : 1);
       if (ctx->force_xdrop_sides) L.sides = ctx->force_xdrop_sides;
-      if (L.sides != 1 && L.rows != 8) L.sides = 1;
+      if (L.sides == 16 && !lanes_ok) L.sides = 1;
+      if (L.sides == 4 && L.rows != 8) L.sides = 1;
+      if (L.sides == 16) {
+        const int64_t want = ((int64_t)(e - k) + 15) / 16;
+        const int64_t fit = (int64_t)ctx->cus * alnk::xdrop_lanes_waves_per_cu();
+        L.grid = (int)std::max<int64_t>(1, std::min(want, fit));
+      }
     }
     L.tb = p.want_cigar != 0 && !dyn_prune; // X-drop codes come from a second pass
     L.small = small;
@@ -801,8 +817,10 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
   PairTask *rerun_q = sw16 ? reinterpret_cast<PairTask *>(ws + plan->rerun_off) : nullptr;
 
   int32_t *widen_cnt = plan->xdrop ? reinterpret_cast<int32_t *>(ws + plan->widen_cnt_off) : nullptr;
+  // counters: sw16 re-run queue; X-drop widening queues (2) and the lanes
+  // kernel's work queue (2)
   alnk::ValidateArgs va{bp, plan->n, hsc.alphabet, d_res, sw16 ? rerun_cnt : widen_cnt,
-                        sw16 ? 1 : (plan->xdrop ? 2 : 0)};
+                        sw16 ? 1 : (plan->xdrop ? 4 : 0)};
   HIP_TRY(ctx, timed_launch(ctx, "validate", st, [&] { return alnk::launch_validate(va, st); }));
 
   if (!plan->launches.empty() && plan->launches[0].kind == K_SEARCH) {
@@ -927,6 +945,34 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
     if (L.kind == K_DIAG) {
       if (plan->xtb_count > 0) continue; // the traceback pass above replaces it
       const int widen_rows = plan->xdrop ? 16 : 0;
+      if (L.sides == 16) {
+        alnk::XdlArgs xa;
+        xa.b = bp;
+        xa.tasks = dtasks + L.first;
+        xa.ntasks = L.count;
+        xa.queue = widen_cnt + 2;
+        xa.xdrop = plan->p.xdrop;
+        xa.gap_open = hsc.gap_open;
+        xa.gap_extend = hsc.gap_extend;
+        xa.match = hsc.match;
+        xa.mismatch = hsc.mismatch;
+        xa.res = d_res;
+        xa.widen_count = widen_cnt;
+        xa.widen = wq0;
+        xa.widen_rows = widen_rows;
+        if (!per_pair) {
+          HIP_TRY(ctx, timed_launch(ctx, "xdrop_lanes", st, [&] {
+                    return alnk::launch_xdrop_lanes(xa, L.grid, st);
+                  }));
+        } else {
+          for (int32_t k = 0; k < L.count; ++k) {
+            xa.tasks = dtasks + L.first + k;
+            xa.ntasks = 1;
+            HIP_TRY(ctx, alnk::launch_xdrop_lanes(xa, 1, st));
+          }
+        }
+        continue;
+      }
       auto go = [&](const alnk::DiagArgs &da) {
         return L.sides == 4 ? alnk::launch_xdrop_group(plan->p.prune, da, st)
                             : alnk::launch_diag(L.rows, L.mode, plan->p.prune, L.tb, da, st);

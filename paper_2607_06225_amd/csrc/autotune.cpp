@@ -117,8 +117,10 @@ aln_status aln_autotune(aln_ctx *ctx, int32_t scoring_id, const aln_params *para
                           p.width != ALN_W_I32;
   if (p.prune == ALN_XDROP || p.prune == ALN_ZDROP) {
     // X-drop and Z-drop share the kernel family and its tile choice;
-    // candidates rows x sides: 4x1, 2x1, 8x1, 8x4 (encoded rows + 100*(sides-1))
-    static const int c[4] = {4, 2, 8, 308};
+    // candidates rows x sides: 4x1, 4x16, 8x1, 8x4 (encoded rows +
+    // 100*(sides-1)); 4x16 is the sixteen-sides kernel where the plan
+    // qualifies, else 4x1
+    static const int c[4] = {4, 1504, 8, 308};
     const int best = pick(c, 4, t.xdrop_ms, 4, [&](int code) {
       ctx->force_xdrop_rows = code % 100;
       ctx->force_xdrop_sides = code / 100 + 1;
@@ -181,7 +183,7 @@ aln_status aln_set_tuning(aln_ctx *ctx, const aln_tuning *tuning) {
     const int xs = tuning->xdrop_sides, w = tuning->sw16_wide_pct;
     if (!(s == 4 || s == 8 || s == 12 || s == 16) ||
         !(r == 0 || r == 8 || r == 16 || r == 24 || r == 32) || !(x == 2 || x == 4 || x == 8) ||
-        !(xs == 1 || (xs == 4 && x == 8)) || w < -1 || w > 10000)
+        !(xs == 1 || (xs == 4 && x == 8) || (xs == 16 && x == 4)) || w < -1 || w > 10000)
       return alnrt::fail(ctx, ALN_E_INVAL, "tile choice outside the kernels' tiles");
   }
   ctx->tuning = *tuning;

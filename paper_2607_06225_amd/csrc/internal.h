@@ -145,6 +145,21 @@ struct DiagArgs {
   int32_t match_mismatch;     // 1: the scoring is one match and one mismatch score
 };
 
+// X-drop extension, sixteen sides per wavefront (match / mismatch scoring,
+// alphabet <= 4, no traceback): a persistent grid takes tasks from a queue.
+struct XdlArgs {
+  BatchPtrs b;
+  const PairTask *tasks;     // longest first
+  int32_t ntasks;
+  int32_t *queue;            // two counters, zero at launch; zero again at exit
+  int32_t xdrop;
+  int32_t gap_open, gap_extend, match, mismatch;
+  aln_result *res;
+  int32_t *widen_count;      // regions wider than 64 cells per antidiagonal
+  PairTask *widen;
+  int32_t widen_rows;        // RD of the wider kernel
+};
+
 // Score-major search for unit-cost edit distance: one workgroup per task,
 // of `waves` wavefronts (1: one F row in LDS; 4: two rows, the previous
 // score's and the current one's).
@@ -200,6 +215,9 @@ hipError_t launch_diag(int rows, int mode, int prune, bool tb, const DiagArgs &a
 // wavefront, 8 diagonals per lane
 hipError_t launch_xdrop_group(int prune, const DiagArgs &a, hipStream_t s);
 hipError_t launch_walk_diag(const WalkArgs &a, hipStream_t s);
+hipError_t launch_xdrop_lanes(const XdlArgs &a, int waves, hipStream_t s);
+int xdrop_lanes_waves_per_cu(); // resident wavefronts per CU
+size_t xdrop_lanes_lds_bytes();
 hipError_t launch_search(const SearchArgs &a, hipStream_t s);
 // elt_bytes 1 (uint8 triangle) or 2 (int16); block 256, 512 or 1024 threads;
 // stride one of kFoldStrides

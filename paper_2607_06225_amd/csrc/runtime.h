@@ -51,7 +51,8 @@ struct LaunchDesc {
   int32_t count;
   int32_t lds_bnd;
   int32_t lds_prof;
-  int sides = 1; // X-drop: extension sides per wavefront
+  int sides = 1; // X-drop: extension sides per wavefront (16: the persistent lanes kernel)
+  int grid = 0;  // X-drop lanes kernel: wavefronts of the persistent grid
   int waves = 1; // full matrix: wavefronts per pair (strip pipeline)
   int max_n = 0; // largest reference length of the launch
   int32_t lds_f = 0;  // search: LDS bytes of one furthest-row array

@@ -88,7 +88,7 @@ def xdrop_batch(rng, lengths, X, div=0.15, name="xd"):
                         name=name)
 
 
-XDROP_TILES = [(4, 1), (8, 4)]  # (diagonals per lane, extension sides per wavefront)
+XDROP_TILES = [(4, 1), (8, 4), (4, 16)]  # (window per lane, extension sides per wavefront)
 
 
 def with_xdrop_tile(ctx, tile):

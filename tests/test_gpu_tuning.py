@@ -45,11 +45,11 @@ def test_autotune_strips_with_cigar(ctx):
 
 
 def test_autotune_xdrop(ctx):
-    t = tune_and_check(ctx, W.xdrop_ext(n=3000, seed=63), "xdrop", (2, 4, 8))
-    assert t["xdrop_sides"] in (1, 4)
+    t = tune_and_check(ctx, W.xdrop_ext(n=3000, seed=63), "xdrop", (4, 8))
+    assert (t["xdrop_rows"], t["xdrop_sides"]) in ((4, 1), (4, 16), (8, 1), (8, 4))
 
 
-@pytest.mark.parametrize("tile,sides", [(2, 1), (8, 1), (8, 4)])
+@pytest.mark.parametrize("tile,sides", [(2, 1), (8, 1), (8, 4), (4, 16)])
 def test_every_xdrop_start_window_is_bit_exact(ctx, tile, sides):
     from paper_2607_06225_amd import aln
     b = W.xdrop_ext(n=1500, seed=70 + tile + sides)
@@ -80,6 +80,7 @@ def test_set_tuning_round_trip_and_validation(ctx):
                              got["sw16_wide_pct"]) == (8, 24, 2, 150)
     for bad in ({"sw16_rows": 5}, {"strip_rows": 12}, {"xdrop_rows": 16},
                 {"xdrop_rows": 4, "xdrop_sides": 4}, {"xdrop_sides": 2},
+                {"xdrop_rows": 8, "xdrop_sides": 16},
                 {"sw16_wide_pct": -2}, {"sw16_wide_pct": 10001}):
         with pytest.raises(aln.AlnError):
             ctx.set_tuning(dict({"sw16_rows": 16, "strip_rows": 0, "xdrop_rows": 8,
