@@ -257,9 +257,13 @@ def bit_exact_check(batch, res, cig, work, ores, k, rate, budget_s):
         bad += compare(sub, res[rest], [cig[i] for i in rest] if cig is not None else None, o)
         checked += rest.size
         log(f"[bench] checked {rest.size} more pairs in {time.perf_counter() - t0:.1f} s")
-    how = ("every pair" if checked == batch.n else
-           f"the first {k} pairs and every {max(1, (batch.n - k) // max(checked - k, 1))}-th "
-           f"pair after them")
+    if checked == batch.n:
+        how = "every pair"
+    elif checked == k:
+        how = f"the first {k} pairs (the CPU baseline's sample) only"
+    else:
+        how = (f"the first {k} pairs and every {max(1, (batch.n - k) // (checked - k))}-th "
+               f"pair after them")
     return dict(pairs=int(checked), of=int(batch.n), sample=how, mismatches=len(bad),
                 first=bad[:3])
 

@@ -163,6 +163,7 @@ __global__ __launch_bounds__(64) void xdrop_lanes_kernel(XdlArgs a) {
   for (;;) {
     // ---- idle sides take the next task (the list is longest first)
     bool need = !active && !exhausted;
+    bool fresh = false;
     while (__ballot(need)) {
       if (need) {
         int t = 0;
@@ -186,15 +187,7 @@ __global__ __launch_bounds__(64) void xdrop_lanes_kernel(XdlArgs a) {
           } else {
             Q = a.b.q + a.b.q_off[pair];
             R = a.b.r + a.b.r_off[pair];
-            // k = 0: the cell (0,0) with H = 0 at d = 0 (pos 32, parity 0);
-            // its E and F outputs are the gap open (frame of k = 1)
-#pragma unroll
-            for (int m = 0; m < XC; ++m) H0[m] = H1[m] = E0[m] = F0[m] = E1[m] = F1[m] = XNEG;
-            if (gl == 2) {
-              H0[0] = 0;
-              E0[0] = go;
-              F0[0] = go;
-            }
+            fresh = true; // arrays reset below, outside this loop
             base = -64;
             k = 1;
             kE = ge;
@@ -215,12 +208,27 @@ __global__ __launch_bounds__(64) void xdrop_lanes_kernel(XdlArgs a) {
       need = !active && !exhausted;
     }
     if (!__ballot(active)) break;
+    // new sides: every slot minus infinity but the cell (0,0) with H = 0 at
+    // d = 0 (pos 32, parity 0), whose E and F outputs are the gap open in the
+    // frame of k = 1
+    if (__ballot(fresh)) {
+      if (fresh) {
+#pragma unroll
+        for (int m = 0; m < XC; ++m) H0[m] = H1[m] = E0[m] = F0[m] = E1[m] = F1[m] = XNEG;
+        if (gl == 2) {
+          H0[0] = 0;
+          E0[0] = go;
+          F0[0] = go;
+        }
+      }
+    }
 
     // one antidiagonal of parity P (P == k & 1 for every active side)
     auto step = [&](auto ptag) {
       constexpr int P = decltype(ptag)::value;
-      // ---- keep the rings ahead of the window
-      for (;;) {
+      // ---- keep the rings ahead of the window (26 codes of margin; the
+      // window moves at most two codes per antidiagonal pair)
+      for (; P == 1;) {
         const int topq = ((k - base - P) >> 1) - 1;  // query code of pos 0
         const int topr = ((k + base + P) >> 1) + 62; // reference code of pos 63
         const bool sq = active && qtop < topq + 26;
