@@ -384,41 +384,72 @@ __device__ void strip_task(const StripArgs &a, int task, int wave, int lane, uin
 }
 
 // ---------------------------------------------------------------- validate
-// Initialises every result and flags pairs holding a code >= alphabet.
+// Initialises every result and flags pairs holding a code >= alphabet.  One
+// wavefront per pair (grid-stride); the codes are read as 16-byte vectors
+// between the first and last 16-byte boundaries, bytewise before and after.
+
+// Some byte of w exceeds n (n <= 127), with lim = (127 - n) * 0x01010101: a
+// byte below 128 carries into its top bit exactly when it exceeds n, a byte
+// of 128 or more has it set already (its carry into the next byte can only
+// raise a flag the word already has).
+__device__ __forceinline__ uint32_t byte_above(uint32_t w, uint32_t lim) {
+  return ((w + lim) | w) & 0x80808080u;
+}
+
+__device__ __forceinline__ uint32_t seq_bad(const uint8_t *s, int64_t len, int lane, int A,
+                                            uint32_t lim) {
+  const uintptr_t a0 = reinterpret_cast<uintptr_t>(s), e = a0 + (uintptr_t)len;
+  const uintptr_t b0 = (a0 + 15) & ~(uintptr_t)15, b1 = e & ~(uintptr_t)15;
+  uint32_t bad = 0;
+  if (len <= 0) return 0;
+  if (b0 >= b1) { // no whole 16-byte block
+    for (int64_t k = lane; k < len; k += 64) bad |= s[k] >= A;
+    return bad;
+  }
+  const int h = (int)(b0 - a0), t = (int)(e - b1); // 0..15 each
+  if (lane < h) bad |= s[lane] >= A;
+  if (lane < t) bad |= reinterpret_cast<const uint8_t *>(b1)[lane] >= A;
+  const uint4 *v = reinterpret_cast<const uint4 *>(b0);
+  const int64_t nv = (int64_t)((b1 - b0) >> 4);
+  for (int64_t k = lane; k < nv; k += 64) {
+    const uint4 x = v[k];
+    bad |= byte_above(x.x, lim) | byte_above(x.y, lim) | byte_above(x.z, lim) |
+           byte_above(x.w, lim);
+  }
+  return bad;
+}
+
 __global__ __launch_bounds__(256) void validate_kernel(ValidateArgs a) {
-  const int p = blockIdx.x;
-  if (p >= a.n) return;
-  __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  const int M = a.b.q_len[p], N = a.b.r_len[p];
-  const uint8_t *Q = a.b.q + a.b.q_off[p];
-  const uint8_t *Rs = a.b.r + a.b.r_off[p];
-  int mine = 0;
-  for (int k = threadIdx.x; k < M; k += blockDim.x) mine |= (Q[k] >= a.alphabet);
-  for (int k = threadIdx.x; k < N; k += blockDim.x) mine |= (Rs[k] >= a.alphabet);
-  if (mine) atomicOr(&bad, 1);
-  __syncthreads();
-  if (p == 0 && a.reset_counter && (int)threadIdx.x < a.n_reset) a.reset_counter[threadIdx.x] = 0;
-  if (threadIdx.x == 0) {
-    aln_result *r = a.res + p;
-    r->score = 0;
-    r->q_end = 0;
-    r->r_end = 0;
-    r->q_begin = 0;
-    r->r_begin = 0;
-    r->status = bad ? ALN_R_BAD_SYMBOL : ALN_R_OK;
-    r->flags = 0;
-    r->cigar_len = 0;
-    r->cells = 0;
-    r->cigar_off = 0;
+  const int lane = threadIdx.x & 63;
+  if (blockIdx.x == 0 && a.reset_counter && (int)threadIdx.x < a.n_reset)
+    a.reset_counter[threadIdx.x] = 0;
+  const int waves = gridDim.x * (blockDim.x >> 6);
+  const uint32_t lim = (uint32_t)(127 - (a.alphabet - 1)) * 0x01010101u;
+  for (int p = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); p < a.n; p += waves) {
+    const uint32_t bad = seq_bad(a.b.q + a.b.q_off[p], a.b.q_len[p], lane, a.alphabet, lim) |
+                         seq_bad(a.b.r + a.b.r_off[p], a.b.r_len[p], lane, a.alphabet, lim);
+    const bool any = __ballot(bad != 0) != 0;
+    if (lane == 0) {
+      aln_result *r = a.res + p;
+      r->score = 0;
+      r->q_end = 0;
+      r->r_end = 0;
+      r->q_begin = 0;
+      r->r_begin = 0;
+      r->status = any ? ALN_R_BAD_SYMBOL : ALN_R_OK;
+      r->flags = 0;
+      r->cigar_len = 0;
+      r->cells = 0;
+      r->cigar_off = 0;
+    }
   }
 }
 
 // ---------------------------------------------------------------- launchers
 hipError_t launch_validate(const ValidateArgs &a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(validate_kernel, dim3(a.n), dim3(256), 0, s, a);
+  const int blocks = a.n < 4 * 4096 ? (a.n + 3) / 4 : 4096; // four wavefronts each, grid-stride
+  hipLaunchKernelGGL(validate_kernel, dim3(blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
