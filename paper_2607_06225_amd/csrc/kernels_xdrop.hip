@@ -43,9 +43,9 @@
 // per lane and antidiagonal.
 //
 // Best cell: keys (H' << 6 | pos) give, per antidiagonal, the highest score
-// and among equals the largest d (smallest i); the running best is a 64-bit
-// key (score, -i, -j).  Survivor bounds come from per-lane survivor masks and
-// quad DPP minima / maxima.  The window slides by one cell when the
+// and among equals the largest d (smallest i); the running best is the score
+// with a key (-i, -j) for ties.  Survivor bounds come from per-lane survivor
+// masks and quad DPP minima / maxima.  The window slides by one cell when the
 // candidate range reaches an edge; a region wider than 64 cells goes to the
 // widening queue (the one-side kernel with wider windows).
 #include "internal.h"
@@ -65,27 +65,32 @@ constexpr int kRingStride = kRing + kRingMirror;
 constexpr int kSides = 16;         // sides per wavefront
 
 // quad DPP: lane l reads lane l-1 (shr) / l+1 (shl) of its quad; the quad's
-// edge lane gets `edge`
+// edge lane gets `edge`.  quad_perm always names a lane of the quad, so every
+// lane reads a defined value and bound_ctrl changes nothing; with it and no
+// old value the compiler folds the move into the instruction that uses it.
+template <int CTRL> __device__ __forceinline__ int quad_dpp(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);
+}
 __device__ __forceinline__ int quad_shr1(int v, int edge, bool first) {
-  const int x = __builtin_amdgcn_update_dpp(v, v, 0x90, 0xf, 0xf, false); // quad_perm 0,0,1,2
+  const int x = quad_dpp<0x90>(v); // quad_perm 0,0,1,2
   return first ? edge : x;
 }
 __device__ __forceinline__ int quad_shl1(int v, int edge, bool last) {
-  const int x = __builtin_amdgcn_update_dpp(v, v, 0xF9, 0xf, 0xf, false); // quad_perm 1,2,3,3
+  const int x = quad_dpp<0xF9>(v); // quad_perm 1,2,3,3
   return last ? edge : x;
 }
 __device__ __forceinline__ int quad_max(int v) {
-  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xf, 0xf, false)); // quad_perm 1,0,3,2
-  v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xf, 0xf, false)); // quad_perm 2,3,0,1
+  v = max(v, quad_dpp<0xB1>(v)); // quad_perm 1,0,3,2
+  v = max(v, quad_dpp<0x4E>(v)); // quad_perm 2,3,0,1
   return v;
 }
 __device__ __forceinline__ int quad_min(int v) {
-  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xf, 0xf, false));
-  v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xf, 0xf, false));
+  v = min(v, quad_dpp<0xB1>(v));
+  v = min(v, quad_dpp<0x4E>(v));
   return v;
 }
 __device__ __forceinline__ int quad_bcast0(int v) {
-  return __builtin_amdgcn_update_dpp(v, v, 0x00, 0xf, 0xf, false); // quad_perm 0,0,0,0
+  return quad_dpp<0x00>(v); // quad_perm 0,0,0,0
 }
 
 // 16 ring bytes from `addr` (any alignment; the mirror covers the wrap)
@@ -131,7 +136,9 @@ __global__ __launch_bounds__(64) void xdrop_lanes_kernel(XdlArgs a) {
   bool active = false, exhausted = false;
   int task = 0, pair = 0, M = 0, N = 0, base = 0, k = 0, kE = 0, T = XBIG;
   int plo = 1, phi = 0, qtop = 0, rtop = 0;
-  long long best64 = 0, cells = 0;
+  int best = 0;         // best score so far
+  uint32_t best_key = 0; // its cell: (0xffff - i) << 16 | (0xffff - j)
+  long long cells = 0;
   const uint8_t *Q = nullptr, *R = nullptr;
 
   // 32 codes per call into a ring (the query reversed), padding (4) past
@@ -191,7 +198,8 @@ __global__ __launch_bounds__(64) void xdrop_lanes_kernel(XdlArgs a) {
             base = -64;
             k = 1;
             kE = ge;
-            best64 = 0xffffffffLL; // score 0 at (0,0)
+            best = 0; // score 0 at (0,0)
+            best_key = 0xffffffffu;
             T = -X - kE;
             plo = 31; // candidates of k = 1: d = -1, 1
             phi = 32;
@@ -256,9 +264,9 @@ __global__ __launch_bounds__(64) void xdrop_lanes_kernel(XdlArgs a) {
       {
         const int lo = min(max(plo - XC * gl, 0), XC);
         const int hi = min(max(phi - XC * gl + 1, 0), XC);
-        const uint32_t run = hi > lo ? (1u << (hi - lo)) - 1u : 0u;
-        inr_rev = run << (XC - hi);
-        const uint32_t out = ~(run << lo);
+        // hi >= lo always (an idle side has plo = phi + 1)
+        inr_rev = ((1u << (hi - lo)) - 1u) << (XC - hi);
+        const uint32_t out = ~(((1u << (hi - lo)) - 1u) << lo);
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
           const uint32_t nib = (out >> (4 * w)) & 15u;
@@ -310,16 +318,17 @@ __global__ __launch_bounds__(64) void xdrop_lanes_kernel(XdlArgs a) {
         const int hs = kmax >> 6, ps = kmax & 63;
         const int d = base + 2 * ps + P;
         const int bi = (k - d) >> 1, bj = k - bi;
-        const uint32_t pos_key = ((uint32_t)(0xffff - bi) << 16) | (uint32_t)(0xffff - bj);
-        const long long cand = (long long)(((unsigned long long)(long long)(hs + kE)) << 32) |
-                               (long long)pos_key;
-        best64 = max(best64, cand);
+        const uint32_t key = ((uint32_t)(0xffff - bi) << 16) | (uint32_t)(0xffff - bj);
+        const int cs = hs + kE;
+        if (cs > best || (cs == best && key > best_key)) {
+          best = cs;
+          best_key = key;
+        }
       }
       // ---- next antidiagonal: candidates in the other parity's positions,
       // clipped to the matrix
       const int kn = k + 1;
       const int kEn = kE + ge;
-      const int best = (int)(best64 >> 32);
       int nlo = P == 0 ? f - 1 : f, nhi = P == 0 ? l : l + 1;
       const int dlo = max(-kn, kn - 2 * M), dhi = min(kn, 2 * N - kn);
       nlo = max(nlo, (dlo - base - (1 - P)) >> 1);
@@ -343,8 +352,8 @@ __global__ __launch_bounds__(64) void xdrop_lanes_kernel(XdlArgs a) {
             dst->aux = src->aux;
           } else {
             res->score = best;
-            res->q_end = 0xffff - (int)((best64 >> 16) & 0xffff);
-            res->r_end = 0xffff - (int)(best64 & 0xffff);
+            res->q_end = 0xffff - (int)(best_key >> 16);
+            res->r_end = 0xffff - (int)(best_key & 0xffffu);
             res->cells = cells;
           }
         }
