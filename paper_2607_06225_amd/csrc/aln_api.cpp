@@ -591,11 +591,12 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
   // arithmetic fits: offset-frame scores in one byte, the out-of-range
   // penalty (-128) below every threshold (X < 128 + 2|e|), end cells in 16
   // bits and keys (score << 6) in 31.
-  const bool lanes_ok =
-      p.prune == ALN_XDROP && !p.want_cigar && hs.match_mismatch && hs.alphabet <= 4 &&
+  const bool lanes_fit =
+      p.prune == ALN_XDROP && hs.match_mismatch && hs.alphabet <= 4 &&
       (int64_t)p.xdrop <= 127 - 2LL * hs.gap_extend && hs.match - 2 * hs.gap_extend <= 127 &&
       hs.mismatch - 2 * hs.gap_extend >= -128 && maxM <= 65535 && maxN <= 65535 &&
       ((int64_t)maxM + maxN) * (1 - hs.gap_extend + std::max(hs.match, 0)) < (1LL << 23);
+  const bool lanes_ok = lanes_fit && !p.want_cigar;
   std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
     if (a.kind != b.kind) return a.kind < b.kind;
     if (a.waves != b.waves) return a.waves < b.waves;
@@ -624,7 +625,7 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
       if (L.sides == 4 && L.rows != 8) L.sides = 1;
       if (L.sides == 16) {
         const int64_t want = ((int64_t)(e - k) + 15) / 16;
-        const int64_t fit = (int64_t)ctx->cus * alnk::xdrop_lanes_waves_per_cu();
+        const int64_t fit = (int64_t)ctx->cus * alnk::xdrop_lanes_waves_per_cu(false);
         L.grid = (int)std::max<int64_t>(1, std::min(want, fit));
       }
     }
@@ -679,6 +680,17 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
   if (dyn_prune && p.want_cigar) {
     pl->xtb_first = (int32_t)pl->tasks.size();
     pl->xtb_count = n;
+    // the sixteen-sides kernel writes the codes where its arithmetic fits,
+    // unless a tuned tile other than its own asks for the one-side pass
+    const int tuned_sides = ctx->force_xdrop_sides
+                                ? ctx->force_xdrop_sides
+                                : (ctx->tuning.valid ? ctx->tuning.xdrop_sides : 16);
+    pl->xtb_lanes = lanes_fit && tuned_sides == 16;
+    if (pl->xtb_lanes) {
+      const int64_t want = ((int64_t)n + 15) / 16;
+      const int64_t fit = (int64_t)ctx->cus * alnk::xdrop_lanes_waves_per_cu(true);
+      pl->xtb_grid = (int)std::max<int64_t>(1, std::min(want, fit));
+    }
     std::vector<int32_t> order(n);
     for (int32_t i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
@@ -719,7 +731,8 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     pl->widen_cnt_off = pl->tasks_bytes;
     pl->widen_off[0] = pl->widen_cnt_off + kAlign;
     pl->widen_off[1] = pl->widen_off[0] + align_up(sizeof(PairTask) * (size_t)std::max(n, 1));
-    pl->tasks_bytes = pl->widen_off[1] + align_up(sizeof(PairTask) * (size_t)std::max(n, 1));
+    pl->widen_off[2] = pl->widen_off[1] + align_up(sizeof(PairTask) * (size_t)std::max(n, 1));
+    pl->tasks_bytes = pl->widen_off[2] + (pl->xtb_lanes ? align_up(sizeof(PairTask) * (size_t)std::max(n, 1)) : 0);
   }
   pl->tb_base = pl->tasks_bytes;
   pl->tb_bytes = tb_off;
@@ -817,10 +830,11 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
   PairTask *rerun_q = sw16 ? reinterpret_cast<PairTask *>(ws + plan->rerun_off) : nullptr;
 
   int32_t *widen_cnt = plan->xdrop ? reinterpret_cast<int32_t *>(ws + plan->widen_cnt_off) : nullptr;
-  // counters: sw16 re-run queue; X-drop widening queues (2) and the lanes
-  // kernel's work queue (2)
+  // counters: sw16 re-run queue; X-drop widening queues (2), the lanes
+  // kernel's work queue (2) and its queue of pairs for the one-side pass with
+  // codes (1)
   alnk::ValidateArgs va{bp, plan->n, hsc.alphabet, d_res, sw16 ? rerun_cnt : widen_cnt,
-                        sw16 ? 1 : (plan->xdrop ? 4 : 0)};
+                        sw16 ? 1 : (plan->xdrop ? 5 : 0)};
   HIP_TRY(ctx, timed_launch(ctx, "validate", st, [&] { return alnk::launch_validate(va, st); }));
 
   if (!plan->launches.empty() && plan->launches[0].kind == K_SEARCH) {
@@ -926,7 +940,41 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
   };
   PairTask *wq0 = plan->xdrop ? reinterpret_cast<PairTask *>(ws + plan->widen_off[0]) : nullptr;
   PairTask *wq1 = plan->xdrop ? reinterpret_cast<PairTask *>(ws + plan->widen_off[1]) : nullptr;
-  if (plan->xtb_count > 0) {
+  PairTask *wq2 = plan->xtb_lanes ? reinterpret_cast<PairTask *>(ws + plan->widen_off[2]) : nullptr;
+  if (plan->xtb_lanes) {
+    // codes from the sixteen-sides kernel; pairs whose region outgrows its
+    // window are recomputed with codes by the one-side pass (queue 2)
+    alnk::XdlArgs xa;
+    xa.b = bp;
+    xa.tasks = dtasks + plan->xtb_first;
+    xa.ntasks = plan->xtb_count;
+    xa.queue = widen_cnt + 2;
+    xa.xdrop = plan->p.xdrop;
+    xa.gap_open = hsc.gap_open;
+    xa.gap_extend = hsc.gap_extend;
+    xa.match = hsc.match;
+    xa.mismatch = hsc.mismatch;
+    xa.res = d_res;
+    xa.widen_count = widen_cnt + 4;
+    xa.widen = wq2;
+    xa.widen_rows = 4;
+    xa.tb = ws + plan->tb_base;
+    if (!per_pair) {
+      HIP_TRY(ctx, timed_launch(ctx, "xdrop_lanes_tb", st, [&] {
+                return alnk::launch_xdrop_lanes(true, xa, plan->xtb_grid, st);
+              }));
+    } else {
+      for (int32_t k = 0; k < plan->xtb_count; ++k) {
+        xa.tasks = dtasks + plan->xtb_first + k;
+        xa.ntasks = 1;
+        HIP_TRY(ctx, alnk::launch_xdrop_lanes(true, xa, 1, st));
+      }
+    }
+    alnk::DiagArgs d = diag_args(wq2, plan->n, widen_cnt + 4, 16, widen_cnt, wq0);
+    HIP_TRY(ctx, timed_launch(ctx, "xdrop_tb", st, [&] {
+              return alnk::launch_diag(4, ALN_EXTEND, plan->p.prune, true, d, st);
+            }));
+  } else if (plan->xtb_count > 0) {
     // X-drop / Z-drop with CIGAR: one pass per pair computes the results and
     // writes the traceback codes; regions that outgrow its window go to the
     // widening queue below (score only) and the walk decides their CIGAR
@@ -947,6 +995,7 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
       const int widen_rows = plan->xdrop ? 16 : 0;
       if (L.sides == 16) {
         alnk::XdlArgs xa;
+        xa.tb = nullptr;
         xa.b = bp;
         xa.tasks = dtasks + L.first;
         xa.ntasks = L.count;
@@ -962,13 +1011,13 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
         xa.widen_rows = widen_rows;
         if (!per_pair) {
           HIP_TRY(ctx, timed_launch(ctx, "xdrop_lanes", st, [&] {
-                    return alnk::launch_xdrop_lanes(xa, L.grid, st);
+                    return alnk::launch_xdrop_lanes(false, xa, L.grid, st);
                   }));
         } else {
           for (int32_t k = 0; k < L.count; ++k) {
             xa.tasks = dtasks + L.first + k;
             xa.ntasks = 1;
-            HIP_TRY(ctx, alnk::launch_xdrop_lanes(xa, 1, st));
+            HIP_TRY(ctx, alnk::launch_xdrop_lanes(false, xa, 1, st));
           }
         }
         continue;
@@ -1032,7 +1081,8 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
     wa.b = bp;
     wa.mode = plan->p.mode;
     wa.layout = 0;
-    wa.diag_stride = plan->xtb_count > 0 ? 2 : 8;
+    wa.diag_stride = plan->xtb_lanes ? 1 : (plan->xtb_count > 0 ? 2 : 8);
+    wa.dyn_ntasks = nullptr;
     wa.sc = dsc;
     wa.tb = ws + plan->tb_base;
     wa.res = d_res;
@@ -1052,6 +1102,11 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
       for (int32_t k = 0; k < plan->n_strip_tb; ++k) HIP_TRY(ctx, walk(0, dtasks + k, 1));
       for (int32_t k = 0; k < plan->n_diag_tb; ++k)
         HIP_TRY(ctx, walk(1, dtasks + plan->first_diag_tb + k, 1));
+    }
+    if (plan->xtb_lanes) { // the pairs the one-side pass recomputed, in its layout
+      wa.diag_stride = 2;
+      wa.dyn_ntasks = widen_cnt + 4;
+      HIP_TRY(ctx, timed_launch(ctx, "walk", st, [&] { return walk(1, wq2, plan->n); }));
     }
   }
   return ALN_OK;

@@ -75,7 +75,9 @@ struct WalkArgs {
   int32_t mode;
   int32_t layout;     // 0: strip layout, 1: diagonal layout
   int32_t diag_stride; // diagonal layout: code bytes per lane and antidiagonal
-                       // pair (8: bands; 2: X-drop / Z-drop, 4 diagonals per lane)
+                       // pair (8: bands; 2: X-drop / Z-drop, 4 diagonals per lane;
+                       // 1: the sixteen-sides X-drop kernel's 32 bytes per antidiagonal)
+  const int32_t *dyn_ntasks; // device-side task count (a re-run queue), or null
   const DevScoring *sc;
   const uint8_t *tb;
   aln_result *res;
@@ -158,6 +160,7 @@ struct XdlArgs {
   int32_t *widen_count;      // regions wider than 64 cells per antidiagonal
   PairTask *widen;
   int32_t widen_rows;        // RD of the wider kernel
+  uint8_t *tb;               // traceback form: code regions (task tb_off)
 };
 
 // Score-major search for unit-cost edit distance: one workgroup per task,
@@ -215,8 +218,10 @@ hipError_t launch_diag(int rows, int mode, int prune, bool tb, const DiagArgs &a
 // wavefront, 8 diagonals per lane
 hipError_t launch_xdrop_group(int prune, const DiagArgs &a, hipStream_t s);
 hipError_t launch_walk_diag(const WalkArgs &a, hipStream_t s);
-hipError_t launch_xdrop_lanes(const XdlArgs &a, int waves, hipStream_t s);
-int xdrop_lanes_waves_per_cu(); // resident wavefronts per CU
+// tb: the form that also writes traceback codes (4 x 8 bytes per side and
+// antidiagonal, after the window bases)
+hipError_t launch_xdrop_lanes(bool tb, const XdlArgs &a, int waves, hipStream_t s);
+int xdrop_lanes_waves_per_cu(bool tb); // resident wavefronts per CU
 size_t xdrop_lanes_lds_bytes();
 hipError_t launch_search(const SearchArgs &a, hipStream_t s);
 // elt_bytes 1 (uint8 triangle) or 2 (int16); block 256, 512 or 1024 threads;

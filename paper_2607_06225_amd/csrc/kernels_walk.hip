@@ -355,6 +355,15 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
 // i) - dbase(k), lane e / RD, slot e mod RD.  A block is 64 antidiagonals:
 // 2048*S bytes of codes plus 64 window bases.
 //
+// S = 1 is the layout of the sixteen-sides X-drop kernel: per antidiagonal 32
+// bytes, the 64 cells of its window; cell (i, j) of antidiagonal k sits at
+// pos = ((j - i) - dbase(k) - (k & 1)) / 2, byte 8 (pos >> 4) + 4 ((pos >> 3)
+// & 1) + (7 - (pos & 7)) / 2, the high nibble for even pos.  Its low two bits
+// say "not the diagonal" and "not E" (the walk maps them to its diagonal / E
+// / F choice); bits 2 and 3 are the opening bits as in the other layouts.  A
+// pair that overflowed that kernel's window is marked in its task (aux) and
+// walked in the S = 2 layout by the pass that recomputed it.
+//
 // The walk advances by whole runs.  The two most recent blocks (the one
 // holding the walk's antidiagonal and the one before) stay in two LDS slots,
 // and the next older block is in flight in registers.  Every lane m < 32
@@ -377,8 +386,10 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
   __shared__ uint8_t qwin[256], rwin[256];
   const int lane = threadIdx.x;
   const int task = blockIdx.x;
-  if (task >= a.ntasks) return;
+  const int ntasks = a.dyn_ntasks ? min(*a.dyn_ntasks, a.ntasks) : a.ntasks;
+  if (task >= ntasks) return;
   const PairTask tk = a.tasks[task];
+  if (S == 1 && tk.aux != 0) return; // recomputed and walked in the S = 2 layout
   const int p = tk.pair;
   aln_result *res = a.res + p;
   const int status = uni(res->status);
@@ -399,8 +410,9 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
   const uint8_t *Qs = a.b.q + a.b.q_off[p];
   const uint8_t *Rs = a.b.r + a.b.r_off[p];
   const int RD = uni(tk.rows);
-  // S: code bytes per lane and antidiagonal pair
-  constexpr int blk_bytes = 2048 * S;    // one block: 32 antidiagonal pairs x 64 lanes
+  // S: code bytes per lane and antidiagonal pair (S = 1: 32 bytes per
+  // antidiagonal)
+  constexpr int blk_bytes = 2048 * S;    // one block: 64 antidiagonals
   constexpr int n4 = 2 * S;              // uint4 per lane per block
   static_assert(n4 <= kPre, "block larger than the prefetch registers");
   const int inv = (65536 + RD - 1) / RD; // e / RD = (e * inv) >> 16 for 0 <= e < 64*RD
@@ -415,12 +427,13 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
   uint4 pre[kPre];
   int pre_aux = 0, pre_blk = -1, cur = -1;
   auto fetch = [&](int b) {
-    const int pairs = min(32, nks - b * 32);
-    const uint4 *src = cod + (size_t)b * 128 * S; // 32 pairs x 64 lanes x S bytes
+    // uint4 of the block that hold stored antidiagonals
+    const int have = S == 1 ? min(64, nk - b * 64) * 2 : min(32, nks - b * 32) * 4 * S;
+    const uint4 *src = cod + (size_t)b * 128 * S; // 2048 S bytes per block
 #pragma unroll
     for (int m = 0; m < kPre; ++m) {
       const int u = lane + 64 * m;
-      if (m < n4) pre[m] = u < pairs * 4 * S ? src[u] : make_uint4(0u, 0u, 0u, 0u);
+      if (m < n4) pre[m] = u < have ? src[u] : make_uint4(0u, 0u, 0u, 0u);
     }
     pre_aux = dbh[b * 64 + lane];
     pre_blk = b;
@@ -454,6 +467,18 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
   auto code_at = [&](int ii, int jj, bool &bad_lane) -> int {
     const int kk = ii + jj;
     const int slot = (kk >> 6) & 1;
+    if (S == 1) {
+      const int pos = ((jj - ii) - dbl[slot][kk & 63] - (kk & 1)) >> 1;
+      if ((unsigned)pos >= 64u) {
+        bad_lane = true;
+        return 0;
+      }
+      const int byte = slot * blk_bytes + (kk & 63) * 32 + (pos >> 4) * 8 + ((pos >> 3) & 1) * 4 +
+                       ((7 - (pos & 7)) >> 1);
+      const int c = (codes0[byte] >> (((7 - (pos & 7)) & 1) * 4)) & 15;
+      // not-diagonal, not-E -> 0 diagonal, 1 E, 2 F
+      return (c & 12) | ((c & 1) + (c & (c >> 1) & 1));
+    }
     const int e = (jj - ii) - dbl[slot][kk & 63];
     if ((unsigned)e >= (unsigned)(64 * RD)) {
       bad_lane = true;
@@ -630,6 +655,8 @@ hipError_t launch_walk_diag(const WalkArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(walk_diag_wave<8>, dim3(a.ntasks), dim3(64), (size_t)2 * 2048 * 8, s, a);
   else if (a.diag_stride == 2)
     hipLaunchKernelGGL(walk_diag_wave<2>, dim3(a.ntasks), dim3(64), (size_t)2 * 2048 * 2, s, a);
+  else if (a.diag_stride == 1)
+    hipLaunchKernelGGL(walk_diag_wave<1>, dim3(a.ntasks), dim3(64), (size_t)2 * 2048 * 1, s, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -42,6 +42,16 @@
 // side in LDS rings (query reversed) and read as one unaligned 16-byte run
 // per lane and antidiagonal.
 //
+// Traceback codes (the form with CIGAR): per antidiagonal and side 32 bytes,
+// 8 per lane, written by the lanes that hold a candidate cell, plus the
+// window base.  Cell m of a lane sits in dword m >> 3 at nibble 7 - (m & 7);
+// its bits, high to low: F passed down opened from H (F-open), E passed right
+// opened from H (E-open), H not from E, H not from the diagonal -- so H takes
+// the diagonal, then E, then F, and a gap opens before it extends.  The codes
+// of a survivor are those of the pruned recurrence: every value compared on
+// the optimal path is at or above its antidiagonal's threshold, hence not a
+// stale one.
+//
 // Best cell: keys (H' << 6 | pos) give, per antidiagonal, the highest score
 // and among equals the largest d (smallest i); the running best is the score
 // with a key (-i, -j) for ties.  Survivor bounds come from per-lane survivor
@@ -104,6 +114,14 @@ __device__ __forceinline__ void ring16(const uint8_t *ring, int addr, uint32_t (
   for (int k = 0; k < 4; ++k) w[k] = __builtin_amdgcn_alignbyte(x[k + 1], x[k], sh);
 }
 
+// v = 2 v + bit, the bit taken from a compare's lane mask as a carry
+__device__ __forceinline__ void shift_in(uint32_t &v, bool bit) {
+  const unsigned long long km = __builtin_amdgcn_ballot_w64(bit);
+  unsigned long long cc;
+  asm("v_addc_co_u32_e64 %0, %1, %2, %2, %3" : "=v"(v), "=s"(cc) : "v"(v), "s"(km));
+  (void)cc;
+}
+
 // byte b of the result = byte 3 - b of x
 __device__ __forceinline__ uint32_t byte_reverse(uint32_t x) {
   return __builtin_amdgcn_perm(0u, x, 0x00010203u);
@@ -111,7 +129,11 @@ __device__ __forceinline__ uint32_t byte_reverse(uint32_t x) {
 
 } // namespace
 
-__global__ __launch_bounds__(64) void xdrop_lanes_kernel(XdlArgs a) {
+// three wavefronts per SIMD: the form with traceback needs a few registers
+// more than fit, and spills two of them on its task-start path
+template <bool TB>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void
+xdrop_lanes_kernel(XdlArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int lane = threadIdx.x & 63;
   const int gl = lane & 3;        // lane within the side's quad
@@ -140,6 +162,8 @@ __global__ __launch_bounds__(64) void xdrop_lanes_kernel(XdlArgs a) {
   uint32_t best_key = 0; // its cell: (0xffff - i) << 16 | (0xffff - j)
   long long cells = 0;
   const uint8_t *Q = nullptr, *R = nullptr;
+  int *tb_base = nullptr;   // traceback: window base per antidiagonal
+  uint2 *tb_codes = nullptr; // traceback: 4 x 8 bytes per antidiagonal
 
   // 32 codes per call into a ring (the query reversed), padding (4) past
   // the sequence; lane gl stages codes top + 8gl .. top + 8gl + 7
@@ -194,6 +218,12 @@ __global__ __launch_bounds__(64) void xdrop_lanes_kernel(XdlArgs a) {
           } else {
             Q = a.b.q + a.b.q_off[pair];
             R = a.b.r + a.b.r_off[pair];
+            if (TB) {
+              const int nk = M + N + 1;
+              uint8_t *tbp = a.tb + a.tasks[t].tb_off;
+              tb_base = reinterpret_cast<int *>(tbp);
+              tb_codes = reinterpret_cast<uint2 *>(tbp + (size_t)((nk + 63) / 64) * 64 * 4);
+            }
             fresh = true; // arrays reset below, outside this loop
             base = -64;
             k = 1;
@@ -277,7 +307,7 @@ __global__ __launch_bounds__(64) void xdrop_lanes_kernel(XdlArgs a) {
       }
       // ---- the cells
       int kmax = INT32_MIN;
-      uint32_t sb = 0;
+      uint32_t sb = 0, code0 = 0, code1 = 0;
       const int xin = P == 0 ? quad_shr1(E1[XC - 1], XNEG, qfirst)
                              : quad_shl1(F0[0], XNEG, qlast);
 #pragma unroll
@@ -302,10 +332,18 @@ __global__ __launch_bounds__(64) void xdrop_lanes_kernel(XdlArgs a) {
         }
         kmax = max(kmax, (h << 6) | m); // a removed cell never beats a kept one
         // shift the survivor bit in: sb = 2 sb + keep (cell m ends at bit 15 - m)
-        const unsigned long long km = __builtin_amdgcn_ballot_w64(keep);
-        unsigned long long cc;
-        asm("v_addc_co_u32_e64 %0, %1, %2, %2, %3" : "=v"(sb), "=s"(cc) : "v"(sb), "s"(km));
-        (void)cc;
+        shift_in(sb, keep);
+        if (TB) { // the cell's code, high bit first
+          uint32_t &c = m < 8 ? code0 : code1;
+          shift_in(c, t >= fin);
+          shift_in(c, t >= ein);
+          shift_in(c, ein < h);
+          shift_in(c, hp + s < h);
+        }
+      }
+      if (TB && active) {
+        if (inr_rev) tb_codes[(size_t)k * 4 + gl] = make_uint2(code0, code1);
+        if (qfirst) tb_base[k] = base;
       }
       sb &= inr_rev;
       // ---- the antidiagonal's outcome per side
@@ -340,6 +378,9 @@ __global__ __launch_bounds__(64) void xdrop_lanes_kernel(XdlArgs a) {
         if (qfirst) {
           aln_result *res = a.res + pair;
           if (wide) {
+            // score only: the wider one-side kernel; with traceback: the
+            // one-side pass that writes codes in its own layout (the walk of
+            // this layout skips the pair, marked in its task)
             res->flags |= ALN_F_WIDENED;
             const int slot = atomicAdd(a.widen_count, 1);
             const PairTask *src = a.tasks + task;
@@ -349,7 +390,8 @@ __global__ __launch_bounds__(64) void xdrop_lanes_kernel(XdlArgs a) {
             dst->tb_off = src->tb_off;
             dst->cigar_off = src->cigar_off;
             dst->cigar_cap = src->cigar_cap;
-            dst->aux = src->aux;
+            dst->aux = 0;
+            if (TB) const_cast<PairTask *>(a.tasks)[task].aux = 1;
           } else {
             res->score = best;
             res->q_end = 0xffff - (int)(best_key >> 16);
@@ -435,17 +477,23 @@ __global__ __launch_bounds__(64) void xdrop_lanes_kernel(XdlArgs a) {
 
 size_t xdrop_lanes_lds_bytes() { return (size_t)kSides * 2 * kRingStride; }
 
-hipError_t launch_xdrop_lanes(const XdlArgs &a, int waves, hipStream_t s) {
+hipError_t launch_xdrop_lanes(bool tb, const XdlArgs &a, int waves, hipStream_t s) {
   if (a.ntasks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(xdrop_lanes_kernel, dim3(waves), dim3(64), xdrop_lanes_lds_bytes(), s, a);
+  if (tb)
+    hipLaunchKernelGGL(xdrop_lanes_kernel<true>, dim3(waves), dim3(64), xdrop_lanes_lds_bytes(), s, a);
+  else
+    hipLaunchKernelGGL(xdrop_lanes_kernel<false>, dim3(waves), dim3(64), xdrop_lanes_lds_bytes(), s, a);
   return hipGetLastError();
 }
 
-int xdrop_lanes_waves_per_cu() {
+int xdrop_lanes_waves_per_cu(bool tb) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, xdrop_lanes_kernel, 64,
-                                                   xdrop_lanes_lds_bytes()) != hipSuccess)
-    return 4;
+  const hipError_t e =
+      tb ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, xdrop_lanes_kernel<true>, 64,
+                                                        xdrop_lanes_lds_bytes())
+         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, xdrop_lanes_kernel<false>, 64,
+                                                        xdrop_lanes_lds_bytes());
+  if (e != hipSuccess) return 4;
   return nb > 0 ? nb : 1;
 }
 

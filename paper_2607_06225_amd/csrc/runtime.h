@@ -86,7 +86,11 @@ struct aln_plan {
   uint64_t sw16_off = 0, sw16_items_off = 0, sw16_single_off = 0, rerun_cnt_off = 0, rerun_off = 0;
   alnrt::LaunchDesc rerun{};
   // X-drop widening queues: counters (ws offset) and two queues of n tasks
-  uint64_t widen_cnt_off = 0, widen_off[2] = {0, 0};
+  uint64_t widen_cnt_off = 0, widen_off[3] = {0, 0, 0};
+  // X-drop with CIGAR on the sixteen-sides kernel (codes 32 B per antidiagonal);
+  // pairs that outgrow its window go to the one-side pass with codes (queue 2)
+  bool xtb_lanes = false;
+  int xtb_grid = 0;
   bool xdrop = false;
   int32_t n_strip_tb = 0, first_diag_tb = 0, n_diag_tb = 0; // walk ranges
   int32_t xtb_first = 0, xtb_count = 0; // X-drop / Z-drop traceback-pass tasks

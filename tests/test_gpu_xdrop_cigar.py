@@ -13,7 +13,10 @@ from tests.parity import oracle_batch
 
 pytestmark = pytest.mark.gpu
 
-TILES = [(4, 1), (8, 4)]  # score pass: (diagonals per lane, extension sides per wavefront)
+# (window per lane, extension sides per wavefront): for X-drop, (4, 16) is the
+# sixteen-sides kernel writing 32-byte codes per antidiagonal, the others the
+# one-side pass with codes; Z-drop always takes the one-side pass
+TILES = [(4, 1), (8, 4), (4, 16)]
 WINDOW_SPAN = 250          # widest candidate span the traceback window holds
 
 

@@ -236,3 +236,121 @@ def test_lanes_extension_workload_sample(ctx):
     b = W.xdrop_ext(n=4000, seed=4141)
     res, _ = run(ctx, b)
     assert compare(b, res, None, oracle_batch(b)) == []
+
+
+# ---------------------------------------------------------------- with CIGAR
+def cigar_check(b, res, cig):
+    from tests.test_gpu_xdrop_cigar import check
+    return check(b, res, cig, oracle_batch(b, want_cigar=True))
+
+
+def cbatch(qs, rs, X, match=2, mismatch=-4, go=-4, ge=-2, A=4, name="lanes_cigar"):
+    m = np.full((A, A), mismatch, dtype=np.int32)
+    np.fill_diagonal(m, match)
+    return W.pack_pairs(qs, rs, m, go, ge, W.EXTEND, W.XDROP, xdrop=X, want_cigar=True,
+                        name=name)
+
+
+def families(ctx, b, **kw):
+    from paper_2607_06225_amd import aln
+    ctx.set_tuning({"valid": 0})
+    ctx.set_profiling(True)
+    try:
+        res, cig = aln.align(ctx, b, **kw)
+        fams = ctx.kernel_times()
+    finally:
+        ctx.set_profiling(False)
+    return res, cig, fams
+
+
+@pytest.mark.parametrize("X", [0, 7, 30, 100, 131])
+def test_lanes_cigar_edge_shapes(ctx, X):
+    rng = np.random.default_rng(1300 + X)
+    lengths = EDGE + [(int(rng.integers(1, 900)), int(rng.integers(1, 900))) for _ in range(60)]
+    qs, rs = pairs(rng, lengths)
+    b = cbatch(qs, rs, X, name=f"lanes_cigar_X{X}")
+    res, cig, fams = families(ctx, b)
+    assert "xdrop_lanes_tb" in fams, fams
+    assert cigar_check(b, res, cig) == []
+
+
+@pytest.mark.parametrize("sc", SCORINGS)
+def test_lanes_cigar_scorings(ctx, sc):
+    match, mismatch, go, ge, X = sc
+    rng = np.random.default_rng(abs(hash(("c",) + sc)) % (1 << 31))
+    lengths = EDGE + [(int(rng.integers(1, 600)), int(rng.integers(1, 600))) for _ in range(40)]
+    qs, rs = pairs(rng, lengths, rate=0.1)
+    b = cbatch(qs, rs, X, match, mismatch, go, ge, name=f"lanes_cigar_sc{sc}")
+    res, cig, fams = families(ctx, b)
+    assert "xdrop_lanes_tb" in fams, fams
+    assert cigar_check(b, res, cig) == []
+
+
+def test_lanes_cigar_window_slides(ctx):
+    rng = np.random.default_rng(78)
+    qs, rs = [], []
+    for k in range(40):
+        ref = rng.integers(0, 4, size=int(rng.integers(600, 2000))).astype(np.uint8)
+        q = ref.copy()
+        pos = 80
+        while pos < len(q) - 60:
+            g = int(rng.integers(3, 25))
+            if rng.random() < 0.5:
+                q = np.concatenate([q[:pos], q[pos + g:]])
+            else:
+                q = np.concatenate([q[:pos], rng.integers(0, 4, size=g).astype(np.uint8),
+                                    q[pos:]])
+            pos += int(rng.integers(60, 200))
+        sub = rng.random(len(q)) < 0.03
+        q[sub] = (q[sub] + 1) % 4
+        qs.append(q)
+        rs.append(ref)
+    for X in (60, 131):
+        b = cbatch(qs, rs, X, name=f"lanes_cigar_slide_X{X}")
+        res, cig, _ = families(ctx, b)
+        assert cigar_check(b, res, cig) == []
+
+
+@pytest.mark.parametrize("sc", [(1, -1, 0, -1, 129), (1, -2, 0, 0, 127)])
+def test_lanes_cigar_overflow_goes_to_one_side_pass(ctx, sc):
+    """Regions wider than 64 cells: the one-side pass recomputes the pair with
+    its own codes (CIGAR up to a 250-diagonal span, CIGAR_CAP beyond), the
+    rest keep the sixteen-sides kernel's codes; all as the oracle says."""
+    from paper_2607_06225_amd import aln
+    match, mismatch, go, ge, X = sc
+    rng = np.random.default_rng(15)
+    qs, rs = [], []
+    for L in (50, 300, 600, 1500):
+        x = rng.integers(0, 4, size=L).astype(np.uint8)
+        qs.append(x)
+        rs.append(x.copy())
+    qs2, rs2 = pairs(rng, [(400, 400)] * 6, rate=0.2)
+    b = cbatch(qs + qs2, rs + rs2, X, match, mismatch, go, ge, name=f"lanes_cigar_ovf{sc}")
+    res, cig, fams = families(ctx, b)
+    assert "xdrop_lanes_tb" in fams and "xdrop_tb" in fams, fams
+    assert cigar_check(b, res, cig) == []
+    assert all(int(f) & aln.F_WIDENED for f in res["flags"][1:4])
+
+
+def test_lanes_cigar_per_pair_and_graph_match(ctx):
+    rng = np.random.default_rng(16)
+    qs, rs = pairs(rng, [(300, 310), (50, 60), (800, 790), (0, 4), (1, 1)])
+    qi = rng.integers(0, 4, size=500).astype(np.uint8)
+    qs.append(qi)
+    rs.append(qi.copy())
+    b = cbatch(qs, rs, 129, 1, -1, 0, -1, name="lanes_cigar_pp")
+    r1, c1, _ = families(ctx, b)
+    r2, c2, _ = families(ctx, b, per_pair=True)
+    r3, c3, _ = families(ctx, b, graph=True)
+    assert np.array_equal(r1, r2) and np.array_equal(r1, r3)
+    assert all(np.array_equal(x, y) for x, y in zip(c1, c2))
+    assert all(np.array_equal(x, y) for x, y in zip(c1, c3))
+    assert cigar_check(b, r1, c1) == []
+
+
+def test_lanes_cigar_workload_sample(ctx):
+    b = W.xdrop_ext(n=1200, seed=4242)
+    b.want_cigar = True
+    res, cig, fams = families(ctx, b)
+    assert "xdrop_lanes_tb" in fams, fams
+    assert cigar_check(b, res, cig) == []
