@@ -215,6 +215,16 @@ int32_t aln_abi_version(void);
 /* Create a context on HIP device `device`; the context owns scoring tables,
  * plans' staging memory, streams of the server and the autotune cache. */
 aln_status aln_create(aln_ctx **ctx, int32_t device);
+
+/* A context without a device, for planning only (capacity planning, host
+ * tests of the planner): aln_set_scoring keeps the scheme on the host,
+ * aln_plan_create / aln_fold_plan_create plan and report footprints,
+ * aln_plan_describe lists the launches and tasks.  Every call that would
+ * touch a device (execute, graph capture, autotune, server, probe) returns
+ * ALN_E_DEVICE after its argument checks.  cus and lds_per_cu stand in for
+ * the device's compute units and LDS bytes per CU (0: 256 and 160 KiB, an
+ * MI355X).  Errors: ALN_E_INVAL (negative sizes), ALN_E_NOMEM. */
+aln_status aln_create_host(aln_ctx **ctx, int32_t cus, int32_t lds_per_cu);
 void aln_destroy(aln_ctx *ctx);
 /* Message of the last failed call on ctx (empty string if none). */
 const char *aln_last_error(const aln_ctx *ctx);
@@ -231,6 +241,39 @@ aln_status aln_plan_create(aln_ctx *ctx, int32_t scoring_id,
                            const aln_params *params, int32_t n,
                            const int32_t *q_len_host, const int32_t *r_len_host,
                            aln_plan **plan, aln_footprint *fp);
+
+/* One kernel launch of a plan's fill (re-runs that depend on device results
+ * -- widening, int32 re-runs -- and the walks are not listed). */
+typedef struct {
+  char family[24];  /* "sw16", "strip_i32", "diag_band", "xdrop_lanes",
+                       "xdrop_lanes_tb", "xdrop_group", "xdrop", "xdrop_tb",
+                       "zdrop", "zdrop_tb", "search", "search_affine", "fold" */
+  int32_t tile;     /* rows or window per lane (fold: triangle row stride)   */
+  int32_t sides;    /* X-drop: sides per wavefront; sw16: 2 pairs per lane;
+                       strips: wavefronts per pair; fold: bytes per element  */
+  int32_t first;    /* its tasks in the plan's task list                     */
+  int32_t count;
+} aln_launch_info;  /* 40 bytes */
+
+/* One pair (sequence, for folding) as a launch runs it. */
+typedef struct {
+  int32_t launch;    /* index into the launches                              */
+  int32_t pair;      /* index into the batch                                 */
+  int64_t tb_off;    /* its traceback codes in the workspace's traceback
+                        area (-1: none)                                      */
+  int64_t tb_bytes;  /* bytes reserved for them                              */
+  int64_t cigar_off; /* first word of its CIGAR slot (-1: no CIGAR)          */
+  int32_t cigar_cap; /* words in the slot                                    */
+  int32_t tile;      /* as the launch's, per task                            */
+} aln_task_info;     /* 40 bytes */
+
+/* Describe a plan: fills up to max_launches launches and up to max_tasks
+ * tasks (either pointer may be null to count only), sets *n_launches (may
+ * be null) and returns the number of tasks (a packed int16 task of two pairs
+ * counts twice), or ALN_E_INVAL.  Host work only. */
+int64_t aln_plan_describe(const aln_plan *plan, aln_launch_info *launches,
+                          int32_t max_launches, int32_t *n_launches,
+                          aln_task_info *tasks, int64_t max_tasks);
 void aln_plan_destroy(aln_plan *plan);
 
 /* Run a plan on a batch whose lengths equal those it was planned with.

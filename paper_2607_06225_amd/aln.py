@@ -99,6 +99,16 @@ COMPLETION_DTYPE = np.dtype(
        ("t_submit", "<f8"), ("t_launch", "<f8"), ("t_done", "<f8")])
 assert COMPLETION_DTYPE.itemsize == 104
 
+class _LaunchInfo(ctypes.Structure):
+    _fields_ = [("family", ctypes.c_char * 24), ("tile", ctypes.c_int32),
+                ("sides", ctypes.c_int32), ("first", ctypes.c_int32), ("count", ctypes.c_int32)]
+
+
+TASK_INFO_DTYPE = np.dtype([("launch", np.int32), ("pair", np.int32), ("tb_off", np.int64),
+                            ("tb_bytes", np.int64), ("cigar_off", np.int64),
+                            ("cigar_cap", np.int32), ("tile", np.int32)])
+
+
 class _Tuning(ctypes.Structure):
     _fields_ = [("valid", ctypes.c_int32), ("sw16_rows", ctypes.c_int32),
                 ("strip_rows", ctypes.c_int32), ("xdrop_rows", ctypes.c_int32),
@@ -115,8 +125,8 @@ _lib = None
 
 # every symbol include/aln.h declares
 EXPORTS = [
-    "aln_abi_version", "aln_create", "aln_destroy", "aln_last_error",
-    "aln_set_scoring", "aln_plan_create", "aln_plan_destroy", "aln_execute",
+    "aln_abi_version", "aln_create", "aln_create_host", "aln_destroy", "aln_last_error",
+    "aln_set_scoring", "aln_plan_create", "aln_plan_describe", "aln_plan_destroy", "aln_execute",
     "aln_execute_noalloc", "aln_execute_per_pair", "aln_graph_capture", "aln_graph_launch",
     "aln_set_profiling", "aln_kernel_times", "aln_autotune", "aln_get_tuning", "aln_set_tuning",
     "aln_valu_probe", "aln_fold_plan_create", "aln_fold_execute",
@@ -137,6 +147,8 @@ def load_library(path=LIB_PATH):
     sig = {
         "aln_abi_version": ([], I32),
         "aln_create": ([P, I32], I32),
+        "aln_create_host": ([P, I32, I32], I32),
+        "aln_plan_describe": ([P, P, I32, P, P, ctypes.c_int64], ctypes.c_int64),
         "aln_destroy": ([P], None),
         "aln_last_error": ([P], ctypes.c_char_p),
         "aln_set_scoring": ([P, P, P], I32),
@@ -194,6 +206,21 @@ class Plan:
         self.n = n
         self.params = params
 
+    def describe(self):
+        """(launches, tasks) of aln_plan_describe: a list of dicts and an
+        ndarray of TASK_INFO_DTYPE."""
+        nl = ctypes.c_int32()
+        nt = int(self.ctx.lib.aln_plan_describe(self.handle, None, 0, ctypes.byref(nl), None, 0))
+        if nt < 0:
+            raise AlnError(f"aln_plan_describe failed ({nt})")
+        L = (_LaunchInfo * max(nl.value, 1))()
+        tasks = np.zeros(nt, dtype=TASK_INFO_DTYPE)
+        self.ctx.lib.aln_plan_describe(self.handle, L, nl.value, ctypes.byref(nl),
+                                       tasks.ctypes.data, nt)
+        launches = [dict(family=L[k].family.decode(), tile=int(L[k].tile), sides=int(L[k].sides),
+                         first=int(L[k].first), count=int(L[k].count)) for k in range(nl.value)]
+        return launches, tasks
+
     def close(self):
         if self.handle is not None:
             self.ctx.lib.aln_plan_destroy(self.handle)
@@ -232,6 +259,19 @@ class Context:
         h = ctypes.c_void_p()
         self._check(self.lib.aln_create(ctypes.byref(h), int(device)), None)
         self.handle = h
+
+    @classmethod
+    def host(cls, cus=0, lds_per_cu=0):
+        """A context without a device (aln_create_host): planning and
+        footprints only; anything that would run on a device raises."""
+        self = cls.__new__(cls)
+        self.lib = load_library()
+        self.device = -1
+        h = ctypes.c_void_p()
+        self.handle = None
+        self._check(self.lib.aln_create_host(ctypes.byref(h), int(cus), int(lds_per_cu)), None)
+        self.handle = h
+        return self
 
     def _check(self, rc, handle="self"):
         if rc != 0:

@@ -120,8 +120,24 @@ aln_status aln_create(aln_ctx **ctx, int32_t device) {
   return ALN_OK;
 }
 
+aln_status aln_create_host(aln_ctx **ctx, int32_t cus, int32_t lds_per_cu) {
+  if (!ctx || cus < 0 || lds_per_cu < 0) return ALN_E_INVAL;
+  *ctx = nullptr;
+  aln_ctx *c = new (std::nothrow) aln_ctx;
+  if (!c) return ALN_E_NOMEM;
+  c->device = -1;
+  if (cus > 0) c->cus = cus;
+  if (lds_per_cu > 0) c->lds_per_cu = lds_per_cu;
+  *ctx = c;
+  return ALN_OK;
+}
+
 void aln_destroy(aln_ctx *ctx) {
   if (!ctx) return;
+  if (ctx->device < 0) {
+    delete ctx;
+    return;
+  }
   (void)hipSetDevice(ctx->device);
   for (DevScoring *d : ctx->dsc) (void)hipFree(d);
   for (auto &t : ctx->timed) {
@@ -204,6 +220,12 @@ aln_status aln_set_scoring(aln_ctx *ctx, const aln_scoring *sc, int32_t *scoring
     }
     h.rowtab[a] = w;
   }
+  if (ctx->device < 0) { // no device: the host mirror only
+    ctx->dsc.push_back(nullptr);
+    ctx->hsc.push_back(h);
+    *scoring_id = (int32_t)ctx->dsc.size() - 1;
+    return ALN_OK;
+  }
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   DevScoring *d = nullptr;
   HIP_TRY(ctx, hipMalloc(&d, sizeof(DevScoring)));
@@ -219,6 +241,48 @@ aln_status aln_set_scoring(aln_ctx *ctx, const aln_scoring *sc, int32_t *scoring
 }
 
 } // extern "C"
+
+// Resident wavefronts per CU of the sixteen-sides X-drop kernel: the
+// device's occupancy, or three per SIMD (its register count) without one.
+static int lanes_waves_per_cu(const aln_ctx *ctx, bool tb) {
+  return ctx->device < 0 ? 12 : alnk::xdrop_lanes_waves_per_cu(tb);
+}
+
+// Interior cells (1 <= i <= M, 1 <= j <= N) of the static band: row i keeps
+// floor(iN/M) - w <= j <= floor(iN/M) + w.  Rows whose band is clipped by
+// column 1 or column N are counted one by one (the centre floor(iN/M) is
+// non-decreasing in i, so they form a prefix and a suffix of the rows); every
+// other row holds 2w + 1 cells.
+static int64_t band_cells(int64_t M, int64_t N, int64_t w) {
+  if (M <= 0 || N <= 0) return 0;
+  if (w >= std::max(M, N)) return M * N;
+  auto centre = [&](int64_t i) { return i * N / M; };
+  auto row = [&](int64_t i) {
+    const int64_t lo = std::max<int64_t>(1, centre(i) - w), hi = std::min(N, centre(i) + w);
+    return hi >= lo ? hi - lo + 1 : 0;
+  };
+  // last row clipped on the left (centre <= w), first clipped on the right
+  int64_t a = 0, lo = 1, hi = M;
+  while (lo <= hi) {
+    const int64_t mid = (lo + hi) / 2;
+    if (centre(mid) <= w) { a = mid; lo = mid + 1; } else { hi = mid - 1; }
+  }
+  int64_t b = M + 1;
+  lo = 1;
+  hi = M;
+  while (lo <= hi) {
+    const int64_t mid = (lo + hi) / 2;
+    if (centre(mid) + w > N) { b = mid; hi = mid - 1; } else { lo = mid + 1; }
+  }
+  int64_t total = 0;
+  if (b <= a + 1) {
+    for (int64_t i = 1; i <= M; ++i) total += row(i);
+    return total;
+  }
+  for (int64_t i = 1; i <= a; ++i) total += row(i);
+  for (int64_t i = b; i <= M; ++i) total += row(i);
+  return total + (b - a - 1) * (2 * w + 1);
+}
 
 aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params *params, int32_t n,
                              const int32_t *q_len_host, const int32_t *r_len_host,
@@ -557,6 +621,7 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
                       i, (long long)width);
         }
         it.cost = (double)(M + N) * it.rows;
+        pl->cells += band_cells(M, N, p.band_w);
       } else {
         it.rows = ctx->tuning.valid ? ctx->tuning.xdrop_rows : 4;
         if (ctx->force_xdrop_rows) it.rows = ctx->force_xdrop_rows;
@@ -625,7 +690,7 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
       if (L.sides == 4 && L.rows != 8) L.sides = 1;
       if (L.sides == 16) {
         const int64_t want = ((int64_t)(e - k) + 15) / 16;
-        const int64_t fit = (int64_t)ctx->cus * alnk::xdrop_lanes_waves_per_cu(false);
+        const int64_t fit = (int64_t)ctx->cus * lanes_waves_per_cu(ctx, false);
         L.grid = (int)std::max<int64_t>(1, std::min(want, fit));
       }
     }
@@ -688,7 +753,7 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     pl->xtb_lanes = lanes_fit && tuned_sides == 16;
     if (pl->xtb_lanes) {
       const int64_t want = ((int64_t)n + 15) / 16;
-      const int64_t fit = (int64_t)ctx->cus * alnk::xdrop_lanes_waves_per_cu(true);
+      const int64_t fit = (int64_t)ctx->cus * lanes_waves_per_cu(ctx, true);
       pl->xtb_grid = (int)std::max<int64_t>(1, std::min(want, fit));
     }
     std::vector<int32_t> order(n);
@@ -767,11 +832,9 @@ aln_status aln_plan_create(aln_ctx *ctx, int32_t scoring_id, const aln_params *p
   aln_plan *pl = nullptr;
   aln_status st = plan_build(ctx, scoring_id, params, n, q_len_host, r_len_host, &pl);
   if (st != ALN_OK) return st;
-  if (hipHostMalloc(&pl->pinned, std::max<uint64_t>(pl->upload_bytes, 1), hipHostMallocDefault) !=
-      hipSuccess) {
+  if (alnrt::plan_alloc_staging(pl) != ALN_OK) {
     delete pl;
-    return fail(ctx, ALN_E_NOMEM, "pinned staging for %llu bytes",
-                (unsigned long long)pl->upload_bytes);
+    return fail(ctx, ALN_E_NOMEM, "staging for %llu bytes", (unsigned long long)pl->upload_bytes);
   }
   plan_stage(pl, pl->pinned);
   if (fp) {
@@ -788,7 +851,10 @@ void aln_plan_destroy(aln_plan *plan) {
   if (!plan) return;
   if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
   if (plan->graph) (void)hipGraphDestroy(plan->graph);
-  if (plan->pinned && plan->own_pinned) (void)hipHostFree(plan->pinned);
+  if (plan->pinned && plan->own_pinned) {
+    if (plan->host_staging) std::free(plan->pinned);
+    else (void)hipHostFree(plan->pinned);
+  }
   delete plan;
 }
 
@@ -809,7 +875,19 @@ aln_status alnrt::exec_check(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, v
   if (plan->p.want_cigar && (!d_cigar || cigar_words < plan->cigar_words))
     return fail(ctx, ALN_E_CAPACITY, "CIGAR buffer %llu < %llu words",
                 (unsigned long long)cigar_words, (unsigned long long)plan->cigar_words);
+  if (ctx->device < 0) return fail(ctx, ALN_E_DEVICE, "the context has no device");
   return ALN_OK;
+}
+
+aln_status alnrt::plan_alloc_staging(aln_plan *pl) {
+  const size_t bytes = (size_t)std::max<uint64_t>(pl->upload_bytes, 1);
+  if (pl->ctx->device < 0) {
+    pl->pinned = std::malloc(bytes);
+    pl->host_staging = true;
+    return pl->pinned ? ALN_OK : ALN_E_NOMEM;
+  }
+  return hipHostMalloc(&pl->pinned, bytes, hipHostMallocDefault) == hipSuccess ? ALN_OK
+                                                                               : ALN_E_NOMEM;
 }
 
 extern "C" {
@@ -1159,6 +1237,97 @@ aln_status aln_graph_capture(aln_ctx *ctx, aln_plan *plan, const aln_batch *batc
   return ALN_OK;
 }
 
+int64_t aln_plan_describe(const aln_plan *plan, aln_launch_info *launches, int32_t max_launches,
+                          int32_t *n_launches, aln_task_info *tasks, int64_t max_tasks) {
+  if (!plan || max_launches < 0 || max_tasks < 0) return ALN_E_INVAL;
+  int32_t nl = 0;
+  int64_t nt = 0;
+  auto add_launch = [&](const char *fam, int tile, int sides, int64_t first, int64_t count) {
+    if (launches && nl < max_launches) {
+      aln_launch_info &L = launches[nl];
+      memset(&L, 0, sizeof L);
+      std::snprintf(L.family, sizeof L.family, "%s", fam);
+      L.tile = tile;
+      L.sides = sides;
+      L.first = (int32_t)first;
+      L.count = (int32_t)count;
+    }
+    ++nl;
+  };
+  auto add_task = [&](int32_t launch, int32_t pair, int64_t tb_off, int64_t tb_bytes,
+                      int64_t cigar_off, int32_t cigar_cap, int32_t tile) {
+    if (tasks && nt < max_tasks) {
+      aln_task_info &T = tasks[nt];
+      T.launch = launch;
+      T.pair = pair;
+      T.tb_off = tb_off;
+      T.tb_bytes = tb_bytes;
+      T.cigar_off = cigar_off;
+      T.cigar_cap = cigar_cap;
+      T.tile = tile;
+    }
+    ++nt;
+  };
+  // traceback bytes of a task: up to the next reservation (offsets grow in
+  // task order), the last up to the end of the traceback area
+  std::vector<int64_t> tb_end(plan->tasks.size(), (int64_t)plan->tb_bytes);
+  {
+    int64_t next = (int64_t)plan->tb_bytes;
+    for (size_t k = plan->tasks.size(); k-- > 0;) {
+      if (plan->tasks[k].tb_off >= 0) {
+        tb_end[k] = next;
+        next = plan->tasks[k].tb_off;
+      }
+    }
+  }
+  auto pair_tasks = [&](int32_t launch, int64_t first, int64_t count) {
+    for (int64_t k = first; k < first + count; ++k) {
+      const alnk::PairTask &t = plan->tasks[(size_t)k];
+      const bool tb = t.tb_off >= 0 && plan->p.want_cigar;
+      add_task(launch, t.pair, tb ? t.tb_off : -1, tb ? tb_end[(size_t)k] - t.tb_off : 0,
+               plan->p.want_cigar ? t.cigar_off : -1, plan->p.want_cigar ? t.cigar_cap : 0, t.rows);
+    }
+  };
+  if (plan->fold) {
+    for (const auto &F : plan->fold_launches) {
+      const int32_t id = nl;
+      add_launch("fold", F.stride, F.elt, F.first, F.count);
+      for (int32_t k = F.first; k < F.first + F.count; ++k)
+        add_task(id, plan->fold_tasks[(size_t)k].seq, -1, 0, -1, 0, F.stride);
+    }
+  } else if (plan->xtb_count > 0) {
+    const int32_t id = nl;
+    const char *fam = plan->xtb_lanes ? "xdrop_lanes_tb"
+                                      : (plan->p.prune == ALN_ZDROP ? "zdrop_tb" : "xdrop_tb");
+    add_launch(fam, 4, plan->xtb_lanes ? 16 : 1, plan->xtb_first, plan->xtb_count);
+    pair_tasks(id, plan->xtb_first, plan->xtb_count);
+  } else {
+    for (const LaunchDesc &L : plan->launches) {
+      const int32_t id = nl;
+      if (L.kind == K_SW16) {
+        add_launch("sw16", L.rows, 2, L.first, L.count);
+        for (int32_t k = L.first; k < L.first + L.count; ++k) {
+          const alnk::Sw16Task &t = plan->sw16_tasks[(size_t)k];
+          add_task(id, t.pa, -1, 0, -1, 0, L.rows);
+          if (t.pb >= 0) add_task(id, t.pb, -1, 0, -1, 0, L.rows);
+        }
+        continue;
+      }
+      const char *fam = "strip_i32";
+      if (L.kind == K_SEARCH) fam = L.pen_x > 0 ? "search_affine" : "search";
+      if (L.kind == K_DIAG) {
+        if (plan->p.prune == ALN_BAND) fam = "diag_band";
+        else if (plan->p.prune == ALN_ZDROP) fam = L.sides == 4 ? "zdrop_group" : "zdrop";
+        else fam = L.sides == 16 ? "xdrop_lanes" : (L.sides == 4 ? "xdrop_group" : "xdrop");
+      }
+      add_launch(fam, L.rows, L.kind == K_STRIP ? L.waves : L.sides, L.first, L.count);
+      pair_tasks(id, L.first, L.count);
+    }
+  }
+  if (n_launches) *n_launches = nl;
+  return nt;
+}
+
 aln_status aln_graph_launch(aln_ctx *ctx, aln_plan *plan, void *stream) {
   if (!ctx || !plan || !plan->gexec) return fail(ctx, ALN_E_INVAL, "no captured graph");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
@@ -1263,10 +1432,9 @@ aln_status aln_fold_plan_create(aln_ctx *ctx, const aln_fold_params *params, int
   pl->tasks_bytes = align_up(std::max<uint64_t>(pl->upload_bytes, 1));
   pl->ws_bytes = pl->tasks_bytes;
   pl->cells = cells;
-  if (hipHostMalloc(&pl->pinned, std::max<uint64_t>(pl->upload_bytes, 1), hipHostMallocDefault) !=
-      hipSuccess) {
+  if (alnrt::plan_alloc_staging(pl) != ALN_OK) {
     delete pl;
-    return fail(ctx, ALN_E_NOMEM, "pinned staging");
+    return fail(ctx, ALN_E_NOMEM, "staging");
   }
   plan_stage(pl, pl->pinned);
   if (fp) {
@@ -1289,6 +1457,7 @@ aln_status aln_fold_execute(aln_ctx *ctx, aln_plan *plan, const aln_fold_batch *
   if (!d_ws || ws_bytes < plan->ws_bytes)
     return fail(ctx, ALN_E_CAPACITY, "workspace %llu < %llu bytes", (unsigned long long)ws_bytes,
                 (unsigned long long)plan->ws_bytes);
+  if (ctx->device < 0) return fail(ctx, ALN_E_DEVICE, "the context has no device");
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   HIP_TRY(ctx, hipMemcpyAsync(d_ws, plan->pinned, plan->upload_bytes, hipMemcpyHostToDevice, st));

@@ -65,8 +65,18 @@ struct StripArgs {
 
 // Wavefronts per pair of the full-matrix strip pipeline.
 constexpr int kStripPipeWaves = 4;
+constexpr int kStripCtrWords = 7; // per pipeline wave: prog, cons, 5 result words
+// LDS of a G-wavefront pipeline workgroup beyond its buffers and profiles:
+// prog[G], cons[G] and five result words per wave, then the reference codes
+// (N + 128 bytes, the last 128 zero)
+inline size_t strip_extra_bytes(int G, int n) {
+  return G > 1 ? (size_t)kStripCtrWords * G * 4 + (((size_t)n + 128 + 15) & ~(size_t)15) : 0;
+}
 // LDS bytes of one strip-kernel workgroup.
-size_t strip_lds_bytes(int waves, int lds_bnd, int lds_prof, int max_n);
+inline size_t strip_lds_bytes(int waves, int lds_bnd, int lds_prof, int max_n) {
+  const size_t per = (size_t)(lds_bnd + lds_prof);
+  return waves == 1 ? 4 * per : (size_t)waves * per + strip_extra_bytes(waves, max_n);
+}
 
 struct WalkArgs {
   BatchPtrs b;
@@ -205,7 +215,11 @@ struct FoldArgs {
 // Row strides (elements) of the folded triangle, and the LDS bytes of one
 // folding workgroup for sequences up to max_n long (stride >= max_n + 1).
 constexpr int kFoldStrides[4] = {128, 256, 384, 512};
-size_t fold_lds_bytes(int elt_bytes, int stride, int max_n);
+constexpr int kFoldCtlSlots = 3; // per-span survivor / best slots, reused every third span
+inline size_t fold_lds_bytes(int elt_bytes, int stride, int max_n) {
+  return (((size_t)((max_n + 1) / 2) * stride * elt_bytes + 15) & ~(size_t)15) +
+         (((size_t)max_n + 15) & ~(size_t)15) + ((size_t)max_n + 4 * kFoldCtlSlots) * sizeof(int);
+}
 
 // Launchers (defined in the kernel translation units).
 hipError_t launch_validate(const ValidateArgs &a, hipStream_t s);

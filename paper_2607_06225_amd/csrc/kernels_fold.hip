@@ -47,7 +47,6 @@ namespace alnk {
 
 namespace {
 
-constexpr int kFoldCtlSlots = 3; // per-span survivor / best slots, reused every third span
 
 // element traits: minus infinity and the per-term / final encodings
 template <typename T, bool XD> struct FoldElt;
@@ -349,10 +348,6 @@ __global__ __launch_bounds__(B) void fold_kernel(FoldArgs a) {
   }
 }
 
-size_t fold_lds_bytes(int elt_bytes, int stride, int max_n) {
-  return (((size_t)((max_n + 1) / 2) * stride * elt_bytes + 15) & ~(size_t)15) +
-         (((size_t)max_n + 15) & ~(size_t)15) + ((size_t)max_n + 4 * kFoldCtlSlots) * sizeof(int);
-}
 
 template <typename T, bool XD, int B, int SC>
 static hipError_t launch_fold_t(const FoldArgs &a, hipStream_t s) {

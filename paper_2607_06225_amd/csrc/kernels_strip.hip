@@ -45,7 +45,6 @@ __device__ __forceinline__ int wave_max(int v) {
 // The spin bound only turns a broken invariant into ALN_R_INTERNAL instead
 // of a hung workgroup.
 constexpr int kSpinLimit = 1 << 22;
-constexpr int kStripCtrWords = 7; // per pipeline wave: prog, cons, 5 result words
 
 __device__ __forceinline__ bool lds_wait_geq(int *ctr, int need) {
   for (int k = 0; k < kSpinLimit; ++k) {
@@ -453,12 +452,6 @@ hipError_t launch_validate(const ValidateArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// LDS of a G-wavefront pipeline workgroup beyond its buffers and profiles:
-// prog[G], cons[G] and five result words per wave, then the reference codes
-// (N + 128 bytes, the last 128 zero)
-inline size_t strip_extra_bytes(int G, int n) {
-  return G > 1 ? (size_t)kStripCtrWords * G * 4 + (((size_t)n + 128 + 15) & ~(size_t)15) : 0;
-}
 
 template <int R, int MODE, bool TB, bool SMALLA, int G>
 static hipError_t launch_strip_t(const StripArgs &a, hipStream_t s) {
@@ -491,10 +484,6 @@ static hipError_t launch_strip_r(int mode, bool tb, bool small, const StripArgs 
   }
 }
 
-size_t strip_lds_bytes(int waves, int lds_bnd, int lds_prof, int max_n) {
-  const size_t per = (size_t)(lds_bnd + lds_prof);
-  return waves == 1 ? 4 * per : (size_t)waves * per + strip_extra_bytes(waves, max_n);
-}
 
 hipError_t launch_strip(int rows, int mode, bool tb, bool small_alphabet, const StripArgs &a,
                         hipStream_t s) {

@@ -11,7 +11,7 @@
 #include "internal.h"
 
 struct aln_ctx {
-  int device = 0;
+  int device = 0; // -1: a context without a device (aln_create_host)
   int cus = 256;                // compute units, and LDS bytes per CU (planner's load model)
   int lds_per_cu = 160 * 1024;
   std::string err;
@@ -103,6 +103,7 @@ struct aln_plan {
   int64_t cells = 0;
   void *pinned = nullptr;   // host staging of the task lists
   bool own_pinned = true;   // false: staging belongs to the server slot
+  bool host_staging = false; // staging in plain host memory (a context without a device)
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   // RNA folding plans (aln_fold_plan_create): parameters, tasks in launch
@@ -130,6 +131,8 @@ void plan_stage(const aln_plan *pl, void *dst);
 // Look up the device address of the fixed no-allocation workspace on
 // ctx->device (current) and keep it in ctx->scratch.
 aln_status scratch_init(aln_ctx *ctx);
+// host staging of a plan's task lists: pinned, or plain memory without a device
+aln_status plan_alloc_staging(aln_plan *pl);
 // Argument checks shared by the execute entry points.
 aln_status exec_check(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, void *d_ws,
                       uint64_t ws_bytes, aln_result *d_res, uint32_t *d_cigar,

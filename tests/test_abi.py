@@ -49,10 +49,10 @@ STRUCTS = {
     "aln_footprint": aln._Footprint, "aln_server_cfg": aln._ServerCfg,
     "aln_request": aln._Request, "aln_server_stats": aln._ServerStats,
     "aln_tuning": aln._Tuning, "aln_fold_params": aln._FoldParams,
-    "aln_fold_batch": aln._FoldBatch,
+    "aln_fold_batch": aln._FoldBatch, "aln_launch_info": aln._LaunchInfo,
 }
 NUMPY_STRUCTS = {"aln_result": aln.RESULT_DTYPE, "aln_completion": aln.COMPLETION_DTYPE,
-                 "aln_fold_result": aln.FOLD_RESULT_DTYPE}
+                 "aln_fold_result": aln.FOLD_RESULT_DTYPE, "aln_task_info": aln.TASK_INFO_DTYPE}
 
 
 def test_header_layouts_match_the_binding(tmp_path):
