@@ -207,7 +207,13 @@ typedef struct {
                              thresholds 25, 40, 60, 80 it was timed with)    */
   double strip_ms[5];     /* candidates 0, 8, 16, 24, 32                      */
   double xdrop_ms[4];     /* candidates 4x1, 4x16, 8x1, 8x4 (rows x sides)    */
-} aln_tuning;             /* 128 bytes */
+  int32_t band_kernel;    /* static bands: 0 (by band width), 1 (antidiagonal
+                             windows), 2 (strips, one wavefront per pair) or 3
+                             (strips, four wavefronts per pair); pairs the
+                             strip form cannot hold stay antidiagonal         */
+  int32_t reserved;
+  double band_ms[3];      /* candidates 1, 2, 3                              */
+} aln_tuning;             /* 160 bytes */
 
 /* ABI version of the loaded library (ALN_ABI_VERSION). */
 int32_t aln_abi_version(void);
@@ -245,12 +251,14 @@ aln_status aln_plan_create(aln_ctx *ctx, int32_t scoring_id,
 /* One kernel launch of a plan's fill (re-runs that depend on device results
  * -- widening, int32 re-runs -- and the walks are not listed). */
 typedef struct {
-  char family[24];  /* "sw16", "strip_i32", "diag_band", "xdrop_lanes",
-                       "xdrop_lanes_tb", "xdrop_group", "xdrop", "xdrop_tb",
-                       "zdrop", "zdrop_tb", "search", "search_affine", "fold" */
+  char family[24];  /* "sw16", "strip_i32", "diag_band", "band_strip",
+                       "xdrop_lanes", "xdrop_lanes_tb", "xdrop_group", "xdrop",
+                       "xdrop_tb", "zdrop", "zdrop_tb", "search",
+                       "search_affine", "fold"                               */
   int32_t tile;     /* rows or window per lane (fold: triangle row stride)   */
   int32_t sides;    /* X-drop: sides per wavefront; sw16: 2 pairs per lane;
-                       strips: wavefronts per pair; fold: bytes per element  */
+                       strips, band strips: wavefronts per pair; fold: bytes
+                       per element                                           */
   int32_t first;    /* its tasks in the plan's task list                     */
   int32_t count;
 } aln_launch_info;  /* 40 bytes */

@@ -114,11 +114,13 @@ class _Tuning(ctypes.Structure):
                 ("strip_rows", ctypes.c_int32), ("xdrop_rows", ctypes.c_int32),
                 ("xdrop_sides", ctypes.c_int32), ("sw16_wide_pct", ctypes.c_int32),
                 ("sw16_ms", ctypes.c_double * 4), ("strip_ms", ctypes.c_double * 5),
-                ("xdrop_ms", ctypes.c_double * 4)]
+                ("xdrop_ms", ctypes.c_double * 4), ("band_kernel", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("band_ms", ctypes.c_double * 3)]
 
 
 SW16_TILES, STRIP_TILES = (16, 12, 8, 4), (0, 8, 16, 24, 32)
 XDROP_TILES = ("4x1", "4x16", "8x1", "8x4")  # window cells per lane x sides per wavefront
+BAND_KERNELS = ("diag", "strip1", "strip4")  # antidiagonal windows; strips, 1 or 4 waves a pair
 
 
 _lib = None
@@ -357,7 +359,9 @@ class Context:
                 "xdrop_sides": int(t.xdrop_sides), "sw16_wide_pct": int(t.sw16_wide_pct),
                 "sw16_ms": dict(zip(SW16_TILES, map(float, t.sw16_ms))),
                 "strip_ms": dict(zip(STRIP_TILES, map(float, t.strip_ms))),
-                "xdrop_ms": dict(zip(XDROP_TILES, map(float, t.xdrop_ms)))}
+                "xdrop_ms": dict(zip(XDROP_TILES, map(float, t.xdrop_ms))),
+                "band_kernel": int(t.band_kernel),
+                "band_ms": dict(zip(BAND_KERNELS, map(float, t.band_ms)))}
 
     def set_tuning(self, tuning):
         t = _Tuning()
@@ -367,6 +371,7 @@ class Context:
         t.xdrop_rows = int(tuning.get("xdrop_rows", 4))
         t.xdrop_sides = int(tuning.get("xdrop_sides", 1))
         t.sw16_wide_pct = int(tuning.get("sw16_wide_pct", 0))
+        t.band_kernel = int(tuning.get("band_kernel", 0))
         self._check(self.lib.aln_set_tuning(self.handle, ctypes.byref(t)))
 
     def set_profiling(self, enable):

@@ -579,7 +579,8 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     int kind;
     int rows;
     double cost;
-    int waves = 1; // full matrix: wavefronts per pair (strip pipeline)
+    int waves = 1; // full matrix / band strips: wavefronts per pair (strip pipeline)
+    int ring = 0;  // band strips: columns of the LDS boundary ring
   };
   std::vector<Item> items;
   items.reserve(n);
@@ -610,17 +611,37 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
       }
       if (p.prune == ALN_BAND) {
         const int64_t w = p.band_w;
-        int64_t width = 2 * w + 6 + ((2 * w + 2) * std::abs((int64_t)N - M) + M - 1) / std::max(M, 1);
-        width = std::min<int64_t>(width, 2LL * std::min(M, N) + 6);
-        it.rows = 0;
-        for (int r : kDiagRows)
-          if (64LL * r - 6 >= width && (!p.want_cigar || r <= 16)) { it.rows = r; break; }
-        if (it.rows == 0) {
-          delete pl;
-          return fail(ctx, ALN_E_UNSUPPORTED, "pair %d: band of %lld diagonals exceeds the window",
-                      i, (long long)width);
+        // strips: a strip's columns fit one LDS ring of at most 2048, and
+        // the pipeline's stamps s*(N+1) + column fit 31 bits
+        int bk = ctx->force_band_kernel
+                     ? ctx->force_band_kernel
+                     : (ctx->tuning.valid ? ctx->tuning.band_kernel : 0);
+        if (bk == 0) bk = 2 * w + 1 >= 256 ? 3 : 1; // wide bands: strips, four wavefronts a pair
+        const int64_t cols = M > 0 && N > 0 ? alnk::band_strip_cols(M, N, (int32_t)std::min<int64_t>(w, 1 << 28), 4) : 0;
+        int64_t ring = 64;
+        while (ring < cols + 2) ring <<= 1;
+        const int64_t nsb = (M + 255) / 256;
+        const bool strip_fit = M > 0 && N > 0 && ring <= 2048 && w < (1 << 28) &&
+                               nsb * ((int64_t)N + 1) + N < (1LL << 31);
+        if (bk >= 2 && strip_fit) {
+          it.kind = K_BAND;
+          it.rows = 4;
+          it.waves = bk == 3 ? alnk::kStripPipeWaves : 1;
+          it.ring = (int)ring;
+          it.cost = (double)nsb * (double)(cols + 63);
+        } else {
+          int64_t width = 2 * w + 6 + ((2 * w + 2) * std::abs((int64_t)N - M) + M - 1) / std::max(M, 1);
+          width = std::min<int64_t>(width, 2LL * std::min(M, N) + 6);
+          it.rows = 0;
+          for (int r : kDiagRows)
+            if (64LL * r - 6 >= width && (!p.want_cigar || r <= 16)) { it.rows = r; break; }
+          if (it.rows == 0) {
+            delete pl;
+            return fail(ctx, ALN_E_UNSUPPORTED, "pair %d: band of %lld diagonals exceeds the window",
+                        i, (long long)width);
+          }
+          it.cost = (double)(M + N) * it.rows;
         }
-        it.cost = (double)(M + N) * it.rows;
         pl->cells += band_cells(M, N, p.band_w);
       } else {
         it.rows = ctx->tuning.valid ? ctx->tuning.xdrop_rows : 4;
@@ -671,11 +692,12 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
   uint64_t tb_off = 0, cg_off = 0;
   for (size_t k = 0; k < items.size();) {
     size_t e = k;
-    int32_t grpN = 0;
+    int32_t grpN = 0, grpRing = 0;
     bool multi = false;
     while (e < items.size() && items[e].kind == items[k].kind && items[e].rows == items[k].rows &&
            items[e].waves == items[k].waves) {
       grpN = std::max(grpN, pl->rlen[items[e].pair]);
+      grpRing = std::max(grpRing, items[e].ring);
       if (items[e].kind == K_STRIP && pl->qlen[items[e].pair] > 64 * items[e].rows) multi = true;
       ++e;
     }
@@ -699,6 +721,11 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     L.first = (int32_t)pl->tasks.size();
     L.count = (int32_t)(e - k);
     L.waves = items[k].waves;
+    if (L.kind == K_BAND) {
+      L.lds_bnd = grpRing * 8;
+      L.lds_prof = small ? 0 : (int32_t)align_up((uint64_t)hs.alphabet * 64 * L.rows, 16);
+      L.max_n = grpN;
+    }
     if (L.kind == K_STRIP) {
       L.lds_bnd = multi ? (int32_t)align_up((uint64_t)(grpN + 1) * 8, 16) : 0;
       L.lds_prof = small ? 0 : (int32_t)align_up((uint64_t)hs.alphabet * 64 * L.rows, 16);
@@ -723,6 +750,10 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
         if (L.kind == K_STRIP) {
           const int64_t ns = (M + 64LL * L.rows - 1) / (64LL * L.rows);
           bytes = (uint64_t)ns * (uint64_t)(N + 63) * 64ULL * (uint64_t)(L.rows / 2);
+        } else if (L.kind == K_BAND) {
+          const int64_t ns = (M + 64LL * L.rows - 1) / (64LL * L.rows);
+          bytes = (uint64_t)ns * 64ULL *
+                  (uint64_t)alnk::band_code_steps(M, N, p.band_w, L.rows) * (uint64_t)(L.rows / 2);
         } else {
           const uint64_t nk = (uint64_t)M + N + 1;
           bytes = (nk + 63) / 64 * 64 * 4 + ((uint64_t)(M + N) / 2 + 1) * 64 * 8;
@@ -786,6 +817,10 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
       if (L.kind == K_DIAG) {
         if (pl->n_diag_tb == 0) pl->first_diag_tb = L.first;
         pl->n_diag_tb += L.count;
+      }
+      if (L.kind == K_BAND) {
+        if (pl->n_band_tb == 0) pl->first_band_tb = L.first;
+        pl->n_band_tb += L.count;
       }
     }
   }
@@ -1127,6 +1162,24 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
     sa.lds_prof = L.lds_prof;
     sa.waves = L.waves;
     sa.max_n = L.max_n;
+    sa.band_w = plan->p.band_w;
+    sa.ring_cols = L.lds_bnd / 8;
+    if (L.kind == K_BAND) {
+      if (!per_pair) {
+        sa.tasks = dtasks + L.first;
+        sa.ntasks = L.count;
+        HIP_TRY(ctx, timed_launch(ctx, "band_strip", st, [&] {
+                  return alnk::launch_band_strip(L.mode, L.tb, L.small, sa, st);
+                }));
+      } else {
+        for (int32_t k = 0; k < L.count; ++k) {
+          sa.tasks = dtasks + L.first + k;
+          sa.ntasks = 1;
+          HIP_TRY(ctx, alnk::launch_band_strip(L.mode, L.tb, L.small, sa, st));
+        }
+      }
+      continue;
+    }
     if (!per_pair) {
       sa.tasks = dtasks + L.first;
       sa.ntasks = L.count;
@@ -1161,6 +1214,7 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
     wa.layout = 0;
     wa.diag_stride = plan->xtb_lanes ? 1 : (plan->xtb_count > 0 ? 2 : 8);
     wa.dyn_ntasks = nullptr;
+    wa.band_w = plan->p.band_w;
     wa.sc = dsc;
     wa.tb = ws + plan->tb_base;
     wa.res = d_res;
@@ -1169,17 +1223,22 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
       wa.tasks = tasks;
       wa.ntasks = nt;
       wa.layout = layout;
-      return layout == 0 ? alnk::launch_walk(0, wa, st) : alnk::launch_walk_diag(wa, st);
+      return layout == 1 ? alnk::launch_walk_diag(wa, st) : alnk::launch_walk(layout, wa, st);
     };
     if (!per_pair) {
       HIP_TRY(ctx, timed_launch(ctx, "walk", st, [&] { return walk(0, dtasks, plan->n_strip_tb); }));
       HIP_TRY(ctx, timed_launch(ctx, "walk", st, [&] {
                 return walk(1, dtasks + plan->first_diag_tb, plan->n_diag_tb);
               }));
+      HIP_TRY(ctx, timed_launch(ctx, "walk", st, [&] {
+                return walk(2, dtasks + plan->first_band_tb, plan->n_band_tb);
+              }));
     } else {
       for (int32_t k = 0; k < plan->n_strip_tb; ++k) HIP_TRY(ctx, walk(0, dtasks + k, 1));
       for (int32_t k = 0; k < plan->n_diag_tb; ++k)
         HIP_TRY(ctx, walk(1, dtasks + plan->first_diag_tb + k, 1));
+      for (int32_t k = 0; k < plan->n_band_tb; ++k)
+        HIP_TRY(ctx, walk(2, dtasks + plan->first_band_tb + k, 1));
     }
     if (plan->xtb_lanes) { // the pairs the one-side pass recomputed, in its layout
       wa.diag_stride = 2;
@@ -1315,12 +1374,14 @@ int64_t aln_plan_describe(const aln_plan *plan, aln_launch_info *launches, int32
       }
       const char *fam = "strip_i32";
       if (L.kind == K_SEARCH) fam = L.pen_x > 0 ? "search_affine" : "search";
+      if (L.kind == K_BAND) fam = "band_strip";
       if (L.kind == K_DIAG) {
         if (plan->p.prune == ALN_BAND) fam = "diag_band";
         else if (plan->p.prune == ALN_ZDROP) fam = L.sides == 4 ? "zdrop_group" : "zdrop";
         else fam = L.sides == 16 ? "xdrop_lanes" : (L.sides == 4 ? "xdrop_group" : "xdrop");
       }
-      add_launch(fam, L.rows, L.kind == K_STRIP ? L.waves : L.sides, L.first, L.count);
+      add_launch(fam, L.rows, (L.kind == K_STRIP || L.kind == K_BAND) ? L.waves : L.sides, L.first,
+                 L.count);
       pair_tasks(id, L.first, L.count);
     }
   }

@@ -161,8 +161,17 @@ aln_status aln_autotune(aln_ctx *ctx, int32_t scoring_id, const aln_params *para
       ctx->force_strip_rows = -1;
       return ms;
     });
+  } else if (p.prune == ALN_BAND) {
+    // antidiagonal windows, or strips with one or four wavefronts per pair
+    static const int c[3] = {1, 2, 3};
+    t.band_kernel = pick(c, 3, t.band_ms, 0, [&](int k) {
+      ctx->force_band_kernel = k;
+      const double ms = run();
+      ctx->force_band_kernel = 0;
+      return ms;
+    });
   } else {
-    return ALN_OK; // bands: the window follows from the band width
+    return ALN_OK;
   }
   if (err != ALN_OK) return err;
   t.valid = 1;
@@ -183,7 +192,8 @@ aln_status aln_set_tuning(aln_ctx *ctx, const aln_tuning *tuning) {
     const int xs = tuning->xdrop_sides, w = tuning->sw16_wide_pct;
     if (!(s == 4 || s == 8 || s == 12 || s == 16) ||
         !(r == 0 || r == 8 || r == 16 || r == 24 || r == 32) || !(x == 2 || x == 4 || x == 8) ||
-        !(xs == 1 || (xs == 4 && x == 8) || (xs == 16 && x == 4)) || w < -1 || w > 10000)
+        !(xs == 1 || (xs == 4 && x == 8) || (xs == 16 && x == 4)) || w < -1 || w > 10000 ||
+        tuning->band_kernel < 0 || tuning->band_kernel > 3)
       return alnrt::fail(ctx, ALN_E_INVAL, "tile choice outside the kernels' tiles");
   }
   ctx->tuning = *tuning;

@@ -61,6 +61,8 @@ struct StripArgs {
   int32_t waves;      // wavefronts per pair: 1, or kStripPipeWaves (a pipeline
                       // of strips handed over through LDS; 4 rows per lane)
   int32_t max_n;      // pipeline: largest N of the launch (reference codes in LDS)
+  int32_t band_w;     // static band on strips: half-width w (band kernel only)
+  int32_t ring_cols;  // band kernel: columns of one LDS boundary ring (power of two)
 };
 
 // Wavefronts per pair of the full-matrix strip pipeline.
@@ -78,16 +80,49 @@ inline size_t strip_lds_bytes(int waves, int lds_bnd, int lds_prof, int max_n) {
   return waves == 1 ? 4 * per : (size_t)waves * per + strip_extra_bytes(waves, max_n);
 }
 
+// Static band on strips (Sec. 7.1 on the schedule of Sec. 6.2): row i keeps
+// c(i) - w <= j <= c(i) + w, c(i) = floor(i*N/M).  Strip s (rows s*64R + 1 ..
+// s*64R + 64R) sweeps columns jlo_s .. jhi_s, the union of its rows' bands
+// clipped to 1..N; its steps run t = 0 .. jhi_s - jlo_s + 63 with lane l on
+// column jlo_s + t - l.
+__host__ __device__ inline int band_centre(int64_t i, int32_t M, int32_t N) {
+  return (int)((i * (int64_t)N) / (int64_t)M);
+}
+// Codes per lane and strip: the lane's R rows have their in-band columns in
+// [c(i) - w, c(i + R - 1) + w], at most 2w + 2 + floor((R-1)N/M) steps; the
+// lane's window starts at the first of them rounded down to 8 steps and is
+// a multiple of 8 steps long.
+__host__ __device__ inline int band_code_steps(int32_t M, int32_t N, int32_t w, int R) {
+  const int64_t v = 2 * (int64_t)w + 9 + ((int64_t)(R - 1) * N) / M;
+  return (int)((v + 7) & ~(int64_t)7);
+}
+// Columns of one strip's range, at most: 2w + 1 + c(i + 64R - 1) - c(i).
+__host__ __device__ inline int64_t band_strip_cols(int32_t M, int32_t N, int32_t w, int R) {
+  const int64_t v = 2 * (int64_t)w + 2 + ((int64_t)(64 * R - 1) * N) / M;
+  return v < N ? v : N;
+}
+// LDS of the band kernel per wave slot: boundary ring (int2 per column),
+// query profile, reference codes of the strip's columns (+192 bytes of the
+// chunk reads past the end); G > 1 adds the pipeline counters.
+__host__ __device__ inline size_t band_slot_bytes(int ring_cols, int lds_prof) {
+  return (size_t)ring_cols * 8 + (size_t)lds_prof + (size_t)ring_cols + 192;
+}
+inline size_t band_lds_bytes(int G, int ring_cols, int lds_prof) {
+  const size_t slot = band_slot_bytes(ring_cols, lds_prof);
+  return G == 1 ? 4 * slot : G * slot + (size_t)kStripCtrWords * G * sizeof(int);
+}
+
 struct WalkArgs {
   BatchPtrs b;
   const PairTask *tasks;
   int32_t ntasks;
   int32_t mode;
-  int32_t layout;     // 0: strip layout, 1: diagonal layout
+  int32_t layout;     // 0: strip layout, 1: diagonal layout, 2: band strips
   int32_t diag_stride; // diagonal layout: code bytes per lane and antidiagonal
                        // pair (8: bands; 2: X-drop / Z-drop, 4 diagonals per lane;
                        // 1: the sixteen-sides X-drop kernel's 32 bytes per antidiagonal)
   const int32_t *dyn_ntasks; // device-side task count (a re-run queue), or null
+  int32_t band_w;            // layout 2: band half-width
   const DevScoring *sc;
   const uint8_t *tb;
   aln_result *res;
@@ -225,6 +260,10 @@ inline size_t fold_lds_bytes(int elt_bytes, int stride, int max_n) {
 hipError_t launch_validate(const ValidateArgs &a, hipStream_t s);
 hipError_t launch_strip(int rows, int mode, bool tb, bool small_alphabet,
                         const StripArgs &a, hipStream_t s);
+// static band on strips, 4 rows per lane; a.waves wavefronts per pair (1 or
+// kStripPipeWaves)
+hipError_t launch_band_strip(int mode, bool tb, bool small_alphabet, const StripArgs &a,
+                             hipStream_t s);
 hipError_t launch_walk(int layout, const WalkArgs &a, hipStream_t s);
 hipError_t launch_sw16(int rows, const Sw16Args &a, hipStream_t s);
 hipError_t launch_diag(int rows, int mode, int prune, bool tb, const DiagArgs &a, hipStream_t s);

@@ -20,6 +20,8 @@
 // 0 diagonal, 1 E, 2 F, 3 LOCAL zero; bit 2: E(i,j) opened from H(i,j-1);
 // bit 3: F(i,j) opened from H(i-1,j)), R codes per lane per step stored
 // contiguously so that a step of the wave writes one coalesced block.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace alnk {
@@ -382,6 +384,429 @@ __device__ void strip_task(const StripArgs &a, int task, int wave, int lane, uin
   res->cells = (int64_t)M * N;
 }
 
+// v = 2v + bit: the bit comes from the lane's compare mask as the carry in
+__device__ __forceinline__ void shift_in(uint32_t &v, bool bit) {
+  const unsigned long long km = __builtin_amdgcn_ballot_w64(bit);
+  unsigned long long cc;
+  asm("v_addc_co_u32_e64 %0, %1, %2, %2, %3" : "=v"(v), "=s"(cc) : "v"(v), "s"(km));
+  (void)cc;
+}
+
+// ---------------------------------------------------------------- band
+// Static band (Sec. 7.1) on the strip schedule.  Strip s sweeps only the
+// columns jlo_s .. jhi_s that hold in-band cells of its rows (the union of
+// the rows' bands, clipped to 1..N); lane l is on column jlo_s + t - l at
+// step t, as in the full-matrix form.  Cells of that range outside a row's
+// band are evaluated and their H is set to minus infinity; E and F need no
+// mask: to the left of a band only F can be finite and it flows down into
+// cells that are also left of the band (the band's left edge never moves
+// left as i grows), to the right only E can be finite and it flows right
+// into cells right of the band.  The boundary cells inside the band (row 0
+// for j <= w, column 0 for rows with c(i) <= w) take their formulas; every
+// other boundary cell is minus infinity.
+//
+// Every lane runs every step.  Before its first column and after its last
+// a lane evaluates columns outside 1..N, all masked to minus infinity,
+// except column 0 where it takes the boundary formula: so a lane enters
+// column jlo_s with exactly the state it needs, and leaves nothing behind
+// that an in-band cell reads.  With no lane idle the step has no branch.
+//
+// The strip's bottom row (H, F per column) goes to an LDS ring of ring_cols
+// columns (column j at j mod ring_cols), which holds a whole strip range:
+// a reader takes the columns of the strip above inside that strip's range
+// and minus infinity outside it.  G > 1 wavefronts run consecutive strips
+// as in the full-matrix pipeline (each strip its own ring, stamps per
+// column).  The strip's reference codes are copied into LDS when it starts,
+// so the step loop issues no global load.  Lane 0's inputs (the reference
+// code and the row above) are read for CH steps at once into lanes 0..CH-1
+// and move down one lane per step.
+//
+// Codes (4 bits per cell): per strip and lane a window of band_code_steps()
+// steps starting at u_l, the lane's first in-band step rounded down to 8,
+// lane-major: 8 steps of a lane are 16 bytes at ((s*64 + l) * Lw + (t -
+// u_l)) * 2.  Each 32-bit word holds 2 steps, the earlier in the high half;
+// a step's 16 bits hold rows 0..3 from the top; a row's nibble, from its
+// top bit: H is not the diagonal term (LOCAL: and not zero), H is not E
+// (LOCAL: or is zero; with the bit above clear this marks a zero), E(i, j)
+// opened from H(i, j-1), F(i, j) opened from H(i-1, j).
+__device__ __forceinline__ int dpp_wave_shl1(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true);
+}
+
+template <int R, int MODE, bool TB, bool SMALLA, int G>
+__device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint8_t *smem) {
+  static_assert(R == 4, "the band kernel is laid out for 4 rows per lane");
+  constexpr int HB = R / 2;       // code bytes per lane and step
+  constexpr int NWC = 8 * HB / 4; // code dwords per lane and 8 steps
+  const PairTask tk = a.tasks[task];
+  const int p = tk.pair;
+  const int M = a.b.q_len[p];
+  const int N = a.b.r_len[p];
+  const uint8_t *Q = a.b.q + a.b.q_off[p];
+  const uint8_t *Rs = a.b.r + a.b.r_off[p];
+  const DevScoring *sc = a.sc;
+  const int A = sc->alphabet;
+  const int go = sc->gap_open, ge = sc->gap_extend, goe = go + ge;
+  aln_result *res = a.res + p;
+
+  if (M == 0 || N == 0) {
+    if (lane == 0 && wave == (G == 1 ? wave : 0)) {
+      if (MODE == ALN_GLOBAL) {
+        res->score = (M + N == 0) ? 0 : go + (M + N) * ge;
+        res->q_end = M;
+        res->r_end = N;
+      } else {
+        res->score = 0;
+        res->q_end = 0;
+        res->r_end = 0;
+      }
+      res->cells = 0;
+    }
+    return;
+  }
+
+  const int w = a.band_w;
+  const int RB = a.ring_cols, RM = RB - 1;
+  const size_t slot = band_slot_bytes(RB, a.lds_prof);
+  uint8_t *mine = smem + (size_t)wave * slot;
+  int8_t *prof = reinterpret_cast<int8_t *>(mine + (size_t)RB * 8);
+  uint8_t *rref = mine + (size_t)RB * 8 + a.lds_prof;
+  int *ctr = reinterpret_cast<int *>(smem + (size_t)G * slot);
+  int *prog = ctr, *cons = ctr + G, *red = ctr + 2 * G;
+  auto ring = [&](int s) { return reinterpret_cast<int2 *>(smem + (size_t)(G == 1 ? wave : s % G) * slot); };
+  auto stamp = [&](int s, int col) { return s * (N + 1) + col; };
+  if (G > 1) {
+    if (threadIdx.x < 2 * G) ctr[threadIdx.x] = -1;
+    __syncthreads();
+  }
+  bool ok = true;
+  const int zero = a.waves - G; // 0: the launcher matches G to a.waves
+
+  constexpr int HS = 64 * R;
+  const int nstrips = (M + HS - 1) / HS;
+  const int Lw = band_code_steps(M, N, w, R);
+  auto col0 = [&](int i) { // H(i, 0) where (i, 0) lies in the band, else minus infinity
+    if (band_centre(i, M, N) > w) return NEG32;
+    return (MODE == ALN_LOCAL || i == 0) ? 0 : go + i * ge;
+  };
+
+  int best = 0, best_i = 0, best_j = 0; // LOCAL / EXTEND (wave-uniform)
+  int gh = NEG32;                       // GLOBAL: H(M,N)
+  int64_t ncells = 0;                   // this lane's in-band cells
+
+  for (int s = (G == 1 ? 0 : wave); s < nstrips; s += G) {
+    const int i0 = s * HS + 1, i1 = min(M, s * HS + HS);
+    const int jlo = max(1, band_centre(i0, M, N) - w);
+    const int jhi = min(N, band_centre(i1, M, N) + w);
+    const int range = max(jhi - jlo + 1, 0);
+    int jlo_p = 1, jhi_p = 0; // the strip above's columns
+    if (s > 0) {
+      jlo_p = max(1, band_centre(i0 - HS, M, N) - w);
+      jhi_p = min(N, band_centre(i0 - 1, M, N) + w);
+    }
+    const int itop = s * HS + lane * R + 1;
+
+    // rows: substitution scores; the band clipped to 1..N as steps, cell in
+    // band iff t - bb[r] (unsigned) <= wd[r]; column 0 (B, jlo = 1 only)
+    uint32_t rowtab[SMALLA ? R : 1];
+    int bb[R], wd[R], B[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = itop + r;
+      B[r] = NEG32;
+      bb[r] = 1 << 30; // no in-band cell: t - bb wraps above every width
+      wd[r] = 0;
+      if (i <= M) {
+        const int c = band_centre(i, M, N);
+        const int lo = max(1, c - w), hi = min(N, c + w);
+        if (hi >= lo) {
+          bb[r] = lo - jlo + lane;
+          wd[r] = hi - lo;
+          ncells += hi - lo + 1;
+        }
+        if (jlo == 1) B[r] = col0(i);
+      }
+      if (SMALLA) {
+        const int cq = (i <= M) ? (int)Q[i - 1] : -1;
+        rowtab[r] = (cq >= 0 && cq < A) ? sc->rowtab[cq] : 0x80808080u;
+      }
+    }
+    if (!SMALLA) {
+      for (int cc = 0; cc < A; ++cc) {
+        uint32_t wdw = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int i = itop + r;
+          const int cq = (i <= M) ? (int)Q[i - 1] : -1;
+          const int v = (cq >= 0 && cq < A) ? sc->mat[cq * kMaxAlphabet + cc] : -128;
+          wdw |= ((uint32_t)(v & 0xff)) << (r * 8);
+        }
+        *reinterpret_cast<uint32_t *>(prof + ((size_t)cc * 64 + lane) * R) = wdw;
+      }
+    }
+    // reference codes of columns jlo .. jhi (zero past the end)
+    for (int k = lane; k < range + 140; k += 64) rref[k] = k < range ? Rs[jlo - 1 + k] : 0;
+
+    // state at column jlo - 1: column 0 by formula, else out of band; lanes
+    // other than 0 rebuild it on their way to column jlo
+    int Hl[R], EN[R], rb[R], rj[R];
+    bool eo[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      Hl[r] = B[r];
+      EN[r] = B[r] == NEG32 ? NEG32 : B[r] + goe;
+      eo[r] = true;
+      rb[r] = 0;
+      rj[r] = 0;
+    }
+    // H(itop - 1, jlo - 1) for lane 0: the strip above (read with the first
+    // feeds), row 0 or column 0
+    int hd_top = (jlo == 1) ? col0(itop - 1) : NEG32;
+    if (s == 0 && jlo > 1)
+      hd_top = (jlo - 1 <= w) ? ((MODE == ALN_LOCAL) ? 0 : go + (jlo - 1) * ge) : NEG32;
+    int out_t = NEG32, out_f = NEG32, out_c = 0;
+
+    const int2 *bnd_in = ring(s + G - 1);
+    int2 *bnd_out = ring(s);
+    const bool has_reader = s + 1 < nstrips;
+    if (G > 1 && has_reader && s >= G) // ring free: the previous generation was read in full
+      ok = ok && lds_wait_geq(&cons[s % G], stamp(s - G, N));
+
+    // code window of this lane
+    int u_l = 1 << 30;
+    uint8_t *tbl = nullptr;
+    if (TB) {
+      if (itop <= M) u_l = (max(1, band_centre(itop, M, N) - w) - jlo + lane) & ~7;
+      tbl = a.tb + tk.tb_off + ((size_t)s * 64 + lane) * (size_t)Lw * HB;
+    }
+    uint32_t acc[NWC];
+#pragma unroll
+    for (int k = 0; k < NWC; ++k) acc[k] = 0;
+
+    // GLOBAL: H(M, N) is the last strip's row M at the step its lane is on column N
+    const bool last = s == nstrips - 1;
+    const int lM = (M - 1 - s * HS) / R, rM = (M - 1 - s * HS) - lM * R;
+    const int t_end = N - jlo + lM;
+
+    constexpr int CH = G > 1 ? 16 : 64; // feed chunk (steps)
+    int fh = 0, ff = 0, fc = 0;         // lane k: the feed of step t + k of the chunk
+    auto load_feeds = [&](int t) {
+      fc = settle((int)rref[t + lane] << 3, zero);
+      const int jf = jlo + t + lane;
+      if (s == 0) {
+        fh = (jf <= w ? ((MODE == ALN_LOCAL) ? 0 : go + jf * ge) : NEG32) + goe;
+        ff = NEG32;
+      } else {
+        const int upto = max(min(jhi_p, jlo + t + CH - 1), 0);
+        if (G > 1) ok = ok && lds_wait_geq(&prog[(s - 1) % G], stamp(s - 1, upto));
+        const int2 v = bnd_in[jf & RM];
+        const bool inr = jf >= jlo_p && jf <= jhi_p;
+        fh = settle(inr ? v.x + goe : NEG32 + goe, zero);
+        ff = settle(inr ? v.y : NEG32, zero);
+        if (t == 0 && jlo > 1) {
+          const int jd = jlo - 1;
+          const int hv = bnd_in[jd & RM].x;
+          if (lane == 0) hd_top = (jd >= jlo_p && jd <= jhi_p) ? hv : NEG32;
+        }
+        if (G > 1) lds_publish(&cons[(s - 1) % G], stamp(s - 1, upto));
+      }
+    };
+
+    // one step; ZC: some lane may be on column 0 (strips with jlo = 1)
+    auto step = [&](auto zc_tag, const int t, const int k) {
+      constexpr bool ZC = decltype(zc_tag)::value;
+      if (k == 0 && (t & (CH - 1)) == 0) load_feeds(t);
+      // lane 0 takes the chunk's next feed, every other lane the lane above
+      const int nh = dpp_wave_shl1(fh), nf = dpp_wave_shl1(ff), nc = dpp_wave_shl1(fc);
+      const int in_t = dpp_wave_shr1(fh, out_t);
+      const int in_f = dpp_wave_shr1(ff, out_f);
+      const int in_c = dpp_wave_shr1(fc, out_c);
+      fh = nh;
+      ff = nf;
+      fc = nc;
+      const bool at0 = ZC && t + 1 == lane; // on column 0 (jlo = 1)
+      int tu = in_t, fu = in_f, hd = hd_top;
+      uint32_t pw = 0;
+      if (!SMALLA) {
+        const int cc = min(in_c >> 3, A - 1);
+        pw = *reinterpret_cast<const uint32_t *>(prof + ((size_t)cc * 64 + lane) * R);
+      }
+      uint32_t &cw = acc[k >> 1];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        int sv;
+        if (SMALLA) sv = __builtin_amdgcn_sbfe((int)rowtab[r], in_c, 8);
+        else sv = __builtin_amdgcn_sbfe((int)pw, r * 8, 8);
+        const int f = max(fu + ge, tu);
+        const int hdiag = hd + sv;
+        int h = max(max(hdiag, EN[r]), f);
+        if (MODE == ALN_LOCAL) h = max(h, 0);
+        h = ((unsigned)(t - bb[r]) <= (unsigned)wd[r]) ? h : NEG32;
+        if (ZC) h = at0 ? B[r] : h;
+        const int tt = h + goe;
+        const int en = max(EN[r] + ge, tt);
+        if (TB) {
+          const bool nd = h != hdiag, ne = h != EN[r];
+          if (MODE == ALN_LOCAL) {
+            const bool z = h == 0;
+            shift_in(cw, nd && !z);
+            shift_in(cw, (nd && ne) || z);
+          } else {
+            shift_in(cw, nd);
+            shift_in(cw, ne);
+          }
+          shift_in(cw, eo[r]);
+          shift_in(cw, f == tu);
+          eo[r] = en == tt;
+        }
+        if (MODE != ALN_GLOBAL) {
+          if (h > rb[r]) {
+            rb[r] = h;
+            rj[r] = jlo + t - lane;
+          }
+        }
+        hd = Hl[r];
+        Hl[r] = h;
+        EN[r] = en;
+        tu = tt;
+        fu = f;
+      }
+      hd_top = in_t - goe;
+      out_t = tu;
+      out_f = fu;
+      out_c = in_c;
+      // lane 63 on a column of the strip: the strip's bottom row
+      if (has_reader && t >= 63 && t - 63 < range && lane == 63)
+        bnd_out[(jlo + t - 63) & RM] = make_int2(Hl[R - 1], fu);
+      if (TB && k == 7) {
+        const int tp = t - 7 - u_l;
+        if ((unsigned)tp < (unsigned)Lw) {
+          uint4 *dst = reinterpret_cast<uint4 *>(tbl + (size_t)tp * HB);
+#pragma unroll
+          for (int v = 0; v < NWC / 4; ++v)
+            dst[v] = make_uint4(acc[4 * v], acc[4 * v + 1], acc[4 * v + 2], acc[4 * v + 3]);
+        }
+      }
+      if (MODE == ALN_GLOBAL && last && t == t_end) {
+        // row rM of lane lM, read row by row (a selected register would go
+        // through memory)
+        int g[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) g[r] = __builtin_amdgcn_readlane(Hl[r], lM);
+        gh = g[0];
+#pragma unroll
+        for (int r = 1; r < R; ++r) gh = rM == r ? g[r] : gh;
+      }
+      // columns <= jlo + t - 63 of this strip's bottom row are written
+      if (G > 1 && has_reader && (t & (CH - 1)) == CH - 1)
+        lds_publish(&prog[s % G], stamp(s, max(min(jhi, jlo + t - 63), 0)));
+    };
+
+    const int T = range > 0 ? range + 63 : 0;
+    const int tz = jlo == 1 ? min(T, 64) : 0; // steps with a lane on column 0
+    int t8 = 0;
+    for (; t8 < tz; t8 += 8) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) step(std::integral_constant<bool, true>{}, t8 + k, k);
+    }
+    for (; t8 < T; t8 += 8) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) step(std::integral_constant<bool, false>{}, t8 + k, k);
+    }
+    if (G > 1) {
+      if (has_reader) lds_publish(&prog[s % G], stamp(s, N));
+      if (s > 0) lds_publish(&cons[(s - 1) % G], stamp(s - 1, N));
+    }
+
+    if (MODE != ALN_GLOBAL) {
+      int lb = 0, li = 0, lj = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = itop + r;
+        if (i <= M && rb[r] > lb) {
+          lb = rb[r];
+          li = i;
+          lj = rj[r];
+        }
+      }
+      const int m = wave_max(lb);
+      const unsigned long long ball = __ballot(lb == m);
+      const int first = __ffsll((unsigned long long)ball) - 1;
+      const int ci = __builtin_amdgcn_readlane(li, first);
+      const int cj = __builtin_amdgcn_readlane(lj, first);
+      if (m > best) {
+        best = m;
+        best_i = ci;
+        best_j = cj;
+      }
+    }
+  }
+
+  // in-band cells: every wavefront adds its strips' count (the result was
+  // zeroed by the validation launch)
+  for (int o = 32; o >= 1; o >>= 1) ncells += __shfl_xor(ncells, o, 64);
+  if (lane == 0 && ncells != 0)
+    atomicAdd(reinterpret_cast<unsigned long long *>(&res->cells), (unsigned long long)ncells);
+
+  if (G > 1) {
+    if (lane == 0) {
+      red[5 * wave + 0] = best;
+      red[5 * wave + 1] = best_i;
+      red[5 * wave + 2] = best_j;
+      red[5 * wave + 3] = gh;
+      red[5 * wave + 4] = ok ? 1 : 0;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    bool all_ok = true;
+    best = red[0];
+    best_i = red[1];
+    best_j = red[2];
+    for (int v = 0; v < G; ++v) {
+      all_ok = all_ok && red[5 * v + 4] != 0;
+      if (v > 0 && strip_better(red[5 * v], red[5 * v + 1], red[5 * v + 2], best, best_i, best_j)) {
+        best = red[5 * v];
+        best_i = red[5 * v + 1];
+        best_j = red[5 * v + 2];
+      }
+    }
+    gh = red[5 * ((nstrips - 1) % G) + 3];
+    if (!all_ok) res->status = ALN_R_INTERNAL;
+  } else if (lane != 0) {
+    return;
+  }
+  if (MODE == ALN_GLOBAL) {
+    if (gh <= NEG32 / 2) {
+      res->score = INT32_MIN;
+      res->status = ALN_R_UNREACHABLE;
+    } else {
+      res->score = gh;
+    }
+    res->q_end = M;
+    res->r_end = N;
+  } else {
+    res->score = best;
+    res->q_end = best_i;
+    res->r_end = best_j;
+  }
+}
+
+template <int R, int MODE, bool TB, bool SMALLA, int G>
+__global__ __launch_bounds__(256) void band_kernel(StripArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (G == 1) {
+    for (int task = blockIdx.x * 4 + wave; task < a.ntasks; task += gridDim.x * 4)
+      band_task<R, MODE, TB, SMALLA, 1>(a, task, wave, lane, smem);
+  } else {
+    for (int task = blockIdx.x; task < a.ntasks; task += gridDim.x) {
+      band_task<R, MODE, TB, SMALLA, G>(a, task, wave, lane, smem);
+      __syncthreads(); // the next task re-initialises the counters
+    }
+  }
+}
+
 // ---------------------------------------------------------------- validate
 // Initialises every result and flags pairs holding a code >= alphabet.  One
 // wavefront per pair (grid-stride); the codes are read as 16-byte vectors
@@ -500,6 +925,45 @@ hipError_t launch_strip(int rows, int mode, bool tb, bool small_alphabet, const 
   case 32: return launch_strip_r<32, 1>(mode, tb, small_alphabet, a, s);
   default: return hipErrorInvalidValue;
   }
+}
+
+template <int MODE, bool TB, bool SMALLA, int G>
+static hipError_t launch_band_t(const StripArgs &a, hipStream_t s) {
+  const size_t lds = band_lds_bytes(G, a.ring_cols, a.lds_prof);
+  auto kern = band_kernel<4, MODE, TB, SMALLA, G>;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  const int blocks = G == 1 ? (a.ntasks + 3) / 4 : a.ntasks;
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * (G == 1 ? 4 : G)), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int G>
+static hipError_t launch_band_g(int mode, bool tb, bool small, const StripArgs &a, hipStream_t s) {
+  switch (mode) {
+  case ALN_GLOBAL:
+    if (tb) return small ? launch_band_t<ALN_GLOBAL, true, true, G>(a, s) : launch_band_t<ALN_GLOBAL, true, false, G>(a, s);
+    return small ? launch_band_t<ALN_GLOBAL, false, true, G>(a, s) : launch_band_t<ALN_GLOBAL, false, false, G>(a, s);
+  case ALN_LOCAL:
+    if (tb) return small ? launch_band_t<ALN_LOCAL, true, true, G>(a, s) : launch_band_t<ALN_LOCAL, true, false, G>(a, s);
+    return small ? launch_band_t<ALN_LOCAL, false, true, G>(a, s) : launch_band_t<ALN_LOCAL, false, false, G>(a, s);
+  case ALN_EXTEND:
+    if (tb) return small ? launch_band_t<ALN_EXTEND, true, true, G>(a, s) : launch_band_t<ALN_EXTEND, true, false, G>(a, s);
+    return small ? launch_band_t<ALN_EXTEND, false, true, G>(a, s) : launch_band_t<ALN_EXTEND, false, false, G>(a, s);
+  default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_band_strip(int mode, bool tb, bool small_alphabet, const StripArgs &a,
+                             hipStream_t s) {
+  if (a.ntasks <= 0) return hipSuccess;
+  if (a.ring_cols < 64 || (a.ring_cols & (a.ring_cols - 1)) != 0) return hipErrorInvalidValue;
+  if (a.waves == kStripPipeWaves) return launch_band_g<kStripPipeWaves>(mode, tb, small_alphabet, a, s);
+  if (a.waves == 1) return launch_band_g<1>(mode, tb, small_alphabet, a, s);
+  return hipErrorInvalidValue;
 }
 
 } // namespace alnk

@@ -96,9 +96,17 @@ struct WaveCigar {
 // F: (i-m, j)) from the two resident blocks (the walk's block and the one
 // before in the same strip), and a run also ends at the first cell outside
 // them; the next iteration makes that cell's block resident.
+//
+// BAND: the static-band strips (columns jlo_s .. jhi_s of strip s, step t =
+// j - jlo_s + lane) with lane-major code windows: lane l of strip s keeps Lw
+// steps from u_l (a multiple of 8) at ((s*64 + l)*Lw + t - u_l)*(R/2).  A
+// block is still TBK steps of every lane (256 bytes a lane), read from each
+// lane's window; the window starts of the walk's strip sit in LDS.
+template <bool BAND>
 __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
   __shared__ __align__(16) uint4 codes4[2][kBlockBytes / 16];
   __shared__ uint8_t qwin[256], rwin[256];
+  __shared__ int ustart[64];
   const int lane = threadIdx.x;
   const int task = blockIdx.x;
   if (task >= a.ntasks) return;
@@ -117,28 +125,61 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
   const uint8_t *Qs = a.b.q + a.b.q_off[p];
   const uint8_t *Rs = a.b.r + a.b.r_off[p];
   const uint8_t *tb = a.tb + tk.tb_off;
-  const int R = uni(tk.rows), HB = R / 2, T = N + 63;
+  const int R = uni(tk.rows), HB = R / 2;
   const int invR = (65536 + R - 1) / R; // v / R = (v * invR) >> 16 for 0 <= v < 64
   const int LTB = R <= 4 ? 7 : (R <= 8 ? 6 : (R <= 16 ? 5 : 4)); // log2 of the block's steps
   const int TBK = 1 << LTB;
+  const int HS = 64 * R;
+  const int bw = a.band_w;
+  // steps of a strip (BAND: an upper bound over the strips)
+  const int T = BAND ? (int)band_strip_cols(M, N, bw, R) + 63 : N + 63;
   const int NTB = (T + TBK - 1) >> LTB;
+  const int Lw = BAND ? band_code_steps(M, N, bw, R) : 0;
   const bool local = a.mode == ALN_LOCAL;
   const uint8_t *codes0 = reinterpret_cast<const uint8_t *>(codes4[0]);
+  // first column of strip s
+  auto strip_jlo = [&](int s) { return BAND ? max(1, band_centre((int64_t)s * HS + 1, M, N) - bw) : 1; };
+  int cjlo = 1; // first column of the resident strip
 
   // block cache: slots hold (cs, cb) and (cs, cb - 1); `pre` holds (cs, cb - 2)
   uint4 pre[kPre];
   int pre_key = -1, cs = -1, cb = -1;
   auto fetch = [&](int s, int b) {
-    const int steps = min(TBK, T - b * TBK);
-    const uint4 *src = reinterpret_cast<const uint4 *>(
-        tb + ((size_t)s * T + (size_t)b * TBK) * 64 * HB);
-    const int n4 = steps * 64 * HB / 16;
+    if (BAND) {
+      // lane segment l = u / 16 of the block, part u % 16 of its 256 bytes
+      const uint8_t *sb = tb + (size_t)s * 64 * (size_t)Lw * HB;
 #pragma unroll
-    for (int m = 0; m < kPre; ++m) {
-      const int u = lane + 64 * m;
-      pre[m] = u < n4 ? src[u] : make_uint4(0u, 0u, 0u, 0u);
+      for (int m = 0; m < kPre; ++m) {
+        const int u = lane + 64 * m;
+        const int l = u >> 4;
+        const int tp = b * TBK - ustart[l] + (u & 15) * (16 / HB);
+        pre[m] = (tp >= 0 && tp < Lw)
+                     ? *reinterpret_cast<const uint4 *>(sb + ((size_t)l * Lw + tp) * HB)
+                     : make_uint4(0u, 0u, 0u, 0u);
+      }
+    } else {
+      const int steps = min(TBK, T - b * TBK);
+      const uint4 *src = reinterpret_cast<const uint4 *>(
+          tb + ((size_t)s * T + (size_t)b * TBK) * 64 * HB);
+      const int n4 = steps * 64 * HB / 16;
+#pragma unroll
+      for (int m = 0; m < kPre; ++m) {
+        const int u = lane + 64 * m;
+        pre[m] = u < n4 ? src[u] : make_uint4(0u, 0u, 0u, 0u);
+      }
     }
     pre_key = s * NTB + b;
+  };
+  // BAND: window starts of strip s's lanes, and its first column
+  auto enter_strip = [&](int s) {
+    if (!BAND) return;
+    const int jlo = strip_jlo(s);
+    const int itop = s * HS + lane * R + 1;
+    const int u = itop <= M ? (max(1, band_centre(itop, M, N) - bw) - jlo + lane) & ~7 : (1 << 30);
+    __syncthreads();
+    ustart[lane] = u;
+    __syncthreads();
+    cjlo = jlo;
   };
   auto install = [&](int key) {
     __syncthreads();
@@ -155,6 +196,7 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
         install(key - 1);
       }
     } else { // first use, or a new strip
+      if (s != cs) enter_strip(s);
       fetch(s, b);
       install(key);
       if (b >= 1) {
@@ -166,7 +208,8 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
     cb = b;
     if (b >= 2) fetch(s, b - 2);
   };
-  // position of row i (while i >= 1): strip rs, lane rl, row rr
+  // position of row i (while i >= 1): strip rs, lane rl, row rr; rjlo the
+  // first column of strip rs
   int i = i_end, j = j_end;
   int rs = 0, rl = 0, rr = 0;
   if (i >= 1) {
@@ -175,6 +218,7 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
     rl = within / R;
     rr = within - rl * R;
   }
+  int rjlo = uni(strip_jlo(rs));
   // position of row i - m, 0 <= m <= 32 (one strip boundary at most)
   auto rowpos = [&](int m, int &s2, int &l2, int &r2) {
     const int x = rr - m;
@@ -194,6 +238,7 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
   auto up_by = [&](int n) {
     int s2, l2, r2;
     rowpos(n, s2, l2, r2);
+    if (BAND && s2 != rs) rjlo = uni(strip_jlo(s2));
     rs = s2;
     rl = l2;
     rr = r2;
@@ -202,10 +247,24 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
   // code of the cell at (strip s2, lane l2, row r2, column jj), or -1 when
   // its block is not resident
   auto code_at = [&](int s2, int l2, int r2, int jj) -> int {
-    const int t = jj - 1 + l2;
+    const int t = jj - cjlo + l2;
     const int b = t >> LTB;
     if (s2 != cs || t < 0 || b > cb || b < cb - 1) return -1;
     const int slot = (s2 * NTB + b) & 1;
+    if (BAND) {
+      const int tp = t - ustart[l2];
+      if (tp < 0 || tp >= Lw) return -1;
+      // two steps a word, the earlier high; rows from the top of a step's
+      // 16 bits; nibble: not-diagonal, not-E (LOCAL: zero with the first
+      // clear), E opened, F opened
+      const int st = t - (b << LTB);
+      const uint32_t wd = reinterpret_cast<const uint32_t *>(codes0)[
+          (slot * kBlockBytes + l2 * (TBK * HB)) / 4 + (st >> 1)];
+      const int nib = (int)(wd >> (((st & 1) ? 0 : 16) + 12 - 4 * r2)) & 15;
+      const int b0 = nib >> 3, b1 = (nib >> 2) & 1;
+      const int hs = b0 ? (b1 ? 2 : 1) : ((local && b1) ? 3 : 0);
+      return hs | ((nib & 2) << 1) | ((nib & 1) << 3);
+    }
     const int byte = slot * kBlockBytes + ((t - (b << LTB)) * 64 + l2) * HB + (r2 >> 1);
     return (codes0[byte] >> ((r2 & 1) * 4)) & 15;
   };
@@ -246,7 +305,7 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
       if (local && (i == 0 || j == 0)) break;
       if (i == 0) { emit_n(ALN_OP_D, j); j = 0; continue; }
       if (j == 0) { emit_n(ALN_OP_I, i); i = 0; continue; }
-      make_resident(rs, (j - 1 + rl) >> LTB);
+      make_resident(rs, (j - rjlo + rl) >> LTB);
       cover(Qs, M, qwin, qbase, max(0, i - 1 - kLook), i - 1);
       cover(Rs, N, rwin, rbase, max(0, j - 1 - kLook), j - 1);
       // lanes m < kLook: the cell m steps up the diagonal
@@ -291,7 +350,7 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
       }
     } else if (state == 1) {
       // D moves: E(i, j-m) opened from H(i, j-m-1) per the code of (i, j-m)
-      make_resident(rs, (j - 1 + rl) >> LTB);
+      make_resident(rs, (j - rjlo + rl) >> LTB);
       const int jj = j - lane;
       const bool in = lane < kLook && jj >= 1;
       const int c = in ? code_at(rs, rl, rr, jj) : -1;
@@ -310,7 +369,7 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
       }
     } else {
       // I moves: F(i-m, j) opened from H(i-m-1, j) per the code of (i-m, j)
-      make_resident(rs, (j - 1 + rl) >> LTB);
+      make_resident(rs, (j - rjlo + rl) >> LTB);
       const int ii = i - lane;
       const bool in = lane < kLook && ii >= 1;
       int c = -1;
@@ -643,9 +702,9 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
 }
 
 hipError_t launch_walk(int layout, const WalkArgs &a, hipStream_t s) {
-  (void)layout;
   if (a.ntasks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(walk_strip_wave, dim3(a.ntasks), dim3(64), 0, s, a);
+  if (layout == 2) hipLaunchKernelGGL(walk_strip_wave<true>, dim3(a.ntasks), dim3(64), 0, s, a);
+  else hipLaunchKernelGGL(walk_strip_wave<false>, dim3(a.ntasks), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

@@ -33,13 +33,14 @@ struct aln_ctx {
   int force_xdrop_rows = 0;
   int force_xdrop_sides = 0;
   int force_sw16_wide_pct = 0;
+  int force_band_kernel = 0;
   // device address of the fixed workspace of aln_execute_noalloc (this device)
   void *scratch = nullptr;
 };
 
 namespace alnrt {
 
-enum Kind { K_STRIP = 0, K_SW16 = 1, K_RERUN = 2, K_DIAG = 3, K_SEARCH = 4 };
+enum Kind { K_STRIP = 0, K_SW16 = 1, K_RERUN = 2, K_DIAG = 3, K_SEARCH = 4, K_BAND = 5 };
 
 struct LaunchDesc {
   int kind;
@@ -93,6 +94,7 @@ struct aln_plan {
   int xtb_grid = 0;
   bool xdrop = false;
   int32_t n_strip_tb = 0, first_diag_tb = 0, n_diag_tb = 0; // walk ranges
+  int32_t first_band_tb = 0, n_band_tb = 0;
   int32_t xtb_first = 0, xtb_count = 0; // X-drop / Z-drop traceback-pass tasks
   uint64_t upload_bytes = 0; // task lists copied to the front of the workspace
   uint64_t tasks_bytes = 0;

@@ -10,6 +10,9 @@ hipError_t launch_validate(const ValidateArgs &, hipStream_t) { return hipErrorN
 hipError_t launch_strip(int, int, bool, bool, const StripArgs &, hipStream_t) {
   return hipErrorNotSupported;
 }
+hipError_t launch_band_strip(int, bool, bool, const StripArgs &, hipStream_t) {
+  return hipErrorNotSupported;
+}
 hipError_t launch_walk(int, const WalkArgs &, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_sw16(int, const Sw16Args &, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_diag(int, int, int, bool, const DiagArgs &, hipStream_t) {

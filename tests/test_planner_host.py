@@ -65,6 +65,10 @@ def test_kernel_choice_per_configuration(hctx):
     assert families(hctx, pk(W.FULL, W.LOCAL)) == ["sw16"]
     assert set(families(hctx, pk(W.FULL, W.GLOBAL))) == {"strip_i32"}
     assert families(hctx, pk(W.BAND, W.GLOBAL, w=20)) == ["diag_band"]
+    # wide bands (2w + 1 >= 256) run on strips, four wavefronts per pair
+    # ((50, 40) lies wholly inside such bands: the full-matrix strips)
+    assert families(hctx, pk(W.BAND, W.GLOBAL, w=127)) == ["strip_i32", "diag_band"]
+    assert families(hctx, pk(W.BAND, W.GLOBAL, w=128)) == ["strip_i32", "band_strip"]
     # X-drop: the sixteen-sides kernel where its byte arithmetic holds
     assert families(hctx, pk(W.XDROP, X=131)) == ["xdrop_lanes"]
     assert families(hctx, pk(W.XDROP, X=132)) == ["xdrop"]          # X >= 128 + 2|e|
@@ -94,13 +98,17 @@ def test_lanes_kernel_needs_side_lengths_below_2_16(hctx):
 
 
 # ------------------------------------------------- oracle-backed fake executor
-def tb_need(family, tile, sides, M, N):
+def tb_need(family, tile, sides, M, N, w=0):
     """Traceback bytes each kernel's layout writes for a pair (M, N)."""
     nk = M + N + 1
     bases = (nk + 63) // 64 * 64 * 4
     if family == "strip_i32":
         ns = -(-M // (64 * tile))
         return ns * (N + 63) * 64 * (tile // 2)
+    if family == "band_strip":  # per strip and lane a window of Lw steps, 8-step aligned
+        ns = -(-M // (64 * tile))
+        lw = (2 * w + 9 + (tile - 1) * N // M + 7) // 8 * 8
+        return ns * 64 * lw * (tile // 2)
     if family == "diag_band":
         return bases + ((M + N) // 2 + 1) * 64 * 8
     if family == "xdrop_lanes_tb":  # its own layout, and room for the one-side pass
@@ -135,7 +143,8 @@ def fake_execute(ctx, b, want_cigar):
         for t in T:
             l = L[int(t["launch"])]
             M, N = int(b.q_len[t["pair"]]), int(b.r_len[t["pair"]])
-            assert int(t["tb_bytes"]) >= tb_need(l["family"], int(t["tile"]), l["sides"], M, N)
+            assert int(t["tb_bytes"]) >= tb_need(l["family"], int(t["tile"]), l["sides"], M, N,
+                                                 int(b.band_w))
             assert int(t["cigar_cap"]) >= M + N + 1
             assert int(ores["cigar_len"][t["pair"]]) <= int(t["cigar_cap"])
         assert p.workspace_bytes >= p.traceback_bytes
@@ -293,3 +302,34 @@ def test_empty_batch_plans(hctx):
     L, T = p.describe()
     assert T.size == 0 and p.cells == 0
     p.close()
+
+
+def test_band_kernel_forced_by_tuning():
+    """The tuned band kernel overrides the width rule; pairs the strips cannot
+    hold (a strip range beyond 2046 columns) stay on antidiagonal windows."""
+    c = aln.Context.host()
+    try:
+        rng = np.random.default_rng(5)
+        qs, rs = random_pairs(rng, [(3000, 3000), (500, 480)])
+        base = dict(sw16_rows=16, strip_rows=0, xdrop_rows=4, xdrop_sides=1)
+
+        def fams(w, k):
+            c.set_tuning(dict(base, band_kernel=k))
+            b = W.pack_pairs(qs, rs, W.dna_matrix(1, -2), -2, -1, W.GLOBAL, W.BAND, band_w=w)
+            p = plan_of(c, b)
+            L, T = p.describe()
+            p.close()
+            # pairs wholly inside the band run on the full-matrix strips
+            return sorted((l["family"], l["sides"]) for l in L if l["family"] != "strip_i32")
+
+        assert fams(20, 1) == [("diag_band", 1)]
+        assert fams(20, 2) == [("band_strip", 1)]
+        assert fams(20, 3) == [("band_strip", 4)]
+        assert fams(300, 1) == [("diag_band", 1)]
+        # (3000, 3000) at w = 894 needs 2 * 894 + 2 + 255 + 2 = 2047 ring columns
+        assert fams(894, 3) == [("band_strip", 4)]
+        assert fams(895, 3) == [("diag_band", 1)]
+        with pytest.raises(aln.AlnError):
+            c.set_tuning(dict(base, band_kernel=5))
+    finally:
+        c.close()
