@@ -100,11 +100,16 @@ struct WaveCigar {
 // BAND: the static-band strips (columns jlo_s .. jhi_s of strip s, step t =
 // j - jlo_s + lane) with lane-major code windows: lane l of strip s keeps Lw
 // steps from u_l (a multiple of 8) at ((s*64 + l)*Lw + t - u_l)*(R/2).  A
-// block is still TBK steps of every lane (256 bytes a lane), read from each
-// lane's window; the window starts of the walk's strip sit in LDS.
+// block is TBK steps of every lane (8 KB, 128 bytes a lane), read from each
+// lane's window (zeros outside it); the window starts of the walk's strip sit
+// in LDS for the reads.
 template <bool BAND>
 __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
-  __shared__ __align__(16) uint4 codes4[2][kBlockBytes / 16];
+  // band strips: 8 KB blocks, so that a launch of thousands of walks stays
+  // resident at once
+  constexpr int BLK = BAND ? kBlockBytes / 2 : kBlockBytes;
+  constexpr int PRE = BLK / 16 / 64;
+  __shared__ __align__(16) uint4 codes4[2][BLK / 16];
   __shared__ uint8_t qwin[256], rwin[256];
   __shared__ int ustart[64];
   const int lane = threadIdx.x;
@@ -127,7 +132,8 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
   const uint8_t *tb = a.tb + tk.tb_off;
   const int R = uni(tk.rows), HB = R / 2;
   const int invR = (65536 + R - 1) / R; // v / R = (v * invR) >> 16 for 0 <= v < 64
-  const int LTB = R <= 4 ? 7 : (R <= 8 ? 6 : (R <= 16 ? 5 : 4)); // log2 of the block's steps
+  // log2 of the block's steps (a lane's share of a block: BLK / 64 bytes)
+  const int LTB = (R <= 4 ? 7 : (R <= 8 ? 6 : (R <= 16 ? 5 : 4))) - (BAND ? 1 : 0);
   const int TBK = 1 << LTB;
   const int HS = 64 * R;
   const int bw = a.band_w;
@@ -142,17 +148,17 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
   int cjlo = 1; // first column of the resident strip
 
   // block cache: slots hold (cs, cb) and (cs, cb - 1); `pre` holds (cs, cb - 2)
-  uint4 pre[kPre];
+  uint4 pre[PRE];
   int pre_key = -1, cs = -1, cb = -1;
   auto fetch = [&](int s, int b) {
     if (BAND) {
-      // lane segment l = u / 16 of the block, part u % 16 of its 256 bytes
+      // lane segment l = u / (PRE) of the block, 16-byte part u % PRE of it
       const uint8_t *sb = tb + (size_t)s * 64 * (size_t)Lw * HB;
 #pragma unroll
-      for (int m = 0; m < kPre; ++m) {
+      for (int m = 0; m < PRE; ++m) {
         const int u = lane + 64 * m;
-        const int l = u >> 4;
-        const int tp = b * TBK - ustart[l] + (u & 15) * (16 / HB);
+        const int l = u / PRE;
+        const int tp = b * TBK - ustart[l] + (u % PRE) * (16 / HB);
         pre[m] = (tp >= 0 && tp < Lw)
                      ? *reinterpret_cast<const uint4 *>(sb + ((size_t)l * Lw + tp) * HB)
                      : make_uint4(0u, 0u, 0u, 0u);
@@ -163,7 +169,7 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
           tb + ((size_t)s * T + (size_t)b * TBK) * 64 * HB);
       const int n4 = steps * 64 * HB / 16;
 #pragma unroll
-      for (int m = 0; m < kPre; ++m) {
+      for (int m = 0; m < PRE; ++m) {
         const int u = lane + 64 * m;
         pre[m] = u < n4 ? src[u] : make_uint4(0u, 0u, 0u, 0u);
       }
@@ -184,7 +190,7 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
   auto install = [&](int key) {
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < kPre; ++m) codes4[key & 1][lane + 64 * m] = pre[m];
+    for (int m = 0; m < PRE; ++m) codes4[key & 1][lane + 64 * m] = pre[m];
     __syncthreads();
   };
   auto make_resident = [&](int s, int b) {
@@ -252,20 +258,21 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
     if (s2 != cs || t < 0 || b > cb || b < cb - 1) return -1;
     const int slot = (s2 * NTB + b) & 1;
     if (BAND) {
-      const int tp = t - ustart[l2];
-      if (tp < 0 || tp >= Lw) return -1;
+      // steps outside the lane's window read as zero codes: only cells of
+      // the band lie on a path, and a run or gap read ahead stops at the
+      // path's next cell, which is inside the band
       // two steps a word, the earlier high; rows from the top of a step's
       // 16 bits; nibble: not-diagonal, not-E (LOCAL: zero with the first
       // clear), E opened, F opened
       const int st = t - (b << LTB);
       const uint32_t wd = reinterpret_cast<const uint32_t *>(codes0)[
-          (slot * kBlockBytes + l2 * (TBK * HB)) / 4 + (st >> 1)];
+          (slot * BLK + l2 * (TBK * HB)) / 4 + (st >> 1)];
       const int nib = (int)(wd >> (((st & 1) ? 0 : 16) + 12 - 4 * r2)) & 15;
       const int b0 = nib >> 3, b1 = (nib >> 2) & 1;
       const int hs = b0 ? (b1 ? 2 : 1) : ((local && b1) ? 3 : 0);
       return hs | ((nib & 2) << 1) | ((nib & 1) << 3);
     }
-    const int byte = slot * kBlockBytes + ((t - (b << LTB)) * 64 + l2) * HB + (r2 >> 1);
+    const int byte = slot * BLK + ((t - (b << LTB)) * 64 + l2) * HB + (r2 >> 1);
     return (codes0[byte] >> ((r2 & 1) * 4)) & 15;
   };
   int qbase = 1 << 30, rbase = 1 << 30;
