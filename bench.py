@@ -285,7 +285,9 @@ def run_workload(name, batch, args, cpu_seconds, pp_cap, check_seconds=0.0, mach
         tdb = db if tb is batch else aln.DeviceBatch(tb)
         t0 = time.perf_counter()
         tuning = ctx.autotune(sid, tdb, batch.mode, batch.prune, batch.band_w, batch.xdrop,
-                              want_cigar=batch.want_cigar)
+                              want_cigar=batch.want_cigar,
+                              cache=None if args.no_tuning_cache else args.tuning_cache,
+                              scoring=(batch.matrix, batch.gap_open, batch.gap_extend))
         tuning = dict(ms=round((time.perf_counter() - t0) * 1e3, 1), sample_pairs=tb.n,
                       **{k: v for k, v in tuning.items() if k != "valid"})
         del tdb
@@ -778,6 +780,12 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="plan with built-in tile costs instead of measured ones")
     ap.add_argument("--no-per-pair", action="store_true")
+    ap.add_argument("--tuning-cache",
+                    default=os.path.expanduser("~/.cache/paper_2607_06225_amd/tuning.json"),
+                    help="JSON file of tile choices kept across runs (per device, library "
+                         "hash, scoring, parameters and batch shape)")
+    ap.add_argument("--no-tuning-cache", action="store_true",
+                    help="time every candidate tile even when a cached choice exists")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="headline: oracle seconds of the CPU baseline (all 10 runs)")
     ap.add_argument("--extra-cpu-seconds", type=float, default=6.0,

@@ -255,6 +255,8 @@ class DeviceBatch:
 
 
 class Context:
+    lib_path = LIB_PATH
+
     def __init__(self, device=0):
         self.lib = load_library()
         self.device = device
@@ -338,10 +340,29 @@ class Context:
         self._check(self.lib.aln_graph_launch(self.handle, plan.handle, _stream_handle(stream)))
 
     def autotune(self, scoring_id, dbatch, mode, prune=FULL, band_w=0, xdrop=0, width=W_AUTO,
-                 want_cigar=False, stream=None):
+                 want_cigar=False, stream=None, cache=None, scoring=None):
         """Time every candidate tile of the kernel family this batch uses on
         the batch itself (a DeviceBatch; pass a sample of a large workload)
-        and keep the fastest for later plans of this context."""
+        and keep the fastest for later plans of this context.
+
+        cache: path of a JSON tuning cache (tuning_cache.py); with
+        scoring=(matrix, gap_open, gap_extend) a cached choice for the same
+        device, library, scoring, parameters and batch shape is applied
+        without timing, and a new one is stored.  The result carries
+        "cached": True when it came from the file."""
+        key = None
+        if cache is not None and scoring is not None:
+            from . import tuning_cache
+            import torch
+            prop = torch.cuda.get_device_properties(self.device)
+            dev = f"{prop.name}/{getattr(prop, 'gcnArchName', '')}"
+            key = tuning_cache.make_key(self.lib_path, dev, scoring[0], scoring[1], scoring[2],
+                                        mode, prune, band_w, xdrop, width, want_cigar,
+                                        dbatch.q_len_host, dbatch.r_len_host)
+            hit = tuning_cache.lookup(cache, key)
+            if hit is not None:
+                self.set_tuning(hit)
+                return dict(self.tuning(), cached=True)
         params = _Params(int(mode), int(prune), int(band_w), int(xdrop), int(width),
                          1 if want_cigar else 0)
         ql = dbatch.q_len_host
@@ -349,7 +370,11 @@ class Context:
         self._check(self.lib.aln_autotune(self.handle, int(scoring_id), ctypes.byref(params),
                                           ctypes.byref(dbatch.c), ql.ctypes.data, rl.ctypes.data,
                                           _stream_handle(stream)))
-        return self.tuning()
+        t = self.tuning()
+        if key is not None:
+            from . import tuning_cache
+            tuning_cache.store(cache, key, {k: v for k, v in t.items() if not k.endswith("_ms")})
+        return dict(t, cached=False)
 
     def tuning(self):
         t = _Tuning()

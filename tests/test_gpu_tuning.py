@@ -85,3 +85,37 @@ def test_set_tuning_round_trip_and_validation(ctx):
         with pytest.raises(aln.AlnError):
             ctx.set_tuning(dict({"sw16_rows": 16, "strip_rows": 0, "xdrop_rows": 8,
                                  "xdrop_sides": 1}, **bad))
+
+
+def test_autotune_band_kernel(ctx):
+    """Bands: the tuner times the antidiagonal kernel and both strip forms."""
+    from paper_2607_06225_amd import aln
+    b = W.band_long(n=16, seed=64, min_len=2000, max_len=12000)
+    sid = ctx.set_scoring(b.matrix, b.gap_open, b.gap_extend)
+    db = aln.DeviceBatch(b)
+    t = ctx.autotune(sid, db, b.mode, b.prune, b.band_w, b.xdrop, want_cigar=True)
+    print(f"[gpu] band tuning: {t}", flush=True)
+    assert t["valid"] and t["band_kernel"] in (1, 2, 3)
+    assert all(ms > 0 for ms in t["band_ms"].values())
+    res, cig = aln.align(ctx, b, scoring_id=sid, dbatch=db)
+    assert compare(b, res, cig, oracle_batch(b)) == []
+
+
+def test_tuning_cache_reuses_choice(ctx, tmp_path):
+    """A cached choice is applied without timing and plans the same kernels."""
+    from paper_2607_06225_amd import aln
+    b = W.sw_protein(n=2000, seed=65)
+    sid = ctx.set_scoring(b.matrix, b.gap_open, b.gap_extend)
+    db = aln.DeviceBatch(b)
+    path = str(tmp_path / "tuning.json")
+    sc = (b.matrix, b.gap_open, b.gap_extend)
+    t1 = ctx.autotune(sid, db, b.mode, b.prune, want_cigar=False, cache=path, scoring=sc)
+    assert t1["cached"] is False
+    ctx.set_tuning({"valid": False})
+    t2 = ctx.autotune(sid, db, b.mode, b.prune, want_cigar=False, cache=path, scoring=sc)
+    assert t2["cached"] is True
+    for k in ("sw16_rows", "strip_rows", "xdrop_rows", "xdrop_sides", "sw16_wide_pct",
+              "band_kernel"):
+        assert t1[k] == t2[k], k
+    res, _ = aln.align(ctx, b, scoring_id=sid, dbatch=db)
+    assert compare(b, res, None, oracle_batch(b)) == []
