@@ -157,7 +157,8 @@ struct Sw16Item {
 // (alphabet + 1) letters x 16 lanes x R rows (equally two pairs x 64 lanes),
 // then the 32x32 int8 substitution matrix.
 inline size_t sw16_lds_bytes(int rows, int alphabet) {
-  return (size_t)8 * (alphabet + 1) * 16 * rows + kMaxAlphabet * kMaxAlphabet;
+  // profiles, the int8 substitution matrix, 64 staged bottom-row entries
+  return (size_t)8 * (alphabet + 1) * 16 * rows + kMaxAlphabet * kMaxAlphabet + 64 * 8;
 }
 
 struct Sw16Args {

@@ -8,7 +8,9 @@
 // consecutive query rows of a G*R-row strip and runs one column behind lane
 // l-1 (an antidiagonal wavefront of R-row tiles); the bottom row's H and F
 // and the reference codes move to the next lane with one DPP shift, and lane
-// 0 is fed the strip's top row through a ring shifted the other way.  A
+// 0 is fed the strip's top row through a ring shifted the other way, and
+// lane G-1's bottom row is staged in LDS and written out G columns at a
+// time.  A
 // wavefront runs either four 16-lane groups or one 64-lane group; the
 // planner gives the wide form to pairs whose strips would otherwise make
 // the launch wait on one wavefront.
@@ -98,6 +100,12 @@ __device__ __forceinline__ uint32_t grp_shl1(uint32_t old, uint32_t v) {
   return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, G == 16 ? 0x101 : 0x130, 0xf, 0xf,
                                                false);
 }
+// left shift with no `old`: lane G-1 reads zero, and the result needs no
+// copy of another register first
+template <int G>
+__device__ __forceinline__ uint32_t grp_shl1z(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, G == 16 ? 0x101 : 0x130, 0xf, 0xf, true);
+}
 
 // One work item of the packed kernel: `count` tasks (two pairs each) on the
 // four 16-lane groups of the wavefront (G = 16), or one task on all 64 lanes
@@ -105,7 +113,7 @@ __device__ __forceinline__ uint32_t grp_shl1(uint32_t old, uint32_t v) {
 // quarter of the strips, and of the serial time, of a 16-lane group.
 template <int R, int G>
 __device__ __forceinline__ void sw16_item(const Sw16Args &a, int8_t *prof, const int8_t *smat,
-                                          int first, int count) {
+                                          uint2 *stage_all, int first, int count) {
   static_assert(G == 16 || G == 64, "group width");
   constexpr int NG = 64 / G;       // groups per wavefront
   constexpr int HS = G * R;        // strip height
@@ -126,6 +134,7 @@ __device__ __forceinline__ void sw16_item(const Sw16Args &a, int8_t *prof, const
   const size_t pair_stride = (size_t)L * G * R;
   int8_t *profA = prof + ((size_t)g * 2 + 0) * pair_stride;
   int8_t *profB = prof + ((size_t)g * 2 + 1) * pair_stride;
+  uint2 *stage = stage_all + g * G; // lane G-1's bottom row over one G-step block
 
   Sw16Task tk;
   if (g < count) tk = a.tasks[first + g];
@@ -187,19 +196,22 @@ __device__ __forceinline__ void sw16_item(const Sw16Args &a, int8_t *prof, const
     for (int r = 0; r < R; ++r) { Hl[r] = 0; EN[r] = 0; kA[r] = 0; kB[r] = 0; }
     uint32_t hd_top = 0;
     uint32_t out_h = 0, out_f = 0;
-    const uint32_t padc2 = (uint32_t)PADC | ((uint32_t)PADC << 16);
+    // reference codes travel as profile offsets, c * G * R bytes (< 2^16),
+    // pair A in the low half, pair B in the high half
+    constexpr uint32_t CS = (uint32_t)G * R;
+    const uint32_t padc2 = (uint32_t)PADC * CS | (((uint32_t)PADC * CS) << 16);
     auto load_c = [&](int col) -> uint32_t {
       const uint32_t ca = (col >= 1 && col <= NA) ? (uint32_t)min((int)RA[col - 1], PADC) : (uint32_t)PADC;
       const uint32_t cb = (col >= 1 && col <= NB) ? (uint32_t)min((int)RB[col - 1], PADC) : (uint32_t)PADC;
-      return ca | (cb << 16);
+      return ca * CS | ((cb * CS) << 16);
     };
     const bool from_bnd = gact && s > 0;
     // Row rings (one per value, shifted left by one lane every step): at the
     // start of G-step block b, lane k holds the strip's top-row input for
-    // column G*b + k + 1, which lane 0 consumes at step G*b + k; lane G-1
-    // inserts its bottom-row output behind it, so after the block lane k
-    // holds the output for column G*b + k + 2 - G, stored in one coalesced
-    // write.  Inputs are prefetched two blocks ahead.
+    // column G*b + k + 1, which lane 0 consumes at step G*b + k.  At step
+    // G*b + k lane G-1 stages its bottom-row output (column G*b + k + 2 - G)
+    // in LDS entry k; after the block lane k writes entry k, one coalesced
+    // store.  Inputs are prefetched two blocks ahead.
     auto load_blk = [&](int blk, uint32_t &c, uint32_t &h, uint32_t &f) {
       const int col = blk * G + gl + 1;
       c = padc2;
@@ -220,17 +232,17 @@ __device__ __forceinline__ void sw16_item(const Sw16Args &a, int8_t *prof, const
     load_blk(2, n2_c, n2_h, n2_f);
     const bool write_bnd = gact && (s + 1 < my_ns);
     auto flush = [&](int t_last, int k_done) {
-      const int col = t_last + gl + 3 - 2 * G;
-      if (write_bnd && (G - 1 - gl) < k_done && col >= 1 && col <= my_nmax)
-        bnd[col] = make_uint2(ring_h, ring_f);
+      const int col = t_last - k_done + 1 + gl + 2 - G; // entry gl: step t_last - k_done + 1 + gl
+      if (write_bnd && gl < k_done && col >= 1 && col <= my_nmax) bnd[col] = stage[gl];
     };
 
     // Reference codes travel one lane per step; lane l's code for step t+1
     // is lane l-1's code for step t, so each step reads the profile words
     // of the next step ahead of use.
+    const int8_t *laneA = profA + (size_t)gl * R, *laneB = profB + (size_t)gl * R;
     auto prof_words = [&](uint32_t cc, uint32_t *wa, uint32_t *wb) {
-      const uint32_t *pa = reinterpret_cast<const uint32_t *>(profA + ((size_t)(cc & 0xffffu) * G + gl) * R);
-      const uint32_t *pb = reinterpret_cast<const uint32_t *>(profB + ((size_t)(cc >> 16) * G + gl) * R);
+      const uint32_t *pa = reinterpret_cast<const uint32_t *>(laneA + (cc & 0xffffu));
+      const uint32_t *pb = reinterpret_cast<const uint32_t *>(laneB + (cc >> 16));
 #pragma unroll
       for (int k = 0; k < NWD; ++k) { wa[k] = pa[k]; wb[k] = pb[k]; }
     };
@@ -255,8 +267,13 @@ __device__ __forceinline__ void sw16_item(const Sw16Args &a, int8_t *prof, const
         n1_c = n2_c; n1_h = n2_h; n1_f = n2_f;
         load_blk(t / G + 2, n2_c, n2_h, n2_f);
       }
+      // the rings move first, so that lane 0's input is taken from the old
+      // ring register in place
+      const uint32_t nh = grp_shl1z<G>(ring_h), nf = grp_shl1z<G>(ring_f);
       const uint32_t in_h = grp_shr1<G>(ring_h, out_h);
       const uint32_t in_f = grp_shr1<G>(ring_f, out_f);
+      ring_h = nh;
+      ring_f = nf;
       ring_c = grp_shl1<G>(ring_c, ring_c);
       const uint32_t lane0_next = (kb == G - 1) ? n1_c : ring_c;
       const uint32_t next_c = grp_shr1<G>(lane0_next, cur_c);
@@ -309,8 +326,7 @@ __device__ __forceinline__ void sw16_item(const Sw16Args &a, int8_t *prof, const
         out_h = Hl[R - 1];
         out_f = fu;
       }
-      ring_h = grp_shl1<G>(out_h, ring_h);
-      ring_f = grp_shl1<G>(out_f, ring_f);
+      if (gl == G - 1) stage[kb] = make_uint2(out_h, out_f);
       cur_c = next_c;
     };
     int t = 0;
@@ -391,6 +407,7 @@ __global__ __launch_bounds__(64) void sw16_kernel(Sw16Args a) {
   // is padding: -128)
   int8_t *prof = reinterpret_cast<int8_t *>(smem);
   int8_t *smat = prof + (size_t)8 * L * 16 * R;
+  uint2 *stage = reinterpret_cast<uint2 *>(smat + kMaxAlphabet * kMaxAlphabet);
   for (int k = threadIdx.x; k < kMaxAlphabet * kMaxAlphabet; k += 64) {
     const int qa = k / kMaxAlphabet, rc = k % kMaxAlphabet;
     smat[k] = (qa < A && rc < A) ? (int8_t)a.sc->mat[k] : (int8_t)-128;
@@ -404,8 +421,8 @@ __global__ __launch_bounds__(64) void sw16_kernel(Sw16Args a) {
   } else if (item >= a.ntasks) {
     return;
   }
-  if (it.count < 0) sw16_item<R, 64>(a, prof, smat, it.first, 1);
-  else sw16_item<R, 16>(a, prof, smat, it.first, it.count);
+  if (it.count < 0) sw16_item<R, 64>(a, prof, smat, stage, it.first, 1);
+  else sw16_item<R, 16>(a, prof, smat, stage, it.first, it.count);
 }
 
 hipError_t launch_sw16(int rows, const Sw16Args &a, hipStream_t s) {
