@@ -196,7 +196,9 @@ typedef struct {
 typedef struct {
   int32_t valid;
   int32_t sw16_rows;      /* 4, 8, 12 or 16                                   */
-  int32_t strip_rows;     /* 0 (per pair), 8, 16, 24 or 32                    */
+  int32_t strip_rows;     /* 0 (per pair and batch), 2 (eight-wavefront
+                             pipeline, 2 rows per lane), 4 (four-wavefront
+                             pipeline, 4 rows), 8, 16, 24 or 32               */
   int32_t xdrop_rows;     /* 2, 4 or 8                                        */
   int32_t xdrop_sides;    /* 1, 4 (with xdrop_rows 8) or 16 (with xdrop_rows
                              4: 16 sides of 4 lanes, 64 cells per side and
@@ -205,7 +207,7 @@ typedef struct {
   int32_t sw16_wide_pct;  /* 0 (default 80), -1 (never) or 1..10000          */
   double sw16_ms[4];      /* candidates 16, 12, 8, 4 (each: best of the wide
                              thresholds 25, 40, 60, 80 it was timed with)    */
-  double strip_ms[5];     /* candidates 0, 8, 16, 24, 32                      */
+  double strip_ms[7];     /* candidates 0, 2, 4, 8, 16, 24, 32                */
   double xdrop_ms[4];     /* candidates 4x1, 4x16, 8x1, 8x4 (rows x sides)    */
   int32_t band_kernel;    /* static bands: 0 (by band width), 1 (antidiagonal
                              windows), 2 (strips, one wavefront per pair) or 3
@@ -213,7 +215,7 @@ typedef struct {
                              strip form cannot hold stay antidiagonal         */
   int32_t reserved;
   double band_ms[3];      /* candidates 1, 2, 3                              */
-} aln_tuning;             /* 160 bytes */
+} aln_tuning;             /* 176 bytes */
 
 /* ABI version of the loaded library (ALN_ABI_VERSION). */
 int32_t aln_abi_version(void);

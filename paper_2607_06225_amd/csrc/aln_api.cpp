@@ -652,23 +652,36 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     items.push_back(it);
   }
   // Strip pipeline: when the full-matrix pairs are too few to give every
-  // SIMD a wavefront of its own, a pair of at least two 256-row strips runs
-  // on kStripPipeWaves wavefronts of one workgroup (4 rows per lane), its
-  // strips handed down through LDS -- unless a fixed strip height is tuned
-  // or forced.  Its boundary buffers hold whole rows, which bounds N.
-  if (srows == 0) {
-    const int G = alnk::kStripPipeWaves;
+  // SIMD a wavefront of its own, a pair of several strips runs on the
+  // wavefronts of one workgroup, its strips handed down through LDS -- unless
+  // a fixed strip height is tuned or forced.  By default, with at most three
+  // quarters of a wavefront per SIMD, four wavefronts of 4 rows per lane
+  // (256-row strips).  Tuned tiles ask for it (4) or for eight wavefronts of
+  // 2 rows (2; 128-row strips, two wavefronts per SIMD of the CU: measured
+  // 3% slower on 1 kbp pairs, where each strip's start behind the one above
+  // sets the pace).  Boundary buffers hold whole rows, which bounds N.
+  if (srows == 0 || srows == 2 || srows == 4) {
     int64_t n_full = 0;
     for (const Item &it : items) n_full += it.kind == K_STRIP;
     const int64_t simds = 4LL * ctx->cus;
+    int R = 0, G = 0;
+    if (srows == 2) {
+      R = 2;
+      G = alnk::kStripPipeWaves2;
+    } else if (srows == 4 || n_full * 4 <= simds * 3) {
+      R = 4;
+      G = alnk::kStripPipeWaves;
+    }
     for (Item &it : items) {
-      if (it.kind != K_STRIP || n_full * 4 > simds * 3) continue;
+      if (it.kind != K_STRIP || G == 0) continue;
       const int32_t M = pl->qlen[it.pair], N = pl->rlen[it.pair];
       const uint64_t bnd = align_up((uint64_t)(N + 1) * 8, 16);
-      const uint64_t prof = small ? 0 : align_up((uint64_t)hs.alphabet * 64 * 4, 16);
-      if (M > 64 * 4 && alnk::strip_lds_bytes(G, (int)bnd, (int)prof, N) <= 160 * 1024) {
-        it.rows = 4;
+      const uint64_t prof = small ? 0 : align_up((uint64_t)hs.alphabet * 64 * R, 16);
+      if (M > 64 * R && alnk::strip_lds_bytes(G, (int)bnd, (int)prof, N) <= 160 * 1024) {
+        it.rows = R;
         it.waves = G;
+      } else if (srows != 0) {
+        it.rows = choose_strip_rows(M, N); // a one-strip pair, or one too wide for the LDS
       }
     }
   }

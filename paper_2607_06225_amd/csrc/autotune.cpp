@@ -154,8 +154,8 @@ aln_status aln_autotune(aln_ctx *ctx, int32_t scoring_id, const aln_params *para
     });
     t.sw16_wide_pct = wide_of[t.sw16_rows] ? wide_of[t.sw16_rows] : 80;
   } else if (p.prune == ALN_FULL) {
-    static const int c[5] = {0, 8, 16, 24, 32};
-    t.strip_rows = pick(c, 5, t.strip_ms, 0, [&](int r) {
+    static const int c[7] = {0, 2, 4, 8, 16, 24, 32};
+    t.strip_rows = pick(c, 7, t.strip_ms, 0, [&](int r) {
       ctx->force_strip_rows = r;
       const double ms = run();
       ctx->force_strip_rows = -1;
@@ -191,7 +191,8 @@ aln_status aln_set_tuning(aln_ctx *ctx, const aln_tuning *tuning) {
     const int s = tuning->sw16_rows, r = tuning->strip_rows, x = tuning->xdrop_rows;
     const int xs = tuning->xdrop_sides, w = tuning->sw16_wide_pct;
     if (!(s == 4 || s == 8 || s == 12 || s == 16) ||
-        !(r == 0 || r == 8 || r == 16 || r == 24 || r == 32) || !(x == 2 || x == 4 || x == 8) ||
+        !(r == 0 || r == 2 || r == 4 || r == 8 || r == 16 || r == 24 || r == 32) ||
+        !(x == 2 || x == 4 || x == 8) ||
         !(xs == 1 || (xs == 4 && x == 8) || (xs == 16 && x == 4)) || w < -1 || w > 10000 ||
         tuning->band_kernel < 0 || tuning->band_kernel > 3)
       return alnrt::fail(ctx, ALN_E_INVAL, "tile choice outside the kernels' tiles");

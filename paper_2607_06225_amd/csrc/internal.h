@@ -58,15 +58,18 @@ struct StripArgs {
   aln_result *res;
   int32_t lds_bnd;    // bytes of LDS per wave for the inter-strip row (0: none)
   int32_t lds_prof;   // bytes of LDS per wave for the query profile (0: none)
-  int32_t waves;      // wavefronts per pair: 1, or kStripPipeWaves (a pipeline
-                      // of strips handed over through LDS; 4 rows per lane)
+  int32_t waves;      // wavefronts per pair: 1, or kStripPipeWaves / kStripPipeWaves2
+                      // (a pipeline of strips handed over through LDS; 4 / 2
+                      // rows per lane)
   int32_t max_n;      // pipeline: largest N of the launch (reference codes in LDS)
   int32_t band_w;     // static band on strips: half-width w (band kernel only)
   int32_t ring_cols;  // band kernel: columns of one LDS boundary ring (power of two)
 };
 
-// Wavefronts per pair of the full-matrix strip pipeline.
+// Wavefronts per pair of the full-matrix strip pipeline: four (4 rows per
+// lane), or eight (2 rows per lane: two wavefronts per SIMD of the CU).
 constexpr int kStripPipeWaves = 4;
+constexpr int kStripPipeWaves2 = 8;
 constexpr int kStripCtrWords = 7; // per pipeline wave: prog, cons, 5 result words
 // LDS of a G-wavefront pipeline workgroup beyond its buffers and profiles:
 // prog[G], cons[G] and five result words per wave, then the reference codes

@@ -81,7 +81,7 @@ __device__ void strip_task(const StripArgs &a, int task, int wave, int lane, uin
 // the task list so that a grid smaller than the list (device-side counts)
 // still covers it.  G > 1: one workgroup of G wavefronts per task.
 template <int R, int MODE, bool TB, bool SMALLA, int G>
-__global__ __launch_bounds__(256) void strip_kernel(StripArgs a) {
+__global__ __launch_bounds__(G == 8 ? 512 : 256) void strip_kernel(StripArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -179,9 +179,13 @@ __device__ void strip_task(const StripArgs &a, int task, int wave, int lane, uin
           int v = (c >= 0 && c < A) ? sc->mat[c * kMaxAlphabet + cc] : -128;
           w[r >> 2] |= ((uint32_t)(v & 0xff)) << ((r & 3) * 8);
         }
-        uint32_t *dst = reinterpret_cast<uint32_t *>(prof + ((size_t)cc * 64 + lane) * R);
+        if constexpr (R == 2) {
+          *reinterpret_cast<uint16_t *>(prof + ((size_t)cc * 64 + lane) * R) = (uint16_t)w[0];
+        } else {
+          uint32_t *dst = reinterpret_cast<uint32_t *>(prof + ((size_t)cc * 64 + lane) * R);
 #pragma unroll
-        for (int k = 0; k < (R + 3) / 4; ++k) dst[k] = w[k];
+          for (int k = 0; k < (R + 3) / 4; ++k) dst[k] = w[k];
+        }
       }
     }
 
@@ -250,9 +254,13 @@ __device__ void strip_task(const StripArgs &a, int task, int wave, int lane, uin
         uint32_t pw[SMALLA ? 1 : (R + 3) / 4];
         if (!SMALLA) {
           const int cc = min(in_c, A - 1);
-          const uint32_t *src = reinterpret_cast<const uint32_t *>(prof + ((size_t)cc * 64 + lane) * R);
+          if constexpr (R == 2) {
+            pw[0] = *reinterpret_cast<const uint16_t *>(prof + ((size_t)cc * 64 + lane) * R);
+          } else {
+            const uint32_t *src = reinterpret_cast<const uint32_t *>(prof + ((size_t)cc * 64 + lane) * R);
 #pragma unroll
-          for (int k = 0; k < (R + 3) / 4; ++k) pw[k] = src[k];
+            for (int k = 0; k < (R + 3) / 4; ++k) pw[k] = src[k];
+          }
         }
         const int c8 = in_c << 3;
         uint32_t cw[NW];
@@ -294,7 +302,9 @@ __device__ void strip_task(const StripArgs &a, int task, int wave, int lane, uin
         out_c = in_c;
         if (write_bnd) bnd_out[j] = make_int2(Hl[R - 1], fu);
         if (TB) {
-          if constexpr (R / 2 < 4) {
+          if constexpr (R == 2) {
+            tbp[(size_t)t * 64 + lane] = (uint8_t)cw[0];
+          } else if constexpr (R / 2 < 4) {
             *reinterpret_cast<uint16_t *>(tbp + ((size_t)t * 64 + lane) * (R / 2)) = (uint16_t)cw[0];
           } else {
             uint32_t *dst = reinterpret_cast<uint32_t *>(tbp + ((size_t)t * 64 + lane) * (R / 2));
@@ -915,6 +925,10 @@ hipError_t launch_strip(int rows, int mode, bool tb, bool small_alphabet, const 
   if (a.ntasks <= 0) return hipSuccess;
   if (a.waves == kStripPipeWaves) {
     if (rows == 4) return launch_strip_r<4, kStripPipeWaves>(mode, tb, small_alphabet, a, s);
+    return hipErrorInvalidValue;
+  }
+  if (a.waves == kStripPipeWaves2) {
+    if (rows == 2) return launch_strip_r<2, kStripPipeWaves2>(mode, tb, small_alphabet, a, s);
     return hipErrorInvalidValue;
   }
   if (a.waves != 1) return hipErrorInvalidValue;

@@ -156,6 +156,24 @@ def test_strip_pipeline_forms(ctx, mode):
         assert compare(b, res, cig, oracle_batch(b)) == []
 
 
+@pytest.mark.parametrize("tile", [2, 4])
+@pytest.mark.parametrize("mode", [W.GLOBAL, W.LOCAL, W.EXTEND])
+def test_strip_pipeline_protein_tiles(ctx, tile, mode):
+    """Both pipeline forms forced by the tuning (eight wavefronts of 2 rows,
+    four of 4) on a 20-letter alphabet (query profile in LDS), with CIGARs;
+    pairs too short for two strips fall back to one wavefront."""
+    from paper_2607_06225_amd import aln
+    rng = np.random.default_rng(53 + tile + mode)
+    lengths = [(int(rng.integers(100, 1800)), int(rng.integers(1, 900))) for _ in range(40)]
+    b = edge_batch(W.protein_matrix(5), -11, -1, mode, True, 5353, lengths, 20)
+    ctx.set_tuning({"sw16_rows": 16, "strip_rows": tile, "xdrop_rows": 4})
+    try:
+        res, cig = run(ctx, b, width=aln.W_I32)
+    finally:
+        ctx.set_tuning({"valid": False})
+    assert compare(b, res, cig, oracle_batch(b)) == []
+
+
 def test_many_pairs_run_one_wavefront_each(ctx):
     """More full-matrix pairs than three quarters of the SIMDs: the planner
     keeps one wavefront per pair (multi-strip pairs included)."""

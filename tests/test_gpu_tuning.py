@@ -41,7 +41,7 @@ def test_autotune_packed_sw(ctx):
 
 
 def test_autotune_strips_with_cigar(ctx):
-    tune_and_check(ctx, W.nw_dna_1k(n=64, seed=62), "strip", (0, 8, 16, 24, 32))
+    tune_and_check(ctx, W.nw_dna_1k(n=64, seed=62), "strip", (0, 2, 4, 8, 16, 24, 32))
 
 
 def test_autotune_xdrop(ctx):
@@ -62,7 +62,7 @@ def test_every_xdrop_start_window_is_bit_exact(ctx, tile, sides):
     assert np.array_equal(rp, rb)
 
 
-@pytest.mark.parametrize("tile", [8, 24])
+@pytest.mark.parametrize("tile", [2, 4, 8, 24])
 def test_every_fixed_strip_tile_is_bit_exact(ctx, tile):
     from paper_2607_06225_amd import aln
     b = W.nw_dna_1k(n=24, seed=80 + tile)
