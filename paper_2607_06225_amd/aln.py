@@ -260,6 +260,14 @@ class Context:
     def __init__(self, device=0):
         self.lib = load_library()
         self.device = device
+        # PyTorch holds the device memory and streams this binding uses: let
+        # it set the device up first (a process whose first HIP call came from
+        # the library has been seen to leave PyTorch without devices)
+        try:
+            import torch
+            torch.cuda.init()
+        except (ImportError, RuntimeError):
+            pass
         h = ctypes.c_void_p()
         self._check(self.lib.aln_create(ctypes.byref(h), int(device)), None)
         self.handle = h
