@@ -210,12 +210,13 @@ typedef struct {
   double strip_ms[7];     /* candidates 0, 2, 4, 8, 16, 24, 32                */
   double xdrop_ms[4];     /* candidates 4x1, 4x16, 8x1, 8x4 (rows x sides)    */
   int32_t band_kernel;    /* static bands: 0 (by band width), 1 (antidiagonal
-                             windows), 2 (strips, one wavefront per pair) or 3
-                             (strips, four wavefronts per pair); pairs the
-                             strip form cannot hold stay antidiagonal         */
+                             windows), strips with 4 rows per lane and one (2)
+                             or four (3) wavefronts per pair, or with 2 rows
+                             per lane and one (4) or four (5); pairs the strip
+                             form cannot hold stay antidiagonal               */
   int32_t reserved;
-  double band_ms[3];      /* candidates 1, 2, 3                              */
-} aln_tuning;             /* 176 bytes */
+  double band_ms[5];      /* candidates 1, 2, 3, 4, 5                        */
+} aln_tuning;             /* 192 bytes */
 
 /* ABI version of the loaded library (ALN_ABI_VERSION). */
 int32_t aln_abi_version(void);

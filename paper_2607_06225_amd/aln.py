@@ -115,12 +115,13 @@ class _Tuning(ctypes.Structure):
                 ("xdrop_sides", ctypes.c_int32), ("sw16_wide_pct", ctypes.c_int32),
                 ("sw16_ms", ctypes.c_double * 4), ("strip_ms", ctypes.c_double * 7),
                 ("xdrop_ms", ctypes.c_double * 4), ("band_kernel", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("band_ms", ctypes.c_double * 3)]
+                ("reserved", ctypes.c_int32), ("band_ms", ctypes.c_double * 5)]
 
 
 SW16_TILES, STRIP_TILES = (16, 12, 8, 4), (0, 2, 4, 8, 16, 24, 32)
 XDROP_TILES = ("4x1", "4x16", "8x1", "8x4")  # window cells per lane x sides per wavefront
-BAND_KERNELS = ("diag", "strip1", "strip4")  # antidiagonal windows; strips, 1 or 4 waves a pair
+# antidiagonal windows; strips of 4 rows per lane, 1 or 4 waves a pair; of 2 rows
+BAND_KERNELS = ("diag", "strip1", "strip4", "strip1_r2", "strip4_r2")
 
 
 _lib = None

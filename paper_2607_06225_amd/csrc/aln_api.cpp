@@ -611,24 +611,26 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
       }
       if (p.prune == ALN_BAND) {
         const int64_t w = p.band_w;
-        // strips: a strip's columns fit one LDS ring of at most 2048, and
-        // the pipeline's stamps s*(N+1) + column fit 31 bits
+        // strips (band_kernel 2..5: one or four wavefronts per pair, 4 or 2
+        // rows per lane): a strip's columns fit one LDS ring of at most 2048,
+        // and the pipeline's stamps s*(N+1) + column fit 31 bits
         int bk = ctx->force_band_kernel
                      ? ctx->force_band_kernel
                      : (ctx->tuning.valid ? ctx->tuning.band_kernel : 0);
-        if (bk == 0) bk = 2 * w + 1 >= 256 ? 3 : 1; // wide bands: strips, four wavefronts a pair
-        const int64_t cols = M > 0 && N > 0 ? alnk::band_strip_cols(M, N, (int32_t)std::min<int64_t>(w, 1 << 28), 4) : 0;
+        if (bk == 0) bk = 2 * w + 1 >= 256 ? 5 : 1; // wide bands: strips, four wavefronts of 2 rows
+        const int brows = (bk == 4 || bk == 5) ? 2 : 4;
+        const int64_t cols = M > 0 && N > 0 ? alnk::band_strip_cols(M, N, (int32_t)std::min<int64_t>(w, 1 << 28), brows) : 0;
         int64_t ring = 64;
         while (ring < cols + 2) ring <<= 1;
-        const int64_t nsb = (M + 255) / 256;
+        const int64_t nsb = (M + 64LL * brows - 1) / (64LL * brows);
         const bool strip_fit = M > 0 && N > 0 && ring <= 2048 && w < (1 << 28) &&
                                nsb * ((int64_t)N + 1) + N < (1LL << 31);
         if (bk >= 2 && strip_fit) {
           it.kind = K_BAND;
-          it.rows = 4;
-          it.waves = bk == 3 ? alnk::kStripPipeWaves : 1;
+          it.rows = brows;
+          it.waves = (bk == 3 || bk == 5) ? alnk::kStripPipeWaves : 1;
           it.ring = (int)ring;
-          it.cost = (double)nsb * (double)(cols + 63);
+          it.cost = (double)nsb * (double)(cols + 63) * brows;
         } else {
           int64_t width = 2 * w + 6 + ((2 * w + 2) * std::abs((int64_t)N - M) + M - 1) / std::max(M, 1);
           width = std::min<int64_t>(width, 2LL * std::min(M, N) + 6);
@@ -1182,13 +1184,13 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
         sa.tasks = dtasks + L.first;
         sa.ntasks = L.count;
         HIP_TRY(ctx, timed_launch(ctx, "band_strip", st, [&] {
-                  return alnk::launch_band_strip(L.mode, L.tb, L.small, sa, st);
+                  return alnk::launch_band_strip(L.rows, L.mode, L.tb, L.small, sa, st);
                 }));
       } else {
         for (int32_t k = 0; k < L.count; ++k) {
           sa.tasks = dtasks + L.first + k;
           sa.ntasks = 1;
-          HIP_TRY(ctx, alnk::launch_band_strip(L.mode, L.tb, L.small, sa, st));
+          HIP_TRY(ctx, alnk::launch_band_strip(L.rows, L.mode, L.tb, L.small, sa, st));
         }
       }
       continue;

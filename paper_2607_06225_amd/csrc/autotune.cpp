@@ -163,8 +163,9 @@ aln_status aln_autotune(aln_ctx *ctx, int32_t scoring_id, const aln_params *para
     });
   } else if (p.prune == ALN_BAND) {
     // antidiagonal windows, or strips with one or four wavefronts per pair
-    static const int c[3] = {1, 2, 3};
-    t.band_kernel = pick(c, 3, t.band_ms, 0, [&](int k) {
+    // and 4 or 2 rows per lane
+    static const int c[5] = {1, 2, 3, 4, 5};
+    t.band_kernel = pick(c, 5, t.band_ms, 0, [&](int k) {
       ctx->force_band_kernel = k;
       const double ms = run();
       ctx->force_band_kernel = 0;
@@ -194,7 +195,7 @@ aln_status aln_set_tuning(aln_ctx *ctx, const aln_tuning *tuning) {
         !(r == 0 || r == 2 || r == 4 || r == 8 || r == 16 || r == 24 || r == 32) ||
         !(x == 2 || x == 4 || x == 8) ||
         !(xs == 1 || (xs == 4 && x == 8) || (xs == 16 && x == 4)) || w < -1 || w > 10000 ||
-        tuning->band_kernel < 0 || tuning->band_kernel > 3)
+        tuning->band_kernel < 0 || tuning->band_kernel > 5)
       return alnrt::fail(ctx, ALN_E_INVAL, "tile choice outside the kernels' tiles");
   }
   ctx->tuning = *tuning;

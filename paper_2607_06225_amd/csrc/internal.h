@@ -93,11 +93,13 @@ __host__ __device__ inline int band_centre(int64_t i, int32_t M, int32_t N) {
 }
 // Codes per lane and strip: the lane's R rows have their in-band columns in
 // [c(i) - w, c(i + R - 1) + w], at most 2w + 2 + floor((R-1)N/M) steps; the
-// lane's window starts at the first of them rounded down to 8 steps and is
-// a multiple of 8 steps long.
+// lane's window starts at the first of them rounded down to a multiple of
+// band_code_align(R) steps (16 bytes of codes) and is a multiple of it long.
+__host__ __device__ inline int band_code_align(int R) { return 32 / R; }
 __host__ __device__ inline int band_code_steps(int32_t M, int32_t N, int32_t w, int R) {
-  const int64_t v = 2 * (int64_t)w + 9 + ((int64_t)(R - 1) * N) / M;
-  return (int)((v + 7) & ~(int64_t)7);
+  const int64_t al = band_code_align(R);
+  const int64_t v = 2 * (int64_t)w + 2 + (al - 1) + ((int64_t)(R - 1) * N) / M;
+  return (int)((v + al - 1) & ~(al - 1));
 }
 // Columns of one strip's range, at most: 2w + 1 + c(i + 64R - 1) - c(i).
 __host__ __device__ inline int64_t band_strip_cols(int32_t M, int32_t N, int32_t w, int R) {
@@ -264,9 +266,9 @@ inline size_t fold_lds_bytes(int elt_bytes, int stride, int max_n) {
 hipError_t launch_validate(const ValidateArgs &a, hipStream_t s);
 hipError_t launch_strip(int rows, int mode, bool tb, bool small_alphabet,
                         const StripArgs &a, hipStream_t s);
-// static band on strips, 4 rows per lane; a.waves wavefronts per pair (1 or
-// kStripPipeWaves)
-hipError_t launch_band_strip(int mode, bool tb, bool small_alphabet, const StripArgs &a,
+// static band on strips, 2 or 4 rows per lane; a.waves wavefronts per pair
+// (1 or kStripPipeWaves)
+hipError_t launch_band_strip(int rows, int mode, bool tb, bool small_alphabet, const StripArgs &a,
                              hipStream_t s);
 hipError_t launch_walk(int layout, const WalkArgs &a, hipStream_t s);
 hipError_t launch_sw16(int rows, const Sw16Args &a, hipStream_t s);

@@ -432,10 +432,11 @@ __device__ __forceinline__ void shift_in(uint32_t &v, bool bit) {
 // and move down one lane per step.
 //
 // Codes (4 bits per cell): per strip and lane a window of band_code_steps()
-// steps starting at u_l, the lane's first in-band step rounded down to 8,
-// lane-major: 8 steps of a lane are 16 bytes at ((s*64 + l) * Lw + (t -
-// u_l)) * 2.  Each 32-bit word holds 2 steps, the earlier in the high half;
-// a step's 16 bits hold rows 0..3 from the top; a row's nibble, from its
+// steps starting at u_l, the lane's first in-band step rounded down to
+// band_code_align(R) (16 bytes), lane-major: step t of lane l is R/2 bytes
+// at ((s*64 + l) * Lw + (t - u_l)) * R/2.  Each 32-bit word holds 8/R
+// steps, the earlier higher; a step's 4R bits hold rows 0..R-1 from the
+// top; a row's nibble, from its
 // top bit: H is not the diagonal term (LOCAL: and not zero), H is not E
 // (LOCAL: or is zero; with the bit above clear this marks a zero), E(i, j)
 // opened from H(i, j-1), F(i, j) opened from H(i-1, j).
@@ -445,7 +446,7 @@ __device__ __forceinline__ int dpp_wave_shl1(int v) {
 
 template <int R, int MODE, bool TB, bool SMALLA, int G>
 __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint8_t *smem) {
-  static_assert(R == 4, "the band kernel is laid out for 4 rows per lane");
+  static_assert(R == 2 || R == 4, "the band kernel is laid out for 2 or 4 rows per lane");
   constexpr int HB = R / 2;       // code bytes per lane and step
   constexpr int NWC = 8 * HB / 4; // code dwords per lane and 8 steps
   const PairTask tk = a.tasks[task];
@@ -551,7 +552,10 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
           const int v = (cq >= 0 && cq < A) ? sc->mat[cq * kMaxAlphabet + cc] : -128;
           wdw |= ((uint32_t)(v & 0xff)) << (r * 8);
         }
-        *reinterpret_cast<uint32_t *>(prof + ((size_t)cc * 64 + lane) * R) = wdw;
+        if constexpr (R == 2)
+          *reinterpret_cast<uint16_t *>(prof + ((size_t)cc * 64 + lane) * R) = (uint16_t)wdw;
+        else
+          *reinterpret_cast<uint32_t *>(prof + ((size_t)cc * 64 + lane) * R) = wdw;
       }
     }
     // reference codes of columns jlo .. jhi (zero past the end)
@@ -574,7 +578,10 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
     int hd_top = (jlo == 1) ? col0(itop - 1) : NEG32;
     if (s == 0 && jlo > 1)
       hd_top = (jlo - 1 <= w) ? ((MODE == ALN_LOCAL) ? 0 : go + (jlo - 1) * ge) : NEG32;
-    int out_t = NEG32, out_f = NEG32, out_c = 0;
+    // out_t: what the lane below takes at step 0, this lane's last row at
+    // column jlo - 1 (lane 1 of a strip with jlo = 1 is then on column 0 and
+    // needs H(itop + R - 1, 0) as the diagonal of its first row at column 1)
+    int out_t = B[R - 1] + goe, out_f = NEG32, out_c = 0;
 
     const int2 *bnd_in = ring(s + G - 1);
     int2 *bnd_out = ring(s);
@@ -586,7 +593,7 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
     int u_l = 1 << 30;
     uint8_t *tbl = nullptr;
     if (TB) {
-      if (itop <= M) u_l = (max(1, band_centre(itop, M, N) - w) - jlo + lane) & ~7;
+      if (itop <= M) u_l = (max(1, band_centre(itop, M, N) - w) - jlo + lane) & ~(band_code_align(R) - 1);
       tbl = a.tb + tk.tb_off + ((size_t)s * 64 + lane) * (size_t)Lw * HB;
     }
     uint32_t acc[NWC];
@@ -639,9 +646,12 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
       uint32_t pw = 0;
       if (!SMALLA) {
         const int cc = min(in_c >> 3, A - 1);
-        pw = *reinterpret_cast<const uint32_t *>(prof + ((size_t)cc * 64 + lane) * R);
+        if constexpr (R == 2)
+          pw = *reinterpret_cast<const uint16_t *>(prof + ((size_t)cc * 64 + lane) * R);
+        else
+          pw = *reinterpret_cast<const uint32_t *>(prof + ((size_t)cc * 64 + lane) * R);
       }
-      uint32_t &cw = acc[k >> 1];
+      uint32_t &cw = acc[(k * R) / 8]; // 8 / R steps per word
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         int sv;
@@ -691,10 +701,14 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
       if (TB && k == 7) {
         const int tp = t - 7 - u_l;
         if ((unsigned)tp < (unsigned)Lw) {
-          uint4 *dst = reinterpret_cast<uint4 *>(tbl + (size_t)tp * HB);
+          if constexpr (NWC == 2) {
+            *reinterpret_cast<uint2 *>(tbl + (size_t)tp * HB) = make_uint2(acc[0], acc[1]);
+          } else {
+            uint4 *dst = reinterpret_cast<uint4 *>(tbl + (size_t)tp * HB);
 #pragma unroll
-          for (int v = 0; v < NWC / 4; ++v)
-            dst[v] = make_uint4(acc[4 * v], acc[4 * v + 1], acc[4 * v + 2], acc[4 * v + 3]);
+            for (int v = 0; v < NWC / 4; ++v)
+              dst[v] = make_uint4(acc[4 * v], acc[4 * v + 1], acc[4 * v + 2], acc[4 * v + 3]);
+          }
         }
       }
       if (MODE == ALN_GLOBAL && last && t == t_end) {
@@ -941,10 +955,10 @@ hipError_t launch_strip(int rows, int mode, bool tb, bool small_alphabet, const 
   }
 }
 
-template <int MODE, bool TB, bool SMALLA, int G>
+template <int R, int MODE, bool TB, bool SMALLA, int G>
 static hipError_t launch_band_t(const StripArgs &a, hipStream_t s) {
   const size_t lds = band_lds_bytes(G, a.ring_cols, a.lds_prof);
-  auto kern = band_kernel<4, MODE, TB, SMALLA, G>;
+  auto kern = band_kernel<R, MODE, TB, SMALLA, G>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -955,28 +969,33 @@ static hipError_t launch_band_t(const StripArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int G>
+template <int R, int G>
 static hipError_t launch_band_g(int mode, bool tb, bool small, const StripArgs &a, hipStream_t s) {
   switch (mode) {
   case ALN_GLOBAL:
-    if (tb) return small ? launch_band_t<ALN_GLOBAL, true, true, G>(a, s) : launch_band_t<ALN_GLOBAL, true, false, G>(a, s);
-    return small ? launch_band_t<ALN_GLOBAL, false, true, G>(a, s) : launch_band_t<ALN_GLOBAL, false, false, G>(a, s);
+    if (tb) return small ? launch_band_t<R, ALN_GLOBAL, true, true, G>(a, s) : launch_band_t<R, ALN_GLOBAL, true, false, G>(a, s);
+    return small ? launch_band_t<R, ALN_GLOBAL, false, true, G>(a, s) : launch_band_t<R, ALN_GLOBAL, false, false, G>(a, s);
   case ALN_LOCAL:
-    if (tb) return small ? launch_band_t<ALN_LOCAL, true, true, G>(a, s) : launch_band_t<ALN_LOCAL, true, false, G>(a, s);
-    return small ? launch_band_t<ALN_LOCAL, false, true, G>(a, s) : launch_band_t<ALN_LOCAL, false, false, G>(a, s);
+    if (tb) return small ? launch_band_t<R, ALN_LOCAL, true, true, G>(a, s) : launch_band_t<R, ALN_LOCAL, true, false, G>(a, s);
+    return small ? launch_band_t<R, ALN_LOCAL, false, true, G>(a, s) : launch_band_t<R, ALN_LOCAL, false, false, G>(a, s);
   case ALN_EXTEND:
-    if (tb) return small ? launch_band_t<ALN_EXTEND, true, true, G>(a, s) : launch_band_t<ALN_EXTEND, true, false, G>(a, s);
-    return small ? launch_band_t<ALN_EXTEND, false, true, G>(a, s) : launch_band_t<ALN_EXTEND, false, false, G>(a, s);
+    if (tb) return small ? launch_band_t<R, ALN_EXTEND, true, true, G>(a, s) : launch_band_t<R, ALN_EXTEND, true, false, G>(a, s);
+    return small ? launch_band_t<R, ALN_EXTEND, false, true, G>(a, s) : launch_band_t<R, ALN_EXTEND, false, false, G>(a, s);
   default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_band_strip(int mode, bool tb, bool small_alphabet, const StripArgs &a,
+hipError_t launch_band_strip(int rows, int mode, bool tb, bool small_alphabet, const StripArgs &a,
                              hipStream_t s) {
   if (a.ntasks <= 0) return hipSuccess;
   if (a.ring_cols < 64 || (a.ring_cols & (a.ring_cols - 1)) != 0) return hipErrorInvalidValue;
-  if (a.waves == kStripPipeWaves) return launch_band_g<kStripPipeWaves>(mode, tb, small_alphabet, a, s);
-  if (a.waves == 1) return launch_band_g<1>(mode, tb, small_alphabet, a, s);
+  if (rows != 2 && rows != 4) return hipErrorInvalidValue;
+  if (a.waves == kStripPipeWaves)
+    return rows == 2 ? launch_band_g<2, kStripPipeWaves>(mode, tb, small_alphabet, a, s)
+                     : launch_band_g<4, kStripPipeWaves>(mode, tb, small_alphabet, a, s);
+  if (a.waves == 1)
+    return rows == 2 ? launch_band_g<2, 1>(mode, tb, small_alphabet, a, s)
+                     : launch_band_g<4, 1>(mode, tb, small_alphabet, a, s);
   return hipErrorInvalidValue;
 }
 

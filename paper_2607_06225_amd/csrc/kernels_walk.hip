@@ -99,7 +99,7 @@ struct WaveCigar {
 //
 // BAND: the static-band strips (columns jlo_s .. jhi_s of strip s, step t =
 // j - jlo_s + lane) with lane-major code windows: lane l of strip s keeps Lw
-// steps from u_l (a multiple of 8) at ((s*64 + l)*Lw + t - u_l)*(R/2).  A
+// steps from u_l (a multiple of 16 bytes) at ((s*64 + l)*Lw + t - u_l)*(R/2).  A
 // block is TBK steps of every lane (8 KB, 128 bytes a lane), read from each
 // lane's window (zeros outside it); the window starts of the walk's strip sit
 // in LDS for the reads.
@@ -132,8 +132,9 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
   const uint8_t *tb = a.tb + tk.tb_off;
   const int R = uni(tk.rows), HB = R / 2;
   const int invR = (65536 + R - 1) / R; // v / R = (v * invR) >> 16 for 0 <= v < 64
-  // log2 of the block's steps (a lane's share of a block: BLK / 64 bytes)
-  const int LTB = (R <= 4 ? 7 : (R <= 8 ? 6 : (R <= 16 ? 5 : 4))) - (BAND ? 1 : 0);
+  // log2 of the block's steps (a lane's share of a block: BLK / 64 bytes;
+  // band strips: 128 bytes, 128 steps at 2 rows per lane, 64 at 4)
+  const int LTB = BAND ? (R <= 2 ? 7 : 6) : (R <= 4 ? 7 : (R <= 8 ? 6 : (R <= 16 ? 5 : 4)));
   const int TBK = 1 << LTB;
   const int HS = 64 * R;
   const int bw = a.band_w;
@@ -181,7 +182,8 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
     if (!BAND) return;
     const int jlo = strip_jlo(s);
     const int itop = s * HS + lane * R + 1;
-    const int u = itop <= M ? (max(1, band_centre(itop, M, N) - bw) - jlo + lane) & ~7 : (1 << 30);
+    const int u = itop <= M ? (max(1, band_centre(itop, M, N) - bw) - jlo + lane) & ~(band_code_align(R) - 1)
+                            : (1 << 30);
     __syncthreads();
     ustart[lane] = u;
     __syncthreads();
@@ -261,13 +263,14 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
       // steps outside the lane's window read as zero codes: only cells of
       // the band lie on a path, and a run or gap read ahead stops at the
       // path's next cell, which is inside the band
-      // two steps a word, the earlier high; rows from the top of a step's
-      // 16 bits; nibble: not-diagonal, not-E (LOCAL: zero with the first
-      // clear), E opened, F opened
+      // 8 / R steps a word, the earlier higher; rows from the top of a
+      // step's 4R bits; nibble: not-diagonal, not-E (LOCAL: zero with the
+      // first clear), E opened, F opened
       const int st = t - (b << LTB);
+      const int spw = 8 / R; // steps per word
       const uint32_t wd = reinterpret_cast<const uint32_t *>(codes0)[
-          (slot * BLK + l2 * (TBK * HB)) / 4 + (st >> 1)];
-      const int nib = (int)(wd >> (((st & 1) ? 0 : 16) + 12 - 4 * r2)) & 15;
+          (slot * BLK + l2 * (TBK * HB)) / 4 + st / spw];
+      const int nib = (int)(wd >> (28 - 4 * R * (st % spw) - 4 * r2)) & 15;
       const int b0 = nib >> 3, b1 = (nib >> 2) & 1;
       const int hs = b0 ? (b1 ? 2 : 1) : ((local && b1) ? 3 : 0);
       return hs | ((nib & 2) << 1) | ((nib & 1) << 3);

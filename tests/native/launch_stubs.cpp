@@ -10,7 +10,7 @@ hipError_t launch_validate(const ValidateArgs &, hipStream_t) { return hipErrorN
 hipError_t launch_strip(int, int, bool, bool, const StripArgs &, hipStream_t) {
   return hipErrorNotSupported;
 }
-hipError_t launch_band_strip(int, bool, bool, const StripArgs &, hipStream_t) {
+hipError_t launch_band_strip(int, int, bool, bool, const StripArgs &, hipStream_t) {
   return hipErrorNotSupported;
 }
 hipError_t launch_walk(int, const WalkArgs &, hipStream_t) { return hipErrorNotSupported; }

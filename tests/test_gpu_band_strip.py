@@ -1,7 +1,7 @@
 """GPU parity of the static band on strips (scores, end cells, cell counts and
 CIGARs) against the CPU oracle, with each band kernel forced through the
-tuning: 1 antidiagonal windows, 2 strips with one wavefront per pair, 3 strips
-with four wavefronts per pair."""
+tuning: 1 antidiagonal windows; strips of 4 rows per lane with one (2) or four
+(3) wavefronts per pair; strips of 2 rows per lane with one (4) or four (5)."""
 import numpy as np
 import pytest
 
@@ -10,7 +10,7 @@ from tests.parity import compare, oracle_batch
 
 pytestmark = pytest.mark.gpu
 
-KERNELS = [2, 3]
+KERNELS = [2, 3, 4, 5]
 
 
 @pytest.fixture(scope="module")
@@ -75,7 +75,7 @@ def test_strip_band_edge_shapes_with_cigar(ctx, kernel, mode, w):
                      want_cigar=True, name=f"sband_w{w}_k{kernel}")
     with_band_kernel(ctx, kernel)
     fam = families(ctx, b)
-    assert ("band_strip", 1 if kernel == 2 else 4) in fam
+    assert ("band_strip", 1 if kernel in (2, 4) else 4) in fam
     res, cig = run(ctx, b)
     assert compare(b, res, cig, oracle_batch(b)) == []
 
@@ -107,15 +107,37 @@ def test_strip_band_protein_matrix(ctx, kernel):
         assert compare(b, res, cig, oracle_batch(b)) == []
 
 
-def test_strip_band_widest_ring(ctx):
+@pytest.mark.parametrize("kernel", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("mode", [W.GLOBAL, W.LOCAL, W.EXTEND])
+def test_strip_band_path_through_column_zero(ctx, kernel, mode):
+    """Queries that are k unmatched letters and then the reference: the best
+    path leaves column 0 at row k, so row k + 1 takes its diagonal from
+    H(k, 0); k = 2 and 4 put that row on lane 1 of the 2- and 4-row strips."""
+    rng = np.random.default_rng(4100 + 7 * mode + kernel)
+    qs, rs = [], []
+    for k in (1, 2, 3, 4, 5, 8):
+        for N in (40, 300):
+            ref = rng.integers(0, 3, size=N).astype(np.uint8)  # letters 0..2
+            qs.append(np.concatenate([np.full(k, 3, np.uint8), ref]))
+            rs.append(ref)
+    b = W.pack_pairs(qs, rs, W.dna_matrix(5, -3), -10, -1, mode, W.BAND, band_w=20,
+                     want_cigar=True, name=f"sband_col0_k{kernel}")
+    with_band_kernel(ctx, kernel)
+    res, cig = run(ctx, b)
+    assert compare(b, res, cig, oracle_batch(b)) == []
+
+
+@pytest.mark.parametrize("kernel,wmax", [(3, 894), (5, 958)])
+def test_strip_band_widest_ring(ctx, kernel, wmax):
     """Bands whose strip range needs the largest ring (2048 columns) run on
     strips; one column more goes to the antidiagonal kernel."""
     rng = np.random.default_rng(91)
     qs, rs = mutated_pairs(rng, [(2600, 2600), (3000, 2900), (700, 650)], 4)
-    with_band_kernel(ctx, 3)
-    # (2600, 2600): 2w + 2 + 255 columns, plus 2, fit 2048 up to w = 894; the
-    # antidiagonal fallback at w = 895 has no CIGAR form that wide
-    for w, fam, cigar in ((894, "band_strip", True), (895, "diag_band", False)):
+    with_band_kernel(ctx, kernel)
+    # (2600, 2600): 2w + 2 + 64R - 1 columns, plus 2, fit 2048 up to w = 894
+    # (R = 4) or 958 (R = 2); the antidiagonal fallback one wider has no
+    # CIGAR form that wide
+    for w, fam, cigar in ((wmax, "band_strip", True), (wmax + 1, "diag_band", False)):
         b = W.pack_pairs(qs, rs, W.dna_matrix(1, -2), -2, -1, W.GLOBAL, W.BAND, band_w=w,
                          want_cigar=cigar, name=f"sband_ring_w{w}")
         got = [f for f, _ in families(ctx, b)]
@@ -124,7 +146,7 @@ def test_strip_band_widest_ring(ctx):
         assert compare(b, res, cig if cigar else None, oracle_batch(b)) == []
 
 
-@pytest.mark.parametrize("kernel", [1, 2, 3])
+@pytest.mark.parametrize("kernel", [1, 2, 3, 4, 5])
 def test_band_long_reads_sample_each_kernel(ctx, kernel):
     """Shortened long-read workload (2-20 kbp, 12% errors, w = 256) with CIGAR."""
     b = W.band_long(n=24, seed=313 + kernel, min_len=2000, max_len=20000)
@@ -154,5 +176,5 @@ def test_band_kernel_tuning_roundtrip(ctx):
     assert ctx.tuning()["band_kernel"] == 2
     with pytest.raises(Exception):
         ctx.set_tuning({"sw16_rows": 16, "strip_rows": 0, "xdrop_rows": 4, "xdrop_sides": 1,
-                        "band_kernel": 4})
+                        "band_kernel": 6})
     ctx.set_tuning({"valid": False})

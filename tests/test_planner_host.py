@@ -105,9 +105,10 @@ def tb_need(family, tile, sides, M, N, w=0):
     if family == "strip_i32":
         ns = -(-M // (64 * tile))
         return ns * (N + 63) * 64 * (tile // 2)
-    if family == "band_strip":  # per strip and lane a window of Lw steps, 8-step aligned
+    if family == "band_strip":  # per strip and lane a window of Lw steps, 16-byte aligned
         ns = -(-M // (64 * tile))
-        lw = (2 * w + 9 + (tile - 1) * N // M + 7) // 8 * 8
+        al = 32 // tile
+        lw = (2 * w + 2 + (al - 1) + (tile - 1) * N // M + al - 1) // al * al
         return ns * 64 * lw * (tile // 2)
     if family == "diag_band":
         return bases + ((M + N) // 2 + 1) * 64 * 8
@@ -325,11 +326,16 @@ def test_band_kernel_forced_by_tuning():
         assert fams(20, 1) == [("diag_band", 1)]
         assert fams(20, 2) == [("band_strip", 1)]
         assert fams(20, 3) == [("band_strip", 4)]
+        assert fams(20, 4) == [("band_strip", 1)]
+        assert fams(20, 5) == [("band_strip", 4)]
         assert fams(300, 1) == [("diag_band", 1)]
         # (3000, 3000) at w = 894 needs 2 * 894 + 2 + 255 + 2 = 2047 ring columns
         assert fams(894, 3) == [("band_strip", 4)]
         assert fams(895, 3) == [("diag_band", 1)]
+        # 2 rows a lane: 2 * 958 + 2 + 127 + 2 = 2047
+        assert fams(958, 5) == [("band_strip", 4)]
+        assert fams(959, 5) == [("diag_band", 1)]
         with pytest.raises(aln.AlnError):
-            c.set_tuning(dict(base, band_kernel=5))
+            c.set_tuning(dict(base, band_kernel=6))
     finally:
         c.close()
