@@ -662,6 +662,13 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
   // 2 rows (2; 128-row strips, two wavefronts per SIMD of the CU: measured
   // 3% slower on 1 kbp pairs, where each strip's start behind the one above
   // sets the pace).  Boundary buffers hold whole rows, which bounds N.
+  //
+  // In the automatic choice the pipelined pairs run on the band strips with a
+  // band past the matrix (the same four-wavefront schedule, 256-row strips):
+  // that kernel's rotating lane-0 feeds and eight-step code stores take
+  // about 18% less time on 1 kbp pairs.  Its LDS ring holds a strip's
+  // columns, so N <= 2046.
+  pl->strip_band_w = p.prune == ALN_BAND ? p.band_w : (1 << 28);
   if (srows == 0 || srows == 2 || srows == 4) {
     int64_t n_full = 0;
     for (const Item &it : items) n_full += it.kind == K_STRIP;
@@ -679,7 +686,15 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
       const int32_t M = pl->qlen[it.pair], N = pl->rlen[it.pair];
       const uint64_t bnd = align_up((uint64_t)(N + 1) * 8, 16);
       const uint64_t prof = small ? 0 : align_up((uint64_t)hs.alphabet * 64 * R, 16);
-      if (M > 64 * R && alnk::strip_lds_bytes(G, (int)bnd, (int)prof, N) <= 160 * 1024) {
+      if (srows == 0 && M > 64 * R && N <= 2046 && pl->strip_band_w >= std::max(M, N)) {
+        int64_t ring = 64;
+        while (ring < (int64_t)N + 2) ring <<= 1;
+        it.kind = K_BAND;
+        it.rows = R;
+        it.waves = G;
+        it.ring = (int)ring;
+        it.cost = (double)((M + 64LL * R - 1) / (64LL * R)) * (double)(N + 63) * R;
+      } else if (M > 64 * R && alnk::strip_lds_bytes(G, (int)bnd, (int)prof, N) <= 160 * 1024) {
         it.rows = R;
         it.waves = G;
       } else if (srows != 0) {
@@ -768,7 +783,8 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
         } else if (L.kind == K_BAND) {
           const int64_t ns = (M + 64LL * L.rows - 1) / (64LL * L.rows);
           bytes = (uint64_t)ns * 64ULL *
-                  (uint64_t)alnk::band_code_steps(M, N, p.band_w, L.rows) * (uint64_t)(L.rows / 2);
+                  (uint64_t)alnk::band_code_steps(M, N, pl->strip_band_w, L.rows) *
+                  (uint64_t)(L.rows / 2);
         } else {
           const uint64_t nk = (uint64_t)M + N + 1;
           bytes = (nk + 63) / 64 * 64 * 4 + ((uint64_t)(M + N) / 2 + 1) * 64 * 8;
@@ -1177,7 +1193,7 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
     sa.lds_prof = L.lds_prof;
     sa.waves = L.waves;
     sa.max_n = L.max_n;
-    sa.band_w = plan->p.band_w;
+    sa.band_w = plan->strip_band_w;
     sa.ring_cols = L.lds_bnd / 8;
     if (L.kind == K_BAND) {
       if (!per_pair) {
@@ -1238,6 +1254,7 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
       wa.tasks = tasks;
       wa.ntasks = nt;
       wa.layout = layout;
+      wa.band_w = layout == 2 ? plan->strip_band_w : plan->p.band_w;
       return layout == 1 ? alnk::launch_walk_diag(wa, st) : alnk::launch_walk(layout, wa, st);
     };
     if (!per_pair) {

@@ -92,13 +92,16 @@ __host__ __device__ inline int band_centre(int64_t i, int32_t M, int32_t N) {
   return (int)((i * (int64_t)N) / (int64_t)M);
 }
 // Codes per lane and strip: the lane's R rows have their in-band columns in
-// [c(i) - w, c(i + R - 1) + w], at most 2w + 2 + floor((R-1)N/M) steps; the
-// lane's window starts at the first of them rounded down to a multiple of
-// band_code_align(R) steps (16 bytes of codes) and is a multiple of it long.
+// [c(i) - w, c(i + R - 1) + w] and in 1..N, at most min(2w + 2 +
+// floor((R-1)N/M), N) steps; the lane's window starts at the first of them
+// rounded down to a multiple of band_code_align(R) steps (16 bytes of codes)
+// and is a multiple of it long.
 __host__ __device__ inline int band_code_align(int R) { return 32 / R; }
 __host__ __device__ inline int band_code_steps(int32_t M, int32_t N, int32_t w, int R) {
   const int64_t al = band_code_align(R);
-  const int64_t v = 2 * (int64_t)w + 2 + (al - 1) + ((int64_t)(R - 1) * N) / M;
+  int64_t span = 2 * (int64_t)w + 2 + ((int64_t)(R - 1) * N) / M;
+  if (span > N) span = N;
+  const int64_t v = span + (al - 1);
   return (int)((v + al - 1) & ~(al - 1));
 }
 // Columns of one strip's range, at most: 2w + 1 + c(i + 64R - 1) - c(i).

@@ -95,6 +95,9 @@ struct aln_plan {
   bool xdrop = false;
   int32_t n_strip_tb = 0, first_diag_tb = 0, n_diag_tb = 0; // walk ranges
   int32_t first_band_tb = 0, n_band_tb = 0;
+  // band strips' half-width: the band's, or for full-matrix pairs on band
+  // strips a width past every pair's (the band then covers the matrix)
+  int32_t strip_band_w = 0;
   int32_t xtb_first = 0, xtb_count = 0; // X-drop / Z-drop traceback-pass tasks
   uint64_t upload_bytes = 0; // task lists copied to the front of the workspace
   uint64_t tasks_bytes = 0;

@@ -63,7 +63,9 @@ def test_kernel_choice_per_configuration(hctx):
                             want_cigar=cigar)
 
     assert families(hctx, pk(W.FULL, W.LOCAL)) == ["sw16"]
-    assert set(families(hctx, pk(W.FULL, W.GLOBAL))) == {"strip_i32"}
+    # full-matrix pairs of several strips, few per SIMD: the four-wavefront
+    # band strips with a band past the matrix; a one-strip pair: strip_i32
+    assert set(families(hctx, pk(W.FULL, W.GLOBAL))) == {"strip_i32", "band_strip"}
     assert families(hctx, pk(W.BAND, W.GLOBAL, w=20)) == ["diag_band"]
     # wide bands (2w + 1 >= 256) run on strips, four wavefronts per pair
     # ((50, 40) lies wholly inside such bands: the full-matrix strips)
@@ -108,7 +110,8 @@ def tb_need(family, tile, sides, M, N, w=0):
     if family == "band_strip":  # per strip and lane a window of Lw steps, 16-byte aligned
         ns = -(-M // (64 * tile))
         al = 32 // tile
-        lw = (2 * w + 2 + (al - 1) + (tile - 1) * N // M + al - 1) // al * al
+        span = min(2 * w + 2 + (tile - 1) * N // M, N)
+        lw = (span + (al - 1) + al - 1) // al * al
         return ns * 64 * lw * (tile // 2)
     if family == "diag_band":
         return bases + ((M + N) // 2 + 1) * 64 * 8
@@ -311,7 +314,7 @@ def test_band_kernel_forced_by_tuning():
     c = aln.Context.host()
     try:
         rng = np.random.default_rng(5)
-        qs, rs = random_pairs(rng, [(3000, 3000), (500, 480)])
+        qs, rs = random_pairs(rng, [(3000, 3000), (100, 90)])
         base = dict(sw16_rows=16, strip_rows=0, xdrop_rows=4, xdrop_sides=1)
 
         def fams(w, k):
@@ -320,7 +323,7 @@ def test_band_kernel_forced_by_tuning():
             p = plan_of(c, b)
             L, T = p.describe()
             p.close()
-            # pairs wholly inside the band run on the full-matrix strips
+            # a one-strip pair wholly inside the band runs on the full-matrix strips
             return sorted((l["family"], l["sides"]) for l in L if l["family"] != "strip_i32")
 
         assert fams(20, 1) == [("diag_band", 1)]
