@@ -620,8 +620,7 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
         if (bk == 0) bk = 2 * w + 1 >= 256 ? 5 : 1; // wide bands: strips, four wavefronts of 2 rows
         const int brows = (bk == 4 || bk == 5) ? 2 : 4;
         const int64_t cols = M > 0 && N > 0 ? alnk::band_strip_cols(M, N, (int32_t)std::min<int64_t>(w, 1 << 28), brows) : 0;
-        int64_t ring = 64;
-        while (ring < cols + 2) ring <<= 1;
+        const int64_t ring = std::max<int64_t>(64, (cols + 2 + 15) / 16 * 16);
         const int64_t nsb = (M + 64LL * brows - 1) / (64LL * brows);
         const bool strip_fit = M > 0 && N > 0 && ring <= 2048 && w < (1 << 28) &&
                                nsb * ((int64_t)N + 1) + N < (1LL << 31);
@@ -687,8 +686,7 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
       const uint64_t bnd = align_up((uint64_t)(N + 1) * 8, 16);
       const uint64_t prof = small ? 0 : align_up((uint64_t)hs.alphabet * 64 * R, 16);
       if (srows == 0 && M > 64 * R && N <= 2046 && pl->strip_band_w >= std::max(M, N)) {
-        int64_t ring = 64;
-        while (ring < (int64_t)N + 2) ring <<= 1;
+        const int64_t ring = std::max<int64_t>(64, ((int64_t)N + 2 + 15) / 16 * 16);
         it.kind = K_BAND;
         it.rows = R;
         it.waves = G;

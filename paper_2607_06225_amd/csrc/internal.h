@@ -94,9 +94,15 @@ __host__ __device__ inline int band_centre(int64_t i, int32_t M, int32_t N) {
 // Codes per lane and strip: the lane's R rows have their in-band columns in
 // [c(i) - w, c(i + R - 1) + w] and in 1..N, at most min(2w + 2 +
 // floor((R-1)N/M), N) steps; the lane's window starts at the first of them
-// rounded down to a multiple of band_code_align(R) steps (16 bytes of codes)
-// and is a multiple of it long.
-__host__ __device__ inline int band_code_align(int R) { return 32 / R; }
+// rounded down to a multiple of band_code_align(R) steps (one piece of
+// band_code_piece(R) bytes, the fill's store unit) and is a multiple of it
+// long.
+// (R = 4: 16 bytes, stored as each 8 steps end; R = 2: 64 bytes, 64 steps,
+// since a lane's 128-byte line then takes 128 steps to fill and smaller
+// stores leave partly written lines to the memory: 133 GB written for 31 GB
+// of band_long codes with 8-byte stores, 44 GB with 64-byte ones)
+__host__ __device__ constexpr int band_code_piece(int R) { return R == 2 ? 64 : 16; }
+__host__ __device__ inline int band_code_align(int R) { return band_code_piece(R) * 2 / R; }
 __host__ __device__ inline int band_code_steps(int32_t M, int32_t N, int32_t w, int R) {
   const int64_t al = band_code_align(R);
   int64_t span = 2 * (int64_t)w + 2 + ((int64_t)(R - 1) * N) / M;

@@ -433,7 +433,7 @@ __device__ __forceinline__ void shift_in(uint32_t &v, bool bit) {
 //
 // Codes (4 bits per cell): per strip and lane a window of band_code_steps()
 // steps starting at u_l, the lane's first in-band step rounded down to
-// band_code_align(R) (16 bytes), lane-major: step t of lane l is R/2 bytes
+// band_code_align(R) (one store piece), lane-major: step t of lane l is R/2 bytes
 // at ((s*64 + l) * Lw + (t - u_l)) * R/2.  Each 32-bit word holds 8/R
 // steps, the earlier higher; a step's 4R bits hold rows 0..R-1 from the
 // top; a row's nibble, from its
@@ -449,6 +449,8 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
   static_assert(R == 2 || R == 4, "the band kernel is laid out for 2 or 4 rows per lane");
   constexpr int HB = R / 2;       // code bytes per lane and step
   constexpr int NWC = 8 * HB / 4; // code dwords per lane and 8 steps
+  constexpr int PW = band_code_piece(R) / 4; // code dwords per store (a piece)
+  constexpr int NG = PW / NWC;                // 8-step groups per piece
   const PairTask tk = a.tasks[task];
   const int p = tk.pair;
   const int M = a.b.q_len[p];
@@ -477,7 +479,9 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
   }
 
   const int w = a.band_w;
-  const int RB = a.ring_cols, RM = RB - 1;
+  // boundary ring of RB columns (a multiple of 16, at least 64): column j at
+  // j mod RB
+  const int RB = a.ring_cols;
   const size_t slot = band_slot_bytes(RB, a.lds_prof);
   uint8_t *mine = smem + (size_t)wave * slot;
   int8_t *prof = reinterpret_cast<int8_t *>(mine + (size_t)RB * 8);
@@ -582,6 +586,7 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
     // column jlo - 1 (lane 1 of a strip with jlo = 1 is then on column 0 and
     // needs H(itop + R - 1, 0) as the diagonal of its first row at column 1)
     int out_t = B[R - 1] + goe, out_f = NEG32, out_c = 0;
+    int wslot = 0, rfeed = 0;
 
     const int2 *bnd_in = ring(s + G - 1);
     int2 *bnd_out = ring(s);
@@ -596,9 +601,29 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
       if (itop <= M) u_l = (max(1, band_centre(itop, M, N) - w) - jlo + lane) & ~(band_code_align(R) - 1);
       tbl = a.tb + tk.tb_off + ((size_t)s * 64 + lane) * (size_t)Lw * HB;
     }
-    uint32_t acc[NWC];
+    uint32_t acc[NWC], pend[PW];
 #pragma unroll
     for (int k = 0; k < NWC; ++k) acc[k] = 0;
+#pragma unroll
+    for (int k = 0; k < PW; ++k) pend[k] = 0;
+
+    // The codes of the last piece (NG groups of 8 steps: band_code_piece()
+    // bytes) wait in `pend` and go out as one aligned store.  tp: the group's
+    // first step in the window (a multiple of 8); `blank` appends a group of
+    // zeros.
+    auto push_group = [&](int tp, bool blank) {
+#pragma unroll
+      for (int v = 0; v < PW - NWC; ++v) pend[v] = pend[v + NWC];
+#pragma unroll
+      for (int v = 0; v < NWC; ++v) pend[PW - NWC + v] = blank ? 0u : acc[v];
+      const int tp0 = tp - 8 * (NG - 1); // first step of the piece
+      if (((tp >> 3) & (NG - 1)) == NG - 1 && (unsigned)tp0 < (unsigned)Lw) {
+        uint4 *dst = reinterpret_cast<uint4 *>(tbl + (size_t)tp0 * HB);
+#pragma unroll
+        for (int v = 0; v < PW / 4; ++v)
+          dst[v] = make_uint4(pend[4 * v], pend[4 * v + 1], pend[4 * v + 2], pend[4 * v + 3]);
+      }
+    };
 
     // GLOBAL: H(M, N) is the last strip's row M at the step its lane is on column N
     const bool last = s == nstrips - 1;
@@ -616,13 +641,15 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
       } else {
         const int upto = max(min(jhi_p, jlo + t + CH - 1), 0);
         if (G > 1) ok = ok && lds_wait_geq(&prog[(s - 1) % G], stamp(s - 1, upto));
-        const int2 v = bnd_in[jf & RM];
+        int rx = rfeed + lane; // jf mod RB: one wrap at most (lane < 64 <= RB)
+        rx = rx >= RB ? rx - RB : rx;
+        const int2 v = bnd_in[rx];
         const bool inr = jf >= jlo_p && jf <= jhi_p;
         fh = settle(inr ? v.x + goe : NEG32 + goe, zero);
         ff = settle(inr ? v.y : NEG32, zero);
         if (t == 0 && jlo > 1) {
           const int jd = jlo - 1;
-          const int hv = bnd_in[jd & RM].x;
+          const int hv = bnd_in[jd % RB].x;
           if (lane == 0) hd_top = (jd >= jlo_p && jd <= jhi_p) ? hv : NEG32;
         }
         if (G > 1) lds_publish(&cons[(s - 1) % G], stamp(s - 1, upto));
@@ -632,7 +659,10 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
     // one step; ZC: some lane may be on column 0 (strips with jlo = 1)
     auto step = [&](auto zc_tag, const int t, const int k) {
       constexpr bool ZC = decltype(zc_tag)::value;
-      if (k == 0 && (t & (CH - 1)) == 0) load_feeds(t);
+      if (k == 0 && (t & (CH - 1)) == 0) {
+        load_feeds(t);
+        rfeed = rfeed + CH >= RB ? rfeed + CH - RB : rfeed + CH;
+      }
       // lane 0 takes the chunk's next feed, every other lane the lane above
       const int nh = dpp_wave_shl1(fh), nf = dpp_wave_shl1(ff), nc = dpp_wave_shl1(fc);
       const int in_t = dpp_wave_shr1(fh, out_t);
@@ -697,20 +727,9 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
       out_c = in_c;
       // lane 63 on a column of the strip: the strip's bottom row
       if (has_reader && t >= 63 && t - 63 < range && lane == 63)
-        bnd_out[(jlo + t - 63) & RM] = make_int2(Hl[R - 1], fu);
-      if (TB && k == 7) {
-        const int tp = t - 7 - u_l;
-        if ((unsigned)tp < (unsigned)Lw) {
-          if constexpr (NWC == 2) {
-            *reinterpret_cast<uint2 *>(tbl + (size_t)tp * HB) = make_uint2(acc[0], acc[1]);
-          } else {
-            uint4 *dst = reinterpret_cast<uint4 *>(tbl + (size_t)tp * HB);
-#pragma unroll
-            for (int v = 0; v < NWC / 4; ++v)
-              dst[v] = make_uint4(acc[4 * v], acc[4 * v + 1], acc[4 * v + 2], acc[4 * v + 3]);
-          }
-        }
-      }
+        bnd_out[wslot] = make_int2(Hl[R - 1], fu);
+      if (t >= 63) wslot = wslot + 1 == RB ? 0 : wslot + 1;
+      if (TB && k == 7) push_group(t - 7 - u_l, false);
       if (MODE == ALN_GLOBAL && last && t == t_end) {
         // row rM of lane lM, read row by row (a selected register would go
         // through memory)
@@ -728,6 +747,8 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
 
     const int T = range > 0 ? range + 63 : 0;
     const int tz = jlo == 1 ? min(T, 64) : 0; // steps with a lane on column 0
+    wslot = jlo % RB; // ring slot of column jlo + t - 63 from step 63 on
+    rfeed = wslot;    // ring slot of column jlo + t at the chunk's first step t
     int t8 = 0;
     for (; t8 < tz; t8 += 8) {
 #pragma unroll
@@ -736,6 +757,10 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
     for (; t8 < T; t8 += 8) {
 #pragma unroll
       for (int k = 0; k < 8; ++k) step(std::integral_constant<bool, false>{}, t8 + k, k);
+    }
+    if (TB) { // the piece the last steps began (blank groups after them)
+#pragma unroll
+      for (int f = 1; f < NG; ++f) push_group(t8 - 8 - u_l + 8 * f, true);
     }
     if (G > 1) {
       if (has_reader) lds_publish(&prog[s % G], stamp(s, N));
@@ -988,7 +1013,7 @@ static hipError_t launch_band_g(int mode, bool tb, bool small, const StripArgs &
 hipError_t launch_band_strip(int rows, int mode, bool tb, bool small_alphabet, const StripArgs &a,
                              hipStream_t s) {
   if (a.ntasks <= 0) return hipSuccess;
-  if (a.ring_cols < 64 || (a.ring_cols & (a.ring_cols - 1)) != 0) return hipErrorInvalidValue;
+  if (a.ring_cols < 64 || a.ring_cols > 2048 || a.ring_cols % 16 != 0) return hipErrorInvalidValue;
   if (rows != 2 && rows != 4) return hipErrorInvalidValue;
   if (a.waves == kStripPipeWaves)
     return rows == 2 ? launch_band_g<2, kStripPipeWaves>(mode, tb, small_alphabet, a, s)

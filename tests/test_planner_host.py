@@ -107,9 +107,9 @@ def tb_need(family, tile, sides, M, N, w=0):
     if family == "strip_i32":
         ns = -(-M // (64 * tile))
         return ns * (N + 63) * 64 * (tile // 2)
-    if family == "band_strip":  # per strip and lane a window of Lw steps, 16-byte aligned
+    if family == "band_strip":  # per strip and lane a window of Lw steps, aligned to a store piece
         ns = -(-M // (64 * tile))
-        al = 32 // tile
+        al = (64 if tile == 2 else 16) * 2 // tile
         span = min(2 * w + 2 + (tile - 1) * N // M, N)
         lw = (span + (al - 1) + al - 1) // al * al
         return ns * 64 * lw * (tile // 2)
