@@ -612,15 +612,16 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
       if (p.prune == ALN_BAND) {
         const int64_t w = p.band_w;
         // strips (band_kernel 2..5: one or four wavefronts per pair, 4 or 2
-        // rows per lane): a strip's columns fit one LDS ring of at most 2048,
-        // and the pipeline's stamps s*(N+1) + column fit 31 bits
+        // rows per lane): a strip's columns and 10 spare ones fit one LDS ring
+        // of at most 2048, and the pipeline's stamps s*(N+1) + column fit 31
+        // bits
         int bk = ctx->force_band_kernel
                      ? ctx->force_band_kernel
                      : (ctx->tuning.valid ? ctx->tuning.band_kernel : 0);
         if (bk == 0) bk = 2 * w + 1 >= 256 ? 5 : 1; // wide bands: strips, four wavefronts of 2 rows
         const int brows = (bk == 4 || bk == 5) ? 2 : 4;
         const int64_t cols = M > 0 && N > 0 ? alnk::band_strip_cols(M, N, (int32_t)std::min<int64_t>(w, 1 << 28), brows) : 0;
-        const int64_t ring = std::max<int64_t>(64, (cols + 2 + 15) / 16 * 16);
+        const int64_t ring = std::max<int64_t>(64, (cols + 10 + 15) / 16 * 16);
         const int64_t nsb = (M + 64LL * brows - 1) / (64LL * brows);
         const bool strip_fit = M > 0 && N > 0 && ring <= 2048 && w < (1 << 28) &&
                                nsb * ((int64_t)N + 1) + N < (1LL << 31);
@@ -666,7 +667,7 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
   // band past the matrix (the same four-wavefront schedule, 256-row strips):
   // that kernel's rotating lane-0 feeds and eight-step code stores take
   // about 18% less time on 1 kbp pairs.  Its LDS ring holds a strip's
-  // columns, so N <= 2046.
+  // columns and 10 more, so N <= 2038.
   pl->strip_band_w = p.prune == ALN_BAND ? p.band_w : (1 << 28);
   if (srows == 0 || srows == 2 || srows == 4) {
     int64_t n_full = 0;
@@ -685,8 +686,8 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
       const int32_t M = pl->qlen[it.pair], N = pl->rlen[it.pair];
       const uint64_t bnd = align_up((uint64_t)(N + 1) * 8, 16);
       const uint64_t prof = small ? 0 : align_up((uint64_t)hs.alphabet * 64 * R, 16);
-      if (srows == 0 && M > 64 * R && N <= 2046 && pl->strip_band_w >= std::max(M, N)) {
-        const int64_t ring = std::max<int64_t>(64, ((int64_t)N + 2 + 15) / 16 * 16);
+      if (srows == 0 && M > 64 * R && N <= 2038 && pl->strip_band_w >= std::max(M, N)) {
+        const int64_t ring = std::max<int64_t>(64, ((int64_t)N + 10 + 15) / 16 * 16);
         it.kind = K_BAND;
         it.rows = R;
         it.waves = G;

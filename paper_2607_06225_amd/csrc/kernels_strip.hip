@@ -591,6 +591,7 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
     const int2 *bnd_in = ring(s + G - 1);
     int2 *bnd_out = ring(s);
     const bool has_reader = s + 1 < nstrips;
+    const bool w63 = has_reader && lane == 63; // lane 63 writes the strip's bottom row
     if (G > 1 && has_reader && s >= G) // ring free: the previous generation was read in full
       ok = ok && lds_wait_geq(&cons[s % G], stamp(s - G, N));
 
@@ -656,9 +657,12 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
       }
     };
 
-    // one step; ZC: some lane may be on column 0 (strips with jlo = 1)
-    auto step = [&](auto zc_tag, const int t, const int k) {
+    // one step; ZC: the first 64 steps (a lane may be on column 0, or before
+    // the strip's bottom row starts at step 63);
+    // GH: the eight steps holding t_end (GLOBAL, last strip)
+    auto step = [&](auto zc_tag, auto gh_tag, const int t, const int k) {
       constexpr bool ZC = decltype(zc_tag)::value;
+      constexpr bool GH = decltype(gh_tag)::value;
       if (k == 0 && (t & (CH - 1)) == 0) {
         load_feeds(t);
         rfeed = rfeed + CH >= RB ? rfeed + CH - RB : rfeed + CH;
@@ -671,7 +675,7 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
       fh = nh;
       ff = nf;
       fc = nc;
-      const bool at0 = ZC && t + 1 == lane; // on column 0 (jlo = 1)
+      const bool at0 = ZC && t + 1 == lane; // on column jlo - 1 (column 0 when jlo = 1)
       int tu = in_t, fu = in_f, hd = hd_top;
       uint32_t pw = 0;
       if (!SMALLA) {
@@ -726,11 +730,12 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
       out_f = fu;
       out_c = in_c;
       // lane 63 on a column of the strip: the strip's bottom row
-      if (has_reader && t >= 63 && t - 63 < range && lane == 63)
-        bnd_out[wslot] = make_int2(Hl[R - 1], fu);
-      if (t >= 63) wslot = wslot + 1 == RB ? 0 : wslot + 1;
+      // (up to 7 columns past jhi at the end: the ring's 8 spare columns
+      // keep them off the columns the reader takes)
+      if (w63 && (!ZC || t >= 63)) bnd_out[wslot] = make_int2(Hl[R - 1], fu);
+      if (!ZC || t >= 63) wslot = wslot + 1 == RB ? 0 : wslot + 1;
       if (TB && k == 7) push_group(t - 7 - u_l, false);
-      if (MODE == ALN_GLOBAL && last && t == t_end) {
+      if (MODE == ALN_GLOBAL && (ZC || GH) && last && t == t_end) {
         // row rM of lane lM, read row by row (a selected register would go
         // through memory)
         int g[R];
@@ -741,22 +746,32 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
         for (int r = 1; r < R; ++r) gh = rM == r ? g[r] : gh;
       }
       // columns <= jlo + t - 63 of this strip's bottom row are written
-      if (G > 1 && has_reader && (t & (CH - 1)) == CH - 1)
+      if (G > 1 && has_reader && k == 7 && (t & (CH - 1)) == CH - 1)
         lds_publish(&prog[s % G], stamp(s, max(min(jhi, jlo + t - 63), 0)));
     };
 
     const int T = range > 0 ? range + 63 : 0;
-    const int tz = jlo == 1 ? min(T, 64) : 0; // steps with a lane on column 0
+    // the first 64 steps take the column-0 form (with jlo > 1 its override
+    // sets H of a column left of every row's band to minus infinity, as the
+    // mask does)
+    const int tz = min(T, 64);
     wslot = jlo % RB; // ring slot of column jlo + t - 63 from step 63 on
     rfeed = wslot;    // ring slot of column jlo + t at the chunk's first step t
     int t8 = 0;
+    using Yes = std::integral_constant<bool, true>;
+    using No = std::integral_constant<bool, false>;
     for (; t8 < tz; t8 += 8) {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) step(std::integral_constant<bool, true>{}, t8 + k, k);
+      for (int k = 0; k < 8; ++k) step(Yes{}, No{}, t8 + k, k);
     }
     for (; t8 < T; t8 += 8) {
+      if (MODE == ALN_GLOBAL && last && (unsigned)(t_end - t8) < 8u) {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) step(std::integral_constant<bool, false>{}, t8 + k, k);
+        for (int k = 0; k < 8; ++k) step(No{}, Yes{}, t8 + k, k);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) step(No{}, No{}, t8 + k, k);
+      }
     }
     if (TB) { // the piece the last steps began (blank groups after them)
 #pragma unroll

@@ -127,15 +127,15 @@ def test_strip_band_path_through_column_zero(ctx, kernel, mode):
     assert compare(b, res, cig, oracle_batch(b)) == []
 
 
-@pytest.mark.parametrize("kernel,wmax", [(3, 894), (5, 958)])
+@pytest.mark.parametrize("kernel,wmax", [(3, 890), (5, 954)])
 def test_strip_band_widest_ring(ctx, kernel, wmax):
     """Bands whose strip range needs the largest ring (2048 columns) run on
     strips; one column more goes to the antidiagonal kernel."""
     rng = np.random.default_rng(91)
     qs, rs = mutated_pairs(rng, [(2600, 2600), (3000, 2900), (700, 650)], 4)
     with_band_kernel(ctx, kernel)
-    # (2600, 2600): 2w + 2 + 64R - 1 columns, plus 2, fit 2048 up to w = 894
-    # (R = 4) or 958 (R = 2); the antidiagonal fallback one wider has no
+    # (2600, 2600): 2w + 2 + 64R - 1 columns, plus 10, fit 2048 up to w = 890
+    # (R = 4) or 954 (R = 2); the antidiagonal fallback one wider has no
     # CIGAR form that wide
     for w, fam, cigar in ((wmax, "band_strip", True), (wmax + 1, "diag_band", False)):
         b = W.pack_pairs(qs, rs, W.dna_matrix(1, -2), -2, -1, W.GLOBAL, W.BAND, band_w=w,

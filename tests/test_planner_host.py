@@ -310,7 +310,7 @@ def test_empty_batch_plans(hctx):
 
 def test_band_kernel_forced_by_tuning():
     """The tuned band kernel overrides the width rule; pairs the strips cannot
-    hold (a strip range beyond 2046 columns) stay on antidiagonal windows."""
+    hold (a strip range beyond 2038 columns) stay on antidiagonal windows."""
     c = aln.Context.host()
     try:
         rng = np.random.default_rng(5)
@@ -332,12 +332,12 @@ def test_band_kernel_forced_by_tuning():
         assert fams(20, 4) == [("band_strip", 1)]
         assert fams(20, 5) == [("band_strip", 4)]
         assert fams(300, 1) == [("diag_band", 1)]
-        # (3000, 3000) at w = 894 needs 2 * 894 + 2 + 255 + 2 = 2047 ring columns
-        assert fams(894, 3) == [("band_strip", 4)]
-        assert fams(895, 3) == [("diag_band", 1)]
-        # 2 rows a lane: 2 * 958 + 2 + 127 + 2 = 2047
-        assert fams(958, 5) == [("band_strip", 4)]
-        assert fams(959, 5) == [("diag_band", 1)]
+        # (3000, 3000) at w = 890 needs 2 * 890 + 2 + 255 + 10 = 2047 ring columns
+        assert fams(890, 3) == [("band_strip", 4)]
+        assert fams(891, 3) == [("diag_band", 1)]
+        # 2 rows a lane: 2 * 954 + 2 + 127 + 10 = 2047
+        assert fams(954, 5) == [("band_strip", 4)]
+        assert fams(955, 5) == [("diag_band", 1)]
         with pytest.raises(aln.AlnError):
             c.set_tuning(dict(base, band_kernel=6))
     finally:
