@@ -479,9 +479,11 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
   }
 
   const int w = a.band_w;
-  // boundary ring of RB columns (a multiple of 16, at least 64): column j at
-  // j mod RB
+  // boundary ring of RB columns (a multiple of 16, at least 64): strip s
+  // keeps its bottom row's column j at (j - jlo_s - 1) mod RB, so the writes
+  // of steps 64.. (columns jlo_s + 1..) fill 8 consecutive slots per 8 steps
   const int RB = a.ring_cols;
+  auto rmod = [&](int x) { x %= RB; return x < 0 ? x + RB : x; };
   const size_t slot = band_slot_bytes(RB, a.lds_prof);
   uint8_t *mine = smem + (size_t)wave * slot;
   int8_t *prof = reinterpret_cast<int8_t *>(mine + (size_t)RB * 8);
@@ -586,7 +588,7 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
     // column jlo - 1 (lane 1 of a strip with jlo = 1 is then on column 0 and
     // needs H(itop + R - 1, 0) as the diagonal of its first row at column 1)
     int out_t = B[R - 1] + goe, out_f = NEG32, out_c = 0;
-    int wslot = 0, rfeed = 0;
+    int wbase = 0, rfeed = 0; // ring slots: this group's first write; the feed chunk's first column
 
     const int2 *bnd_in = ring(s + G - 1);
     int2 *bnd_out = ring(s);
@@ -650,7 +652,7 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
         ff = settle(inr ? v.y : NEG32, zero);
         if (t == 0 && jlo > 1) {
           const int jd = jlo - 1;
-          const int hv = bnd_in[jd % RB].x;
+          const int hv = bnd_in[rmod(jd - jlo_p - 1)].x;
           if (lane == 0) hd_top = (jd >= jlo_p && jd <= jhi_p) ? hv : NEG32;
         }
         if (G > 1) lds_publish(&cons[(s - 1) % G], stamp(s - 1, upto));
@@ -732,8 +734,11 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
       // lane 63 on a column of the strip: the strip's bottom row
       // (up to 7 columns past jhi at the end: the ring's 8 spare columns
       // keep them off the columns the reader takes)
-      if (w63 && (!ZC || t >= 63)) bnd_out[wslot] = make_int2(Hl[R - 1], fu);
-      if (!ZC || t >= 63) wslot = wslot + 1 == RB ? 0 : wslot + 1;
+      if (ZC) {
+        if (k == 7 && t == 63 && w63) bnd_out[RB - 1] = make_int2(Hl[R - 1], fu); // column jlo
+      } else if (w63) {
+        bnd_out[wbase + k] = make_int2(Hl[R - 1], fu); // column jlo + t - 63
+      }
       if (TB && k == 7) push_group(t - 7 - u_l, false);
       if (MODE == ALN_GLOBAL && (ZC || GH) && last && t == t_end) {
         // row rM of lane lM, read row by row (a selected register would go
@@ -755,8 +760,8 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
     // sets H of a column left of every row's band to minus infinity, as the
     // mask does)
     const int tz = min(T, 64);
-    wslot = jlo % RB; // ring slot of column jlo + t - 63 from step 63 on
-    rfeed = wslot;    // ring slot of column jlo + t at the chunk's first step t
+    wbase = 0;                              // steps 64..71: columns jlo + 1..jlo + 8
+    rfeed = s > 0 ? rmod(jlo - jlo_p - 1) : 0; // column jlo in the strip above's ring
     int t8 = 0;
     using Yes = std::integral_constant<bool, true>;
     using No = std::integral_constant<bool, false>;
@@ -772,6 +777,7 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
 #pragma unroll
         for (int k = 0; k < 8; ++k) step(No{}, No{}, t8 + k, k);
       }
+      wbase = wbase + 8 == RB ? 0 : wbase + 8;
     }
     if (TB) { // the piece the last steps began (blank groups after them)
 #pragma unroll
