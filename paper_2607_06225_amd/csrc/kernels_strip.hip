@@ -434,9 +434,9 @@ __device__ __forceinline__ void shift_in(uint32_t &v, bool bit) {
 // Codes (4 bits per cell): per strip and lane a window of band_code_steps()
 // steps starting at u_l, the lane's first in-band step rounded down to
 // band_code_align(R) (one store piece), lane-major: step t of lane l is R/2 bytes
-// at ((s*64 + l) * Lw + (t - u_l)) * R/2.  Each 32-bit word holds 8/R
-// steps, the earlier higher; a step's 4R bits hold rows 0..R-1 from the
-// top; a row's nibble, from its
+// at ((s*64 + l) * Lw + (t - u_l)) * R/2.  Eight steps (t - u_l from a
+// multiple of 8) are R 32-bit words, word r holding row r's eight nibbles,
+// the earlier step higher; a row's nibble, from its
 // top bit: H is not the diagonal term (LOCAL: and not zero), H is not E
 // (LOCAL: or is zero; with the bit above clear this marks a zero), E(i, j)
 // opened from H(i, j-1), F(i, j) opened from H(i-1, j).
@@ -687,7 +687,6 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
         else
           pw = *reinterpret_cast<const uint32_t *>(prof + ((size_t)cc * 64 + lane) * R);
       }
-      uint32_t &cw = acc[(k * R) / 8]; // 8 / R steps per word
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         int sv;
@@ -705,14 +704,14 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
           const bool nd = h != hdiag, ne = h != EN[r];
           if (MODE == ALN_LOCAL) {
             const bool z = h == 0;
-            shift_in(cw, nd && !z);
-            shift_in(cw, (nd && ne) || z);
+            shift_in(acc[r], nd && !z);
+            shift_in(acc[r], (nd && ne) || z);
           } else {
-            shift_in(cw, nd);
-            shift_in(cw, ne);
+            shift_in(acc[r], nd);
+            shift_in(acc[r], ne);
           }
-          shift_in(cw, eo[r]);
-          shift_in(cw, f == tu);
+          shift_in(acc[r], eo[r]); // a word per row: R independent shift chains
+          shift_in(acc[r], f == tu);
           eo[r] = en == tt;
         }
         if (MODE != ALN_GLOBAL) {

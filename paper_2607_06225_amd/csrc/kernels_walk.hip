@@ -263,14 +263,13 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
       // steps outside the lane's window read as zero codes: only cells of
       // the band lie on a path, and a run or gap read ahead stops at the
       // path's next cell, which is inside the band
-      // 8 / R steps a word, the earlier higher; rows from the top of a
-      // step's 4R bits; nibble: not-diagonal, not-E (LOCAL: zero with the
+      // eight steps are R words, word r2 row r2's nibbles, the earlier
+      // step higher; nibble: not-diagonal, not-E (LOCAL: zero with the
       // first clear), E opened, F opened
       const int st = t - (b << LTB);
-      const int spw = 8 / R; // steps per word
       const uint32_t wd = reinterpret_cast<const uint32_t *>(codes0)[
-          (slot * BLK + l2 * (TBK * HB)) / 4 + st / spw];
-      const int nib = (int)(wd >> (28 - 4 * R * (st % spw) - 4 * r2)) & 15;
+          (slot * BLK + l2 * (TBK * HB)) / 4 + (st >> 3) * R + r2];
+      const int nib = (int)(wd >> (28 - 4 * (st & 7))) & 15;
       const int b0 = nib >> 3, b1 = (nib >> 2) & 1;
       const int hs = b0 ? (b1 ? 2 : 1) : ((local && b1) ? 3 : 0);
       return hs | ((nib & 2) << 1) | ((nib & 1) << 3);
