@@ -686,7 +686,8 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
       const int32_t M = pl->qlen[it.pair], N = pl->rlen[it.pair];
       const uint64_t bnd = align_up((uint64_t)(N + 1) * 8, 16);
       const uint64_t prof = small ? 0 : align_up((uint64_t)hs.alphabet * 64 * R, 16);
-      if (srows == 0 && M > 64 * R && N <= 2038 && pl->strip_band_w >= std::max(M, N)) {
+      if ((srows == 0 || srows == 2) && M > 64 * R && N <= 2038 &&
+          pl->strip_band_w >= std::max(M, N)) {
         const int64_t ring = std::max<int64_t>(64, ((int64_t)N + 10 + 15) / 16 * 16);
         it.kind = K_BAND;
         it.rows = R;

@@ -861,7 +861,7 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
 }
 
 template <int R, int MODE, bool TB, bool SMALLA, int G>
-__global__ __launch_bounds__(256) void band_kernel(StripArgs a) {
+__global__ __launch_bounds__(G == 8 ? 512 : 256) void band_kernel(StripArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -1038,6 +1038,8 @@ hipError_t launch_band_strip(int rows, int mode, bool tb, bool small_alphabet, c
   if (a.waves == kStripPipeWaves)
     return rows == 2 ? launch_band_g<2, kStripPipeWaves>(mode, tb, small_alphabet, a, s)
                      : launch_band_g<4, kStripPipeWaves>(mode, tb, small_alphabet, a, s);
+  if (a.waves == kStripPipeWaves2 && rows == 2)
+    return launch_band_g<2, kStripPipeWaves2>(mode, tb, small_alphabet, a, s);
   if (a.waves == 1)
     return rows == 2 ? launch_band_g<2, 1>(mode, tb, small_alphabet, a, s)
                      : launch_band_g<4, 1>(mode, tb, small_alphabet, a, s);
