@@ -43,8 +43,8 @@
 // per lane and antidiagonal.
 //
 // Traceback codes (the form with CIGAR): per antidiagonal and side 32 bytes,
-// 8 per lane, written by the lanes that hold a candidate cell, plus the
-// window base.  Cell m of a lane sits in dword m >> 3 at nibble 7 - (m & 7);
+// 8 per lane, written whole by the side's four lanes, plus the window base
+// (the bases of 8 antidiagonals stored together).  Cell m of a lane sits in dword m >> 3 at nibble 7 - (m & 7);
 // its bits, high to low: F passed down opened from H (F-open), E passed right
 // opened from H (E-open), H not from E, H not from the diagonal -- so H takes
 // the diagonal, then E, then F, and a gap opens before it extends.  The codes
@@ -163,6 +163,7 @@ xdrop_lanes_kernel(XdlArgs a) {
   long long cells = 0;
   const uint8_t *Q = nullptr, *R = nullptr;
   int *tb_base = nullptr;   // traceback: window base per antidiagonal
+  int bb0 = 0, bb1 = 0;     // traceback: two window bases awaiting their store
   uint2 *tb_codes = nullptr; // traceback: 4 x 8 bytes per antidiagonal
 
   // 32 codes per call into a ring (the query reversed), padding (4) past
@@ -342,8 +343,17 @@ xdrop_lanes_kernel(XdlArgs a) {
         }
       }
       if (TB && active) {
-        if (inr_rev) tb_codes[(size_t)k * 4 + gl] = make_uint2(code0, code1);
-        if (qfirst) tb_base[k] = base;
+        // every lane of the side stores, so each antidiagonal's 32 bytes go
+        // out whole (a lane without candidates stores codes no walk reads)
+        tb_codes[(size_t)k * 4 + gl] = make_uint2(code0, code1);
+        // window bases: lane gl keeps those of antidiagonals 8n + 2gl and
+        // 8n + 2gl + 1; the side's four lanes store 8 at once (32 bytes)
+        const int kr = k & 7;
+        if (gl == (kr >> 1)) {
+          if (kr & 1) bb1 = base;
+          else bb0 = base;
+        }
+        if (kr == 7) *reinterpret_cast<uint2 *>(tb_base + (k - 7) + 2 * gl) = make_uint2(bb0, bb1);
       }
       sb &= inr_rev;
       // ---- the antidiagonal's outcome per side
@@ -375,6 +385,11 @@ xdrop_lanes_kernel(XdlArgs a) {
       const bool wide = cont && nhi - nlo > 63;
       if (active && (!cont || wide)) {
         // the extension ends here (or leaves for a wider window)
+        if (TB && (k & 7) != 7) { // the window bases of the last, partial group
+          const int kr = k & 7, at = (k - kr) + 2 * gl;
+          if (2 * gl + 1 <= kr) *reinterpret_cast<uint2 *>(tb_base + at) = make_uint2(bb0, bb1);
+          else if (2 * gl == kr) tb_base[at] = bb0;
+        }
         if (qfirst) {
           aln_result *res = a.res + pair;
           if (wide) {
