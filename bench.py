@@ -79,7 +79,7 @@ BASIC_RATE = 0.25
 PEAK_I32_TOPS = SIMDS * 64 * BASIC_RATE * SPEC_CLOCK_GHZ / 1e3  # 39.32
 KERNEL_WIDTH = {"sw16": "i16"}
 FILL_KERNELS = ("sw16", "strip_i32", "diag_band", "band_strip", "xdrop", "xdrop_lanes", "xdrop_lanes_tb",
-                "zdrop", "xdrop_tb", "zdrop_tb",
+                "zdrop", "zdrop_lanes", "xdrop_tb", "zdrop_tb",
                 "search", "search_affine", "search_affine_wide")
 
 

@@ -706,10 +706,13 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
   // alphabet runs on the sixteen-sides-per-wavefront kernel when its
   // arithmetic fits: offset-frame scores in one byte, the out-of-range
   // penalty (-128) below every threshold (X < 128 + 2|e|), end cells in 16
-  // bits and keys (score << 6) in 31.
+  // bits and keys (score << 6) in 31.  Z-drop too, scores only, when tuned
+  // (its form masks removed and out-of-range cells itself, so Z has no
+  // bound).
+  const bool zd = p.prune == ALN_ZDROP;
   const bool lanes_fit =
-      p.prune == ALN_XDROP && hs.match_mismatch && hs.alphabet <= 4 &&
-      (int64_t)p.xdrop <= 127 - 2LL * hs.gap_extend && hs.match - 2 * hs.gap_extend <= 127 &&
+      (p.prune == ALN_XDROP || zd) && hs.match_mismatch && hs.alphabet <= 4 &&
+      (zd || (int64_t)p.xdrop <= 127 - 2LL * hs.gap_extend) && hs.match - 2 * hs.gap_extend <= 127 &&
       hs.mismatch - 2 * hs.gap_extend >= -128 && maxM <= 65535 && maxN <= 65535 &&
       ((int64_t)maxM + maxN) * (1 - hs.gap_extend + std::max(hs.match, 0)) < (1LL << 23);
   const bool lanes_ok = lanes_fit && !p.want_cigar;
@@ -736,7 +739,10 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     L.rows = items[k].rows;
     L.mode = p.mode;
     if (L.kind == K_DIAG && dyn_prune) {
-      L.sides = ctx->tuning.valid ? ctx->tuning.xdrop_sides : (lanes_ok ? 16 : 1);
+      // Z-drop takes the sixteen-sides form only when tuned: its regions
+      // often outgrow the 64-cell window (at Z = 100, e = -2 nearly every
+      // side, 345 ms against 300 on the one-side kernel)
+      L.sides = ctx->tuning.valid ? ctx->tuning.xdrop_sides : ((lanes_ok && !zd) ? 16 : 1);
       if (ctx->force_xdrop_sides) L.sides = ctx->force_xdrop_sides;
       if (L.sides == 16 && !lanes_ok) L.sides = 1;
       if (L.sides == 4 && L.rows != 8) L.sides = 1;
@@ -812,7 +818,7 @@ aln_status alnrt::plan_build(aln_ctx *ctx, int32_t scoring_id, const aln_params 
     const int tuned_sides = ctx->force_xdrop_sides
                                 ? ctx->force_xdrop_sides
                                 : (ctx->tuning.valid ? ctx->tuning.xdrop_sides : 16);
-    pl->xtb_lanes = lanes_fit && tuned_sides == 16;
+    pl->xtb_lanes = lanes_fit && !zd && tuned_sides == 16;
     if (pl->xtb_lanes) {
       const int64_t want = ((int64_t)n + 15) / 16;
       const int64_t fit = (int64_t)ctx->cus * lanes_waves_per_cu(ctx, true);
@@ -1083,12 +1089,16 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
     return da;
   };
   PairTask *wq0 = plan->xdrop ? reinterpret_cast<PairTask *>(ws + plan->widen_off[0]) : nullptr;
+  bool zd_lanes = false; // Z-drop on the sixteen-sides kernel
+  for (const LaunchDesc &L : plan->launches)
+    zd_lanes = zd_lanes || (L.kind == K_DIAG && L.sides == 16 && plan->p.prune == ALN_ZDROP);
   PairTask *wq1 = plan->xdrop ? reinterpret_cast<PairTask *>(ws + plan->widen_off[1]) : nullptr;
   PairTask *wq2 = plan->xtb_lanes ? reinterpret_cast<PairTask *>(ws + plan->widen_off[2]) : nullptr;
   if (plan->xtb_lanes) {
     // codes from the sixteen-sides kernel; pairs whose region outgrows its
     // window are recomputed with codes by the one-side pass (queue 2)
     alnk::XdlArgs xa;
+    xa.zdrop = 0;
     xa.b = bp;
     xa.tasks = dtasks + plan->xtb_first;
     xa.ntasks = plan->xtb_count;
@@ -1136,10 +1146,11 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
   for (const LaunchDesc &L : plan->launches) {
     if (L.kind == K_DIAG) {
       if (plan->xtb_count > 0) continue; // the traceback pass above replaces it
-      const int widen_rows = plan->xdrop ? 16 : 0;
+      const int widen_rows = plan->xdrop ? (zd_lanes ? 4 : 16) : 0;
       if (L.sides == 16) {
         alnk::XdlArgs xa;
         xa.tb = nullptr;
+        xa.zdrop = plan->p.prune == ALN_ZDROP ? 1 : 0;
         xa.b = bp;
         xa.tasks = dtasks + L.first;
         xa.ntasks = L.count;
@@ -1154,7 +1165,7 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
         xa.widen = wq0;
         xa.widen_rows = widen_rows;
         if (!per_pair) {
-          HIP_TRY(ctx, timed_launch(ctx, "xdrop_lanes", st, [&] {
+          HIP_TRY(ctx, timed_launch(ctx, xa.zdrop ? "zdrop_lanes" : "xdrop_lanes", st, [&] {
                     return alnk::launch_xdrop_lanes(false, xa, L.grid, st);
                   }));
         } else {
@@ -1226,12 +1237,15 @@ static aln_status run_plan(aln_ctx *ctx, aln_plan *plan, const aln_batch *b, voi
     }
   }
   if (plan->xdrop) {
-    // pairs whose surviving region outgrew 256 diagonals, then 1024
+    // pairs whose surviving region outgrew their window: 1024 diagonals, then
+    // 2048.  Z-drop from the sixteen-sides kernel (64 cells) first tries the
+    // one-side kernel's 256 diagonals: Z-drop regions often reach about 100
+    // cells, and that window holds them at a quarter of the wider one's cost.
     const int pr = plan->p.prune;
     const char *fam = pr == ALN_ZDROP ? "zdrop_wide" : "xdrop_wide";
     alnk::DiagArgs d1 = diag_args(wq0, plan->n, widen_cnt, 32, widen_cnt + 1, wq1);
     HIP_TRY(ctx, timed_launch(ctx, fam, st, [&] {
-              return alnk::launch_diag(16, ALN_EXTEND, pr, false, d1, st);
+              return alnk::launch_diag(zd_lanes ? 4 : 16, ALN_EXTEND, pr, false, d1, st);
             }));
     alnk::DiagArgs d2 = diag_args(wq1, plan->n, widen_cnt + 1, 0, nullptr, nullptr);
     HIP_TRY(ctx, timed_launch(ctx, fam, st, [&] {
@@ -1409,7 +1423,8 @@ int64_t aln_plan_describe(const aln_plan *plan, aln_launch_info *launches, int32
       if (L.kind == K_BAND) fam = "band_strip";
       if (L.kind == K_DIAG) {
         if (plan->p.prune == ALN_BAND) fam = "diag_band";
-        else if (plan->p.prune == ALN_ZDROP) fam = L.sides == 4 ? "zdrop_group" : "zdrop";
+        else if (plan->p.prune == ALN_ZDROP)
+          fam = L.sides == 16 ? "zdrop_lanes" : (L.sides == 4 ? "zdrop_group" : "zdrop");
         else fam = L.sides == 16 ? "xdrop_lanes" : (L.sides == 4 ? "xdrop_group" : "xdrop");
       }
       add_launch(fam, L.rows, (L.kind == K_STRIP || L.kind == K_BAND) ? L.waves : L.sides, L.first,

@@ -221,6 +221,7 @@ struct XdlArgs {
   PairTask *widen;
   int32_t widen_rows;        // RD of the wider kernel
   uint8_t *tb;               // traceback form: code regions (task tb_off)
+  int32_t zdrop;             // 1: Z-drop (xdrop holds Z), scores only
 };
 
 // Score-major search for unit-cost edit distance: one workgroup per task,

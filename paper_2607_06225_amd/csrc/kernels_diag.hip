@@ -817,7 +817,9 @@ static hipError_t launch_diag_t(const DiagArgs &a, hipStream_t s) {
   const bool mm = a.match_mismatch != 0;
   const size_t lds = (size_t)4 * 2 * kSeqStride + kMaxAlphabet * kMaxAlphabet;
   int blocks = (a.ntasks + 3) / 4;
-  if (a.dyn_ntasks) blocks = min(blocks, 2048);
+  // a device-counted queue: the wide windows take few pairs (a capped grid,
+  // grid-stride); the 256-diagonal window can take many, a wavefront each
+  if (a.dyn_ntasks && RD >= 16) blocks = min(blocks, 2048);
   if (mm) hipLaunchKernelGGL((diag_kernel<RD, MODE, PRUNE, TB, true>), dim3(blocks), dim3(256), lds, s, a);
   else hipLaunchKernelGGL((diag_kernel<RD, MODE, PRUNE, TB, false>), dim3(blocks), dim3(256), lds, s, a);
   return hipGetLastError();

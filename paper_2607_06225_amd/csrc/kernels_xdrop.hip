@@ -73,6 +73,7 @@ constexpr int kRing = 128;         // codes per ring
 constexpr int kRingMirror = 32;    // first bytes repeated after the ring
 constexpr int kRingStride = kRing + kRingMirror;
 constexpr int kSides = 16;         // sides per wavefront
+constexpr int kZBias = 1 << 20;    // Z-drop: bias of diagonal differences
 
 // quad DPP: lane l reads lane l-1 (shr) / l+1 (shl) of its quad; the quad's
 // edge lane gets `edge`.  quad_perm always names a lane of the quad, so every
@@ -131,7 +132,13 @@ __device__ __forceinline__ uint32_t byte_reverse(uint32_t x) {
 
 // three wavefronts per SIMD: the form with traceback needs a few registers
 // more than fit, and spills two of them on its task-start path
-template <bool TB>
+// ZD: Z-drop (Sec. 9.3) instead of X-drop: a candidate is kept when its H
+// plus its distance |d - d_best| from the best cell's diagonal reaches the
+// threshold.  The thresholds then differ between diagonals, so the pruning
+// above is made explicit: H, E and F of a removed cell or of a cell outside
+// the candidate range are minus infinity, and only kept cells enter the
+// antidiagonal's best.
+template <bool TB, bool ZD>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void
 xdrop_lanes_kernel(XdlArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
@@ -309,6 +316,13 @@ xdrop_lanes_kernel(XdlArgs a) {
       // ---- the cells
       int kmax = INT32_MIN;
       uint32_t sb = 0, code0 = 0, code1 = 0;
+      // Z-drop: this lane's first cell's diagonal minus the best cell's,
+      // biased so that the distance is one unsigned difference per cell
+      uint32_t zlane = 0;
+      if (ZD) {
+        const int bi = 0xffff - (int)(best_key >> 16), bj = 0xffff - (int)(best_key & 0xffffu);
+        zlane = (uint32_t)(base + P + 2 * XC * gl - (bj - bi) + kZBias);
+      }
       const int xin = P == 0 ? quad_shr1(E1[XC - 1], XNEG, qfirst)
                              : quad_shl1(F0[0], XNEG, qlast);
 #pragma unroll
@@ -318,20 +332,30 @@ xdrop_lanes_kernel(XdlArgs a) {
         const int hp = P == 0 ? H0[m] : H1[m];
         const int s = (int)(int8_t)(sc[m >> 2] >> (8 * (m & 3)));
         const int h = max(max(hp + s, ein), fin);
-        const bool keep = h >= T;
+        bool keep = h >= T;
+        if (ZD) {
+          // h + |d - d_best|, d = (first cell's diagonal) + 2m
+          const uint32_t zc = (uint32_t)(kZBias - 2 * m);
+          const int hz = (int)((max(zlane, zc) - min(zlane, zc)) + (uint32_t)h);
+          keep = hz >= T && ((inr_rev >> (XC - 1 - m)) & 1u);
+        }
         const int hm = keep ? h : XNEG;
-        // E and F may take h of a removed cell: below the threshold either way
+        // X-drop: E and F may take h of a removed cell, below the threshold
+        // either way
         const int t = h + go;
+        const int en = (ZD && !keep) ? XNEG : max(ein, t);
+        const int fn = (ZD && !keep) ? XNEG : max(fin, t);
         if (P == 0) {
           H0[m] = hm;
-          E0[m] = max(ein, t);
-          F0[m] = max(fin, t);
+          E0[m] = en;
+          F0[m] = fn;
         } else {
           H1[m] = hm;
-          E1[m] = max(ein, t);
-          F1[m] = max(fin, t);
+          E1[m] = en;
+          F1[m] = fn;
         }
-        kmax = max(kmax, (h << 6) | m); // a removed cell never beats a kept one
+        // X-drop: a removed cell never beats a kept one
+        kmax = max(kmax, (ZD && !keep) ? INT32_MIN : ((h << 6) | m));
         // shift the survivor bit in: sb = 2 sb + keep (cell m ends at bit 15 - m)
         shift_in(sb, keep);
         if (TB) { // the cell's code, high bit first
@@ -494,19 +518,22 @@ size_t xdrop_lanes_lds_bytes() { return (size_t)kSides * 2 * kRingStride; }
 
 hipError_t launch_xdrop_lanes(bool tb, const XdlArgs &a, int waves, hipStream_t s) {
   if (a.ntasks <= 0) return hipSuccess;
+  if (a.zdrop && tb) return hipErrorInvalidValue; // Z-drop codes: the one-side pass
   if (tb)
-    hipLaunchKernelGGL(xdrop_lanes_kernel<true>, dim3(waves), dim3(64), xdrop_lanes_lds_bytes(), s, a);
+    hipLaunchKernelGGL((xdrop_lanes_kernel<true, false>), dim3(waves), dim3(64), xdrop_lanes_lds_bytes(), s, a);
+  else if (a.zdrop)
+    hipLaunchKernelGGL((xdrop_lanes_kernel<false, true>), dim3(waves), dim3(64), xdrop_lanes_lds_bytes(), s, a);
   else
-    hipLaunchKernelGGL(xdrop_lanes_kernel<false>, dim3(waves), dim3(64), xdrop_lanes_lds_bytes(), s, a);
+    hipLaunchKernelGGL((xdrop_lanes_kernel<false, false>), dim3(waves), dim3(64), xdrop_lanes_lds_bytes(), s, a);
   return hipGetLastError();
 }
 
 int xdrop_lanes_waves_per_cu(bool tb) {
   int nb = 0;
   const hipError_t e =
-      tb ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, xdrop_lanes_kernel<true>, 64,
+      tb ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, xdrop_lanes_kernel<true, false>, 64,
                                                         xdrop_lanes_lds_bytes())
-         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, xdrop_lanes_kernel<false>, 64,
+         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, xdrop_lanes_kernel<false, false>, 64,
                                                         xdrop_lanes_lds_bytes());
   if (e != hipSuccess) return 4;
   return nb > 0 ? nb : 1;

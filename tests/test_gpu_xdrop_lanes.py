@@ -207,7 +207,7 @@ def test_lanes_longest_pairs(ctx):
     assert compare(b2, res2, None, oracle_batch(b2)) == []
 
 
-@pytest.mark.parametrize("case", ["x_over_limit", "cigar", "matrix", "zdrop", "alphabet5"])
+@pytest.mark.parametrize("case", ["x_over_limit", "cigar", "matrix", "zdrop_cigar", "alphabet5"])
 def test_lanes_not_used_outside_its_arithmetic(ctx, case):
     """Plans the kernel cannot run exactly go to the one-side kernels."""
     rng = np.random.default_rng(10)
@@ -223,13 +223,52 @@ def test_lanes_not_used_outside_its_arithmetic(ctx, case):
         m = W.dna_matrix(2, -4)
         m[0, 1] = m[1, 0] = -3
         b = W.pack_pairs(qs, rs, m, -4, -2, W.EXTEND, W.XDROP, xdrop=40, name="lanes_mat")
-    elif case == "zdrop":
+    elif case == "zdrop_cigar":
         b = W.pack_pairs(qs, rs, W.dna_matrix(2, -4), -4, -2, W.EXTEND, W.ZDROP, xdrop=40,
-                         name="lanes_zdrop")
+                         want_cigar=True, name="lanes_zdrop_cigar")
     else:
         b = batch(qs, rs, 40, A=5, name="lanes_A5")
     res, cig = run(ctx, b, expect_lanes=False)
     assert compare(b, res, cig, oracle_batch(b)) == []
+
+
+def run_z(ctx, b):
+    """Z-drop scores with the sixteen-sides tile tuned: its Z-drop form runs."""
+    from paper_2607_06225_amd import aln
+    print(f"[gpu] {b.name} n={b.n} Z={b.xdrop}", flush=True)
+    ctx.set_tuning({"sw16_rows": 16, "strip_rows": 0, "xdrop_rows": 4, "xdrop_sides": 16})
+    ctx.set_profiling(True)
+    try:
+        res, _ = aln.align(ctx, b)
+        fams = ctx.kernel_times()
+    finally:
+        ctx.set_profiling(False)
+    assert "zdrop_lanes" in fams and "xdrop_lanes" not in fams, fams
+    return res
+
+
+@pytest.mark.parametrize("Z", [0, 3, 25, 100, 400])
+def test_lanes_zdrop_matches_oracle(ctx, Z):
+    """Z-drop on the sixteen-sides kernel: related and random pairs, lengths
+    from 1 to 1 500 (regions wider than its window go on to the wider
+    one-side kernels), two gap-open scores.  The extension score stays -2:
+    at -1 a gap's cost equals the distance allowance, so a region never
+    narrows and long pairs outgrow the widest window."""
+    rng = np.random.default_rng(600 + Z)
+    lengths = [(int(rng.integers(1, 1500)), int(rng.integers(1, 1500))) for _ in range(60)]
+    qs, rs = pairs(rng, lengths, rate=0.12)
+    qr = [rng.integers(0, 4, size=M).astype(np.uint8) for M, _ in lengths[:10]]
+    for go, ge in ((-4, -2), (0, -2)):
+        b = W.pack_pairs(qs + qr, rs + rs[:10], W.dna_matrix(2, -4), go, ge, W.EXTEND, W.ZDROP,
+                         xdrop=Z, name=f"lanes_z{Z}_o{go}")
+        res = run_z(ctx, b)
+        assert compare(b, res, None, oracle_batch(b)) == []
+
+
+def test_lanes_zdrop_workload_sample(ctx):
+    b = W.zdrop_ext(n=4000, seed=4242)
+    res = run_z(ctx, b)
+    assert compare(b, res, None, oracle_batch(b)) == []
 
 
 def test_lanes_extension_workload_sample(ctx):

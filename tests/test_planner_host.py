@@ -80,6 +80,13 @@ def test_kernel_choice_per_configuration(hctx):
     bp = W.pack_pairs(qp, rp, prot, -11, -1, W.EXTEND, W.XDROP, xdrop=30)
     assert families(hctx, bp) == ["xdrop"]                          # not match/mismatch
     assert families(hctx, pk(W.ZDROP)) == ["zdrop"]
+    assert families(hctx, pk(W.ZDROP, cigar=True)) == ["zdrop_tb"]
+    # the sixteen-sides kernel's Z-drop form when tuned
+    hctx.set_tuning(dict(sw16_rows=16, strip_rows=0, xdrop_rows=4, xdrop_sides=16))
+    try:
+        assert families(hctx, pk(W.ZDROP)) == ["zdrop_lanes"]
+    finally:
+        hctx.set_tuning({"valid": False})
     assert families(hctx, pk(W.XDROP, cigar=True)) == ["xdrop_lanes_tb"]
     assert families(hctx, pk(W.XDROP, X=200, cigar=True)) == ["xdrop_tb"]
     assert families(hctx, pk(W.ZDROP, cigar=True)) == ["zdrop_tb"]
