@@ -662,9 +662,10 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
     // one step; ZC: the first 64 steps (a lane may be on column 0, or before
     // the strip's bottom row starts at step 63);
     // GH: the eight steps holding t_end (GLOBAL, last strip)
-    auto step = [&](auto zc_tag, auto gh_tag, const int t, const int k) {
+    auto step = [&](auto zc_tag, auto gh_tag, auto nm_tag, const int t, const int k) {
       constexpr bool ZC = decltype(zc_tag)::value;
       constexpr bool GH = decltype(gh_tag)::value;
+      constexpr bool NM = decltype(nm_tag)::value; // every lane on an in-band column
       if (k == 0 && (t & (CH - 1)) == 0) {
         load_feeds(t);
         rfeed = rfeed + CH >= RB ? rfeed + CH - RB : rfeed + CH;
@@ -696,7 +697,7 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
         const int hdiag = hd + sv;
         int h = max(max(hdiag, EN[r]), f);
         if (MODE == ALN_LOCAL) h = max(h, 0);
-        h = ((unsigned)(t - bb[r]) <= (unsigned)wd[r]) ? h : NEG32;
+        if (!NM) h = ((unsigned)(t - bb[r]) <= (unsigned)wd[r]) ? h : NEG32;
         if (ZC) h = at0 ? B[r] : h;
         const int tt = h + goe;
         const int en = max(EN[r] + ge, tt);
@@ -766,15 +767,22 @@ __device__ void band_task(const StripArgs &a, int task, int wave, int lane, uint
     using No = std::integral_constant<bool, false>;
     for (; t8 < tz; t8 += 8) {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) step(Yes{}, No{}, t8 + k, k);
+      for (int k = 0; k < 8; ++k) step(Yes{}, No{}, No{}, t8 + k, k);
     }
+    // a band past the matrix (w >= N: every row's band is 1..N): the groups
+    // whose lanes all lie on columns 1..N (steps 64 .. N - 1) need no mask;
+    // rows past M then hold values no kept result reads
+    const int tnm = w >= N ? N - 8 : -1;
     for (; t8 < T; t8 += 8) {
       if (MODE == ALN_GLOBAL && last && (unsigned)(t_end - t8) < 8u) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) step(No{}, Yes{}, t8 + k, k);
+        for (int k = 0; k < 8; ++k) step(No{}, Yes{}, No{}, t8 + k, k);
+      } else if (t8 <= tnm) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) step(No{}, No{}, Yes{}, t8 + k, k);
       } else {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) step(No{}, No{}, t8 + k, k);
+        for (int k = 0; k < 8; ++k) step(No{}, No{}, No{}, t8 + k, k);
       }
       wbase = wbase + 8 == RB ? 0 : wbase + 8;
     }
