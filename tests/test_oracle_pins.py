@@ -326,6 +326,22 @@ def test_band_cell_count_closed_form_square():
         assert per_k == got["cells"]
 
 
+def test_band_cell_count_closed_form_twice_as_wide():
+    """For N = 2M the band centre is c(i) = 2i, so row i keeps
+    [max(1, 2i - w), min(2M, 2i + w)]: 2w + 1 cells less what the matrix
+    clips.  The top rows lose w + 1 - 2i each while 2i <= w, the bottom rows
+    w - 2u (u = M - i) while 2u < w, so for w < M the count is
+    M(2w+1) - a(w - a) - b(w - b + 1), a = floor(w/2), b = ceil(w/2)."""
+    S = dna_matrix(1, -2)
+    rng = np.random.default_rng(15)
+    for M in (1, 2, 5, 17, 40, 93):
+        for w in sorted({0, 1, 2, 3, M // 2, M - 1} & set(range(M))):
+            q, r = rand_seq(rng, M, 4), rand_seq(rng, 2 * M, 4)
+            got = oracle.align(S, -2, -1, q, r, prune=oracle.BAND, band_w=w)
+            a, b = w // 2, (w + 1) // 2
+            assert got["cells"] == M * (2 * w + 1) - a * (w - a) - b * (w - b + 1), (M, w)
+
+
 # ---------------------------------------------------------------- x-drop
 def xdrop_dict(q, r, S, o, e, X, zdrop=False, detail=None):
     """Second, independent implementation of the X-drop rule: cells kept in a
