@@ -126,6 +126,16 @@ inline size_t band_lds_bytes(int G, int ring_cols, int lds_prof) {
   return G == 1 ? 4 * slot : G * slot + (size_t)kStripCtrWords * G * sizeof(int);
 }
 
+// Traceback region of one side of the sixteen-sides X-drop kernel, nb =
+// ceil((M + N + 1) / 64) blocks of 64 antidiagonals: from byte 0 one byte per
+// antidiagonal (its first and last stored 8-cell group, and the window
+// base's step from the antidiagonal before), from xdl_tb_table(nb) per block
+// an int2 (the stream offset of its first code dword, 16-byte aligned, and
+// the window base of the antidiagonal before it), from xdl_tb_stream(nb) the
+// code dwords of every antidiagonal's stored groups, one after the other.
+__host__ __device__ constexpr int64_t xdl_tb_table(int64_t nb) { return 64 * nb; }
+__host__ __device__ constexpr int64_t xdl_tb_stream(int64_t nb) { return 128 * nb; }
+
 struct WalkArgs {
   BatchPtrs b;
   const PairTask *tasks;
@@ -134,7 +144,7 @@ struct WalkArgs {
   int32_t layout;     // 0: strip layout, 1: diagonal layout, 2: band strips
   int32_t diag_stride; // diagonal layout: code bytes per lane and antidiagonal
                        // pair (8: bands; 2: X-drop / Z-drop, 4 diagonals per lane;
-                       // 1: the sixteen-sides X-drop kernel's 32 bytes per antidiagonal)
+                       // 1: the sixteen-sides X-drop kernel's packed 8-cell groups)
   const int32_t *dyn_ntasks; // device-side task count (a re-run queue), or null
   int32_t band_w;            // layout 2: band half-width
   const DevScoring *sc;

@@ -423,14 +423,19 @@ __global__ __launch_bounds__(64) void walk_strip_wave(WalkArgs a) {
 // i) - dbase(k), lane e / RD, slot e mod RD.  A block is 64 antidiagonals:
 // 2048*S bytes of codes plus 64 window bases.
 //
-// S = 1 is the layout of the sixteen-sides X-drop kernel: per antidiagonal 32
-// bytes, the 64 cells of its window; cell (i, j) of antidiagonal k sits at
-// pos = ((j - i) - dbase(k) - (k & 1)) / 2, byte 8 (pos >> 4) + 4 ((pos >> 3)
-// & 1) + (7 - (pos & 7)) / 2, the high nibble for even pos.  Its low two bits
-// say "not the diagonal" and "not E" (the walk maps them to its diagonal / E
-// / F choice); bits 2 and 3 are the opening bits as in the other layouts.  A
-// pair that overflowed that kernel's window is marked in its task (aux) and
-// walked in the S = 2 layout by the pass that recomputed it.
+// S = 1 is the layout of the sixteen-sides X-drop kernel (xdl_tb_table /
+// xdl_tb_stream): per antidiagonal the code dwords of the 8-cell groups g0 ..
+// g1 of its 64-cell window that hold candidates, packed; a byte per
+// antidiagonal (g0, g1, the window base's step) and per 64 antidiagonals the
+// block's stream offset and the window base before it.  Cell (i, j) of antidiagonal
+// k sits at pos = ((j - i) - dbase(k) - (k & 1)) / 2, in group g = pos >> 3
+// (stored if g0 <= g <= g1) at nibble 7 - (pos & 7), the high nibble of a
+// byte for even pos.  A block's offsets and bases come from prefix sums of
+// the bytes when it is fetched.  Its low two bits say "not the diagonal" and
+// "not E" (the walk maps them to its diagonal / E / F choice); bits 2 and 3
+// are the opening bits as in the other layouts.  A pair that overflowed that
+// kernel's window is marked in its task (aux) and walked in the S = 2 layout
+// by the pass that recomputed it.
 //
 // The walk advances by whole runs.  The two most recent blocks (the one
 // holding the walk's antidiagonal and the one before) stay in two LDS slots,
@@ -450,6 +455,10 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
   // two block slots of 2048*S bytes each (dynamic LDS, sized by the stride,
   // so that narrow layouts let more walks share a CU)
   extern __shared__ __align__(16) uint4 codes_dyn[];
+  // per antidiagonal of a resident block: its window base; S = 1: ((in-block
+  // dword of group 0 + 8) << 6 | g1 << 3 | g0) << 8 | the base minus the
+  // block's (hb), which stays in a register (LDS per walk bounds the walks
+  // per CU)
   __shared__ int dbl[2][64];
   __shared__ uint8_t qwin[256], rwin[256];
   const int lane = threadIdx.x;
@@ -488,30 +497,73 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
   const int nks = (M + N) / 2 + 1; // antidiagonal pairs stored
   const uint8_t *tbp = a.tb + tk.tb_off;
   const int *dbh = reinterpret_cast<const int *>(tbp);
-  const uint4 *cod = reinterpret_cast<const uint4 *>(tbp + (size_t)((nk + 63) / 64) * 64 * 4);
+  const int nblk = (nk + 63) / 64;
+  const uint4 *cod = reinterpret_cast<const uint4 *>(tbp + (S == 1 ? (size_t)xdl_tb_stream(nblk)
+                                                                   : (size_t)nblk * 64 * 4));
+  const int2 *xtab = reinterpret_cast<const int2 *>(tbp + xdl_tb_table(nblk));
   const bool local = a.mode == ALN_LOCAL;
 
   // block cache: slots hold blocks cur and cur - 1; `pre` holds cur - 2
   uint4 pre[kPre];
   int pre_aux = 0, pre_blk = -1, cur = -1;
+  uint32_t pre_meta = 0;                // S = 1: the fetched block's byte of antidiagonal 64b + lane
+  int2 head_next = make_int2(0, 0);     // S = 1: table entry of block head_blk, loaded ahead
+  int head_blk = -1;
+  int hb0 = 0, hb1 = 0;                 // S = 1: window base before the block in slot 0 / 1
   auto fetch = [&](int b) {
-    // uint4 of the block that hold stored antidiagonals
+    // uint4 of the block that hold stored antidiagonals (S = 1: at most 8
+    // dwords per antidiagonal, from the block's 16-byte aligned offset,
+    // whose table entry was loaded with the block before when the walk
+    // goes one block back; nothing fetched is waited for here)
     const int have = S == 1 ? min(64, nk - b * 64) * 2 : min(32, nks - b * 32) * 4 * S;
-    const uint4 *src = cod + (size_t)b * 128 * S; // 2048 S bytes per block
+    int2 head = make_int2(0, 0);
+    if (S == 1) head = head_blk == b ? head_next : xtab[b];
+    const uint4 *src = S == 1 ? cod + (head.x >> 2) : cod + (size_t)b * 128 * S; // 2048 S bytes per block
 #pragma unroll
     for (int m = 0; m < kPre; ++m) {
       const int u = lane + 64 * m;
       if (m < n4) pre[m] = u < have ? src[u] : make_uint4(0u, 0u, 0u, 0u);
     }
-    pre_aux = dbh[b * 64 + lane];
+    if (S == 1) {
+      pre_meta = tbp[b * 64 + lane];
+      pre_aux = head.y;
+      if (b >= 1) {
+        head_next = xtab[b - 1];
+        head_blk = b - 1;
+      }
+    } else {
+      pre_aux = dbh[b * 64 + lane];
+    }
     pre_blk = b;
   };
   auto install = [&](int b) { // put block b (already fetched) into its slot
+    int base_l = pre_aux;
+    if (S == 1) {
+      // lane = antidiagonal 64b + lane: its groups' first dword in the block
+      // and its window base, from prefix sums of group counts and base steps
+      // (the block's entry holds the base of antidiagonal 64b - 1)
+      const int g0 = pre_meta & 7, g1 = (pre_meta >> 3) & 7;
+      const int cnt = g1 + 1 - g0;
+      const int st = (int)(pre_meta << 24) >> 30; // the base's step / 2: 0, 1 or -1
+      // both sums in one (counts stay below 2^16), an inclusive DPP scan:
+      // within rows of 16 lanes, then across rows
+      int v = cnt + st * 65536;
+      v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false); // row_shr:1
+      v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false); // row_shr:2
+      v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false); // row_shr:4
+      v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false); // row_shr:8
+      v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false); // row_bcast:15
+      v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false); // row_bcast:31
+      const int csum = v & 0xffff;
+      base_l = ((((csum - cnt - g0 + 8) << 6) | (g1 << 3) | g0) << 8) | (((v - csum) >> 15) & 0xff);
+      if (b & 1) hb1 = pre_aux;
+      else hb0 = pre_aux;
+    }
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < kPre; ++m)
       if (m < n4) codes_dyn[(b & 1) * 128 * S + lane + 64 * m] = pre[m];
-    dbl[b & 1][lane] = pre_aux;
+    dbl[b & 1][lane] = base_l;
     __syncthreads();
   };
   auto make_resident = [&](int b) { // blocks b and b - 1 resident, b - 2 in flight
@@ -536,14 +588,16 @@ __global__ __launch_bounds__(64) void walk_diag_wave(WalkArgs a) {
     const int kk = ii + jj;
     const int slot = (kk >> 6) & 1;
     if (S == 1) {
-      const int pos = ((jj - ii) - dbl[slot][kk & 63] - (kk & 1)) >> 1;
-      if ((unsigned)pos >= 64u) {
-        bad_lane = true;
-        return 0;
-      }
-      const int byte = slot * blk_bytes + (kk & 63) * 32 + (pos >> 4) * 8 + ((pos >> 3) & 1) * 4 +
-                       ((7 - (pos & 7)) >> 1);
-      const int c = (codes0[byte] >> (((7 - (pos & 7)) & 1) * 4)) & 15;
+      const int x = dbl[slot][kk & 63], go = x >> 8;
+      const int pos = ((jj - ii) - (slot ? hb1 : hb0) - (int)(int8_t)(x & 0xff) - (kk & 1)) >> 1;
+      const int g = pos >> 3;
+      // outside the window, or a group without candidates: the (in-slot)
+      // byte read is not used
+      const bool out = (unsigned)pos >= 64u || g < (go & 7) || g > ((go >> 3) & 7);
+      bad_lane |= out;
+      const int dw = ((go >> 6) - 8 + g) & 511;
+      const int byte = slot * blk_bytes + dw * 4 + ((7 - (pos & 7)) >> 1);
+      const int c = out ? 0 : (codes0[byte] >> (((7 - (pos & 7)) & 1) * 4)) & 15;
       // not-diagonal, not-E -> 0 diagonal, 1 E, 2 F
       return (c & 12) | ((c & 1) + (c & (c >> 1) & 1));
     }

@@ -42,9 +42,13 @@
 // side in LDS rings (query reversed) and read as one unaligned 16-byte run
 // per lane and antidiagonal.
 //
-// Traceback codes (the form with CIGAR): per antidiagonal and side 32 bytes,
-// 8 per lane, written whole by the side's four lanes, plus the window base
-// (the bases of 8 antidiagonals stored together).  Cell m of a lane sits in dword m >> 3 at nibble 7 - (m & 7);
+// Traceback codes (the form with CIGAR): per antidiagonal and side only the
+// 8-cell groups (one code dword each) that hold candidate cells, packed one
+// antidiagonal after the other; per antidiagonal a byte with its first and
+// last group and the window base's step, per 64 antidiagonals the stream
+// offset and the window base (the layout of xdl_tb_table / xdl_tb_stream).
+// Lane gl's groups are 2gl and 2gl + 1; cell m of a lane sits in its group
+// m >> 3 at nibble 7 - (m & 7);
 // its bits, high to low: F passed down opened from H (F-open), E passed right
 // opened from H (E-open), H not from E, H not from the diagonal -- so H takes
 // the diagonal, then E, then F, and a gap opens before it extends.  The codes
@@ -169,9 +173,11 @@ xdrop_lanes_kernel(XdlArgs a) {
   uint32_t best_key = 0; // its cell: (0xffff - i) << 16 | (0xffff - j)
   long long cells = 0;
   const uint8_t *Q = nullptr, *R = nullptr;
-  int *tb_base = nullptr;   // traceback: window base per antidiagonal
-  int bb0 = 0, bb1 = 0;     // traceback: two window bases awaiting their store
-  uint2 *tb_codes = nullptr; // traceback: 4 x 8 bytes per antidiagonal
+  // traceback: one byte per antidiagonal, a table entry per 64, the codes
+  uint8_t *tb_meta = nullptr; // the side's region
+  int tcur = 0;               // byte offset in the region of the next code dword
+  int bprev = 0;              // window base of the antidiagonal before
+  uint32_t mlo = 0, mhi = 0;  // lane gl: bytes of antidiagonals 32n + 8gl .. + 7, newest on top
 
   // 32 codes per call into a ring (the query reversed), padding (4) past
   // the sequence; lane gl stages codes top + 8gl .. top + 8gl + 7
@@ -227,10 +233,14 @@ xdrop_lanes_kernel(XdlArgs a) {
             Q = a.b.q + a.b.q_off[pair];
             R = a.b.r + a.b.r_off[pair];
             if (TB) {
-              const int nk = M + N + 1;
+              const int nb = (M + N + 1 + 63) / 64;
               uint8_t *tbp = a.tb + a.tasks[t].tb_off;
-              tb_base = reinterpret_cast<int *>(tbp);
-              tb_codes = reinterpret_cast<uint2 *>(tbp + (size_t)((nk + 63) / 64) * 64 * 4);
+              tb_meta = tbp;
+              tcur = (int)xdl_tb_stream(nb);
+              bprev = -64; // the first window base, set below
+              mlo = 0;
+              mhi = 1u << 24; // antidiagonal 0: no groups (first 1, last 0)
+              if (qfirst) *reinterpret_cast<int2 *>(tbp + xdl_tb_table(nb)) = make_int2(0, -64);
             }
             fresh = true; // arrays reset below, outside this loop
             base = -64;
@@ -367,17 +377,40 @@ xdrop_lanes_kernel(XdlArgs a) {
         }
       }
       if (TB && active) {
-        // every lane of the side stores, so each antidiagonal's 32 bytes go
-        // out whole (a lane without candidates stores codes no walk reads)
-        tb_codes[(size_t)k * 4 + gl] = make_uint2(code0, code1);
-        // window bases: lane gl keeps those of antidiagonals 8n + 2gl and
-        // 8n + 2gl + 1; the side's four lanes store 8 at once (32 bytes)
-        const int kr = k & 7;
-        if (gl == (kr >> 1)) {
-          if (kr & 1) bb1 = base;
-          else bb0 = base;
+        // only the 8-cell groups g0 .. g1 that hold candidates are stored
+        // (a walk reads survivors only), after the antidiagonal before's
+        const int g0 = plo >> 3, span = (phi >> 3) - g0;
+        const int e0 = 2 * gl - g0; // stream slot of this lane's first group
+        uint32_t *dst = reinterpret_cast<uint32_t *>(tb_meta + (tcur + 4 * e0));
+        if ((unsigned)e0 <= (unsigned)span) dst[0] = code0;
+        if ((unsigned)(e0 + 1) <= (unsigned)span) dst[1] = code1;
+        tcur += 4 * (span + 1);
+        // the antidiagonal's byte: g0 (bits 0-2), g1 (3-5) and the window
+        // base's step from the antidiagonal before, (base - bprev) / 2 in
+        // two's complement (bits 6-7).  Lane gl collects those of its 8 of
+        // every 32 antidiagonals, and the side's four lanes store the 32
+        // bytes at once (one whole memory sector: smaller stores cost as
+        // much each)
+        const uint32_t mbyte = ((uint32_t)plo >> 3) | ((uint32_t)phi & 0x38u) |
+                               (((uint32_t)(base - bprev) << 5) & 0xc0u);
+        bprev = base;
+        if (((k >> 3) & 3) == gl) {
+          mlo = __builtin_amdgcn_alignbit(mhi, mlo, 8);
+          mhi = __builtin_amdgcn_alignbit(mbyte, mhi, 8);
         }
-        if (kr == 7) *reinterpret_cast<uint2 *>(tb_base + (k - 7) + 2 * gl) = make_uint2(bb0, bb1);
+        if ((k & 31) == 31) {
+          *reinterpret_cast<uint2 *>(tb_meta + (k - 31) + 8 * gl) = make_uint2(mlo, mhi);
+          if ((k & 63) == 63) {
+            // the next block starts on a 16-byte boundary; its entry holds
+            // the base of its antidiagonal before (the table has room for
+            // one entry past the last block)
+            tcur = (tcur + 15) & ~15;
+            const int nb = (M + N + 64) >> 6;
+            if (qfirst)
+              reinterpret_cast<int2 *>(tb_meta + xdl_tb_table(nb))[(k + 1) >> 6] =
+                  make_int2((tcur - (int)xdl_tb_stream(nb)) >> 2, base);
+          }
+        }
       }
       sb &= inr_rev;
       // ---- the antidiagonal's outcome per side
@@ -409,10 +442,11 @@ xdrop_lanes_kernel(XdlArgs a) {
       const bool wide = cont && nhi - nlo > 63;
       if (active && (!cont || wide)) {
         // the extension ends here (or leaves for a wider window)
-        if (TB && (k & 7) != 7) { // the window bases of the last, partial group
-          const int kr = k & 7, at = (k - kr) + 2 * gl;
-          if (2 * gl + 1 <= kr) *reinterpret_cast<uint2 *>(tb_base + at) = make_uint2(bb0, bb1);
-          else if (2 * gl == kr) tb_base[at] = bb0;
+        if (TB && (k & 31) != 31 && 8 * gl <= (k & 31)) { // the bytes of the last, partial 32
+          const int sh = 8 * gl + 7 > (k & 31) ? 8 * (7 - (k & 7)) : 0; // a partial 8
+          const unsigned long long m8 = ((unsigned long long)mhi << 32 | mlo) >> sh;
+          *reinterpret_cast<uint2 *>(tb_meta + (k & ~31) + 8 * gl) =
+              make_uint2((uint32_t)m8, (uint32_t)(m8 >> 32));
         }
         if (qfirst) {
           aln_result *res = a.res + pair;
