@@ -491,47 +491,50 @@ xdrop_lanes_kernel(XdlArgs a) {
       // ---- keep the candidates inside the window: slide by one cell.  The
       // live arrays are both H and the E / F just written.
       const bool sup = active && plo < 0, sdn = active && phi > 63;
-      if (__ballot(sup)) {
-        if (sup) { // base -= 2: every pos moves up one
+      // The shifts are selects in place under a wave-uniform branch: a
+      // branch on the side's own flag made the compiler copy every array at
+      // its join on every antidiagonal (about 100 moves per lane).
+      if (__ballot(sup)) { // base -= 2: every pos moves up one
 #define XD_SLIDE_UP(A)                                                                      \
   {                                                                                         \
     const int c = quad_shr1(A[XC - 1], XNEG, qfirst);                                       \
-    _Pragma("unroll") for (int m = XC - 1; m > 0; --m) A[m] = A[m - 1];                     \
-    A[0] = c;                                                                               \
+    _Pragma("unroll") for (int m = XC - 1; m > 0; --m) A[m] = sup ? A[m - 1] : A[m];        \
+    A[0] = sup ? c : A[0];                                                                  \
   }
-          XD_SLIDE_UP(H0)
-          XD_SLIDE_UP(H1)
-          if (P == 0) {
-            XD_SLIDE_UP(E0)
-            XD_SLIDE_UP(F0)
-          } else {
-            XD_SLIDE_UP(E1)
-            XD_SLIDE_UP(F1)
-          }
+        XD_SLIDE_UP(H0)
+        XD_SLIDE_UP(H1)
+        if (P == 0) {
+          XD_SLIDE_UP(E0)
+          XD_SLIDE_UP(F0)
+        } else {
+          XD_SLIDE_UP(E1)
+          XD_SLIDE_UP(F1)
+        }
 #undef XD_SLIDE_UP
+        if (sup) {
           base -= 2;
           plo += 1;
           phi += 1;
         }
       }
-      if (__ballot(sdn)) {
-        if (sdn) { // base += 2: every pos moves down one
+      if (__ballot(sdn)) { // base += 2: every pos moves down one
 #define XD_SLIDE_DOWN(A)                                                                    \
   {                                                                                         \
     const int c = quad_shl1(A[0], XNEG, qlast);                                             \
-    _Pragma("unroll") for (int m = 0; m < XC - 1; ++m) A[m] = A[m + 1];                     \
-    A[XC - 1] = c;                                                                          \
+    _Pragma("unroll") for (int m = 0; m < XC - 1; ++m) A[m] = sdn ? A[m + 1] : A[m];        \
+    A[XC - 1] = sdn ? c : A[XC - 1];                                                        \
   }
-          XD_SLIDE_DOWN(H0)
-          XD_SLIDE_DOWN(H1)
-          if (P == 0) {
-            XD_SLIDE_DOWN(E0)
-            XD_SLIDE_DOWN(F0)
-          } else {
-            XD_SLIDE_DOWN(E1)
-            XD_SLIDE_DOWN(F1)
-          }
+        XD_SLIDE_DOWN(H0)
+        XD_SLIDE_DOWN(H1)
+        if (P == 0) {
+          XD_SLIDE_DOWN(E0)
+          XD_SLIDE_DOWN(F0)
+        } else {
+          XD_SLIDE_DOWN(E1)
+          XD_SLIDE_DOWN(F1)
+        }
 #undef XD_SLIDE_DOWN
+        if (sdn) {
           base += 2;
           plo -= 1;
           phi -= 1;
