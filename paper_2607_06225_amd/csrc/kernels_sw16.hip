@@ -301,15 +301,17 @@ __device__ __forceinline__ void sw16_item(const Sw16Args &a, int8_t *prof, const
         }
         uint32_t tu = pk_subsat_u16(in_h, goe2);
         uint32_t fu = in_f;
-        const uint32_t jinv = (0xffffu - (uint32_t)j) & 0xffffu;
+        // 0xffff - j in the low half (the keys take only that half)
+        const uint32_t jinv = 0xffffu - (uint32_t)j;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const uint32_t f = pk_max_i16(pk_add_16(fu, ge2), tu);
           const uint32_t h = pk_max_i16(pk_max_i16(hdg[r], EN[r]), f);
           const uint32_t tt = pk_subsat_u16(h, goe2);
           const uint32_t en = pk_max_i16(pk_add_16(EN[r], ge2), tt);
-          const uint32_t keyA = (h << 16) | jinv;
-          const uint32_t keyB = (h & 0xffff0000u) | jinv;
+          // bytes (high to low): pair A's H, then jinv; pair B's H, then jinv
+          const uint32_t keyA = __builtin_amdgcn_perm(h, jinv, 0x05040100u);
+          const uint32_t keyB = __builtin_amdgcn_perm(h, jinv, 0x07060100u);
           if constexpr (odd) {
             kA[r] = max(kA[r], max(pA[r], keyA));
             kB[r] = max(kB[r], max(pB[r], keyB));
