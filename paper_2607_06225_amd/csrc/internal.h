@@ -100,7 +100,8 @@ __host__ __device__ inline int band_centre(int64_t i, int32_t M, int32_t N) {
 // (R = 4: 16 bytes, stored as each 8 steps end; R = 2: 64 bytes, 64 steps,
 // since a lane's 128-byte line then takes 128 steps to fill and smaller
 // stores leave partly written lines to the memory: 133 GB written for 31 GB
-// of band_long codes with 8-byte stores, 44 GB with 64-byte ones)
+// of band_long codes with 8-byte stores, 51.6 GB with 32-byte ones (whole
+// sectors, and a window of 576 steps instead of 640), 44 GB with 64-byte ones)
 __host__ __device__ constexpr int band_code_piece(int R) { return R == 2 ? 64 : 16; }
 __host__ __device__ inline int band_code_align(int R) { return band_code_piece(R) * 2 / R; }
 __host__ __device__ inline int band_code_steps(int32_t M, int32_t N, int32_t w, int R) {
