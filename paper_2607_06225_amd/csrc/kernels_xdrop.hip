@@ -142,8 +142,10 @@ __device__ __forceinline__ uint32_t byte_reverse(uint32_t x) {
 // above is made explicit: H, E and F of a removed cell or of a cell outside
 // the candidate range are minus infinity, and only kept cells enter the
 // antidiagonal's best.
+// Four wavefronts per SIMD for the X-drop score form (128 VGPRs, no spill in
+// the step), three with codes or Z-drop (they need more registers)
 template <bool TB, bool ZD>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TB || ZD ? 3 : 4))) void
 xdrop_lanes_kernel(XdlArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int lane = threadIdx.x & 63;
